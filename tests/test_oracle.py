@@ -1,0 +1,262 @@
+"""Pins for the oracle: every check here compares the oracle against
+something other than itself (paper values, closed forms, brute force on
+tiny inputs, an independent enumeration route, invariants)."""
+import os
+from itertools import combinations, permutations
+from math import comb, factorial
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle import P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            rows.append(line.split())
+    return rows
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built(oracle_lib):
+    return oracle_lib
+
+
+def test_pattern_universe_pins():
+    names = oracle.named_4()
+    for row in _read_golden("pattern_pins.txt"):
+        if row[0] == "connected_classes":
+            assert len(P.connected_classes(int(row[1]))) == int(row[2])
+        elif row[0] == "connected_labelled":
+            assert P.labeled_connected_count(int(row[1])) == int(row[2])
+        elif row[0] == "aut":
+            assert P.num_automorphisms(4, names[row[1]]) == int(row[2])
+
+
+def test_paper_coefficients():
+    names = oracle.named_4()
+    for p, q, c in _read_golden("paper_coefficients.txt"):
+        assert P.coefficient(4, names[p], names[q]) == int(c), (p, q)
+
+
+def test_pr_e2_equation():
+    # PR-E2 (Section 3.1): C4^E = C4^V + D^V + 3 K4 -- the forward morph row
+    names = oracle.named_4()
+    cls, mat = P.morph_matrix(4)
+    row = dict(zip(cls, mat[cls.index(names["cycle4"])]))
+    expect = {m: 0 for m in cls}
+    expect[names["cycle4"]] = 1
+    expect[names["diamond"]] = 1
+    expect[names["clique4"]] = 3
+    assert row == expect
+
+
+def _copies_by_edge_subsets(k, p_mask, q_mask):
+    """Distinct copies of p inside q, counted by enumerating edge subsets of
+    q and testing isomorphism on the k fixed vertices -- a route that never
+    forms phi or Aut."""
+    q_edges = P.edges_of(k, q_mask)
+    target = P.canonical(k, p_mask)[0]
+    ne = P.edge_count(p_mask)
+    cnt = 0
+    for sub in combinations(q_edges, ne):
+        m = 0
+        for i, j in sub:
+            m |= 1 << P.pair_bit(i, j)
+        if P.canonical(k, m)[0] == target:
+            cnt += 1
+    return cnt
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_coefficients_independent_routes(k):
+    cls = P.connected_classes(k)
+    for p in cls:
+        for q in cls:
+            c = P.coefficient(k, p, q)
+            assert c == _copies_by_edge_subsets(k, p, q)
+        # clique superpattern: every permutation is an injection
+        assert P.coefficient(k, p, P.clique_mask(k)) == factorial(k) // P.num_automorphisms(k, p)
+        assert P.coefficient(k, p, p) == 1
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_coefficients_are_edge_induced_counts_in_q(k):
+    # c(p, q) equals the number of edge-induced p-subgraphs of the data graph q
+    cls = P.connected_classes(k)
+    for q in cls:
+        g = gen.graph_from_mask(k, q)
+        for p in cls:
+            assert oracle.count(g, k, p, induced=False) == P.coefficient(k, p, q)
+
+
+def test_triangles_and_stars_closed_forms():
+    for seed in range(3):
+        g = gen.erdos_renyi(30, 0.3, seed)
+        A = np.zeros((g.n, g.n), dtype=np.int64)
+        for u, v in g.edges():
+            A[u, v] = A[v, u] = 1
+        tri = int(np.trace(A @ A @ A)) // 6
+        assert oracle.count(g, 3, P.clique_mask(3), induced=True) == tri
+        d = g.degrees()
+        star = [m for m in P.connected_classes(4) if P.num_automorphisms(4, m) == 6][0]
+        assert oracle.count(g, 4, star, induced=False) == sum(comb(int(x), 3) for x in d)
+        wedge = [m for m in P.connected_classes(3) if P.edge_count(m) == 2][0]
+        assert oracle.count(g, 3, wedge, induced=False) == sum(comb(int(x), 2) for x in d)
+        # tr(A^4) = 8 C4 + 2m + 4 sum C(d,2)
+        c4 = oracle.named_4()["cycle4"]
+        tr4 = int(np.trace(A @ A @ A @ A))
+        m = g.m
+        assert tr4 == 8 * oracle.count(g, 4, c4, False) + 2 * m + 4 * sum(comb(int(x), 2) for x in d)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_complete_graph(k):
+    N = 7
+    g = gen.complete_graph(N)
+    for p in P.connected_classes(k):
+        assert oracle.count(g, k, p, False) == comb(N, k) * factorial(k) // P.num_automorphisms(k, p)
+        expect_v = comb(N, k) if p == P.clique_mask(k) else 0
+        assert oracle.count(g, k, p, True) == expect_v
+
+
+def test_complete_bipartite_and_cycles():
+    g = gen.complete_bipartite(4, 5)
+    names = oracle.named_4()
+    assert oracle.count(g, 3, P.clique_mask(3), True) == 0
+    assert oracle.count(g, 4, names["cycle4"], True) == comb(4, 2) * comb(5, 2)
+    c = gen.cycle_graph(9)
+    assert oracle.count(c, 4, names["path4"], True) == 9
+    assert oracle.count(c, 4, names["path4"], False) == 9
+    assert oracle.count(c, 4, names["star3"], False) == 0
+    s = gen.star_graph(6)
+    assert oracle.count(s, 4, names["star3"], True) == comb(6, 3)
+
+
+def test_exhaustive_five_vertex_graphs_census_and_morph():
+    """Every graph on 5 vertices: tier A vertex-induced == census; all
+    k-subsets sum to C(n, k); Theorem 3.1 forward holds; Corollary 3.1
+    back-substitution recovers the vertex-induced counts."""
+    for k in (3, 4):
+        cls = P.connected_classes(k)
+        for mask in range(1 << 10):
+            g = gen.graph_from_mask(5, mask)
+            vi = {p: oracle.count(g, k, p, True) for p in cls}
+            ei = {p: oracle.count(g, k, p, False) for p in cls}
+            assert vi == oracle.census(g, k)
+            assert P.edge_induced_from_vertex_induced(k, vi) == ei
+            assert P.vertex_induced_from_edge_induced(k, ei) == vi
+            full = oracle.full_census_tiny(g, k)
+            assert sum(full.values()) == comb(5, k)
+            for p in cls:
+                assert full[p] == vi[p]
+
+
+def test_five_vertex_morph_on_graphs_with_six_vertices():
+    rng = np.random.default_rng(5)
+    cls = P.connected_classes(5)
+    for _ in range(40):
+        mask = int(rng.integers(0, 1 << 15))
+        g = gen.graph_from_mask(6, mask)
+        vi = {p: oracle.count(g, 5, p, True) for p in cls}
+        ei = {p: oracle.count(g, 5, p, False) for p in cls}
+        assert vi == oracle.census(g, 5)
+        assert P.edge_induced_from_vertex_induced(5, vi) == ei
+        assert P.vertex_induced_from_edge_induced(5, ei) == vi
+        full = oracle.full_census_tiny(g, 5)
+        assert sum(full.values()) == comb(6, 5)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_graphs_tiers_agree(seed):
+    g = gen.erdos_renyi(60, 0.15, seed)
+    for k in (4, 5):
+        vi = oracle.motif_counts(g, k, True)
+        assert vi == oracle.census(g, k)
+        ei = oracle.motif_counts(g, k, False)
+        assert P.edge_induced_from_vertex_induced(k, vi) == ei
+    assert oracle.edge_induced_4_from_tier_c(g) == oracle.motif_counts(g, 4, False)
+
+
+def test_tier_c_on_skewed_graph():
+    g = gen.rmat(9, 8, seed=7)
+    assert oracle.edge_induced_4_from_tier_c(g) == oracle.motif_counts(g, 4, False)
+
+
+def test_relabel_invariance():
+    g = gen.erdos_renyi(50, 0.2, 9)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(g.n)
+    e = g.edges()
+    h = gen.from_edges(g.n, perm[e[:, 0]], perm[e[:, 1]])
+    assert oracle.motif_counts(g, 4, True) == oracle.motif_counts(h, 4, True)
+
+
+def test_labeled_counts_sum_to_unlabeled():
+    g = gen.erdos_renyi(40, 0.2, 3)
+    L = 3
+    g = g.with_labels(gen.zipf_labels(g.n, L, 1.2, 4))
+    for k in (3, 4):
+        for p in P.connected_classes(k):
+            unl = oracle.count_maps(g, k, p, False)
+            tot = 0
+            for labs in np.ndindex(*([L] * k)):
+                tot += oracle.count_maps(g, k, p, False, plabels=list(labs))
+            assert tot == unl
+
+
+def test_mni_pins():
+    # one-edge pattern (a, b): support = min(#distinct a-endpoints,
+    # #distinct b-endpoints) over edges whose endpoints carry (a, b)
+    g = gen.erdos_renyi(40, 0.1, 2).with_labels(gen.zipf_labels(40, 3, 1.2, 5))
+    lab = g.labels
+    for a in range(3):
+        for b in range(3):
+            ends_a, ends_b = set(), set()
+            for u, v in g.edges():
+                for x, y in ((u, v), (v, u)):
+                    if lab[x] == a and lab[y] == b:
+                        ends_a.add(x)
+                        ends_b.add(y)
+            expect = min(len(ends_a), len(ends_b))
+            assert oracle.mni_support(g, 2, 1, False, [a, b]) == expect
+    # K_N with one label: every vertex is in every domain
+    kn = gen.complete_graph(6).with_labels(np.zeros(6, dtype=np.uint8))
+    for p in P.connected_classes(4):
+        assert oracle.mni_support(kn, 4, p, False, [0] * 4) == 6
+    # a star with N >= 3 leaves and the 3-star pattern: the centre column has 1
+    s = gen.star_graph(5).with_labels(np.zeros(6, dtype=np.uint8))
+    star = oracle.named_4()["star3"]
+    assert oracle.mni_support(s, 4, star, False, [0] * 4) == 1
+
+
+def test_mni_anti_monotone():
+    g = gen.erdos_renyi(35, 0.15, 8).with_labels(np.zeros(35, dtype=np.uint8))
+    names = oracle.named_4()
+    # path4 is a subpattern of cycle4 and tailed_triangle (same vertex count)
+    sp = oracle.mni_support(g, 4, names["path4"], False, [0] * 4)
+    for sup in ("cycle4", "tailed_triangle", "diamond"):
+        assert sp >= oracle.mni_support(g, 4, names[sup], False, [0] * 4)
+
+
+def test_planted_mistake_is_caught():
+    """A dropped term in the back-substitution must break the identity."""
+    g = gen.erdos_renyi(30, 0.3, 11)
+    ei = oracle.motif_counts(g, 4, False)
+    vi = oracle.motif_counts(g, 4, True)
+    names = oracle.named_4()
+    good = P.vertex_induced_from_edge_induced(4, ei)
+    assert good == vi
+    bad = dict(good)
+    bad[names["cycle4"]] = ei[names["cycle4"]] - good[names["diamond"]]  # drop 3*K4
+    if vi[names["clique4"]]:
+        assert bad != vi
