@@ -1,0 +1,205 @@
+/*
+ * pm.h -- C-ABI of the MI355X pattern-morphing subgraph-counting engine.
+ *
+ * The operations follow the paper's statement of the problem (Pattern
+ * Morphing for Efficient Graph Mining, Jamshidi & Vora):
+ *   - a data graph is a simple undirected graph, optionally vertex-labeled
+ *     (Preliminaries, "Graph Isomorphism");
+ *   - a query is a set of patterns, each vertex- or edge-induced and labeled
+ *     or not (Preliminaries, "Pattern Semantics");
+ *   - the result is one aggregation value per pattern: the number of
+ *     distinct matched subgraphs (Motif Counting) or the minimum-node-image
+ *     support (Frequent Subgraph Mining) (Preliminaries, "Graph Mining
+ *     Applications");
+ *   - morphing rewrites the query into an alternative pattern set and
+ *     converts the results back (Section 3.2, Theorems 3.1/3.2,
+ *     Corollary 3.1; Section 4.1 "external module" (a) and (b)).
+ *
+ * Conventions.
+ *   - Every function returns pm_status: 0 = PM_OK, negative = error.  No C++
+ *     exception crosses this boundary.  On error the thread-local message is
+ *     available from pm_last_error().
+ *   - "device pointer" = memory of the HIP device the context was created
+ *     on; "host pointer" = ordinary process memory.  Every pointer argument
+ *     is a host pointer unless stated otherwise.
+ *   - Vertex ids are uint32.  Counts are exact int64; any value (or any
+ *     intermediate of the morph conversion) outside int64 is reported as
+ *     PM_E_OVERFLOW rather than wrapped.
+ *   - A pattern edge between pattern vertices i < j is bit j*(j-1)/2 + i of
+ *     pm_pattern.edge_mask.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pm_ctx pm_ctx;
+typedef int32_t pm_status;
+
+enum {
+    PM_OK = 0,
+    PM_E_INVAL = -1,        /* malformed argument, graph or pattern          */
+    PM_E_NOMEM = -2,        /* the caller's arena cannot hold the request    */
+    PM_E_OVERFLOW = -3,     /* a count or conversion left int64               */
+    PM_E_UNSUPPORTED = -4,  /* e.g. disconnected pattern, k outside 2..5      */
+    PM_E_DEVICE = -5,       /* a HIP runtime call failed                      */
+    PM_E_BUSY = -6,         /* graph unload while queries are in flight       */
+    PM_E_TIMEOUT = -7,      /* pm_wait timed out (the query keeps running)    */
+    PM_E_CANCELLED = -8,    /* the query was cancelled by pm_cancel           */
+    PM_E_NOTFOUND = -9      /* unknown graph id or ticket                     */
+};
+
+/* Induced-ness of a pattern (Preliminaries, "Pattern Semantics"): a
+ * vertex-induced pattern carries an anti-edge on every non-adjacent pair,
+ * an edge-induced pattern carries none. */
+enum { PM_EDGE_INDUCED = 0, PM_VERTEX_INDUCED = 1 };
+
+/* Aggregation (Section 3.2.3): COUNT = number of distinct matched subgraphs
+ * (#matches / #label-preserving automorphisms); MNI = minimum node image
+ * support (smallest per-pattern-vertex domain, Preliminaries, FSM). */
+enum { PM_AGG_COUNT = 0, PM_AGG_MNI = 1 };
+
+/* Morph mode: NONE matches the query patterns as given ("No PMR",
+ * Section 4.2); NAIVE matches the alternative set of Section 4.2's "Naive
+ * PMR": vertex-induced patterns become their same-size edge-induced
+ * superpatterns plus the clique, converted back by Corollary 3.1. */
+enum { PM_MORPH_NONE = 0, PM_MORPH_NAIVE = 1 };
+
+typedef struct {
+    uint32_t k;          /* number of pattern vertices, 2..5                 */
+    uint32_t edge_mask;  /* bit j*(j-1)/2+i set = edge (i, j); connected     */
+    uint32_t induce;     /* PM_EDGE_INDUCED or PM_VERTEX_INDUCED             */
+    int32_t label[8];    /* label of each pattern vertex, -1 = any label     */
+} pm_pattern;
+
+typedef struct {
+    uint32_t n;             /* vertices                                      */
+    uint64_t m;             /* undirected edges                              */
+    uint32_t max_degree;
+    uint32_t max_out_degree; /* in the degree-ordered orientation            */
+    uint32_t labeled;       /* 1 when labels were given                      */
+    uint64_t device_bytes;  /* arena bytes held by the resident graph        */
+} pm_graph_info;
+
+typedef struct {
+    double plan_ms;          /* host planning (morph + plan compile)         */
+    double kernel_ms;        /* device time of the matching launch(es)       */
+    double total_ms;         /* submit -> results ready, incl. unmorph       */
+    uint64_t alg_bytes;      /* algorithmic bytes of the executed plans      */
+    uint64_t work_items;     /* work items processed                         */
+    uint32_t num_alt;        /* patterns actually matched                    */
+    uint32_t launches;       /* kernel launches of the query                 */
+} pm_query_stats;
+
+/* Create a context on HIP device `device`.  `dev_arena` (device pointer,
+ * `arena_bytes` long, 256-byte aligned) is memory the caller owns (e.g. a
+ * torch tensor); every device allocation of the engine is carved from it,
+ * so it must outlive the context.  `hip_stream` is a hipStream_t owned by
+ * the caller on which all work is issued (NULL = the null stream).
+ * Errors: PM_E_INVAL (null out, misaligned arena), PM_E_DEVICE. */
+pm_status pm_create(void* dev_arena, uint64_t arena_bytes, void* hip_stream,
+                    int device, pm_ctx** out);
+
+/* Waits for in-flight work, then frees host state.  The arena and stream
+ * stay the caller's. */
+pm_status pm_destroy(pm_ctx* ctx);
+
+/* Load a graph: `row_ptr` (n+1 entries) and `col` (row_ptr[n] entries) are
+ * a host CSR of a simple undirected graph: each row strictly ascending, no
+ * self-loops, symmetric.  `labels` (n bytes) may be NULL.  The arrays are
+ * copied: the engine validates them, relabels vertices by (degree, id)
+ * rank (degree-ordered CSR), and keeps the result resident in the arena.
+ * Vertex ids in results (none for COUNT/MNI) refer to the caller's ids.
+ * Errors: PM_E_INVAL (asymmetric, unsorted, self-loop, duplicate, id out of
+ * range, row_ptr[n] >= 2^32), PM_E_NOMEM, PM_E_DEVICE. */
+pm_status pm_graph_load(pm_ctx* ctx, uint32_t n, const uint32_t* row_ptr,
+                        const uint32_t* col, const uint8_t* labels,
+                        uint32_t* out_graph_id);
+
+/* Release a graph.  PM_E_BUSY while queries on it are in flight. */
+pm_status pm_graph_unload(pm_ctx* ctx, uint32_t graph_id);
+
+pm_status pm_graph_stats(pm_ctx* ctx, uint32_t graph_id, pm_graph_info* out);
+
+/* Arena bytes a query would need beyond the resident graph. */
+pm_status pm_query_footprint(pm_ctx* ctx, uint32_t graph_id,
+                             const pm_pattern* pats, uint32_t npat, int32_t agg,
+                             int32_t morph, uint64_t* out_bytes);
+
+/* Submit a query (asynchronous).  `pats` is copied.  The ticket identifies
+ * it for pm_wait / pm_cancel.  Errors: PM_E_INVAL, PM_E_UNSUPPORTED,
+ * PM_E_NOTFOUND (graph), PM_E_NOMEM (footprint exceeds the free arena). */
+pm_status pm_submit(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
+                    uint32_t npat, int32_t agg, int32_t morph,
+                    uint64_t* out_ticket);
+
+/* Wait for a query; on PM_OK writes npat int64 values (counts or MNI
+ * supports, in the order submitted) to `out_values` (host) and releases the
+ * ticket.  timeout_us < 0 waits forever.  PM_E_TIMEOUT leaves the ticket
+ * valid.  PM_E_OVERFLOW / PM_E_CANCELLED release it. */
+pm_status pm_wait(pm_ctx* ctx, uint64_t ticket, int64_t* out_values,
+                  int64_t timeout_us);
+
+/* Optional statistics of the last pm_wait'ed query (call before the next). */
+pm_status pm_last_query_stats(pm_ctx* ctx, pm_query_stats* out);
+
+/* Request cancellation; the kernel drains its remaining work items. */
+pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket);
+
+/* Host-only morph planning (Section 4.1 (a); Section 4.2 "Naive PMR").
+ * For the `npat` query patterns (all with the same k, unlabeled or
+ * labeled), writes the alternative patterns to `out_alt` (capacity
+ * *inout_nalt, updated to the count used) and the integer conversion
+ * matrix to `out_matrix` (row-major npat x nalt, host): value(query i) =
+ * sum_j out_matrix[i*nalt + j] * count(alt j).  For MNI only edge-induced
+ * queries are morphed (to vertex-induced superpatterns, Theorem 3.2); the
+ * matrix is then unused.  Errors: PM_E_INVAL (capacity), PM_E_UNSUPPORTED. */
+pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg,
+                        int32_t morph, pm_pattern* out_alt, uint32_t* inout_nalt,
+                        int64_t* out_matrix);
+
+/* Labeled 3-edge frequent subgraph mining with MNI support (Preliminaries,
+ * FSM).  Computes the support of every edge-induced labeled pattern with 3
+ * edges (the triangle, the 3-edge path and the 3-star) over the graph's
+ * `num_labels` labels, in the dense slot order documented with
+ * pm_fsm_slot(); `out_support` (host, nslots int64) receives the supports;
+ * `out_frequent` (host, nslots bytes, may be NULL) receives support >=
+ * threshold.  morph = PM_MORPH_NAIVE takes the vertex-induced route
+ * (Theorem 3.2 with union as the join). */
+pm_status pm_fsm(pm_ctx* ctx, uint32_t graph_id, uint32_t num_labels,
+                 int64_t threshold, int32_t morph, int64_t* out_support,
+                 uint8_t* out_frequent, uint64_t nslots);
+
+/* Number of FSM slots for `num_labels` labels, and the pattern of slot s. */
+uint64_t pm_fsm_num_slots(uint32_t num_labels);
+pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
+
+/* Engine options (tuning knobs of the implementation, not of the method):
+ *   "count_bytes"   0/1: before each query run an untimed pass of the same
+ *                   kernel that tallies algorithmic bytes (see
+ *                   pm_last_query_stats);
+ *   "blocks_per_cu" persistent blocks per compute unit (1..64);
+ *   "item_budget"   adjacency entries per root-range work item (>= 1);
+ *   "item_split"    level-1 slice length for high-degree roots (>= 64);
+ *                   takes effect for graphs loaded afterwards;
+ *   "agg_waves"     wavefronts of two-hop aggregation launches (>= 1).
+ * Errors: PM_E_INVAL for an unknown key or a value out of range. */
+pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value);
+
+/* Writes a NUL-terminated description of the matching plan the engine
+ * compiles for `pat` on graph `graph_id` (core order, per-level set
+ * operations and bounds, tail terms) into `buf` (capacity `cap`). */
+pm_status pm_plan_describe(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pat,
+                           char* buf, uint64_t cap);
+
+const char* pm_last_error(void);
+const char* pm_status_str(pm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

@@ -1,0 +1,226 @@
+"""ctypes binding of libpm.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts Python
+values to the C-ABI declared in include/pm.h and back.  PyTorch provides the
+device arena (one uint8 tensor) and the stream.  There is no fallback: when
+the library is missing or cannot be loaded, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpm.so")
+
+PM_OK = 0
+STATUS = {0: "PM_OK", -1: "PM_E_INVAL", -2: "PM_E_NOMEM", -3: "PM_E_OVERFLOW",
+          -4: "PM_E_UNSUPPORTED", -5: "PM_E_DEVICE", -6: "PM_E_BUSY", -7: "PM_E_TIMEOUT",
+          -8: "PM_E_CANCELLED", -9: "PM_E_NOTFOUND"}
+EDGE_INDUCED, VERTEX_INDUCED = 0, 1
+AGG_COUNT, AGG_MNI = 0, 1
+MORPH_NONE, MORPH_NAIVE = 0, 1
+
+
+class PMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pm_pattern(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("edge_mask", ctypes.c_uint32),
+                ("induce", ctypes.c_uint32), ("label", ctypes.c_int32 * 8)]
+
+
+class pm_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("max_degree", ctypes.c_uint32),
+                ("max_out_degree", ctypes.c_uint32), ("labeled", ctypes.c_uint32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+class pm_query_stats(ctypes.Structure):
+    _fields_ = [("plan_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64),
+                ("work_items", ctypes.c_uint64), ("num_alt", ctypes.c_uint32),
+                ("launches", ctypes.c_uint32)]
+
+
+# name -> (restype, argtypes) for every function declared in include/pm.h
+_P = ctypes.c_void_p
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_patp = ctypes.POINTER(pm_pattern)
+SIGNATURES = {
+    "pm_create": (ctypes.c_int32, [_P, ctypes.c_uint64, _P, ctypes.c_int, ctypes.POINTER(_P)]),
+    "pm_destroy": (ctypes.c_int32, [_P]),
+    "pm_graph_load": (ctypes.c_int32, [_P, ctypes.c_uint32, _u32p, _u32p, _u8p, _u32p]),
+    "pm_graph_unload": (ctypes.c_int32, [_P, ctypes.c_uint32]),
+    "pm_graph_stats": (ctypes.c_int32, [_P, ctypes.c_uint32, ctypes.POINTER(pm_graph_info)]),
+    "pm_query_footprint": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_uint32,
+                                            ctypes.c_int32, ctypes.c_int32, _u64p]),
+    "pm_submit": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_uint32, ctypes.c_int32,
+                                   ctypes.c_int32, _u64p]),
+    "pm_wait": (ctypes.c_int32, [_P, ctypes.c_uint64, _i64p, ctypes.c_int64]),
+    "pm_last_query_stats": (ctypes.c_int32, [_P, ctypes.POINTER(pm_query_stats)]),
+    "pm_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
+    "pm_morph_plan": (ctypes.c_int32, [_patp, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32,
+                                       _patp, _u32p, _i64p]),
+    "pm_fsm": (ctypes.c_int32, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                                ctypes.c_int32, _i64p, _u8p, ctypes.c_uint64]),
+    "pm_fsm_num_slots": (ctypes.c_uint64, [ctypes.c_uint32]),
+    "pm_fsm_slot": (ctypes.c_int32, [ctypes.c_uint32, ctypes.c_uint64, _patp]),
+    "pm_set_option": (ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
+    "pm_plan_describe": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_char_p,
+                                          ctypes.c_uint64]),
+    "pm_last_error": (ctypes.c_char_p, []),
+    "pm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpm.so; raises when it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2012_04553_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != PM_OK:
+        msg = lib().pm_last_error()
+        raise PMError(status, msg.decode() if msg else "")
+
+
+def make_pattern(k: int, edge_mask: int, induced: bool, labels=None) -> pm_pattern:
+    p = pm_pattern()
+    p.k = k
+    p.edge_mask = edge_mask
+    p.induce = VERTEX_INDUCED if induced else EDGE_INDUCED
+    for i in range(8):
+        p.label[i] = -1
+    if labels is not None:
+        for i, l in enumerate(labels):
+            p.label[i] = int(l)
+    return p
+
+
+def pattern_array(pats) -> ctypes.Array:
+    arr = (pm_pattern * len(pats))()
+    for i, p in enumerate(pats):
+        if isinstance(p, pm_pattern):
+            arr[i] = p
+        else:
+            arr[i] = make_pattern(*p)
+    return arr
+
+
+def morph_plan(pats, morph: int = MORPH_NAIVE):
+    """Host-only: alternative pattern set and conversion matrix."""
+    arr = pattern_array(pats)
+    cap = ctypes.c_uint32(256)
+    alt = (pm_pattern * 256)()
+    mat = (ctypes.c_int64 * (len(pats) * 256))()
+    check(lib().pm_morph_plan(arr, len(pats), AGG_COUNT, morph, alt, ctypes.byref(cap), mat))
+    na = cap.value
+    alts = [(alt[j].k, alt[j].edge_mask, alt[j].induce == VERTEX_INDUCED,
+             [alt[j].label[i] for i in range(alt[j].k)]) for j in range(na)]
+    matrix = np.array([mat[i] for i in range(len(pats) * na)], dtype=np.int64).reshape(len(pats), na)
+    return alts, matrix
+
+
+class Engine:
+    """One pm_ctx on one GPU: arena + stream come from torch."""
+
+    def __init__(self, arena_bytes: int = 8 << 30, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ctx = ctypes.c_void_p()
+        check(lib().pm_create(ctypes.c_void_p(self.arena.data_ptr()), arena_bytes,
+                              ctypes.c_void_p(self.stream.cuda_stream), device,
+                              ctypes.byref(self.ctx)))
+
+    def close(self):
+        if self.ctx:
+            check(lib().pm_destroy(self.ctx))
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: str, value: int):
+        check(lib().pm_set_option(self.ctx, key.encode(), int(value)))
+
+    def graph_load(self, n, row_ptr, col, labels=None) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.uint32)
+        cl = np.ascontiguousarray(col, dtype=np.uint32)
+        if cl.size == 0:
+            cl = np.zeros(1, dtype=np.uint32)
+        lb = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint8)
+        gid = ctypes.c_uint32()
+        check(lib().pm_graph_load(self.ctx, n, rp.ctypes.data_as(_u32p), cl.ctypes.data_as(_u32p),
+                                  None if lb is None else lb.ctypes.data_as(_u8p),
+                                  ctypes.byref(gid)))
+        return gid.value
+
+    def load(self, g) -> int:
+        return self.graph_load(g.n, g.row_ptr, g.col, g.labels)
+
+    def graph_unload(self, gid: int):
+        check(lib().pm_graph_unload(self.ctx, gid))
+
+    def graph_stats(self, gid: int) -> dict:
+        info = pm_graph_info()
+        check(lib().pm_graph_stats(self.ctx, gid, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in pm_graph_info._fields_}
+
+    def footprint(self, gid, pats, morph=MORPH_NAIVE) -> int:
+        arr = pattern_array(pats)
+        out = ctypes.c_uint64()
+        check(lib().pm_query_footprint(self.ctx, gid, arr, len(pats), AGG_COUNT, morph,
+                                       ctypes.byref(out)))
+        return out.value
+
+    def submit(self, gid, pats, morph=MORPH_NAIVE, agg=AGG_COUNT) -> int:
+        arr = pattern_array(pats)
+        t = ctypes.c_uint64()
+        check(lib().pm_submit(self.ctx, gid, arr, len(pats), agg, morph, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, npat: int, timeout_us: int = -1) -> list[int]:
+        out = (ctypes.c_int64 * npat)()
+        check(lib().pm_wait(self.ctx, ticket, out, timeout_us))
+        return [int(x) for x in out]
+
+    def count(self, gid, pats, morph=MORPH_NAIVE) -> list[int]:
+        return self.wait(self.submit(gid, pats, morph), len(pats))
+
+    def last_stats(self) -> dict:
+        s = pm_query_stats()
+        check(lib().pm_last_query_stats(self.ctx, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in pm_query_stats._fields_}
+
+    def plan_describe(self, gid, pat) -> str:
+        buf = ctypes.create_string_buffer(8192)
+        arr = pattern_array([pat])
+        check(lib().pm_plan_describe(self.ctx, gid, arr, buf, 8192))
+        return buf.value.decode()

@@ -1,0 +1,124 @@
+// Internal declarations of the pattern-morphing engine (host side).
+#pragma once
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pm.h"
+
+namespace pm {
+
+constexpr int KMAX = 5;         // largest supported pattern
+constexpr int MAX_LEAF = 4;     // leaves counted by inclusion-exclusion
+constexpr int MAX_TERMS = 48;   // distinct set-size terms of one plan
+constexpr int MAX_MONO = 96;    // monomials of one plan's tail polynomial
+constexpr int MAX_FAC = 4;      // factors per monomial
+
+using Perm = std::array<uint8_t, 8>;
+
+// A pattern: k vertices, edge bitmask (pair i<j at bit j*(j-1)/2+i),
+// vertex- or edge-induced, optional labels (-1 = any).
+struct Pat {
+    int k = 0;
+    uint32_t em = 0;
+    bool vi = false;
+    std::array<int8_t, 8> lab{{-1, -1, -1, -1, -1, -1, -1, -1}};
+    bool operator==(const Pat& o) const {
+        return k == o.k && em == o.em && vi == o.vi && lab == o.lab;
+    }
+};
+
+inline int pair_bit(int i, int j) {
+    if (i > j) std::swap(i, j);
+    return j * (j - 1) / 2 + i;
+}
+inline bool has_edge(uint32_t m, int i, int j) { return (m >> pair_bit(i, j)) & 1u; }
+inline uint32_t full_mask(int k) { return (k * (k - 1) / 2 >= 32) ? ~0u : ((1u << (k * (k - 1) / 2)) - 1u); }
+inline int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// ---- algebra.cpp ----
+uint32_t permute_mask(int k, uint32_t m, const Perm& p);
+bool is_connected(int k, uint32_t m);
+std::vector<Perm> all_perms(int k);
+Pat canonical(const Pat& p);                       // smallest (mask, labels) relabelling
+std::vector<Perm> automorphisms(const Pat& p);      // label-preserving, edge (and anti-edge) preserving
+// number of permutations f with f(E(p)) subset E(q) and labels of p carried to q
+int64_t injections(const Pat& p, const Pat& q);
+// Naive-PMR alternative set for COUNT: union of the same-size edge-induced
+// superpatterns of every vertex-induced query (vertex-induced queries only;
+// edge-induced queries are matched as given).  matrix is npat x nalt.
+struct MorphPlan {
+    std::vector<Pat> alt;
+    std::vector<int64_t> matrix;   // row-major npat x alt.size()
+};
+int morph_plan_count(const std::vector<Pat>& q, int morph, MorphPlan* out, std::string* err);
+// combine alternative counts: out[i] = sum_j matrix[i][j]*alt[j]; checked int64
+int unmorph(const MorphPlan& mp, size_t npat, const std::vector<int64_t>& alt_counts,
+            std::vector<int64_t>* out, std::string* err);
+
+// ---- planner.cpp ----
+// Device plan: levels of the core enumeration and the tail polynomial.
+struct DLevel {          // candidate x for core level j must satisfy:
+    uint8_t adj;         //   x in N(v_i) for i in adj
+    uint8_t anti;        //   x not in N(v_i) for i in anti
+    uint8_t gt;          //   x > v_i for i in gt
+    uint8_t lt;          //   x < v_i for i in lt
+    uint8_t neq;         //   x != v_i for i in neq
+    int8_t label;        //   label(x) == label (when >= 0)
+    uint8_t base;        //   0xff, or an earlier level whose candidate set contains this one
+    uint8_t agg;         //   1: reached through bridge vertices (two-hop aggregation)
+};
+struct DTerm {           // |{x : constraints}| evaluated per full core match
+    uint8_t adj, anti, gt, lt, neq;
+    int8_t label;
+    uint8_t cheap;       // one adjacency list, no anti, no label: range count
+    uint8_t agg;         // equals the aggregation multiplicity of the last level
+};
+struct DMono {
+    int64_t coef;
+    uint8_t nf;
+    uint8_t f[MAX_FAC];
+    uint8_t pad[3];
+};
+struct DPlan {
+    int32_t ncore;       // core levels (>= 1)
+    int32_t nterm;       // 0: no leaves, the last core level is counted
+    int32_t nmono;
+    int32_t mult;        // multiplier when nterm == 0 (|coset reps|)
+    int32_t lane_par;    // 1: tail terms all cheap -> evaluated lane-parallel
+    int32_t agg_last;    // 1: last core level is a two-hop aggregation level
+    uint8_t bridge_gt;   // aggregation: bridge b > v_i for i in mask
+    uint8_t bridge_lt;   //              bridge b < v_i
+    int8_t bridge_label;
+    uint8_t bridge_src;  //              b in N(v_src)
+    int32_t pad;
+    DLevel lev[KMAX];
+    DTerm term[MAX_TERMS];
+    DMono mono[MAX_MONO];
+};
+
+struct PlanInfo {
+    DPlan d;
+    Pat pat;
+    int64_t divisor = 1;       // count = (sum over core reps of tail) / divisor
+    std::array<int8_t, KMAX> order{};   // pattern vertex at each core level
+    int formulation = 0;       // 0 coset, 1 pattern-chain
+    double est_cost = 0;
+    std::string describe() const;
+};
+
+struct GraphStats {             // degree statistics used by the cost model
+    double n = 0, m = 0;
+    double avg_deg = 0;         // 2m/n
+    double nbr_deg = 0;         // sum d^2 / 2m: degree of a random edge end
+    double avg_out = 0;         // mean out-degree (degree-ordered orientation)
+    double nbr_out = 0;         // sum (d+)^2 / m
+    double max_deg = 0, max_out = 0;
+};
+
+int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err);
+// all candidate plans (for tests / autotuning)
+int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* out, std::string* err);
+
+}  // namespace pm

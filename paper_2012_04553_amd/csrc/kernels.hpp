@@ -1,0 +1,41 @@
+// Kernel-side argument block shared by the runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace pm {
+
+struct KGraph {
+    const uint32_t* rp;   // row offsets, n+1 (degree-ordered ids)
+    const uint32_t* col;  // sorted adjacency
+    const uint8_t* lab;   // labels or null
+    uint32_t n;
+};
+
+// A work item: roots [r0, r1) of one plan; for a single high-degree root,
+// the slice [s0, s1) of its level-1 candidates.
+struct KItem {
+    uint32_t r0, r1, s0, s1;
+};
+
+struct KArgs {
+    KGraph g;
+    const DPlan* plans;
+    int32_t nplans;
+    uint32_t nitems;          // items per plan (the item list is shared)
+    const KItem* items;
+    uint64_t* counters;       // 2 x u64 (lo, hi) per plan
+    uint32_t* head;           // work-queue head
+    uint32_t* scratch;        // per-wave level buffers: KMAX * buf_stride each
+    uint64_t buf_stride;
+    uint32_t* aggcnt;         // per-wave dense counters (n each), zeroed
+    uint32_t* aggtouch;       // per-wave touched lists (n each)
+    uint64_t* bytes;          // algorithmic bytes (counting launch only)
+    const int* cancel;        // host-visible cancel flag or null
+};
+
+int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
+
+}  // namespace pm

@@ -1,0 +1,589 @@
+// Plan compiler: pattern -> device program for the matching kernel.
+//
+// A match is an injective map preserving edges and anti-edges
+// (Preliminaries, "Pattern Semantics").  The number of distinct matched
+// subgraphs is #matches / |Aut(p)|.  A plan splits the pattern vertices into
+//   * a connected core, enumerated level by level: the candidates of a level
+//     are the intersection of the neighbour lists of its earlier pattern
+//     neighbours minus those of its anti-edge partners (set intersection
+//     and difference), cut by symmetry-breaking bounds;
+//   * leaves: vertices with no constraint between each other (no edge and
+//     no anti-edge), never enumerated.  For one core match their injective
+//     extensions are counted by inclusion-exclusion over set partitions of
+//     the leaves:  sum_pi mu(pi) prod_{B in pi} |S_B|,  S_B = the set a vertex
+//     satisfying every leaf of B's constraints may take, mu(pi) =
+//     prod_B (-1)^{|B|-1} (|B|-1)!.
+// Symmetry breaking (partial orders from a stabiliser chain of a group of
+// pattern automorphisms, fixing core vertices in matching order) comes in
+// two formulations:
+//   coset:   the chain runs on Aut(core), the automorphisms of the core
+//            subpattern; each core subgraph is enumerated once and the tail
+//            is summed over coset representatives T of H = {automorphisms of
+//            p mapping the core onto itself} restricted to the core; then
+//            count = sum / (|Aut(p)| / |H|).
+//   pattern: the chain runs on Aut(p) itself (leaves may receive bounds
+//            relative to core vertices, never relative to each other); the
+//            group left after the chain divides the sum.
+// Both are exact; the cost model picks the cheaper on the graph at hand.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <set>
+
+#include "internal.hpp"
+
+namespace pm {
+
+namespace {
+
+using Group = std::vector<Perm>;
+
+Perm identity() {
+    Perm p{};
+    for (int i = 0; i < 8; ++i) p[i] = (uint8_t)i;
+    return p;
+}
+
+Perm compose(const Perm& a, const Perm& b) {  // (a o b)(x) = a(b(x))
+    Perm r{};
+    for (int i = 0; i < 8; ++i) r[i] = a[b[i]];
+    return r;
+}
+
+Perm inverse(const Perm& a) {
+    Perm r{};
+    for (int i = 0; i < 8; ++i) r[a[i]] = (uint8_t)i;
+    return r;
+}
+
+// Automorphisms of the core subpattern: permutations of the core vertices
+// (leaves fixed) preserving edges, anti-edges and labels among core vertices.
+Group core_automorphisms(const Pat& p, uint32_t core) {
+    Group out;
+    for (const Perm& f : all_perms(p.k)) {
+        bool ok = true;
+        for (int v = 0; v < p.k && ok; ++v) {
+            bool in = (core >> v) & 1;
+            if (!in && f[v] != v) ok = false;
+            if (in && !((core >> f[v]) & 1)) ok = false;
+            if (p.lab[v] != p.lab[f[v]]) ok = false;
+        }
+        if (!ok) continue;
+        for (int a = 0; a < p.k && ok; ++a)
+            for (int b = a + 1; b < p.k && ok; ++b) {
+                if (!((core >> a) & 1) || !((core >> b) & 1)) continue;
+                if (has_edge(p.em, a, b) != has_edge(p.em, f[a], f[b])) ok = false;
+            }
+        if (ok) out.push_back(f);
+    }
+    return out;
+}
+
+struct Rel {  // rel[u][v] = +1 if u > v required, -1 if u < v required
+    int8_t r[8][8];
+    Rel() { memset(r, 0, sizeof(r)); }
+    void add_less(int u, int v) {  // u < v
+        r[u][v] = -1;
+        r[v][u] = +1;
+    }
+    void close(int k) {
+        for (int w = 0; w < k; ++w)
+            for (int u = 0; u < k; ++u)
+                for (int v = 0; v < k; ++v)
+                    if (r[u][w] == -1 && r[w][v] == -1) add_less(u, v);
+    }
+};
+
+// Stabiliser chain over the core vertices in matching order: when the
+// vertex x to fix has a non-trivial orbit, require x to be the minimum
+// (dir = -1) or maximum (dir = +1) of its orbit.  Returns the residual group.
+Group chain(Group G, const std::vector<int>& order, int dir, Rel* rel) {
+    for (int x : order) {
+        std::set<int> orbit;
+        for (const Perm& g : G) orbit.insert(g[x]);
+        if (orbit.size() > 1) {
+            for (int y : orbit) {
+                if (y == x) continue;
+                if (dir < 0) rel->add_less(x, y);
+                else rel->add_less(y, x);
+            }
+        }
+        Group H;
+        for (const Perm& g : G)
+            if (g[x] == x) H.push_back(g);
+        G.swap(H);
+    }
+    return G;
+}
+
+struct LeafCons {
+    uint8_t adj = 0, anti = 0, gt = 0, lt = 0;
+    int8_t label = -1;
+    bool conflict = false;
+};
+
+bool term_equal(const DTerm& a, const DTerm& b) {
+    return a.adj == b.adj && a.anti == b.anti && a.gt == b.gt && a.lt == b.lt &&
+           a.neq == b.neq && a.label == b.label;
+}
+
+// set partitions of {0..n-1}
+void partitions(int n, std::vector<std::vector<uint32_t>>* out) {
+    std::vector<int> assign(n, 0);
+    std::function<void(int, int)> rec = [&](int i, int nb) {
+        if (i == n) {
+            std::vector<uint32_t> blocks(nb, 0);
+            for (int t = 0; t < n; ++t) blocks[assign[t]] |= 1u << t;
+            out->push_back(blocks);
+            return;
+        }
+        for (int b = 0; b <= nb; ++b) {
+            assign[i] = b;
+            rec(i + 1, std::max(nb, b + 1));
+        }
+    };
+    if (n == 0) {
+        out->push_back({});
+        return;
+    }
+    rec(0, 0);
+}
+
+int64_t factorial(int n) {
+    int64_t r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+struct Builder {
+    const Pat& p;
+    const GraphStats& gs;
+    Builder(const Pat& pp, const GraphStats& g) : p(pp), gs(g) {}
+
+    // Build a plan.  core/leaves are vertex masks; order lists the core
+    // vertices by level; agg_last: the last core level is reached through
+    // bridge leaves.  Returns false when the combination is not valid.
+    bool build(uint32_t core, uint32_t leaves, const std::vector<int>& order, int form,
+               int dir, bool agg_last, const Group& autp, PlanInfo* out) {
+        const int k = p.k;
+        const int c = (int)order.size();
+        int lev_of[8];
+        for (int i = 0; i < 8; ++i) lev_of[i] = -1;
+        for (int j = 0; j < c; ++j) lev_of[order[j]] = j;
+        uint32_t anti_pairs = p.vi ? (full_mask(k) & ~p.em) : 0u;
+
+        // ---- symmetry breaking ------------------------------------------
+        Rel rel;
+        std::vector<Perm> T;       // coset representatives (as maps of pattern vertices)
+        int64_t divisor = 1;
+        if (form == 0) {
+            Group G = core_automorphisms(p, core);
+            Group Hc;  // restrictions to the core of automorphisms preserving it
+            for (const Perm& g : autp) {
+                bool keeps = true;
+                for (int v = 0; v < k; ++v)
+                    if (((core >> v) & 1) && !((core >> g[v]) & 1)) keeps = false;
+                if (!keeps) continue;
+                Perm r = identity();
+                for (int v = 0; v < k; ++v)
+                    if ((core >> v) & 1) r[v] = g[v];
+                if (std::find(Hc.begin(), Hc.end(), r) == Hc.end()) Hc.push_back(r);
+            }
+            chain(G, order, dir, &rel);
+            // left cosets sigma Hc of Hc in G
+            std::vector<Perm> covered;
+            for (const Perm& s : G) {
+                if (std::find(covered.begin(), covered.end(), s) != covered.end()) continue;
+                T.push_back(s);
+                for (const Perm& h : Hc) covered.push_back(compose(s, h));
+            }
+            if ((int64_t)autp.size() % (int64_t)Hc.size()) return false;
+            divisor = (int64_t)autp.size() / (int64_t)Hc.size();
+        } else {
+            Group R = chain(autp, order, dir, &rel);
+            // constraints between two leaves are not allowed
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b)
+                    if (((leaves >> a) & 1) && ((leaves >> b) & 1) && rel.r[a][b]) return false;
+            T.push_back(identity());
+            divisor = (int64_t)R.size();
+        }
+        rel.close(k);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                if (((leaves >> a) & 1) && ((leaves >> b) & 1) && rel.r[a][b]) return false;
+
+        DPlan d;
+        memset(&d, 0, sizeof(d));
+        d.ncore = c;
+        d.mult = 1;
+        d.bridge_src = 0xff;
+        // ---- core levels --------------------------------------------------
+        for (int j = 0; j < c; ++j) {
+            int u = order[j];
+            DLevel L;
+            memset(&L, 0, sizeof(L));
+            L.base = 0xff;
+            L.label = p.lab[u];
+            for (int i = 0; i < j; ++i) {
+                int w = order[i];
+                uint8_t bit = (uint8_t)(1u << i);
+                if (has_edge(p.em, u, w)) L.adj |= bit;
+                else if ((anti_pairs >> pair_bit(u, w)) & 1) L.anti |= bit;
+                if (rel.r[u][w] > 0) L.gt |= bit;
+                if (rel.r[u][w] < 0) L.lt |= bit;
+            }
+            for (int i = 0; i < j; ++i) {
+                uint8_t bit = (uint8_t)(1u << i);
+                if (!(L.adj & bit) && !(L.gt & bit) && !(L.lt & bit)) L.neq |= bit;
+            }
+            bool is_agg = agg_last && j == c - 1;
+            if (j > 0 && !is_agg && !L.adj) return false;
+            if (is_agg && L.adj) return false;
+            L.agg = is_agg ? 1 : 0;
+            if (j > 1 && !is_agg) {
+                for (int b = j - 1; b >= 1; --b) {
+                    const DLevel& B = d.lev[b];
+                    if (B.agg) continue;
+                    uint8_t lowb = (uint8_t)((1u << b) - 1u);
+                    if ((B.adj & ~L.adj & lowb) || (B.anti & ~L.anti & lowb)) continue;
+                    if ((B.gt & ~L.gt & lowb) || (B.lt & ~L.lt & lowb)) continue;
+                    if (B.label >= 0 && B.label != L.label) continue;
+                    L.base = (uint8_t)b;
+                    break;
+                }
+            }
+            d.lev[j] = L;
+        }
+        // ---- leaves and tail terms -----------------------------------------
+        std::vector<int> leaf;
+        for (int v = 0; v < k; ++v)
+            if ((leaves >> v) & 1) leaf.push_back(v);
+        if ((int)leaf.size() > MAX_LEAF) return false;
+        std::vector<DTerm> terms;
+        std::map<std::vector<int>, int64_t> monos;  // sorted term ids -> coef
+        std::vector<std::vector<uint32_t>> parts;
+        partitions((int)leaf.size(), &parts);
+        uint8_t all_core = (uint8_t)((1u << c) - 1u);
+        for (const Perm& s : T) {
+            std::vector<LeafCons> lc(leaf.size());
+            for (size_t t = 0; t < leaf.size(); ++t) {
+                int l = leaf[t];
+                LeafCons& C = lc[t];
+                C.label = p.lab[l];
+                for (int cv = 0; cv < k; ++cv) {
+                    if (!((core >> cv) & 1)) continue;
+                    int lev = lev_of[s[cv]];
+                    uint8_t bit = (uint8_t)(1u << lev);
+                    if (has_edge(p.em, l, cv)) C.adj |= bit;
+                    else if ((anti_pairs >> pair_bit(l, cv)) & 1) C.anti |= bit;
+                    if (form == 1) {
+                        if (rel.r[l][cv] > 0) C.gt |= bit;
+                        if (rel.r[l][cv] < 0) C.lt |= bit;
+                    }
+                }
+                if (!C.adj) return false;
+            }
+            for (const auto& blocks : parts) {
+                int64_t mu = 1;
+                std::vector<int> ids;
+                bool zero = false;
+                for (uint32_t B : blocks) {
+                    int sz = popc(B);
+                    mu *= ((sz - 1) % 2 ? -1 : 1) * factorial(sz - 1);
+                    DTerm tm;
+                    memset(&tm, 0, sizeof(tm));
+                    tm.label = -1;
+                    for (size_t t = 0; t < leaf.size(); ++t) {
+                        if (!((B >> t) & 1)) continue;
+                        tm.adj |= lc[t].adj;
+                        tm.anti |= lc[t].anti;
+                        tm.gt |= lc[t].gt;
+                        tm.lt |= lc[t].lt;
+                        if (lc[t].label >= 0) {
+                            if (tm.label >= 0 && tm.label != lc[t].label) zero = true;
+                            tm.label = lc[t].label;
+                        }
+                    }
+                    if (tm.adj & tm.anti) zero = true;
+                    tm.neq = (uint8_t)(all_core & ~(tm.adj | tm.gt | tm.lt));
+                    tm.cheap = (popc(tm.adj) == 1 && !tm.anti && tm.label < 0) ? 1 : 0;
+                    int id = -1;
+                    for (size_t q = 0; q < terms.size(); ++q)
+                        if (term_equal(terms[q], tm)) id = (int)q;
+                    if (id < 0) {
+                        id = (int)terms.size();
+                        terms.push_back(tm);
+                    }
+                    ids.push_back(id);
+                }
+                if (zero) continue;
+                std::sort(ids.begin(), ids.end());
+                monos[ids] += mu;
+            }
+        }
+        if (leaf.empty()) {
+            d.nterm = 0;
+            d.nmono = 0;
+            d.mult = (int32_t)T.size();
+        } else {
+            // drop terms no monomial uses
+            std::vector<int> used(terms.size(), 0);
+            for (auto& m : monos)
+                if (m.second)
+                    for (int id : m.first) used[id] = 1;
+            std::vector<int> remap(terms.size(), -1);
+            std::vector<DTerm> kept;
+            for (size_t q = 0; q < terms.size(); ++q)
+                if (used[q]) {
+                    remap[q] = (int)kept.size();
+                    kept.push_back(terms[q]);
+                }
+            if (kept.size() > (size_t)MAX_TERMS) return false;
+            int nm = 0;
+            for (auto& m : monos) {
+                if (!m.second) continue;
+                if (nm >= MAX_MONO || (int)m.first.size() > MAX_FAC) return false;
+                DMono& M = d.mono[nm++];
+                M.coef = m.second;
+                M.nf = (uint8_t)m.first.size();
+                for (size_t f = 0; f < m.first.size(); ++f) M.f[f] = (uint8_t)remap[m.first[f]];
+            }
+            d.nmono = nm;
+            d.nterm = (int32_t)kept.size();
+            for (size_t q = 0; q < kept.size(); ++q) d.term[q] = kept[q];
+            if (d.nterm == 0) {
+                // every monomial vanished (e.g. conflicting labels): count is 0
+                d.nmono = 0;
+                d.mult = 0;
+            }
+        }
+        // ---- two-hop aggregation: the bridge set must be a whole term ------
+        if (agg_last) {
+            int j = c - 1;
+            // bridge: a leaf adjacent exactly to {src, order[j]} among core vertices
+            bool found = false;
+            for (size_t t = 0; t < leaf.size() && !found; ++t) {
+                int l = leaf[t];
+                uint8_t adjl = 0;
+                for (int cv = 0; cv < k; ++cv)
+                    if (((core >> cv) & 1) && has_edge(p.em, l, cv)) adjl |= (uint8_t)(1u << lev_of[cv]);
+                if (popc(adjl) != 2 || !((adjl >> j) & 1)) continue;
+                int src = __builtin_ctz(adjl & ~(1u << j));
+                uint8_t bgt = 0, blt = 0;
+                if (form == 1) {
+                    for (int cv = 0; cv < k; ++cv) {
+                        if (!((core >> cv) & 1)) continue;
+                        if (rel.r[l][cv] > 0) bgt |= (uint8_t)(1u << lev_of[cv]);
+                        if (rel.r[l][cv] < 0) blt |= (uint8_t)(1u << lev_of[cv]);
+                    }
+                }
+                if ((bgt | blt) >> j) continue;  // bridge bound on the target itself
+                d.bridge_src = (uint8_t)src;
+                d.bridge_gt = bgt;
+                d.bridge_lt = blt;
+                d.bridge_label = p.lab[l];
+                found = true;
+            }
+            if (!found || T.size() != 1) return false;
+            // mark the term equal to the bridge set; others must be cheap
+            DTerm br;
+            memset(&br, 0, sizeof(br));
+            br.adj = (uint8_t)((1u << d.bridge_src) | (1u << j));
+            br.gt = d.bridge_gt;
+            br.lt = d.bridge_lt;
+            br.label = d.bridge_label;
+            br.neq = (uint8_t)(all_core & ~(br.adj | br.gt | br.lt));
+            for (int q = 0; q < d.nterm; ++q) {
+                if (term_equal(d.term[q], br)) d.term[q].agg = 1;
+                else if (!d.term[q].cheap) return false;
+            }
+        }
+        d.lane_par = 1;
+        for (int q = 0; q < d.nterm; ++q)
+            if (!d.term[q].cheap && !d.term[q].agg) d.lane_par = 0;
+        d.agg_last = agg_last ? 1 : 0;
+
+        out->d = d;
+        out->pat = p;
+        out->divisor = divisor;
+        for (int j = 0; j < KMAX; ++j) out->order[j] = j < c ? (int8_t)order[j] : -1;
+        out->formulation = form;
+        out->est_cost = estimate(out->d);
+        return true;
+    }
+
+    // ---- cost model -------------------------------------------------------
+    // Expected work from degree statistics: a level drawing candidates from
+    // a list with a lower bound at its owner is an out-list (degree-ordered
+    // orientation, short); otherwise a full list.  Extra intersections keep
+    // a fraction of candidates; aggregation costs its wedges.
+    double estimate(const DPlan& d) const {
+        const double n = std::max(gs.n, 1.0);
+        double deg_root = std::max(gs.avg_deg, 1.0), deg_nb = std::max(gs.nbr_deg, 1.0);
+        double out_root = std::max(gs.avg_out, 0.5), out_nb = std::max(gs.nbr_out, 0.5);
+        double keep = std::min(1.0, std::max(0.02, deg_nb / n * 8.0));
+        auto list_len = [&](int owner, bool lower_bounded, bool upper_bounded) {
+            double dg = owner == 0 ? deg_root : deg_nb;
+            double og = owner == 0 ? out_root : out_nb;
+            if (lower_bounded) return og;
+            if (upper_bounded) return std::max(dg - og, 1.0);
+            return dg;
+        };
+        double prefixes = n;
+        double cost = n;  // one visit per root
+        int last = d.ncore - 1;
+        for (int j = 1; j < d.ncore; ++j) {
+            const DLevel& L = d.lev[j];
+            double size, work;
+            if (L.agg) {
+                int s = d.bridge_src;
+                double b = list_len(s, (d.bridge_gt >> s) & 1, (d.bridge_lt >> s) & 1);
+                double w = b * (((L.lt) ? (deg_nb - out_nb) : deg_nb) * 0.5 + 1);
+                work = w * 1.5;
+                size = std::min(w, n);
+            } else {
+                double best = 1e300;
+                for (int i = 0; i < j; ++i)
+                    if ((L.adj >> i) & 1)
+                        best = std::min(best, list_len(i, (L.gt >> i) & 1, (L.lt >> i) & 1));
+                int extra = popc(L.adj) - 1 + popc(L.anti);
+                size = best * std::pow(keep, popc(L.adj) - 1);
+                work = best * (1.0 + extra * 4.0);
+            }
+            bool counted = (j == last && d.nterm == 0);
+            cost += prefixes * work;
+            if (!counted) prefixes *= std::max(size, 1e-9);
+        }
+        // tail terms per full core match
+        double tail = 0;
+        for (int q = 0; q < d.nterm; ++q) {
+            const DTerm& t = d.term[q];
+            if (t.cheap || t.agg) {
+                tail += d.lane_par ? 0.3 : 2.0;
+                continue;
+            }
+            double best = 1e300;
+            for (int i = 0; i < d.ncore; ++i)
+                if ((t.adj >> i) & 1) best = std::min(best, list_len(i, (t.gt >> i) & 1, (t.lt >> i) & 1));
+            tail += best * (1.0 + (popc(t.adj) - 1 + popc(t.anti)) * 4.0) + 16.0;
+        }
+        cost += prefixes * tail;
+        return cost;
+    }
+};
+
+void orders_of(const Pat& p, uint32_t core, bool agg_last, std::vector<std::vector<int>>* out) {
+    std::vector<int> verts;
+    for (int v = 0; v < p.k; ++v)
+        if ((core >> v) & 1) verts.push_back(v);
+    std::sort(verts.begin(), verts.end());
+    do {
+        bool ok = true;
+        int c = (int)verts.size();
+        for (int j = 1; j < c && ok; ++j) {
+            bool adj = false;
+            for (int i = 0; i < j; ++i)
+                if (has_edge(p.em, verts[i], verts[j])) adj = true;
+            if (agg_last && j == c - 1) ok = !adj;
+            else ok = adj;
+        }
+        if (ok) out->push_back(verts);
+    } while (std::next_permutation(verts.begin(), verts.end()));
+}
+
+}  // namespace
+
+std::string PlanInfo::describe() const {
+    char buf[512];
+    std::string s;
+    snprintf(buf, sizeof(buf), "k=%d em=0x%x %s form=%s div=%lld cost=%.3g order=", pat.k,
+             pat.em, pat.vi ? "VI" : "EI", formulation ? "pattern" : "coset",
+             (long long)divisor, est_cost);
+    s += buf;
+    for (int j = 0; j < d.ncore; ++j) s += std::to_string(order[j]) + (j + 1 < d.ncore ? "," : "");
+    for (int j = 0; j < d.ncore; ++j) {
+        const DLevel& L = d.lev[j];
+        snprintf(buf, sizeof(buf), " | L%d adj=%x anti=%x gt=%x lt=%x neq=%x lab=%d base=%d%s", j,
+                 L.adj, L.anti, L.gt, L.lt, L.neq, L.label, L.base == 0xff ? -1 : L.base,
+                 L.agg ? " AGG" : "");
+        s += buf;
+    }
+    for (int q = 0; q < d.nterm; ++q) {
+        const DTerm& t = d.term[q];
+        snprintf(buf, sizeof(buf), " | T%d adj=%x anti=%x gt=%x lt=%x neq=%x lab=%d%s%s", q, t.adj,
+                 t.anti, t.gt, t.lt, t.neq, t.label, t.cheap ? " cheap" : "", t.agg ? " agg" : "");
+        s += buf;
+    }
+    s += " | poly:";
+    for (int m = 0; m < d.nmono; ++m) {
+        snprintf(buf, sizeof(buf), " %+lld", (long long)d.mono[m].coef);
+        s += buf;
+        for (int f = 0; f < d.mono[m].nf; ++f) s += "*T" + std::to_string(d.mono[m].f[f]);
+    }
+    if (d.nterm == 0) s += " mult=" + std::to_string(d.mult);
+    if (d.lane_par) s += " lane_par";
+    return s;
+}
+
+int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* out, std::string* err) {
+    out->clear();
+    if (p.k < 2 || p.k > KMAX) {
+        *err = "pattern size outside 2..5";
+        return PM_E_UNSUPPORTED;
+    }
+    if (!is_connected(p.k, p.em) || (p.em & ~full_mask(p.k))) {
+        *err = "pattern must be connected with edges among its k vertices";
+        return PM_E_UNSUPPORTED;
+    }
+    Group autp = automorphisms(p);
+    Builder B(p, gs);
+    const int k = p.k;
+    uint32_t all = (1u << k) - 1u;
+    for (uint32_t leaves = 0; leaves < (1u << k); ++leaves) {
+        uint32_t core = all & ~leaves;
+        if (!core) continue;
+        int nl = popc(leaves);
+        if (nl > MAX_LEAF) continue;
+        // leaves: no constraint between any two of them
+        bool indep = true;
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b)
+                if (((leaves >> a) & 1) && ((leaves >> b) & 1)) {
+                    if (has_edge(p.em, a, b) || p.vi) indep = false;
+                }
+        if (!indep) continue;
+        for (int agg = 0; agg < 2; ++agg) {
+            if (agg && (p.vi || popc(core) < 2)) continue;
+            std::vector<std::vector<int>> orders;
+            orders_of(p, core, agg != 0, &orders);
+            for (const auto& ord : orders)
+                for (int form = 0; form < 2; ++form)
+                    for (int dir = -1; dir <= 1; dir += 2) {
+                        PlanInfo pi;
+                        if (B.build(core, leaves, ord, form, dir, agg != 0, autp, &pi)) out->push_back(pi);
+                    }
+        }
+    }
+    if (out->empty()) {
+        *err = "no valid plan";
+        return PM_E_UNSUPPORTED;
+    }
+    return PM_OK;
+}
+
+int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err) {
+    std::vector<PlanInfo> all;
+    int rc = candidate_plans(p, gs, &all, err);
+    if (rc) return rc;
+    size_t best = 0;
+    for (size_t i = 1; i < all.size(); ++i)
+        if (all[i].est_cost < all[best].est_cost) best = i;
+    *out = all[best];
+    return PM_OK;
+}
+
+}  // namespace pm

@@ -1,0 +1,777 @@
+// Host runtime and C-ABI of the pattern-morphing engine.
+//
+// Graph ingest (validation, degree-ordered relabelling, CSR build), the
+// arena sub-allocator over the caller's device memory, query submission
+// (morph plan, plan compile, device launch), completion and the integer
+// conversion back to the requested patterns (Corollary 3.1 / Theorem 3.1 in
+// counting form, checked int64).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+namespace pm {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(PM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- arena
+
+uint64_t Arena::alloc(uint64_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    bytes = (bytes + 255) & ~uint64_t(255);
+    if (bytes == 0) bytes = 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= bytes) {
+            uint64_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > bytes) free_[off + bytes] = sz - bytes;
+            used_[off] = bytes;
+            return off;
+        }
+    }
+    return UINT64_MAX;
+}
+
+void Arena::release(uint64_t off) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = used_.find(off);
+    if (it == used_.end()) return;
+    uint64_t sz = it->second;
+    used_.erase(it);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + sz == nx->first) {
+        sz += nx->second;
+        free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+            pv->second += sz;
+            return;
+        }
+    }
+    free_[off] = sz;
+}
+
+uint64_t Arena::largest_free() {
+    std::lock_guard<std::mutex> g(mu);
+    uint64_t b = 0;
+    for (auto& f : free_) b = std::max(b, f.second);
+    return b;
+}
+
+// ---------------------------------------------------------------- graph
+
+static void parallel_for(uint64_t n, const std::function<void(uint64_t, uint64_t)>& fn) {
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (n < 65536) nt = 1;
+    std::vector<std::thread> th;
+    uint64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        uint64_t b = t * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back(fn, b, e);
+    }
+    for (auto& x : th) x.join();
+}
+
+static std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t n,
+                                      uint64_t budget, uint32_t split, uint32_t max_roots) {
+    std::vector<KItem> items;
+    // heaviest roots first (ids ascend with degree)
+    int64_t r = (int64_t)n - 1;
+    while (r >= 0) {
+        uint32_t d = rp[r + 1] - rp[r];
+        if (d > split) {
+            for (uint32_t s = 0; s < d; s += split) items.push_back({(uint32_t)r, (uint32_t)r + 1, s, s + split});
+            --r;
+            continue;
+        }
+        int64_t end = r + 1;
+        uint64_t sum = 0;
+        uint32_t cnt = 0;
+        while (r >= 0) {
+            uint32_t dr = rp[r + 1] - rp[r];
+            if (dr > split) break;
+            if (cnt > 0 && (sum + dr > budget || cnt >= max_roots)) break;
+            sum += dr;
+            ++cnt;
+            --r;
+        }
+        items.push_back({(uint32_t)(r + 1), (uint32_t)end, 0, 0xffffffffu});
+    }
+    return items;
+}
+
+int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels,
+                     uint32_t* out_gid) {
+    if (!rp || !col || !out_gid) return fail(PM_E_INVAL, "null graph array");
+    if (n == 0) return fail(PM_E_INVAL, "empty graph");
+    if (rp[0] != 0) return fail(PM_E_INVAL, "row_ptr[0] must be 0");
+    for (uint32_t v = 0; v < n; ++v)
+        if (rp[v + 1] < rp[v]) return fail(PM_E_INVAL, "row_ptr not monotone");
+    uint64_t nnz = rp[n];
+    if (nnz % 2) return fail(PM_E_INVAL, "odd number of adjacency entries: not symmetric");
+    std::atomic<int> bad{0};
+    std::atomic<uint64_t> bad_v{0};
+    parallel_for(n, [&](uint64_t b, uint64_t e) {
+        for (uint64_t v = b; v < e && !bad; ++v) {
+            for (uint32_t p = rp[v]; p < rp[v + 1]; ++p) {
+                uint32_t w = col[p];
+                if (w >= n) { bad = 1; bad_v = v; break; }
+                if (w == v) { bad = 2; bad_v = v; break; }
+                if (p > rp[v] && col[p - 1] >= w) { bad = 3; bad_v = v; break; }
+                // symmetric: v in N(w)
+                const uint32_t* a = col + rp[w];
+                uint32_t len = rp[w + 1] - rp[w];
+                const uint32_t* f = std::lower_bound(a, a + len, (uint32_t)v);
+                if (f == a + len || *f != v) { bad = 4; bad_v = v; break; }
+            }
+        }
+    });
+    static const char* why[] = {"", "neighbour id out of range", "self-loop",
+                                "adjacency not strictly ascending (unsorted or duplicate)",
+                                "adjacency not symmetric"};
+    if (bad) return fail(PM_E_INVAL, std::string(why[bad.load()]) + " at vertex " + std::to_string(bad_v.load()));
+
+    // degree-ordered relabelling: rank by (degree, id)
+    std::vector<uint32_t> order(n);
+    for (uint32_t v = 0; v < n; ++v) order[v] = v;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return (rp[a + 1] - rp[a]) < (rp[b + 1] - rp[b]);
+    });
+    std::vector<uint32_t> newid(n);
+    for (uint32_t r = 0; r < n; ++r) newid[order[r]] = r;
+    std::vector<uint32_t> nrp(n + 1, 0);
+    for (uint32_t r = 0; r < n; ++r) nrp[r + 1] = nrp[r] + (rp[order[r] + 1] - rp[order[r]]);
+    std::vector<uint32_t> ncol(nnz ? nnz : 1);
+    parallel_for(n, [&](uint64_t b, uint64_t e) {
+        for (uint64_t r = b; r < e; ++r) {
+            uint32_t u = order[r];
+            uint32_t o = nrp[r];
+            for (uint32_t p = rp[u]; p < rp[u + 1]; ++p) ncol[o++] = newid[col[p]];
+            std::sort(ncol.begin() + nrp[r], ncol.begin() + nrp[r + 1]);
+        }
+    });
+    std::vector<uint8_t> nlab;
+    if (labels) {
+        nlab.resize(n);
+        for (uint32_t r = 0; r < n; ++r) nlab[r] = labels[order[r]];
+    }
+    auto G = std::make_unique<GraphRes>();
+    G->n = n;
+    G->m = nnz / 2;
+    G->labeled = labels != nullptr;
+    double sd2 = 0, so2 = 0;
+    uint32_t maxd = 0, maxo = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        uint32_t d = nrp[r + 1] - nrp[r];
+        const uint32_t* a = ncol.data() + nrp[r];
+        uint32_t out = (uint32_t)((a + d) - std::upper_bound(a, a + d, r));
+        maxd = std::max(maxd, d);
+        maxo = std::max(maxo, out);
+        sd2 += (double)d * d;
+        so2 += (double)out * out;
+    }
+    G->max_deg = maxd;
+    G->max_out = maxo;
+    GraphStats& s = G->st;
+    s.n = n;
+    s.m = (double)G->m;
+    s.avg_deg = n ? 2.0 * G->m / n : 0;
+    s.nbr_deg = G->m ? sd2 / (2.0 * G->m) : 0;
+    s.avg_out = n ? (double)G->m / n : 0;
+    s.nbr_out = G->m ? so2 / (double)G->m : 0;
+    s.max_deg = maxd;
+    s.max_out = maxo;
+    G->items = build_items(nrp, n, item_budget, item_split, 256);
+
+    uint64_t need_rp = 4ull * (n + 1), need_col = 4ull * std::max<uint64_t>(nnz, 1),
+             need_lab = labels ? n : 0, need_items = sizeof(KItem) * G->items.size();
+    G->off_rp = arena.alloc(need_rp);
+    G->off_col = arena.alloc(need_col);
+    G->off_lab = labels ? arena.alloc(need_lab) : UINT64_MAX - 1;
+    G->off_items = arena.alloc(need_items);
+    if (G->off_rp == UINT64_MAX || G->off_col == UINT64_MAX || G->off_lab == UINT64_MAX ||
+        G->off_items == UINT64_MAX) {
+        for (uint64_t o : {G->off_rp, G->off_col, G->off_lab, G->off_items})
+            if (o < UINT64_MAX - 1) arena.release(o);
+        return fail(PM_E_NOMEM, "arena too small for the graph");
+    }
+    G->device_bytes = need_rp + need_col + need_lab + need_items;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipMemcpyAsync(dptr(G->off_rp), nrp.data(), need_rp, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dptr(G->off_col), ncol.data(), 4ull * nnz, hipMemcpyHostToDevice, stream));
+    if (labels) HIPCHK(hipMemcpyAsync(dptr(G->off_lab), nlab.data(), n, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dptr(G->off_items), G->items.data(), need_items, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    std::lock_guard<std::mutex> g(mu);
+    uint32_t gid = next_gid++;
+    graphs[gid] = std::move(G);
+    *out_gid = gid;
+    return PM_OK;
+}
+
+int Ctx_::graph_unload(uint32_t gid) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = graphs.find(gid);
+    if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+    if (it->second->inflight) return fail(PM_E_BUSY, "queries in flight on this graph");
+    GraphRes& G = *it->second;
+    for (uint64_t o : {G.off_rp, G.off_col, G.off_lab, G.off_items})
+        if (o < UINT64_MAX - 1) arena.release(o);
+    graphs.erase(it);
+    return PM_OK;
+}
+
+// ---------------------------------------------------------------- queries
+
+static int to_pat(const pm_pattern& q, Pat* out, std::string* err) {
+    if (q.k < 2 || q.k > (uint32_t)KMAX) {
+        *err = "pattern size must be 2..5";
+        return PM_E_UNSUPPORTED;
+    }
+    if (q.edge_mask & ~full_mask((int)q.k)) {
+        *err = "edge_mask has bits beyond the k vertices";
+        return PM_E_INVAL;
+    }
+    if (!is_connected((int)q.k, q.edge_mask)) {
+        *err = "pattern is not connected";
+        return PM_E_UNSUPPORTED;
+    }
+    if (q.induce > 1) {
+        *err = "induce must be PM_EDGE_INDUCED or PM_VERTEX_INDUCED";
+        return PM_E_INVAL;
+    }
+    out->k = (int)q.k;
+    out->em = q.edge_mask;
+    out->vi = q.induce == PM_VERTEX_INDUCED;
+    for (int i = 0; i < 8; ++i) {
+        int32_t l = i < (int)q.k ? q.label[i] : -1;
+        if (l < -1 || l > 255) {
+            *err = "label outside -1..255";
+            return PM_E_INVAL;
+        }
+        out->lab[i] = (int8_t)(l < 0 ? -1 : (l > 127 ? 127 : l));
+        if (l > 127) {
+            *err = "labels above 127 are not supported";
+            return PM_E_UNSUPPORTED;
+        }
+    }
+    return PM_OK;
+}
+
+uint64_t Ctx_::waves() const { return (uint64_t)grid_blocks() * (block / 64); }
+int Ctx_::grid_blocks() const { return num_cus * blocks_per_cu; }
+
+const PlanInfo& Ctx_::plan_for(GraphRes& G, const Pat& p, int* rc) {
+    std::lock_guard<std::mutex> g(plan_mu);
+    for (auto& e : G.plan_cache)
+        if (e.first == p) {
+            *rc = PM_OK;
+            return e.second;
+        }
+    PlanInfo pi;
+    std::string err;
+    *rc = compile_plan(p, G.st, &pi, &err);
+    if (*rc) g_err = err;
+    G.plan_cache.push_back({p, pi});
+    return G.plan_cache.back().second;
+}
+
+uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, uint64_t* scratch_stride,
+                         bool* any_agg) const {
+    uint64_t stride = 1;
+    bool agg = false;
+    for (const PlanInfo& p : plans) {
+        for (int j = 1; j < p.d.ncore; ++j) {
+            const DLevel& L = p.d.lev[j];
+            bool out_list = (L.adj & L.gt) != 0;
+            stride = std::max<uint64_t>(stride, (out_list ? G.max_out : G.max_deg) + 64);
+        }
+        if (p.d.agg_last) agg = true;
+    }
+    stride = (stride + 63) & ~uint64_t(63);
+    *scratch_stride = stride;
+    *any_agg = agg;
+    uint64_t b = 0;
+    b += sizeof(DPlan) * plans.size() + 16 * plans.size() + 256 * 3;
+    b += waves() * (uint64_t)KMAX * stride * 4;
+    return b;
+}
+
+int Ctx_::ensure_agg(uint32_t n) {
+    uint64_t need = agg_waves() * (uint64_t)n * 4;
+    if (agg_off != UINT64_MAX && agg_n >= n) return PM_OK;
+    if (agg_off != UINT64_MAX) {
+        arena.release(agg_off);
+        arena.release(agg_touch_off);
+        agg_off = agg_touch_off = UINT64_MAX;
+    }
+    agg_off = arena.alloc(need);
+    agg_touch_off = arena.alloc(need);
+    if (agg_off == UINT64_MAX || agg_touch_off == UINT64_MAX) {
+        if (agg_off != UINT64_MAX) arena.release(agg_off);
+        agg_off = agg_touch_off = UINT64_MAX;
+        return fail(PM_E_NOMEM, "arena too small for the aggregation counters");
+    }
+    agg_n = n;
+    HIPCHK(hipMemsetAsync(dptr(agg_off), 0, need, stream));
+    return PM_OK;
+}
+
+int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph,
+                 uint64_t* ticket) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!pats || !ticket || npat == 0) return fail(PM_E_INVAL, "null patterns or ticket");
+    if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "pm_submit supports PM_AGG_COUNT; use pm_fsm for MNI");
+    if (morph != PM_MORPH_NONE && morph != PM_MORPH_NAIVE) return fail(PM_E_INVAL, "unknown morph mode");
+    GraphRes* G;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = graphs.find(gid);
+        if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+        G = it->second.get();
+    }
+    auto Q = std::make_unique<Query>();
+    Q->gid = gid;
+    Q->npat = npat;
+    std::vector<Pat> ps(npat);
+    for (uint32_t i = 0; i < npat; ++i) {
+        std::string err;
+        int rc = to_pat(pats[i], &ps[i], &err);
+        if (rc) return fail(rc, err);
+        for (int v = 0; v < ps[i].k; ++v)
+            if (ps[i].lab[v] >= 0 && !G->labeled) return fail(PM_E_INVAL, "labeled pattern on an unlabeled graph");
+    }
+    std::string err;
+    int rc = morph_plan_count(ps, morph, &Q->mp, &err);
+    if (rc) return fail(rc, err);
+    for (const Pat& a : Q->mp.alt) {
+        int prc;
+        const PlanInfo& pi = plan_for(*G, a, &prc);
+        if (prc) return fail(prc, g_err);
+        Q->plans.push_back(pi);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    Q->stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    Q->stats.num_alt = (uint32_t)Q->plans.size();
+    Q->t_submit = t0;
+    rc = launch(*G, *Q);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(mu);
+    uint64_t tk = next_ticket++;
+    G->inflight++;
+    queries[tk] = std::move(Q);
+    *ticket = tk;
+    return PM_OK;
+}
+
+int Ctx_::launch(GraphRes& G, Query& Q) {
+    const size_t np = Q.plans.size();
+    uint64_t stride;
+    bool any_agg;
+    uint64_t need = footprint(G, Q.plans, &stride, &any_agg);
+    HIPCHK(hipSetDevice(device));
+    if (any_agg) {
+        int rc = ensure_agg(G.n);
+        if (rc) return rc;
+    }
+    Q.off_mem = arena.alloc(need);
+    if (Q.off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
+    char* base = (char*)dptr(Q.off_mem);
+    uint64_t o = 0;
+    auto carve = [&](uint64_t bytes) {
+        char* p = base + o;
+        o += (bytes + 255) & ~uint64_t(255);
+        return p;
+    };
+    DPlan* dplans = (DPlan*)carve(sizeof(DPlan) * np);
+    uint64_t* counters = (uint64_t*)carve(16 * np);
+    uint32_t* heads = (uint32_t*)carve(256);
+    uint64_t* bytes = (uint64_t*)carve(256);
+    uint32_t* scratch = (uint32_t*)carve(waves() * (uint64_t)KMAX * stride * 4);
+    std::vector<DPlan> hp(np);
+    for (size_t i = 0; i < np; ++i) hp[i] = Q.plans[i].d;
+    HIPCHK(hipMemcpyAsync(dplans, hp.data(), sizeof(DPlan) * np, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemsetAsync(counters, 0, 16 * np, stream));
+    HIPCHK(hipMemsetAsync(heads, 0, 256, stream));
+    HIPCHK(hipMemsetAsync(bytes, 0, 256, stream));
+
+    KArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g.rp = (const uint32_t*)dptr(G.off_rp);
+    a.g.col = (const uint32_t*)dptr(G.off_col);
+    a.g.lab = G.labeled ? (const uint8_t*)dptr(G.off_lab) : nullptr;
+    a.g.n = G.n;
+    a.items = (const KItem*)dptr(G.off_items);
+    a.nitems = (uint32_t)G.items.size();
+    a.scratch = scratch;
+    a.buf_stride = stride;
+    a.bytes = bytes;
+    a.cancel = nullptr;
+    if (any_agg) {
+        a.aggcnt = (uint32_t*)dptr(agg_off);
+        a.aggtouch = (uint32_t*)dptr(agg_touch_off);
+    }
+    // plans without aggregation in one launch, aggregation plans in another
+    // (their grid is bounded by the dense counter arrays)
+    std::vector<int> groups[2];
+    for (size_t i = 0; i < np; ++i) groups[Q.plans[i].d.agg_last ? 1 : 0].push_back((int)i);
+    // the launch needs contiguous plans: we launch per contiguous run
+    if (!Q.ev_start) {
+        HIPCHK(hipEventCreate(&Q.ev_start));
+        HIPCHK(hipEventCreate(&Q.ev_stop));
+    }
+    if (count_bytes) {
+        // untimed counting pass (same kernel, byte tally enabled)
+        for (int grp = 0; grp < 2; ++grp) {
+            for (int pi : groups[grp]) {
+                KArgs b = a;
+                b.plans = dplans + pi;
+                b.nplans = 1;
+                b.counters = counters + 2 * pi;
+                b.head = heads + 1 + pi % 60;
+                HIPCHK(hipMemsetAsync(b.head, 0, 4, stream));
+                int gb = grp ? (int)std::max<uint64_t>(1, agg_waves() / (block / 64)) : grid_blocks();
+                if (launch_match(b, gb, block, true, stream)) return fail(PM_E_DEVICE, "kernel launch failed");
+            }
+        }
+        HIPCHK(hipMemsetAsync(counters, 0, 16 * np, stream));
+    }
+    HIPCHK(hipEventRecord(Q.ev_start, stream));
+    Q.stats.launches = 0;
+    // group 0: one multi-plan launch when the plans are contiguous
+    {
+        int i = 0;
+        while (i < (int)np) {
+            int grp = Q.plans[i].d.agg_last ? 1 : 0;
+            int j = i;
+            while (j < (int)np && (Q.plans[j].d.agg_last ? 1 : 0) == grp) ++j;
+            KArgs b = a;
+            b.plans = dplans + i;
+            b.nplans = j - i;
+            b.counters = counters + 2 * i;
+            b.head = heads + (Q.stats.launches % 60) + 1;
+            HIPCHK(hipMemsetAsync(b.head, 0, 4, stream));
+            int gb = grp ? (int)std::max<uint64_t>(1, agg_waves() / (block / 64)) : grid_blocks();
+            if (launch_match(b, gb, block, false, stream)) return fail(PM_E_DEVICE, "kernel launch failed");
+            Q.stats.launches++;
+            i = j;
+        }
+    }
+    HIPCHK(hipEventRecord(Q.ev_stop, stream));
+    Q.host_counters.resize(2 * np + 1);
+    HIPCHK(hipMemcpyAsync(Q.host_counters.data(), counters, 16 * np, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(&Q.host_counters[2 * np], bytes, 8, hipMemcpyDeviceToHost, stream));
+    if (!Q.ev_done) HIPCHK(hipEventCreate(&Q.ev_done));
+    HIPCHK(hipEventRecord(Q.ev_done, stream));
+    Q.stats.work_items = (uint64_t)G.items.size() * np;
+    return PM_OK;
+}
+
+int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
+    Query* Q;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = queries.find(ticket);
+        if (it == queries.end()) return fail(PM_E_NOTFOUND, "unknown ticket");
+        Q = it->second.get();
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        hipError_t e = hipEventQuery(Q->ev_done);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) return fail(PM_E_DEVICE, std::string("query failed: ") + hipGetErrorString(e));
+        if (timeout_us >= 0) {
+            double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+            if (us > (double)timeout_us) return fail(PM_E_TIMEOUT, "timeout");
+        }
+        std::this_thread::yield();
+    }
+    float kms = 0;
+    hipEventElapsedTime(&kms, Q->ev_start, Q->ev_stop);
+    Q->stats.kernel_ms = kms;
+    size_t np = Q->plans.size();
+    std::vector<int64_t> alt(np);
+    int rc = PM_OK;
+    for (size_t i = 0; i < np; ++i) {
+        unsigned __int128 v = ((unsigned __int128)Q->host_counters[2 * i + 1] << 64) | Q->host_counters[2 * i];
+        int64_t dv = Q->plans[i].divisor;
+        if (v % (unsigned __int128)dv) {
+            rc = fail(PM_E_DEVICE, "internal: match total not divisible by the plan divisor");
+            break;
+        }
+        v /= (unsigned __int128)dv;
+        if (v > (unsigned __int128)INT64_MAX) {
+            rc = fail(PM_E_OVERFLOW, "count exceeds int64");
+            break;
+        }
+        alt[i] = (int64_t)v;
+    }
+    std::vector<int64_t> res;
+    if (rc == PM_OK) {
+        std::string err;
+        rc = unmorph(Q->mp, Q->npat, alt, &res, &err);
+        if (rc) fail(rc, err);
+    }
+    if (rc == PM_OK && out) memcpy(out, res.data(), sizeof(int64_t) * Q->npat);
+    Q->stats.alg_bytes = Q->host_counters[2 * np];
+    Q->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - Q->t_submit).count();
+    last_stats = Q->stats;
+    last_alt = alt;
+    // release
+    std::lock_guard<std::mutex> g(mu);
+    arena.release(Q->off_mem);
+    hipEventDestroy(Q->ev_start);
+    hipEventDestroy(Q->ev_stop);
+    hipEventDestroy(Q->ev_done);
+    auto git = graphs.find(Q->gid);
+    if (git != graphs.end()) git->second->inflight--;
+    queries.erase(ticket);
+    return rc;
+}
+
+}  // namespace pm
+
+// ================================================================ C-ABI
+
+using namespace pm;
+
+struct pm_ctx {
+    Ctx_ c;
+};
+
+extern "C" {
+
+pm_status pm_create(void* dev_arena, uint64_t arena_bytes, void* hip_stream, int device, pm_ctx** out) {
+    if (!out || !dev_arena) return fail(PM_E_INVAL, "null arena or out");
+    if (((uintptr_t)dev_arena) & 255) return fail(PM_E_INVAL, "arena must be 256-byte aligned");
+    if (hipSetDevice(device) != hipSuccess) return fail(PM_E_DEVICE, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(PM_E_DEVICE, "hipGetDeviceProperties failed");
+    pm_ctx* c = new pm_ctx();
+    c->c.device = device;
+    c->c.stream = (hipStream_t)hip_stream;
+    c->c.arena.base = (uintptr_t)dev_arena;
+    c->c.arena.size = arena_bytes;
+    c->c.arena.free_[0] = arena_bytes & ~uint64_t(255);
+    c->c.num_cus = prop.multiProcessorCount;
+    *out = c;
+    return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx* ctx) {
+    if (!ctx) return PM_E_INVAL;
+    hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+    return PM_OK;
+}
+
+pm_status pm_graph_load(pm_ctx* ctx, uint32_t n, const uint32_t* row_ptr, const uint32_t* col,
+                        const uint8_t* labels, uint32_t* out_graph_id) {
+    if (!ctx) return fail(PM_E_INVAL, "null ctx");
+    try {
+        return ctx->c.graph_load(n, row_ptr, col, labels, out_graph_id);
+    } catch (const std::exception& e) {
+        return fail(PM_E_NOMEM, std::string("host allocation failed: ") + e.what());
+    }
+}
+
+pm_status pm_graph_unload(pm_ctx* ctx, uint32_t gid) {
+    if (!ctx) return fail(PM_E_INVAL, "null ctx");
+    return ctx->c.graph_unload(gid);
+}
+
+pm_status pm_graph_stats(pm_ctx* ctx, uint32_t gid, pm_graph_info* out) {
+    if (!ctx || !out) return fail(PM_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> g(ctx->c.mu);
+    auto it = ctx->c.graphs.find(gid);
+    if (it == ctx->c.graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+    const GraphRes& G = *it->second;
+    out->n = G.n;
+    out->m = G.m;
+    out->max_degree = G.max_deg;
+    out->max_out_degree = G.max_out;
+    out->labeled = G.labeled;
+    out->device_bytes = G.device_bytes;
+    return PM_OK;
+}
+
+pm_status pm_query_footprint(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, uint32_t npat, int32_t agg,
+                             int32_t morph, uint64_t* out_bytes) {
+    if (!ctx || !pats || !out_bytes) return fail(PM_E_INVAL, "null argument");
+    GraphRes* G;
+    {
+        std::lock_guard<std::mutex> g(ctx->c.mu);
+        auto it = ctx->c.graphs.find(gid);
+        if (it == ctx->c.graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+        G = it->second.get();
+    }
+    if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "footprint: COUNT only");
+    std::vector<Pat> ps(npat);
+    for (uint32_t i = 0; i < npat; ++i) {
+        std::string err;
+        int rc = to_pat(pats[i], &ps[i], &err);
+        if (rc) return fail(rc, err);
+    }
+    MorphPlan mp;
+    std::string err;
+    int rc = morph_plan_count(ps, morph, &mp, &err);
+    if (rc) return fail(rc, err);
+    std::vector<PlanInfo> plans;
+    for (const Pat& a : mp.alt) {
+        int prc;
+        plans.push_back(ctx->c.plan_for(*G, a, &prc));
+        if (prc) return prc;
+    }
+    uint64_t stride;
+    bool any_agg;
+    *out_bytes = ctx->c.footprint(*G, plans, &stride, &any_agg);
+    return PM_OK;
+}
+
+pm_status pm_submit(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, uint32_t npat, int32_t agg,
+                    int32_t morph, uint64_t* out_ticket) {
+    if (!ctx) return fail(PM_E_INVAL, "null ctx");
+    try {
+        return ctx->c.submit(gid, pats, npat, agg, morph, out_ticket);
+    } catch (const std::exception& e) {
+        return fail(PM_E_NOMEM, std::string("host allocation failed: ") + e.what());
+    }
+}
+
+pm_status pm_wait(pm_ctx* ctx, uint64_t ticket, int64_t* out_values, int64_t timeout_us) {
+    if (!ctx) return fail(PM_E_INVAL, "null ctx");
+    return ctx->c.wait(ticket, out_values, timeout_us);
+}
+
+pm_status pm_last_query_stats(pm_ctx* ctx, pm_query_stats* out) {
+    if (!ctx || !out) return fail(PM_E_INVAL, "null argument");
+    *out = ctx->c.last_stats;
+    return PM_OK;
+}
+
+pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket) {
+    if (!ctx) return fail(PM_E_INVAL, "null ctx");
+    std::lock_guard<std::mutex> g(ctx->c.mu);
+    if (!ctx->c.queries.count(ticket)) return fail(PM_E_NOTFOUND, "unknown ticket");
+    return fail(PM_E_UNSUPPORTED, "cancellation is not supported for batch queries");
+}
+
+pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg, int32_t morph, pm_pattern* out_alt,
+                        uint32_t* inout_nalt, int64_t* out_matrix) {
+    if (!pats || !inout_nalt) return fail(PM_E_INVAL, "null argument");
+    if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "morph plans for MNI are internal to pm_fsm");
+    std::vector<Pat> ps(npat);
+    for (uint32_t i = 0; i < npat; ++i) {
+        std::string err;
+        int rc = to_pat(pats[i], &ps[i], &err);
+        if (rc) return fail(rc, err);
+    }
+    MorphPlan mp;
+    std::string err;
+    int rc = morph_plan_count(ps, morph, &mp, &err);
+    if (rc) return fail(rc, err);
+    uint32_t na = (uint32_t)mp.alt.size();
+    if (*inout_nalt < na || !out_alt) {
+        *inout_nalt = na;
+        return fail(PM_E_INVAL, "out_alt capacity too small");
+    }
+    *inout_nalt = na;
+    for (uint32_t j = 0; j < na; ++j) {
+        pm_pattern& o = out_alt[j];
+        o.k = (uint32_t)mp.alt[j].k;
+        o.edge_mask = mp.alt[j].em;
+        o.induce = mp.alt[j].vi ? PM_VERTEX_INDUCED : PM_EDGE_INDUCED;
+        for (int i = 0; i < 8; ++i) o.label[i] = mp.alt[j].lab[i];
+    }
+    if (out_matrix)
+        for (size_t i = 0; i < mp.matrix.size(); ++i) out_matrix[i] = mp.matrix[i];
+    return PM_OK;
+}
+
+const char* pm_last_error(void) { return g_err.c_str(); }
+
+const char* pm_status_str(pm_status s) {
+    switch (s) {
+        case PM_OK: return "PM_OK";
+        case PM_E_INVAL: return "PM_E_INVAL";
+        case PM_E_NOMEM: return "PM_E_NOMEM";
+        case PM_E_OVERFLOW: return "PM_E_OVERFLOW";
+        case PM_E_UNSUPPORTED: return "PM_E_UNSUPPORTED";
+        case PM_E_DEVICE: return "PM_E_DEVICE";
+        case PM_E_BUSY: return "PM_E_BUSY";
+        case PM_E_TIMEOUT: return "PM_E_TIMEOUT";
+        case PM_E_CANCELLED: return "PM_E_CANCELLED";
+        case PM_E_NOTFOUND: return "PM_E_NOTFOUND";
+        default: return "PM_E_UNKNOWN";
+    }
+}
+
+pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
+    if (!ctx || !key) return fail(PM_E_INVAL, "null argument");
+    std::string k(key);
+    Ctx_& c = ctx->c;
+    if (k == "count_bytes") c.count_bytes = value != 0;
+    else if (k == "blocks_per_cu" && value >= 1 && value <= 64) c.blocks_per_cu = (int)value;
+    else if (k == "item_budget" && value >= 1) c.item_budget = (uint64_t)value;
+    else if (k == "item_split" && value >= 64) c.item_split = (uint32_t)value;
+    else if (k == "agg_waves" && value >= 1) c.agg_waves_opt = (uint64_t)value;
+    else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
+    return PM_OK;
+}
+
+pm_status pm_plan_describe(pm_ctx* ctx, uint32_t gid, const pm_pattern* pat, char* buf, uint64_t cap) {
+    if (!ctx || !pat || !buf || !cap) return fail(PM_E_INVAL, "null argument");
+    GraphRes* G;
+    {
+        std::lock_guard<std::mutex> g(ctx->c.mu);
+        auto it = ctx->c.graphs.find(gid);
+        if (it == ctx->c.graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+        G = it->second.get();
+    }
+    Pat p;
+    std::string err;
+    int rc = to_pat(*pat, &p, &err);
+    if (rc) return fail(rc, err);
+    int prc;
+    const PlanInfo& pi = ctx->c.plan_for(*G, p, &prc);
+    if (prc) return prc;
+    std::string s = pi.describe();
+    snprintf(buf, cap, "%s", s.c_str());
+    return PM_OK;
+}
+
+uint64_t pm_fsm_num_slots(uint32_t num_labels) { return 0 * num_labels; }
+pm_status pm_fsm_slot(uint32_t, uint64_t, pm_pattern*) { return fail(PM_E_UNSUPPORTED, "FSM not built yet"); }
+pm_status pm_fsm(pm_ctx*, uint32_t, uint32_t, int64_t, int32_t, int64_t*, uint8_t*, uint64_t) {
+    return fail(PM_E_UNSUPPORTED, "FSM not built yet");
+}
+
+}  // extern "C"

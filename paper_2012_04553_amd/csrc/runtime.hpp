@@ -1,0 +1,94 @@
+// Host runtime state of a pm_ctx.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace pm {
+
+extern thread_local std::string g_err;
+int fail(int code, const std::string& msg);
+
+// First-fit sub-allocator over the caller's device arena (offsets).
+struct Arena {
+    uintptr_t base = 0;
+    uint64_t size = 0;
+    std::map<uint64_t, uint64_t> free_;  // offset -> bytes
+    std::map<uint64_t, uint64_t> used_;
+    std::mutex mu;
+    uint64_t alloc(uint64_t bytes);       // UINT64_MAX when full
+    void release(uint64_t off);
+    uint64_t largest_free();
+};
+
+struct GraphRes {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    bool labeled = false;
+    uint32_t max_deg = 0, max_out = 0;
+    GraphStats st;
+    uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_lab = UINT64_MAX, off_items = UINT64_MAX;
+    uint64_t device_bytes = 0;
+    std::vector<KItem> items;
+    std::vector<std::pair<Pat, PlanInfo>> plan_cache;
+    int inflight = 0;
+};
+
+struct Query {
+    uint32_t gid = 0;
+    uint32_t npat = 0;
+    MorphPlan mp;
+    std::vector<PlanInfo> plans;
+    uint64_t off_mem = UINT64_MAX;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
+    std::vector<uint64_t> host_counters;
+    pm_query_stats stats{};
+    std::chrono::steady_clock::time_point t_submit;
+};
+
+struct Ctx_ {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    int num_cus = 1;
+    int blocks_per_cu = 4;
+    int block = 256;
+    uint64_t item_budget = 4096;
+    uint32_t item_split = 2048;
+    bool count_bytes = false;
+    uint64_t agg_waves_opt = 512;
+    std::mutex mu, plan_mu;
+    std::map<uint32_t, std::unique_ptr<GraphRes>> graphs;
+    std::map<uint64_t, std::unique_ptr<Query>> queries;
+    uint32_t next_gid = 1;
+    uint64_t next_ticket = 1;
+    uint64_t agg_off = UINT64_MAX, agg_touch_off = UINT64_MAX;
+    uint32_t agg_n = 0;
+    pm_query_stats last_stats{};
+    std::vector<int64_t> last_alt;
+
+    void* dptr(uint64_t off) const { return (void*)(arena.base + off); }
+    int grid_blocks() const;
+    uint64_t waves() const;
+    uint64_t agg_waves() const { return std::min<uint64_t>(agg_waves_opt, waves()); }
+    int graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels, uint32_t* gid);
+    int graph_unload(uint32_t gid);
+    const PlanInfo& plan_for(GraphRes& G, const Pat& p, int* rc);
+    uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, uint64_t* stride, bool* any_agg) const;
+    int ensure_agg(uint32_t n);
+    int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
+    int launch(GraphRes& G, Query& Q);
+    int wait(uint64_t ticket, int64_t* out, int64_t timeout_us);
+};
+
+}  // namespace pm
