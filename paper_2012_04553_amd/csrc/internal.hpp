@@ -74,6 +74,8 @@ struct DTerm {           // |{x : constraints}| evaluated per full core match
     int8_t label;
     uint8_t cheap;       // one adjacency list, no anti, no label: range count
     uint8_t agg;         // equals the aggregation multiplicity of the last level
+    uint8_t sure;        // cheap terms: neq levels known adjacent to the list owner
+    uint8_t pad[3];
 };
 struct DMono {
     int64_t coef;
@@ -104,7 +106,14 @@ struct PlanInfo {
     int64_t divisor = 1;       // count = (sum over core reps of tail) / divisor
     std::array<int8_t, KMAX> order{};   // pattern vertex at each core level
     int formulation = 0;       // 0 coset, 1 pattern-chain
-    double est_cost = 0;
+    double est_cost = 0;       // kernel work of this plan alone
+    double total_cost = 0;     // including the sub-pattern counts it needs
+    // Quotient form: the kernel sums only the product of the single-leaf set
+    // sizes; the merged-leaf terms of the inclusion-exclusion are counts of
+    // smaller patterns:  count = (hmult * kernel_sum - sum w_q count(q)) / autp.
+    bool rewrite = false;
+    int64_t hmult = 1, autp = 1;
+    std::vector<std::pair<Pat, int64_t>> subs;
     std::string describe() const;
 };
 
@@ -115,6 +124,9 @@ struct GraphStats {             // degree statistics used by the cost model
     double avg_out = 0;         // mean out-degree (degree-ordered orientation)
     double nbr_out = 0;         // sum (d+)^2 / m
     double max_deg = 0, max_out = 0;
+    // joint per-vertex sums for exact two-level costs (p = out-degree d+,
+    // q = in-degree d- in the degree-ordered orientation, d = degree)
+    double s_pp = 0, s_pq = 0, s_pd = 0, s_qq = 0, s_qd = 0, s_dd = 0;
 };
 
 int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err);

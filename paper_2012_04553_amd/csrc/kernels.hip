@@ -1,22 +1,24 @@
-// Matching kernels for gfx950 (wave64).
+// Matching kernel for gfx950 (wave64).
 //
-// One wavefront works on one work item at a time, taken from an atomic
-// queue: a range of roots (vertices in degree order) of one plan, or a
-// slice of the level-1 candidates of a single high-degree root.  From a
-// root the wave extends partial matches level by level (the core of the
-// plan).  The candidates of a level are produced cooperatively: the 64
-// lanes stream 64 consecutive entries of the shortest bounded driver list
-// (a neighbour list, or an earlier level's candidate buffer that contains
-// this level's), each lane tests its entry against the other neighbour
-// lists of the level (binary search: membership for edges, non-membership
-// for anti-edges), against the symmetry-breaking bounds, injectivity and the
-// label, and a ballot + popcount either counts the survivors or compacts
-// them in order into the level buffer.  At a full core match the tail
-// polynomial over set sizes gives the number of injective leaf extensions
-// (see the plan compiler); when every tail term is a plain range count the
-// lanes evaluate it for 64 last-level candidates in parallel.  A plan whose
-// last core vertex is reached only through bridge leaves aggregates
-// two-hop multiplicities in a per-wave dense counter array.
+// One wavefront takes one work item at a time from an atomic queue: a
+// range of roots (vertex ids ascend with degree, so a range holds roots of
+// similar degree) of one plan, or a slice of the level-1 candidates of one
+// high-degree root.  Core levels are enumerated depth first.  Upper levels
+// are wave-cooperative: the 64 lanes stream 64 consecutive entries of the
+// shortest bounded driver list (a neighbour list, or the buffer of an
+// earlier level that contains this level's candidates), each lane tests its
+// entry against the other lists of the level (binary search: membership
+// for pattern edges, non-membership for anti-edges), the symmetry-breaking
+// bounds, injectivity and the label, and ballot + mbcnt compact the
+// survivors in order into the level buffer.  The candidates of the
+// second-to-last core level are then spread over the lanes: every lane
+// finishes its own partial match - counting the last level, or walking it
+// and evaluating the tail polynomial over leaf-set sizes - with sequential
+// set operations, so one wave keeps 64 independent memory streams in flight
+// on the short (degree-oriented) lists that dominate power-law graphs.
+// A plan whose last core vertex is reached only through bridge leaves
+// aggregates two-hop multiplicities in a per-wave dense counter array, the
+// lanes scanning different bridges.
 //
 // Counts accumulate per lane in 128 bits, are reduced across the wave and
 // added to a 128-bit global counter per plan (two 64-bit atomics with
@@ -31,6 +33,8 @@ namespace pm {
 typedef unsigned __int128 u128;
 typedef __int128 i128;
 
+constexpr uint32_t NOB = 0xffffffffu;  // "no upper bound"
+
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t lo,
                                                      uint32_t hi, uint32_t x) {
     while (lo < hi) {
@@ -41,168 +45,172 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
     return lo;
 }
 
-__device__ __forceinline__ bool contains(const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi,
-                                         uint32_t x) {
-    uint32_t p = lower_bound_u32(col, lo, hi, x);
-    return p < hi && col[p] == x;
+__device__ __forceinline__ bool in_sorted(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
+                                          uint32_t x) {
+    uint32_t p = lower_bound_u32(a, lo, hi, x);
+    return p < hi && a[p] == x;
+}
+
+// Entries of N(v) within [lo, hi): the split index (first neighbour above
+// v) answers the common bounds lo = v+1 and hi = v without a search.
+__device__ __forceinline__ void list_range(const KGraph& g, uint32_t v, uint32_t lo, uint32_t hi,
+                                           uint32_t& b, uint32_t& e) {
+    const uint32_t s = g.rp[v], t = g.rp[v + 1], sp = g.split[v];
+    if (lo == 0) b = s;
+    else if (lo == v + 1) b = sp;
+    else if (lo > v) b = lower_bound_u32(g.col, sp, t, lo);
+    else b = lower_bound_u32(g.col, s, sp, lo);
+    if (hi == NOB) e = t;
+    else if (hi == v) e = sp;
+    else if (hi > v) e = lower_bound_u32(g.col, b > sp ? b : sp, t, hi);
+    else e = lower_bound_u32(g.col, b, sp, hi);
+    if (e < b) e = b;
 }
 
 __device__ __forceinline__ int wave_lane() { return __lane_id(); }
 
-__device__ __forceinline__ uint32_t bcast(uint32_t x) {
-    return __builtin_amdgcn_readfirstlane(x);
+__device__ __forceinline__ uint32_t bcast(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
+    return (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
 struct Ctx {
-    const KArgs* a;
+    KGraph g;
     const DPlan* P;
-    uint32_t v[KMAX];       // core vertices matched so far (wave-uniform)
-    uint32_t* buf;          // per-wave level buffers
+    uint32_t v[KMAX];        // wave-uniform prefix of the core match
+    uint32_t* buf;           // per-wave level buffers
     uint64_t stride;
-    uint32_t size[KMAX];    // candidates per level buffer
-    uint64_t bytes;         // algorithmic bytes (when counting)
+    uint32_t size[KMAX];     // entries in each level buffer
+    uint64_t bytes;          // algorithmic bytes (counting build only)
 };
 
-// Bounds [lo, hi) implied by gt/lt masks over the matched core vertices.
-__device__ __forceinline__ void bounds_of(const Ctx& c, uint8_t gt, uint8_t lt, uint32_t& lo,
+__device__ __forceinline__ void bounds_of(const uint32_t* vv, uint8_t gt, uint8_t lt, uint32_t& lo,
                                           uint32_t& hi) {
     lo = 0;
-    hi = 0xffffffffu;
+    hi = NOB;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
-        if ((gt >> i) & 1) lo = max(lo, c.v[i] + 1);
-        if ((lt >> i) & 1) hi = min(hi, c.v[i]);
+        if ((gt >> i) & 1) lo = max(lo, vv[i] + 1);
+        if ((lt >> i) & 1) hi = min(hi, vv[i]);
     }
 }
 
-// Generic filter over a driver range.  MODE 0: count, 1: compact into out.
-// Returns the number of survivors (wave-uniform).
-template <int MODE, bool BYTES>
-__device__ uint32_t filter_range(Ctx& c, const uint32_t* __restrict__ drv, uint32_t b, uint32_t e,
-                                 uint8_t chk_adj, uint8_t anti, uint8_t neq, int8_t label,
-                                 uint32_t lo, uint32_t hi, uint32_t* __restrict__ out) {
-    const uint32_t* __restrict__ rp = c.a->g.rp;
-    const uint32_t* __restrict__ col = c.a->g.col;
-    const uint8_t* __restrict__ lab = c.a->g.lab;
-    const int lane = wave_lane();
-    // neighbour-list ranges of the lists to probe, restricted to [lo, hi)
-    uint32_t pb[KMAX], pe[KMAX];
+// Shortest bounded adjacency list among `adj` (per lane when vv differs).
+__device__ __forceinline__ int pick_driver(const KGraph& g, const uint32_t* vv, uint8_t adj, uint32_t lo,
+                                           uint32_t hi, uint32_t& b, uint32_t& e) {
+    uint32_t best = NOB;
+    int bi = 0;
+    b = e = 0;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
-        pb[i] = pe[i] = 0;
-        if (((chk_adj | anti) >> i) & 1) {
-            uint32_t s = rp[c.v[i]], t = rp[c.v[i] + 1];
-            pb[i] = lo ? lower_bound_u32(col, s, t, lo) : s;
-            pe[i] = hi != 0xffffffffu ? lower_bound_u32(col, pb[i], t, hi) : t;
-            if (BYTES) c.bytes += 8 + 4ull * (pe[i] - pb[i]);
+        if (!((adj >> i) & 1)) continue;
+        uint32_t sb, se;
+        list_range(g, vv[i], lo, hi, sb, se);
+        if (se - sb < best) {
+            best = se - sb;
+            bi = i;
+            b = sb;
+            e = se;
         }
     }
-    if (BYTES) c.bytes += 4ull * (e - b);
+    return bi;
+}
+
+// Per-candidate test against probe lists, injectivity and label.
+struct Probe {
+    uint32_t pb[KMAX], pe[KMAX];
+    uint8_t adj, anti, neq;
+    int8_t label;
+};
+
+__device__ __forceinline__ uint64_t make_probe(const KGraph& g, const uint32_t* vv, uint8_t adj, uint8_t anti,
+                                               uint8_t neq, int8_t label, uint32_t lo, uint32_t hi,
+                                               Probe& pr) {
+    uint64_t bytes = 0;
+    pr.adj = adj;
+    pr.anti = anti;
+    pr.neq = neq;
+    pr.label = label;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        pr.pb[i] = pr.pe[i] = 0;
+        if (((adj | anti) >> i) & 1) {
+            list_range(g, vv[i], lo, hi, pr.pb[i], pr.pe[i]);
+            bytes += 8 + 4ull * (pr.pe[i] - pr.pb[i]);
+        }
+    }
+    return bytes;
+}
+
+__device__ __forceinline__ bool probe_ok(const KGraph& g, const uint32_t* vv, const Probe& pr, uint32_t x) {
+    if (pr.label >= 0 && g.lab[x] != (uint8_t)pr.label) return false;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+        if (((pr.neq >> i) & 1) && x == vv[i]) return false;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        if (((pr.adj >> i) & 1) && !in_sorted(g.col, pr.pb[i], pr.pe[i], x)) return false;
+        if (((pr.anti >> i) & 1) && in_sorted(g.col, pr.pb[i], pr.pe[i], x)) return false;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------- wave-cooperative level
+
+// Materialise the candidates of core level j (wave-uniform prefix c.v).
+template <bool BYTES>
+__device__ uint32_t wave_level(Ctx& c, int j) {
+    const DLevel L = c.P->lev[j];
+    const int lane = wave_lane();
+    uint32_t lo, hi;
+    bounds_of(c.v, L.gt, L.lt, lo, hi);
+    uint32_t* out = c.buf + (uint64_t)j * c.stride;
+    if (lo >= hi) return 0;
+    const uint32_t* drv;
+    uint32_t b, e;
+    uint8_t chk = L.adj, anti = L.anti;
+    if (L.base != 0xff) {
+        const uint32_t* bb = c.buf + (uint64_t)L.base * c.stride;
+        uint32_t n = c.size[L.base];
+        b = lo ? lower_bound_u32(bb, 0, n, lo) : 0;
+        e = hi != NOB ? lower_bound_u32(bb, b, n, hi) : n;
+        drv = bb;
+        chk &= (uint8_t)~c.P->lev[L.base].adj;
+        anti &= (uint8_t)~c.P->lev[L.base].anti;
+    } else {
+        int bi = pick_driver(c.g, c.v, L.adj, lo, hi, b, e);
+        drv = c.g.col;
+        chk &= (uint8_t)~(1u << bi);
+        if (BYTES && lane == 0) c.bytes += 8;
+    }
+    Probe pr;
+    uint64_t pbytes = make_probe(c.g, c.v, chk, anti, L.neq, L.label, lo, hi, pr);
+    if (BYTES && lane == 0) c.bytes += pbytes + 4ull * (e - b);
     uint32_t total = 0;
     for (uint32_t base = b; base < e; base += 64) {
         uint32_t idx = base + lane;
         bool ok = idx < e;
         uint32_t x = ok ? drv[idx] : 0;
-        if (ok && label >= 0) ok = lab[x] == (uint8_t)label;
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (ok && ((neq >> i) & 1)) ok = x != c.v[i];
-        }
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (ok && ((chk_adj >> i) & 1)) ok = contains(col, pb[i], pe[i], x);
-            if (ok && ((anti >> i) & 1)) ok = !contains(col, pb[i], pe[i], x);
-        }
+        ok = ok && probe_ok(c.g, c.v, pr, x);
         uint64_t m = __ballot(ok);
-        if (MODE == 1) {
-            uint32_t pos = total + (uint32_t)__builtin_amdgcn_mbcnt_hi(
-                                       (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-            if (ok) out[pos] = x;
-        }
+        if (ok) out[total + lane_prefix(m)] = x;
         total += (uint32_t)__popcll(m);
     }
     return total;
 }
 
-// Candidate set of core level j (MODE 1 compacts into the level buffer).
+// ---------------------------------------------------------------- per-lane work
+
+// Per-lane filter over level j (prefix vv complete below j).  MODE 0 counts;
+// MODE 1 evaluates the tail for every survivor and returns it in `sum`.
 template <int MODE, bool BYTES>
-__device__ uint32_t level_set(Ctx& c, int j) {
-    const DLevel L = c.P->lev[j];
-    const uint32_t* __restrict__ rp = c.a->g.rp;
-    const uint32_t* __restrict__ col = c.a->g.col;
-    uint32_t lo, hi;
-    bounds_of(c, L.gt, L.lt, lo, hi);
-    uint32_t* out = c.buf + (uint64_t)j * c.stride;
-    if (lo >= hi) return 0;
-    const uint32_t* drv;
-    uint32_t b, e;
-    uint8_t chk = L.adj;
-    if (L.base != 0xff) {
-        const uint32_t* bb = c.buf + (uint64_t)L.base * c.stride;
-        uint32_t n = c.size[L.base];
-        b = lo ? lower_bound_u32(bb, 0, n, lo) : 0;
-        e = hi != 0xffffffffu ? lower_bound_u32(bb, b, n, hi) : n;
-        drv = bb;
-        chk &= (uint8_t)~c.P->lev[L.base].adj;
-    } else {
-        // shortest bounded adjacency list drives
-        uint32_t best = 0xffffffffu;
-        int bi = 0;
-        b = e = 0;
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (!((L.adj >> i) & 1)) continue;
-            uint32_t s = rp[c.v[i]], t = rp[c.v[i] + 1];
-            uint32_t sb = lo ? lower_bound_u32(col, s, t, lo) : s;
-            uint32_t se = hi != 0xffffffffu ? lower_bound_u32(col, sb, t, hi) : t;
-            if (se - sb < best) {
-                best = se - sb;
-                bi = i;
-                b = sb;
-                e = se;
-            }
-        }
-        drv = col;
-        chk &= (uint8_t)~(1u << bi);
-        if (BYTES) c.bytes += 8;
-    }
-    uint8_t anti = L.anti;
-    if (L.base != 0xff) anti &= (uint8_t)~c.P->lev[L.base].anti;
-    return filter_range<MODE, BYTES>(c, drv, b, e, chk, anti, L.neq, L.label, lo, hi, out);
-}
-
-// ---- tail terms --------------------------------------------------------
-
-// Range count for a cheap term: |N(v_a) within bounds| minus matched core
-// vertices that lie in that range (injectivity).  Per lane, v_last given.
-__device__ __forceinline__ uint64_t cheap_term(const Ctx& c, const DTerm& t, const uint32_t* vv) {
-    const uint32_t* __restrict__ rp = c.a->g.rp;
-    const uint32_t* __restrict__ col = c.a->g.col;
-    uint32_t lo = 0, hi = 0xffffffffu;
-    int a = 0;
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-        if ((t.gt >> i) & 1) lo = max(lo, vv[i] + 1);
-        if ((t.lt >> i) & 1) hi = min(hi, vv[i]);
-        if ((t.adj >> i) & 1) a = i;
-    }
-    if (lo >= hi) return 0;
-    uint32_t s = rp[vv[a]], e = rp[vv[a] + 1];
-    uint32_t b = lo ? lower_bound_u32(col, s, e, lo) : s;
-    uint32_t f = hi != 0xffffffffu ? lower_bound_u32(col, b, e, hi) : e;
-    uint64_t cnt = f - b;
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-        if (!((t.neq >> i) & 1)) continue;
-        uint32_t y = vv[i];
-        if (y >= lo && y < hi && contains(col, b, f, y)) --cnt;
-    }
-    return cnt;
-}
+__device__ uint64_t lane_level(Ctx& c, uint32_t* vv, int j, u128& sum);
 
 __device__ __forceinline__ u128 poly_eval(const DPlan* P, const uint64_t* tv) {
     i128 s = 0;
-    for (int m = 0; m < P->nmono; ++m) {
+    const int nm = P->nmono;
+    for (int m = 0; m < nm; ++m) {
         const DMono M = P->mono[m];
         i128 prod = (i128)M.coef;
         for (int f = 0; f < M.nf; ++f) prod *= (i128)tv[M.f[f]];
@@ -211,160 +219,133 @@ __device__ __forceinline__ u128 poly_eval(const DPlan* P, const uint64_t* tv) {
     return s > 0 ? (u128)s : (u128)0;
 }
 
-// Lane-parallel tail: all terms cheap (or the aggregation multiplicity).
+// One tail term for the full core match vv (per lane).
 template <bool BYTES>
-__device__ __forceinline__ u128 tail_lane(Ctx& c, const uint32_t* vv, uint64_t aggm) {
-    uint64_t tv[MAX_TERMS];
-    const int nt = c.P->nterm;
-    for (int q = 0; q < nt; ++q) {
-        const DTerm t = c.P->term[q];
-        tv[q] = t.agg ? aggm : cheap_term(c, t, vv);
-        if (BYTES && !t.agg) c.bytes += 8;
-    }
-    return poly_eval(c.P, tv);
-}
-
-// Wave-cooperative tail for one full core match (c.v complete).
-template <bool BYTES>
-__device__ u128 tail_wave(Ctx& c) {
-    uint64_t tv[MAX_TERMS];
-    const uint32_t* __restrict__ rp = c.a->g.rp;
-    const uint32_t* __restrict__ col = c.a->g.col;
-    const int nt = c.P->nterm;
-    for (int q = 0; q < nt; ++q) {
-        const DTerm t = c.P->term[q];
-        if (t.cheap) {
-            tv[q] = cheap_term(c, t, c.v);
-            if (BYTES) c.bytes += 8;
-            continue;
-        }
-        uint32_t lo, hi;
-        bounds_of(c, t.gt, t.lt, lo, hi);
-        if (lo >= hi) {
-            tv[q] = 0;
-            continue;
-        }
-        uint32_t best = 0xffffffffu, b = 0, e = 0;
-        int bi = 0;
+__device__ __forceinline__ uint64_t lane_term(Ctx& c, const uint32_t* vv, const DTerm& t, uint64_t aggm) {
+    if (t.agg) return aggm;
+    uint32_t lo, hi;
+    bounds_of(vv, t.gt, t.lt, lo, hi);
+    if (lo >= hi) return 0;
+    if (t.cheap) {
+        int a = __builtin_ctz((uint32_t)t.adj);
+        uint32_t b, e;
+        list_range(c.g, vv[a], lo, hi, b, e);
+        uint64_t cnt = e - b;
 #pragma unroll
         for (int i = 0; i < KMAX; ++i) {
-            if (!((t.adj >> i) & 1)) continue;
-            uint32_t s = rp[c.v[i]], f = rp[c.v[i] + 1];
-            uint32_t sb = lo ? lower_bound_u32(col, s, f, lo) : s;
-            uint32_t se = hi != 0xffffffffu ? lower_bound_u32(col, sb, f, hi) : f;
-            if (se - sb < best) {
-                best = se - sb;
-                bi = i;
-                b = sb;
-                e = se;
-            }
+            if (!((t.neq >> i) & 1)) continue;
+            uint32_t y = vv[i];
+            if (y >= lo && y < hi && (((t.sure >> i) & 1) || in_sorted(c.g.col, b, e, y))) --cnt;
         }
         if (BYTES) c.bytes += 8;
-        tv[q] = filter_range<0, BYTES>(c, col, b, e, (uint8_t)(t.adj & ~(1u << bi)), t.anti, t.neq,
-                                        t.label, lo, hi, nullptr);
+        return cnt;
     }
+    uint32_t b, e;
+    int bi = pick_driver(c.g, vv, t.adj, lo, hi, b, e);
+    Probe pr;
+    uint64_t pbytes = make_probe(c.g, vv, (uint8_t)(t.adj & ~(1u << bi)), t.anti, t.neq, t.label, lo, hi, pr);
+    if (BYTES) c.bytes += 8 + pbytes + 4ull * (e - b);
+    uint64_t cnt = 0;
+    for (uint32_t p = b; p < e; ++p)
+        if (probe_ok(c.g, vv, pr, c.g.col[p])) ++cnt;
+    return cnt;
+}
+
+template <bool BYTES>
+__device__ __forceinline__ u128 lane_tail(Ctx& c, const uint32_t* vv, uint64_t aggm) {
+    uint64_t tv[MAX_TERMS];
+    const int nt = c.P->nterm;
+    for (int q = 0; q < nt; ++q) tv[q] = lane_term<BYTES>(c, vv, c.P->term[q], aggm);
     return poly_eval(c.P, tv);
 }
 
-// ---- last core level ---------------------------------------------------
-
-template <bool BYTES>
-__device__ void last_level(Ctx& c, int j, uint32_t s0, uint32_t s1, u128& acc) {
-    const DPlan* P = c.P;
-    const int lane = wave_lane();
-    if (P->nterm == 0) {
-        if (P->mult == 0) return;
-        uint32_t n;
-        if (j == 1 && (s0 != 0 || s1 != 0xffffffffu)) {
-            n = level_set<1, BYTES>(c, j);
-            uint32_t e = min(s1, n);
-            n = e > s0 ? e - s0 : 0;
-        } else {
-            n = level_set<0, BYTES>(c, j);
-        }
-        if (lane == 0) acc += (u128)n * (u128)(uint32_t)P->mult;
-        return;
-    }
-    uint32_t n = level_set<1, BYTES>(c, j);
-    const uint32_t* bj = c.buf + (uint64_t)j * c.stride;
-    uint32_t b = 0, e = n;
-    if (j == 1) {
-        b = min(s0, n);
-        e = min(s1, n);
-    }
-    if (P->lane_par) {
-        uint32_t vv[KMAX];
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
-        for (uint32_t base = b; base < e; base += 64) {
-            uint32_t idx = base + lane;
-            if (idx < e) {
-                vv[j] = bj[idx];
-                acc += tail_lane<BYTES>(c, vv, 0);
-            }
-        }
+template <int MODE, bool BYTES>
+__device__ uint64_t lane_level(Ctx& c, uint32_t* vv, int j, u128& sum) {
+    const DLevel L = c.P->lev[j];
+    uint32_t lo, hi;
+    bounds_of(vv, L.gt, L.lt, lo, hi);
+    if (lo >= hi) return 0;
+    const uint32_t* drv;
+    uint32_t b, e;
+    uint8_t chk = L.adj, anti = L.anti;
+    if (L.base != 0xff) {
+        const uint32_t* bb = c.buf + (uint64_t)L.base * c.stride;
+        uint32_t n = c.size[L.base];
+        b = lo ? lower_bound_u32(bb, 0, n, lo) : 0;
+        e = hi != NOB ? lower_bound_u32(bb, b, n, hi) : n;
+        drv = bb;
+        chk &= (uint8_t)~c.P->lev[L.base].adj;
+        anti &= (uint8_t)~c.P->lev[L.base].anti;
     } else {
-        for (uint32_t idx = b; idx < e; ++idx) {
-            c.v[j] = bj[idx];
-            u128 r = tail_wave<BYTES>(c);
-            if (lane == 0) acc += r;
+        int bi = pick_driver(c.g, vv, L.adj, lo, hi, b, e);
+        drv = c.g.col;
+        chk &= (uint8_t)~(1u << bi);
+        if (BYTES) c.bytes += 8;
+    }
+    Probe pr;
+    uint64_t pbytes = make_probe(c.g, vv, chk, anti, L.neq, L.label, lo, hi, pr);
+    if (BYTES) c.bytes += pbytes + 4ull * (e - b);
+    uint64_t cnt = 0;
+    for (uint32_t p = b; p < e; ++p) {
+        uint32_t x = drv[p];
+        if (!probe_ok(c.g, vv, pr, x)) continue;
+        if (MODE == 0) {
+            ++cnt;
+        } else {
+            vv[j] = x;
+            sum += lane_tail<BYTES>(c, vv, 0);
         }
     }
+    return cnt;
 }
 
+// ---------------------------------------------------------------- aggregation
+
 // Two-hop aggregation for the last core level j: targets x reached from
-// bridges y in N(v_src) (bridge bounds and label), counted in a per-wave
-// dense array; then every touched target is evaluated lane-parallel with
-// its multiplicity.
+// bridges y in N(v_src) (bridge bounds and label) are counted in a per-wave
+// dense array; every touched target is then evaluated lane-parallel with
+// its multiplicity as the bridge term.
 template <bool BYTES>
-__device__ void agg_level(Ctx& c, int j, uint32_t wid, u128& acc) {
+__device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const KArgs& a, u128& acc) {
     const DPlan* P = c.P;
     const DLevel L = P->lev[j];
-    const uint32_t* __restrict__ rp = c.a->g.rp;
-    const uint32_t* __restrict__ col = c.a->g.col;
-    const uint8_t* __restrict__ lab = c.a->g.lab;
     const int lane = wave_lane();
-    uint32_t* cnt = c.a->aggcnt + (uint64_t)wid * c.a->g.n;
-    uint32_t* touched = c.a->aggtouch + (uint64_t)wid * c.a->g.n;
-    uint32_t blo, bhi;
-    bounds_of(c, P->bridge_gt, P->bridge_lt, blo, bhi);
-    uint32_t lo, hi;
-    bounds_of(c, L.gt, L.lt, lo, hi);
+    uint32_t* cnt = a.aggcnt + (uint64_t)wid * c.g.n;
+    uint32_t* touched = a.aggtouch + (uint64_t)wid * c.g.n;
+    uint32_t blo, bhi, lo, hi;
+    bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
+    bounds_of(c.v, L.gt, L.lt, lo, hi);
     if (blo >= bhi || lo >= hi) return;
-    const uint32_t src = c.v[P->bridge_src];
-    uint32_t s = rp[src], t = rp[src + 1];
-    uint32_t bb = blo ? lower_bound_u32(col, s, t, blo) : s;
-    uint32_t be = bhi != 0xffffffffu ? lower_bound_u32(col, bb, t, bhi) : t;
-    if (BYTES) c.bytes += 8 + 4ull * (be - bb);
-    uint32_t ntouch = 0;
-    for (uint32_t p = bb; p < be; ++p) {
-        uint32_t y = col[p];
-        if (P->bridge_label >= 0 && lab[y] != (uint8_t)P->bridge_label) continue;
+    uint32_t bb, be;
+    list_range(c.g, c.v[P->bridge_src], blo, bhi, bb, be);
+    if (BYTES && lane == 0) c.bytes += 8 + 4ull * (be - bb);
+    if (lane == 0) *s_touch = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t base = bb; base < be; base += 64) {
+        uint32_t idx = base + lane;
+        if (idx >= be) continue;
+        uint32_t y = c.g.col[idx];
+        if (P->bridge_label >= 0 && c.g.lab[y] != (uint8_t)P->bridge_label) continue;
         bool core = false;
         for (int i = 0; i < j; ++i) core |= (y == c.v[i]);
         if (core) continue;
-        uint32_t ys = rp[y], ye = rp[y + 1];
-        uint32_t yb = lo ? lower_bound_u32(col, ys, ye, lo) : ys;
-        uint32_t yf = hi != 0xffffffffu ? lower_bound_u32(col, yb, ye, hi) : ye;
+        uint32_t yb, yf;
+        list_range(c.g, y, lo, hi, yb, yf);
         if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
-        for (uint32_t base = yb; base < yf; base += 64) {
-            uint32_t idx = base + lane;
-            bool ok = idx < yf;
-            uint32_t x = ok ? col[idx] : 0;
-            if (ok && L.label >= 0) ok = lab[x] == (uint8_t)L.label;
+        for (uint32_t p = yb; p < yf; ++p) {
+            uint32_t x = c.g.col[p];
+            if (L.label >= 0 && c.g.lab[x] != (uint8_t)L.label) continue;
+            bool skip = false;
 #pragma unroll
             for (int i = 0; i < KMAX; ++i)
-                if (ok && ((L.neq >> i) & 1)) ok = x != c.v[i];
-            bool fresh = false;
-            if (ok) fresh = atomicAdd(&cnt[x], 1u) == 0u;
-            uint64_t m = __ballot(fresh);
-            uint32_t pos = ntouch + (uint32_t)__builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-            if (fresh) touched[pos] = x;
-            ntouch += (uint32_t)__popcll(m);
+                if (((L.neq >> i) & 1) && x == c.v[i]) skip = true;
+            if (skip) continue;
+            if (atomicAdd(&cnt[x], 1u) == 0u) touched[atomicAdd(s_touch, 1u)] = x;
         }
     }
+    __builtin_amdgcn_wave_barrier();
     __threadfence_block();
+    const uint32_t ntouch = bcast(*(volatile uint32_t*)s_touch);
     uint32_t vv[KMAX];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
@@ -375,17 +356,18 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, u128& acc) {
             uint32_t m = cnt[x];
             cnt[x] = 0;
             vv[j] = x;
-            acc += tail_lane<BYTES>(c, vv, m);
+            acc += lane_tail<BYTES>(c, vv, m);
         }
     }
     __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
 }
 
-// ---- wave reduction and flush -------------------------------------------
+// ---------------------------------------------------------------- flush
 
 __device__ __forceinline__ void flush(const KArgs& a, int plan, u128 acc) {
     uint64_t lo = (uint64_t)acc, hi = (uint64_t)(acc >> 64);
-    // wave-wide 128-bit sum: reduce as four 32-bit limbs carried in 64 bits
+    // wave-wide 128-bit sum as four 32-bit limbs carried in 64 bits
     uint64_t l0 = lo & 0xffffffffu, l1 = lo >> 32, l2 = hi & 0xffffffffu, l3 = hi >> 32;
     for (int off = 32; off >= 1; off >>= 1) {
         l0 += __shfl_xor(l0, off);
@@ -408,12 +390,40 @@ __device__ __forceinline__ void flush(const KArgs& a, int plan, u128 acc) {
     }
 }
 
+// ---------------------------------------------------------------- kernel
+
+// Lanes take the entries [b, e) of the level-j buffer as v_j and finish
+// the match (j = ncore - 2).
+template <bool BYTES>
+__device__ __forceinline__ void lanes_finish(Ctx& c, int j, uint32_t b, uint32_t e, u128& acc) {
+    const DPlan* P = c.P;
+    const int lane = wave_lane();
+    const int last = P->ncore - 1;
+    const uint32_t* bj = c.buf + (uint64_t)j * c.stride;
+    for (uint32_t base = b; base < e; base += 64) {
+        uint32_t idx = base + lane;
+        if (idx >= e) continue;
+        uint32_t vv[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
+        vv[j] = bj[idx];
+        if (P->nterm == 0) {
+            u128 dummy = 0;
+            acc += (u128)lane_level<0, BYTES>(c, vv, last, dummy) * (u128)(uint32_t)P->mult;
+        } else {
+            lane_level<1, BYTES>(c, vv, last, acc);
+        }
+    }
+}
+
 template <bool BYTES>
 __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
+    __shared__ uint32_t s_touch[4];
     const int lane = wave_lane();
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    uint32_t* my_touch = &s_touch[threadIdx.x >> 6];
     Ctx c;
-    c.a = &a;
+    c.g = a.g;
     c.stride = a.buf_stride;
     c.buf = a.scratch + (uint64_t)wid * (uint64_t)KMAX * a.buf_stride;
     c.bytes = 0;
@@ -425,7 +435,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
         if (lane == 0) it = atomicAdd(a.head, 1u);
         it = bcast(it);
         if (it >= total) break;
-        if (a.cancel && *(volatile int*)a.cancel) break;
+        if (a.cancel && *(volatile const int*)a.cancel) break;
         const int pi = (int)(it / a.nitems);
         const KItem item = a.items[it % a.nitems];
         if (pi != cur) {
@@ -438,25 +448,13 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
         const int nc = P->ncore;
         const int8_t rl = P->lev[0].label;
         if (nc == 1) {
-            if (item.s0 != 0) continue;
-            if (P->nterm == 0) {
-                // single-vertex pattern: unsupported by the planner (k >= 2)
-                continue;
-            }
-            if (P->lane_par) {
-                for (uint32_t base = item.r0; base < item.r1; base += 64) {
-                    uint32_t r = base + lane;
-                    if (r < item.r1 && (rl < 0 || a.g.lab[r] == (uint8_t)rl)) {
-                        uint32_t vv[KMAX] = {r, 0, 0, 0, 0};
-                        acc += tail_lane<BYTES>(c, vv, 0);
-                    }
-                }
-            } else {
-                for (uint32_t r = item.r0; r < item.r1; ++r) {
-                    if (rl >= 0 && a.g.lab[r] != (uint8_t)rl) continue;
-                    c.v[0] = r;
-                    u128 t = tail_wave<BYTES>(c);
-                    if (lane == 0) acc += t;
+            // lanes take roots; every tail term is evaluated per lane
+            if (item.s0 != 0 || P->nterm == 0) continue;
+            for (uint32_t base = item.r0; base < item.r1; base += 64) {
+                uint32_t r = base + lane;
+                if (r < item.r1 && (rl < 0 || a.g.lab[r] == (uint8_t)rl)) {
+                    uint32_t vv[KMAX] = {r, 0, 0, 0, 0};
+                    acc += lane_tail<BYTES>(c, vv, 0);
                 }
             }
             continue;
@@ -466,18 +464,42 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             c.v[0] = r;
             if (nc == 2) {
                 if (P->agg_last) {
-                    if (item.s0 == 0) agg_level<BYTES>(c, 1, wid, acc);
-                } else {
-                    last_level<BYTES>(c, 1, item.s0, item.s1, acc);
+                    if (item.s0 == 0) agg_level<BYTES>(c, 1, wid, my_touch, a, acc);
+                    continue;
+                }
+                uint32_t n = wave_level<BYTES>(c, 1);
+                uint32_t b = min(item.s0, n), e = min(item.s1, n);
+                if (P->nterm == 0) {
+                    if (lane == 0 && e > b) acc += (u128)(e - b) * (u128)(uint32_t)P->mult;
+                    continue;
+                }
+                const uint32_t* b1 = c.buf + c.stride;
+                for (uint32_t base = b; base < e; base += 64) {
+                    uint32_t idx = base + lane;
+                    if (idx >= e) continue;
+                    uint32_t vv[KMAX] = {r, b1[idx], 0, 0, 0};
+                    acc += lane_tail<BYTES>(c, vv, 0);
                 }
                 continue;
             }
-            // levels 1 .. nc-2 enumerated, level nc-1 handled by last_level
+            // nc >= 3: levels 1 .. nc-2 materialised, lanes finish
+            const int pen = nc - 2;
             uint32_t pos[KMAX], end[KMAX];
-            int j = 1;
-            c.size[1] = level_set<1, BYTES>(c, 1);
+            c.size[1] = wave_level<BYTES>(c, 1);
             pos[1] = min(item.s0, c.size[1]);
             end[1] = min(item.s1, c.size[1]);
+            if (pen == 1) {
+                if (P->agg_last) {
+                    for (uint32_t q = pos[1]; q < end[1]; ++q) {
+                        c.v[1] = c.buf[c.stride + q];
+                        agg_level<BYTES>(c, 2, wid, my_touch, a, acc);
+                    }
+                } else {
+                    lanes_finish<BYTES>(c, 1, pos[1], end[1], acc);
+                }
+                continue;
+            }
+            int j = 1;
             while (j >= 1) {
                 if (pos[j] >= end[j]) {
                     --j;
@@ -485,13 +507,20 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                 }
                 c.v[j] = c.buf[(uint64_t)j * c.stride + pos[j]];
                 ++pos[j];
-                if (j + 1 == nc - 1) {
-                    if (P->agg_last) agg_level<BYTES>(c, j + 1, wid, acc);
-                    else last_level<BYTES>(c, j + 1, 0, 0xffffffffu, acc);
+                ++j;
+                c.size[j] = wave_level<BYTES>(c, j);
+                if (j == pen) {
+                    if (P->agg_last) {
+                        for (uint32_t q = 0; q < c.size[j]; ++q) {
+                            c.v[j] = c.buf[(uint64_t)j * c.stride + q];
+                            agg_level<BYTES>(c, j + 1, wid, my_touch, a, acc);
+                        }
+                    } else {
+                        lanes_finish<BYTES>(c, j, 0, c.size[j], acc);
+                    }
+                    --j;
                     continue;
                 }
-                ++j;
-                c.size[j] = level_set<1, BYTES>(c, j);
                 pos[j] = 0;
                 end[j] = c.size[j];
             }

@@ -10,6 +10,7 @@ namespace pm {
 struct KGraph {
     const uint32_t* rp;   // row offsets, n+1 (degree-ordered ids)
     const uint32_t* col;  // sorted adjacency
+    const uint32_t* split;  // per vertex: index of the first neighbour above it
     const uint8_t* lab;   // labels or null
     uint32_t n;
 };

@@ -167,7 +167,8 @@ struct Builder {
     // vertices by level; agg_last: the last core level is reached through
     // bridge leaves.  Returns false when the combination is not valid.
     bool build(uint32_t core, uint32_t leaves, const std::vector<int>& order, int form,
-               int dir, bool agg_last, const Group& autp, PlanInfo* out) {
+               int dir, bool agg_last, const Group& autp, PlanInfo* out, bool product_only = false) {
+        if (product_only && (form != 0 || p.vi || agg_last || popc(leaves) < 2)) return false;
         const int k = p.k;
         const int c = (int)order.size();
         int lev_of[8];
@@ -178,7 +179,7 @@ struct Builder {
         // ---- symmetry breaking ------------------------------------------
         Rel rel;
         std::vector<Perm> T;       // coset representatives (as maps of pattern vertices)
-        int64_t divisor = 1;
+        int64_t divisor = 1, hc_size = 1;
         if (form == 0) {
             Group G = core_automorphisms(p, core);
             Group Hc;  // restrictions to the core of automorphisms preserving it
@@ -202,6 +203,7 @@ struct Builder {
             }
             if ((int64_t)autp.size() % (int64_t)Hc.size()) return false;
             divisor = (int64_t)autp.size() / (int64_t)Hc.size();
+            hc_size = (int64_t)Hc.size();
         } else {
             Group R = chain(autp, order, dir, &rel);
             // constraints between two leaves are not allowed
@@ -265,8 +267,10 @@ struct Builder {
         if ((int)leaf.size() > MAX_LEAF) return false;
         std::vector<DTerm> terms;
         std::map<std::vector<int>, int64_t> monos;  // sorted term ids -> coef
-        std::vector<std::vector<uint32_t>> parts;
-        partitions((int)leaf.size(), &parts);
+        std::vector<std::vector<uint32_t>> all_parts, parts;
+        partitions((int)leaf.size(), &all_parts);
+        for (const auto& bl : all_parts)
+            if (!product_only || bl.size() == leaf.size()) parts.push_back(bl);
         uint8_t all_core = (uint8_t)((1u << c) - 1u);
         for (const Perm& s : T) {
             std::vector<LeafCons> lc(leaf.size());
@@ -311,6 +315,12 @@ struct Builder {
                     if (tm.adj & tm.anti) zero = true;
                     tm.neq = (uint8_t)(all_core & ~(tm.adj | tm.gt | tm.lt));
                     tm.cheap = (popc(tm.adj) == 1 && !tm.anti && tm.label < 0) ? 1 : 0;
+                    if (tm.cheap) {
+                        int a = __builtin_ctz((uint32_t)tm.adj);
+                        for (int i = 0; i < c; ++i)
+                            if (((tm.neq >> i) & 1) && has_edge(p.em, order[a], order[i]))
+                                tm.sure |= (uint8_t)(1u << i);
+                    }
                     int id = -1;
                     for (size_t q = 0; q < terms.size(); ++q)
                         if (term_equal(terms[q], tm)) id = (int)q;
@@ -402,6 +412,55 @@ struct Builder {
                 else if (!d.term[q].cheap) return false;
             }
         }
+        // ---- quotient patterns of the merged-leaf terms ----------------------
+        std::map<std::pair<uint32_t, std::array<int8_t, 8>>, int64_t> subw;
+        if (product_only) {
+            for (const auto& blocks : all_parts) {
+                if (blocks.size() == leaf.size()) continue;
+                Pat q;
+                q.vi = false;
+                int idx[8];
+                int nq = 0;
+                for (int v = 0; v < k; ++v)
+                    if ((core >> v) & 1) {
+                        idx[v] = nq;
+                        q.lab[nq] = p.lab[v];
+                        ++nq;
+                    }
+                bool conflict = false;
+                std::vector<int> bidx;
+                for (uint32_t B : blocks) {
+                    int8_t lb = -1;
+                    for (size_t t = 0; t < leaf.size(); ++t) {
+                        if (!((B >> t) & 1)) continue;
+                        int8_t l = p.lab[leaf[t]];
+                        if (l >= 0) {
+                            if (lb >= 0 && lb != l) conflict = true;
+                            lb = l;
+                        }
+                    }
+                    q.lab[nq] = lb;
+                    bidx.push_back(nq++);
+                }
+                if (conflict) continue;
+                q.k = nq;
+                for (int a = 0; a < k; ++a)
+                    for (int b2 = a + 1; b2 < k; ++b2)
+                        if (((core >> a) & 1) && ((core >> b2) & 1) && has_edge(p.em, a, b2))
+                            q.em |= 1u << pair_bit(idx[a], idx[b2]);
+                for (size_t bi = 0; bi < blocks.size(); ++bi)
+                    for (size_t t = 0; t < leaf.size(); ++t) {
+                        if (!((blocks[bi] >> t) & 1)) continue;
+                        for (int cv = 0; cv < k; ++cv)
+                            if (((core >> cv) & 1) && has_edge(p.em, leaf[t], cv))
+                                q.em |= 1u << pair_bit(bidx[bi], idx[cv]);
+                    }
+                int64_t aq = (int64_t)automorphisms(q).size();
+                Pat cq = canonical(q);
+                cq.vi = false;
+                subw[{cq.em | ((uint32_t)cq.k << 24), cq.lab}] += aq;
+            }
+        }
         d.lane_par = 1;
         for (int q = 0; q < d.nterm; ++q)
             if (!d.term[q].cheap && !d.term[q].agg) d.lane_par = 0;
@@ -413,65 +472,133 @@ struct Builder {
         for (int j = 0; j < KMAX; ++j) out->order[j] = j < c ? (int8_t)order[j] : -1;
         out->formulation = form;
         out->est_cost = estimate(out->d);
+        out->total_cost = out->est_cost;
+        out->rewrite = product_only;
+        out->subs.clear();
+        if (product_only) {
+            out->hmult = hc_size;
+            out->autp = (int64_t)autp.size();
+            for (auto& e : subw) {
+                Pat q;
+                q.k = (int)(e.first.first >> 24);
+                q.em = e.first.first & 0xffffffu;
+                q.vi = false;
+                q.lab = e.first.second;
+                out->subs.push_back({q, e.second});
+            }
+        }
         return true;
     }
 
     // ---- cost model -------------------------------------------------------
-    // Expected work from degree statistics: a level drawing candidates from
-    // a list with a lower bound at its owner is an out-list (degree-ordered
-    // orientation, short); otherwise a full list.  Extra intersections keep
-    // a fraction of candidates; aggregation costs its wedges.
+    // Expected work from degree statistics.  The first two levels use exact
+    // joint sums over the degree sequence (power-law graphs make degrees of
+    // adjacent levels strongly correlated); deeper levels use neighbour
+    // averages.  A list bounded below by its owner is an out-list of the
+    // degree-ordered orientation (short), bounded above an in-list.
+    // type: +1 out-list, -1 in-list, 0 whole list.
+    static int list_type(const DLevel& L, int owner) {
+        if ((L.gt >> owner) & 1) return 1;
+        if ((L.lt >> owner) & 1) return -1;
+        return 0;
+    }
+    double root_sum(int type) const {  // sum over roots of one list of the root
+        return type == 0 ? 2.0 * gs.m : gs.m;
+    }
+    // sum over (v0, v1) pairs of the length of a list of v0 (owner 0) or v1
+    double pair_sum(int rel, int owner, int type) const {
+        // rel: +1 v1 in N+(v0), -1 v1 in N-(v0), 0 either
+        auto S = [&](char a, char b) {  // sum_v a(v) b(v)
+            auto key = std::string() + a + b;
+            if (key == "pp") return gs.s_pp;
+            if (key == "pq" || key == "qp") return gs.s_pq;
+            if (key == "pd" || key == "dp") return gs.s_pd;
+            if (key == "qq") return gs.s_qq;
+            if (key == "qd" || key == "dq") return gs.s_qd;
+            return gs.s_dd;
+        };
+        char t = type > 0 ? 'p' : (type < 0 ? 'q' : 'd');
+        if (rel == 0) return pair_sum(1, owner, type) + pair_sum(-1, owner, type);
+        if (owner == 0) return S(rel > 0 ? 'p' : 'q', t);
+        return S(rel > 0 ? 'q' : 'p', t);
+    }
     double estimate(const DPlan& d) const {
         const double n = std::max(gs.n, 1.0);
-        double deg_root = std::max(gs.avg_deg, 1.0), deg_nb = std::max(gs.nbr_deg, 1.0);
-        double out_root = std::max(gs.avg_out, 0.5), out_nb = std::max(gs.nbr_out, 0.5);
+        const double m = std::max(gs.m, 1.0);
+        double deg_nb = std::max(gs.nbr_deg, 1.0), out_nb = std::max(gs.nbr_out, 0.5);
         double keep = std::min(1.0, std::max(0.02, deg_nb / n * 8.0));
-        auto list_len = [&](int owner, bool lower_bounded, bool upper_bounded) {
-            double dg = owner == 0 ? deg_root : deg_nb;
-            double og = owner == 0 ? out_root : out_nb;
-            if (lower_bounded) return og;
-            if (upper_bounded) return std::max(dg - og, 1.0);
-            return dg;
+        auto nb_len = [&](int type) {
+            if (type > 0) return out_nb;
+            if (type < 0) return std::max(deg_nb - out_nb, 1.0);
+            return deg_nb;
         };
-        double prefixes = n;
-        double cost = n;  // one visit per root
-        int last = d.ncore - 1;
+        double prefixes = n;   // partial matches entering the next level
+        double cost = n;
+        int rel1 = 0;          // how v1 relates to v0
+        const int last = d.ncore - 1;
         for (int j = 1; j < d.ncore; ++j) {
             const DLevel& L = d.lev[j];
-            double size, work;
+            double total, work;
             if (L.agg) {
                 int s = d.bridge_src;
-                double b = list_len(s, (d.bridge_gt >> s) & 1, (d.bridge_lt >> s) & 1);
-                double w = b * (((L.lt) ? (deg_nb - out_nb) : deg_nb) * 0.5 + 1);
-                work = w * 1.5;
-                size = std::min(w, n);
-            } else {
-                double best = 1e300;
+                int bt = ((d.bridge_gt >> s) & 1) ? 1 : (((d.bridge_lt >> s) & 1) ? -1 : 0);
+                double bridges = (j == 1) ? root_sum(bt) : prefixes * nb_len(bt);
+                // second hop: the bridge's list, bounded like the target
+                int tt = 0;
                 for (int i = 0; i < j; ++i)
-                    if ((L.adj >> i) & 1)
-                        best = std::min(best, list_len(i, (L.gt >> i) & 1, (L.lt >> i) & 1));
-                int extra = popc(L.adj) - 1 + popc(L.anti);
-                size = best * std::pow(keep, popc(L.adj) - 1);
-                work = best * (1.0 + extra * 4.0);
-            }
-            bool counted = (j == last && d.nterm == 0);
-            cost += prefixes * work;
-            if (!counted) prefixes *= std::max(size, 1e-9);
-        }
-        // tail terms per full core match
-        double tail = 0;
-        for (int q = 0; q < d.nterm; ++q) {
-            const DTerm& t = d.term[q];
-            if (t.cheap || t.agg) {
-                tail += d.lane_par ? 0.3 : 2.0;
+                    if ((L.lt >> i) & 1) tt = -1;
+                double hop = (bt < 0 && tt < 0) ? gs.s_pd / m : (tt < 0 ? deg_nb * 0.5 : deg_nb);
+                work = bridges * hop * 1.5;
+                total = std::min(bridges * hop, prefixes * n);
+                cost += work;
+                prefixes = std::max(total, 1e-9);
                 continue;
             }
             double best = 1e300;
-            for (int i = 0; i < d.ncore; ++i)
-                if ((t.adj >> i) & 1) best = std::min(best, list_len(i, (t.gt >> i) & 1, (t.lt >> i) & 1));
-            tail += best * (1.0 + (popc(t.adj) - 1 + popc(t.anti)) * 4.0) + 16.0;
+            for (int i = 0; i < j; ++i) {
+                if (!((L.adj >> i) & 1)) continue;
+                int type = list_type(L, i);
+                double sum;
+                if (j == 1) sum = root_sum(type);
+                else if (j == 2 && i <= 1) sum = pair_sum(rel1, i, type);
+                else sum = prefixes * nb_len(type);
+                best = std::min(best, sum);
+            }
+            if (j == 1) {
+                for (int i = 0; i < 1; ++i) rel1 = list_type(L, 0);
+            }
+            int extra = popc(L.adj) - 1 + popc(L.anti);
+            total = best * std::pow(keep, popc(L.adj) - 1);
+            work = best * (1.0 + extra * 2.0);
+            bool counted = (j == last && d.nterm == 0);
+            cost += work;
+            if (!counted) prefixes = std::max(total, 1e-9);
         }
-        cost += prefixes * tail;
+        // tail terms per full core match
+        double tail_work = 0;
+        for (int q = 0; q < d.nterm; ++q) {
+            const DTerm& t = d.term[q];
+            if (t.agg) {
+                tail_work += prefixes * 0.5;
+                continue;
+            }
+            if (t.cheap) {
+                tail_work += prefixes * (1.0 + 2.0 * popc(t.neq & ~t.sure));
+                continue;
+            }
+            double best = 1e300;
+            for (int i = 0; i < d.ncore; ++i) {
+                if (!((t.adj >> i) & 1)) continue;
+                int type = ((t.gt >> i) & 1) ? 1 : (((t.lt >> i) & 1) ? -1 : 0);
+                double sum;
+                if (d.ncore == 1) sum = root_sum(type);
+                else if (d.ncore == 2 && !d.agg_last) sum = pair_sum(rel1, i, type);
+                else sum = prefixes * nb_len(type);
+                best = std::min(best, sum);
+            }
+            tail_work += best * (1.0 + (popc(t.adj) - 1 + popc(t.anti)) * 2.0) + prefixes * 4.0;
+        }
+        cost += tail_work;
         return cost;
     }
 };
@@ -500,9 +627,9 @@ void orders_of(const Pat& p, uint32_t core, bool agg_last, std::vector<std::vect
 std::string PlanInfo::describe() const {
     char buf[512];
     std::string s;
-    snprintf(buf, sizeof(buf), "k=%d em=0x%x %s form=%s div=%lld cost=%.3g order=", pat.k,
+    snprintf(buf, sizeof(buf), "k=%d em=0x%x %s form=%s div=%lld cost=%.3g total=%.3g order=", pat.k,
              pat.em, pat.vi ? "VI" : "EI", formulation ? "pattern" : "coset",
-             (long long)divisor, est_cost);
+             (long long)divisor, est_cost, total_cost);
     s += buf;
     for (int j = 0; j < d.ncore; ++j) s += std::to_string(order[j]) + (j + 1 < d.ncore ? "," : "");
     for (int j = 0; j < d.ncore; ++j) {
@@ -525,6 +652,16 @@ std::string PlanInfo::describe() const {
         for (int f = 0; f < d.mono[m].nf; ++f) s += "*T" + std::to_string(d.mono[m].f[f]);
     }
     if (d.nterm == 0) s += " mult=" + std::to_string(d.mult);
+    if (rewrite) {
+        snprintf(buf, sizeof(buf), " | quotient: (%lld*sum", (long long)hmult);
+        s += buf;
+        for (auto& q : subs) {
+            snprintf(buf, sizeof(buf), " - %lld*N(k=%d em=0x%x)", (long long)q.second, q.first.k, q.first.em);
+            s += buf;
+        }
+        snprintf(buf, sizeof(buf), ")/%lld", (long long)autp);
+        s += buf;
+    }
     if (d.lane_par) s += " lane_par";
     return s;
 }
@@ -565,6 +702,10 @@ int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* o
                     for (int dir = -1; dir <= 1; dir += 2) {
                         PlanInfo pi;
                         if (B.build(core, leaves, ord, form, dir, agg != 0, autp, &pi)) out->push_back(pi);
+                        if (!agg && form == 0 && !p.vi && popc(leaves) >= 2) {
+                            PlanInfo pq;
+                            if (B.build(core, leaves, ord, form, dir, false, autp, &pq, true)) out->push_back(pq);
+                        }
                     }
         }
     }
@@ -579,9 +720,27 @@ int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string*
     std::vector<PlanInfo> all;
     int rc = candidate_plans(p, gs, &all, err);
     if (rc) return rc;
+    // cost of every sub-pattern a quotient plan needs (its own best plan)
+    std::map<std::pair<uint32_t, std::array<int8_t, 8>>, double> sub_cost;
+    for (PlanInfo& pi : all) {
+        double extra = 0;
+        for (auto& sq : pi.subs) {
+            auto key = std::make_pair(sq.first.em | ((uint32_t)sq.first.k << 24), sq.first.lab);
+            auto it = sub_cost.find(key);
+            if (it == sub_cost.end()) {
+                PlanInfo sp;
+                std::string e2;
+                double c = 1e300;
+                if (compile_plan(sq.first, gs, &sp, &e2) == PM_OK) c = sp.total_cost;
+                it = sub_cost.emplace(key, c).first;
+            }
+            extra += it->second;
+        }
+        pi.total_cost = pi.est_cost + extra;
+    }
     size_t best = 0;
     for (size_t i = 1; i < all.size(); ++i)
-        if (all[i].est_cost < all[best].est_cost) best = i;
+        if (all[i].total_cost < all[best].total_cost) best = i;
     *out = all[best];
     return PM_OK;
 }

@@ -187,7 +187,7 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     G->n = n;
     G->m = nnz / 2;
     G->labeled = labels != nullptr;
-    double sd2 = 0, so2 = 0;
+    double sd2 = 0, so2 = 0, s_pq = 0, s_pd = 0, s_qq = 0, s_qd = 0;
     uint32_t maxd = 0, maxo = 0;
     for (uint32_t r = 0; r < n; ++r) {
         uint32_t d = nrp[r + 1] - nrp[r];
@@ -195,8 +195,19 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
         uint32_t out = (uint32_t)((a + d) - std::upper_bound(a, a + d, r));
         maxd = std::max(maxd, d);
         maxo = std::max(maxo, out);
+        double q = (double)(d - out);
         sd2 += (double)d * d;
         so2 += (double)out * out;
+        s_pq += (double)out * q;
+        s_pd += (double)out * d;
+        s_qq += q * q;
+        s_qd += q * d;
+    }
+    std::vector<uint32_t> nsplit(n);
+    for (uint32_t r = 0; r < n; ++r) {
+        const uint32_t* a = ncol.data() + nrp[r];
+        uint32_t d = nrp[r + 1] - nrp[r];
+        nsplit[r] = nrp[r] + (uint32_t)(std::upper_bound(a, a + d, r) - a);
     }
     G->max_deg = maxd;
     G->max_out = maxo;
@@ -209,24 +220,32 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     s.nbr_out = G->m ? so2 / (double)G->m : 0;
     s.max_deg = maxd;
     s.max_out = maxo;
+    s.s_pp = so2;
+    s.s_pq = s_pq;
+    s.s_pd = s_pd;
+    s.s_qq = s_qq;
+    s.s_qd = s_qd;
+    s.s_dd = sd2;
     G->items = build_items(nrp, n, item_budget, item_split, 256);
 
     uint64_t need_rp = 4ull * (n + 1), need_col = 4ull * std::max<uint64_t>(nnz, 1),
              need_lab = labels ? n : 0, need_items = sizeof(KItem) * G->items.size();
     G->off_rp = arena.alloc(need_rp);
     G->off_col = arena.alloc(need_col);
+    G->off_split = arena.alloc(4ull * n);
     G->off_lab = labels ? arena.alloc(need_lab) : UINT64_MAX - 1;
     G->off_items = arena.alloc(need_items);
     if (G->off_rp == UINT64_MAX || G->off_col == UINT64_MAX || G->off_lab == UINT64_MAX ||
-        G->off_items == UINT64_MAX) {
-        for (uint64_t o : {G->off_rp, G->off_col, G->off_lab, G->off_items})
+        G->off_items == UINT64_MAX || G->off_split == UINT64_MAX) {
+        for (uint64_t o : {G->off_rp, G->off_col, G->off_split, G->off_lab, G->off_items})
             if (o < UINT64_MAX - 1) arena.release(o);
         return fail(PM_E_NOMEM, "arena too small for the graph");
     }
-    G->device_bytes = need_rp + need_col + need_lab + need_items;
+    G->device_bytes = need_rp + need_col + 4ull * n + need_lab + need_items;
     HIPCHK(hipSetDevice(device));
     HIPCHK(hipMemcpyAsync(dptr(G->off_rp), nrp.data(), need_rp, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dptr(G->off_col), ncol.data(), 4ull * nnz, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dptr(G->off_split), nsplit.data(), 4ull * n, hipMemcpyHostToDevice, stream));
     if (labels) HIPCHK(hipMemcpyAsync(dptr(G->off_lab), nlab.data(), n, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dptr(G->off_items), G->items.data(), need_items, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
@@ -243,7 +262,7 @@ int Ctx_::graph_unload(uint32_t gid) {
     if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
     if (it->second->inflight) return fail(PM_E_BUSY, "queries in flight on this graph");
     GraphRes& G = *it->second;
-    for (uint64_t o : {G.off_rp, G.off_col, G.off_lab, G.off_items})
+    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items})
         if (o < UINT64_MAX - 1) arena.release(o);
     graphs.erase(it);
     return PM_OK;
@@ -302,6 +321,32 @@ const PlanInfo& Ctx_::plan_for(GraphRes& G, const Pat& p, int* rc) {
     if (*rc) g_err = err;
     G.plan_cache.push_back({p, pi});
     return G.plan_cache.back().second;
+}
+
+int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
+                       std::vector<PlanInfo>* plans) {
+    std::vector<Pat> cl = alt;
+    std::vector<PlanInfo> pl;
+    for (size_t i = 0; i < cl.size(); ++i) {
+        int rc;
+        PlanInfo pi = plan_for(G, cl[i], &rc);
+        if (rc) return rc;
+        for (auto& sq : pi.subs)
+            if (std::find(cl.begin(), cl.end(), sq.first) == cl.end()) cl.push_back(sq.first);
+        pl.push_back(pi);
+    }
+    std::vector<size_t> idx(cl.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        return pl[a].d.agg_last < pl[b].d.agg_last;
+    });
+    closure->clear();
+    plans->clear();
+    for (size_t i : idx) {
+        closure->push_back(cl[i]);
+        plans->push_back(pl[i]);
+    }
+    return PM_OK;
 }
 
 uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, uint64_t* scratch_stride,
@@ -372,12 +417,8 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
     std::string err;
     int rc = morph_plan_count(ps, morph, &Q->mp, &err);
     if (rc) return fail(rc, err);
-    for (const Pat& a : Q->mp.alt) {
-        int prc;
-        const PlanInfo& pi = plan_for(*G, a, &prc);
-        if (prc) return fail(prc, g_err);
-        Q->plans.push_back(pi);
-    }
+    rc = plan_closure(*G, Q->mp.alt, &Q->closure, &Q->plans);
+    if (rc) return fail(rc, g_err);
     auto t1 = std::chrono::steady_clock::now();
     Q->stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     Q->stats.num_alt = (uint32_t)Q->plans.size();
@@ -427,6 +468,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     memset(&a, 0, sizeof(a));
     a.g.rp = (const uint32_t*)dptr(G.off_rp);
     a.g.col = (const uint32_t*)dptr(G.off_col);
+    a.g.split = (const uint32_t*)dptr(G.off_split);
     a.g.lab = G.labeled ? (const uint8_t*)dptr(G.off_lab) : nullptr;
     a.g.n = G.n;
     a.items = (const KItem*)dptr(G.off_items);
@@ -518,22 +560,57 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
     hipEventElapsedTime(&kms, Q->ev_start, Q->ev_stop);
     Q->stats.kernel_ms = kms;
     size_t np = Q->plans.size();
-    std::vector<int64_t> alt(np);
+    // closure counts, smallest patterns first (quotient plans need them)
+    std::vector<__int128> cnt(np, -1);
+    std::vector<size_t> order(np);
+    for (size_t i = 0; i < np; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return Q->closure[a].k < Q->closure[b].k; });
     int rc = PM_OK;
-    for (size_t i = 0; i < np; ++i) {
+    for (size_t oi = 0; oi < np && rc == PM_OK; ++oi) {
+        size_t i = order[oi];
+        const PlanInfo& pi = Q->plans[i];
         unsigned __int128 v = ((unsigned __int128)Q->host_counters[2 * i + 1] << 64) | Q->host_counters[2 * i];
-        int64_t dv = Q->plans[i].divisor;
-        if (v % (unsigned __int128)dv) {
-            rc = fail(PM_E_DEVICE, "internal: match total not divisible by the plan divisor");
+        if (v >> 120) {
+            rc = fail(PM_E_OVERFLOW, "match total exceeds 120 bits");
             break;
         }
-        v /= (unsigned __int128)dv;
-        if (v > (unsigned __int128)INT64_MAX) {
+        __int128 c;
+        if (pi.rewrite) {
+            __int128 acc = (__int128)pi.hmult * (__int128)v;
+            for (auto& sq : pi.subs) {
+                size_t j = std::find(Q->closure.begin(), Q->closure.end(), sq.first) - Q->closure.begin();
+                if (j >= np || cnt[j] < 0) {
+                    rc = fail(PM_E_DEVICE, "internal: quotient sub-pattern missing");
+                    break;
+                }
+                acc -= (__int128)sq.second * cnt[j];
+            }
+            if (rc) break;
+            if (acc < 0 || acc % pi.autp) {
+                rc = fail(PM_E_DEVICE, "internal: quotient combination not exact");
+                break;
+            }
+            c = acc / pi.autp;
+        } else {
+            if (v % (unsigned __int128)pi.divisor) {
+                rc = fail(PM_E_DEVICE, "internal: match total not divisible by the plan divisor");
+                break;
+            }
+            c = (__int128)(v / (unsigned __int128)pi.divisor);
+        }
+        if (c > (__int128)INT64_MAX) {
             rc = fail(PM_E_OVERFLOW, "count exceeds int64");
             break;
         }
-        alt[i] = (int64_t)v;
+        cnt[i] = c;
     }
+    std::vector<int64_t> alt(Q->mp.alt.size(), 0);
+    if (rc == PM_OK)
+        for (size_t j = 0; j < alt.size(); ++j) {
+            size_t i = std::find(Q->closure.begin(), Q->closure.end(), Q->mp.alt[j]) - Q->closure.begin();
+            alt[j] = (int64_t)cnt[i];
+        }
     std::vector<int64_t> res;
     if (rc == PM_OK) {
         std::string err;
@@ -645,11 +722,9 @@ pm_status pm_query_footprint(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, 
     int rc = morph_plan_count(ps, morph, &mp, &err);
     if (rc) return fail(rc, err);
     std::vector<PlanInfo> plans;
-    for (const Pat& a : mp.alt) {
-        int prc;
-        plans.push_back(ctx->c.plan_for(*G, a, &prc));
-        if (prc) return prc;
-    }
+    std::vector<Pat> closure;
+    rc = ctx->c.plan_closure(*G, mp.alt, &closure, &plans);
+    if (rc) return fail(rc, g_err);
     uint64_t stride;
     bool any_agg;
     *out_bytes = ctx->c.footprint(*G, plans, &stride, &any_agg);

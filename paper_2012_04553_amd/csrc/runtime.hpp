@@ -37,7 +37,8 @@ struct GraphRes {
     bool labeled = false;
     uint32_t max_deg = 0, max_out = 0;
     GraphStats st;
-    uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_lab = UINT64_MAX, off_items = UINT64_MAX;
+    uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_split = UINT64_MAX, off_lab = UINT64_MAX,
+             off_items = UINT64_MAX;
     uint64_t device_bytes = 0;
     std::vector<KItem> items;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
@@ -48,7 +49,8 @@ struct Query {
     uint32_t gid = 0;
     uint32_t npat = 0;
     MorphPlan mp;
-    std::vector<PlanInfo> plans;
+    std::vector<Pat> closure;        // patterns matched on the device
+    std::vector<PlanInfo> plans;     // one per closure entry
     uint64_t off_mem = UINT64_MAX;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
     std::vector<uint64_t> host_counters;
@@ -84,6 +86,10 @@ struct Ctx_ {
     int graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels, uint32_t* gid);
     int graph_unload(uint32_t gid);
     const PlanInfo& plan_for(GraphRes& G, const Pat& p, int* rc);
+    // alternative patterns plus every sub-pattern their quotient plans need,
+    // aggregation plans last (they run in a launch of their own)
+    int plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
+                     std::vector<PlanInfo>* plans);
     uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, uint64_t* stride, bool* any_agg) const;
     int ensure_agg(uint32_t n);
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
