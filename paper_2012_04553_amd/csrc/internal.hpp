@@ -14,6 +14,7 @@ constexpr int MAX_LEAF = 4;     // leaves counted by inclusion-exclusion
 constexpr int MAX_TERMS = 48;   // distinct set-size terms of one plan
 constexpr int MAX_MONO = 96;    // monomials of one plan's tail polynomial
 constexpr int MAX_FAC = 4;      // factors per monomial
+constexpr int LOCAL_MAX = 1024; // largest out-neighbourhood of the bitmap clique mode
 
 using Perm = std::array<uint8_t, 8>;
 
@@ -94,7 +95,8 @@ struct DPlan {
     uint8_t bridge_lt;   //              bridge b < v_i
     int8_t bridge_label;
     uint8_t bridge_src;  //              b in N(v_src)
-    int32_t pad;
+    int32_t local;       // 1: clique with a total order, counted on a bitmap
+                         //    of the root's out-neighbourhood
     DLevel lev[KMAX];
     DTerm term[MAX_TERMS];
     DMono mono[MAX_MONO];

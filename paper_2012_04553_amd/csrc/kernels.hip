@@ -363,6 +363,87 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
     __builtin_amdgcn_wave_barrier();
 }
 
+// ---------------------------------------------------------------- bitmap cliques
+
+// Cliques with a total order live in the out-neighbourhood C of the root:
+// lanes build one bitmap row per member x of C (bit j set when C[j] is an
+// out-neighbour of x, by a merge of the two sorted lists), then count the
+// deeper levels with word-wise AND and popcount over the rows.
+template <bool BYTES>
+__device__ void local_clique(Ctx& c, uint32_t s0, uint32_t s1, u128& acc) {
+    const int lane = wave_lane();
+    const int nc = c.P->ncore;
+    const uint32_t v0 = c.v[0];
+    const uint32_t b = c.g.split[v0], e = c.g.rp[v0 + 1];
+    const uint32_t s = e - b;
+    if (BYTES && lane == 0) c.bytes += 8 + 4ull * s;
+    if (s < (uint32_t)(nc - 1) || s0 >= s) return;
+    const uint32_t W = (s + 63) >> 6;
+    uint64_t* rows = (uint64_t*)c.buf;
+    const uint32_t* C1 = c.g.col + b;
+    for (uint32_t i = lane; i < s; i += 64) {
+        const uint32_t x = C1[i];
+        uint32_t p = c.g.split[x];
+        const uint32_t pe = c.g.rp[x + 1];
+        if (BYTES) c.bytes += 8 + 4ull * (pe - p) + 4ull * (s - i - 1);
+        uint64_t* row = rows + (uint64_t)i * W;
+        uint32_t q = i + 1;
+        uint32_t cw = q >> 6;
+        for (uint32_t w = 0; w < cw && w < W; ++w) row[w] = 0;
+        uint64_t bits = 0;
+        while (q < s && p < pe) {
+            const uint32_t a = C1[q], y = c.g.col[p];
+            if (a == y) bits |= 1ull << (q & 63);
+            if (y <= a) ++p;
+            if (a <= y) {
+                ++q;
+                if ((q >> 6) != cw) {
+                    row[cw] = bits;
+                    bits = 0;
+                    ++cw;
+                }
+            }
+        }
+        if (cw < W) row[cw++] = bits;
+        for (; cw < W; ++cw) row[cw] = 0;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t ie = min(s, s1);
+    for (uint32_t i = s0 + lane; i < ie; i += 64) {
+        const uint64_t* ri = rows + (uint64_t)i * W;
+        uint64_t cnt = 0;
+        if (nc == 3) {
+            for (uint32_t w = 0; w < W; ++w) cnt += __popcll(ri[w]);
+        } else {
+            for (uint32_t w = 0; w < W; ++w) {
+                uint64_t m = ri[w];
+                while (m) {
+                    const uint32_t j = (w << 6) + __builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint64_t* rj = rows + (uint64_t)j * W;
+                    if (nc == 4) {
+                        for (uint32_t w2 = j >> 6; w2 < W; ++w2) cnt += __popcll(ri[w2] & rj[w2]);
+                    } else {
+                        for (uint32_t w2 = j >> 6; w2 < W; ++w2) {
+                            uint64_t t = ri[w2] & rj[w2];
+                            while (t) {
+                                const uint32_t k = (w2 << 6) + __builtin_ctzll(t);
+                                t &= t - 1;
+                                const uint64_t* rk = rows + (uint64_t)k * W;
+                                for (uint32_t w3 = k >> 6; w3 < W; ++w3) cnt += __popcll(ri[w3] & rj[w3] & rk[w3]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        acc += (u128)cnt;
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ---------------------------------------------------------------- flush
 
 __device__ __forceinline__ void flush(const KArgs& a, int plan, u128 acc) {
@@ -462,6 +543,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
         for (uint32_t r = item.r0; r < item.r1; ++r) {
             if (rl >= 0 && a.g.lab[r] != (uint8_t)rl) continue;
             c.v[0] = r;
+            if (P->local) {
+                local_clique<BYTES>(c, item.s0, item.s1, acc);
+                continue;
+            }
             if (nc == 2) {
                 if (P->agg_last) {
                     if (item.s0 == 0) agg_level<BYTES>(c, 1, wid, my_touch, a, acc);

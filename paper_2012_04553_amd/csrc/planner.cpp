@@ -465,6 +465,19 @@ struct Builder {
         for (int q = 0; q < d.nterm; ++q)
             if (!d.term[q].cheap && !d.term[q].agg) d.lane_par = 0;
         d.agg_last = agg_last ? 1 : 0;
+        // clique with a total ascending order: every level lies in the
+        // out-neighbourhood of the root and above all earlier levels
+        d.local = 0;
+        if (p.em == full_mask(k) && c == k && k >= 3 && d.nterm == 0 && !agg_last && d.mult == 1 &&
+            gs.max_out <= LOCAL_MAX) {
+            bool ok = true;
+            for (int j = 1; j < c; ++j) {
+                uint8_t below = (uint8_t)((1u << j) - 1u);
+                if (d.lev[j].adj != below || d.lev[j].gt != below || d.lev[j].anti || d.lev[j].label >= 0)
+                    ok = false;
+            }
+            d.local = ok ? 1 : 0;
+        }
 
         out->d = d;
         out->pat = p;
@@ -523,6 +536,12 @@ struct Builder {
         return S(rel > 0 ? 'q' : 'p', t);
     }
     double estimate(const DPlan& d) const {
+        if (d.local) {
+            // row build: merge of each out-list with the root's out-list;
+            // counting: word operations per local edge and deeper level
+            double rows = gs.s_pq + gs.s_pp;
+            return gs.n + rows * 0.5 + gs.s_pp * 0.1 * (d.ncore - 2);
+        }
         const double n = std::max(gs.n, 1.0);
         const double m = std::max(gs.m, 1.0);
         double deg_nb = std::max(gs.nbr_deg, 1.0), out_nb = std::max(gs.nbr_out, 0.5);
@@ -663,6 +682,7 @@ std::string PlanInfo::describe() const {
         s += buf;
     }
     if (d.lane_par) s += " lane_par";
+    if (d.local) s += " local_bitmap";
     return s;
 }
 

@@ -360,6 +360,11 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
             stride = std::max<uint64_t>(stride, (out_list ? G.max_out : G.max_deg) + 64);
         }
         if (p.d.agg_last) agg = true;
+        if (p.d.local) {
+            // bitmap rows: max_out rows of ceil(max_out/64) 64-bit words
+            uint64_t words = (uint64_t)G.max_out * ((G.max_out + 63) / 64);
+            stride = std::max<uint64_t>(stride, (2 * words + KMAX - 1) / KMAX + 64);
+        }
     }
     stride = (stride + 63) & ~uint64_t(63);
     *scratch_stride = stride;
