@@ -186,9 +186,24 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "item_budget"   adjacency entries per root-range work item (>= 1);
  *   "item_split"    level-1 slice length for high-degree roots (>= 64);
  *                   takes effect for graphs loaded afterwards;
- *   "agg_waves"     wavefronts of two-hop aggregation launches (>= 1).
+ *   "agg_waves"     wavefronts of two-hop aggregation launches (>= 1);
+ *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
+ *                   hipGraph on first use and replay it afterwards.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */
 pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value);
+
+/* Batching: tune the launch of one query set on one graph.  Times the
+ * whole multi-pattern launch under a coordinate search over blocks per
+ * compute unit {1,2,4,8}, root budget per work item {1K,4K,16K,64K}
+ * adjacency entries and hub slice {512,2K,8K}, and keeps the fastest for
+ * that (graph, matched pattern set): later pm_submit calls of the same set
+ * use it.  Results are cached per context and, when the environment
+ * variable PM_AUTOTUNE_CACHE names a file, appended there and reloaded by
+ * later contexts.  `out_cfg` (3 int64, may be NULL) receives the chosen
+ * values, `out_ms` (may be NULL) the tuned kernel time in milliseconds.
+ * Errors: as pm_submit. */
+pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
+                      uint32_t npat, int32_t morph, int64_t* out_cfg, double* out_ms);
 
 /* Writes a NUL-terminated description of the matching plan the engine
  * compiles for `pat` on graph `graph_id` (core order, per-level set

@@ -75,6 +75,8 @@ SIGNATURES = {
     "pm_fsm_num_slots": (ctypes.c_uint64, [ctypes.c_uint32]),
     "pm_fsm_slot": (ctypes.c_int32, [ctypes.c_uint32, ctypes.c_uint64, _patp]),
     "pm_set_option": (ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
+    "pm_autotune": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_uint32, ctypes.c_int32,
+                                     _i64p, ctypes.POINTER(ctypes.c_double)]),
     "pm_plan_describe": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_char_p,
                                           ctypes.c_uint64]),
     "pm_last_error": (ctypes.c_char_p, []),
@@ -218,6 +220,13 @@ class Engine:
         s = pm_query_stats()
         check(lib().pm_last_query_stats(self.ctx, ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in pm_query_stats._fields_}
+
+    def autotune(self, gid, pats, morph=MORPH_NAIVE):
+        arr = pattern_array(pats)
+        cfg = (ctypes.c_int64 * 3)()
+        ms = ctypes.c_double()
+        check(lib().pm_autotune(self.ctx, gid, arr, len(pats), morph, cfg, ctypes.byref(ms)))
+        return {"blocks_per_cu": cfg[0], "item_budget": cfg[1], "item_split": cfg[2], "ms": ms.value}
 
     def plan_describe(self, gid, pat) -> str:
         buf = ctypes.create_string_buffer(8192)

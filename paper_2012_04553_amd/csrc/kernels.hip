@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace pm {
@@ -617,6 +619,19 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
         for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
         if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
     }
+}
+
+__global__ void zero_kernel(uint32_t* p, uint64_t words) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+int launch_zero(uint32_t* p, uint64_t words, hipStream_t s) {
+    int grid = (int)std::min<uint64_t>(1024, (words + 255) / 256);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, s, p, words);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s) {

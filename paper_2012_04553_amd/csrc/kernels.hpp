@@ -38,5 +38,7 @@ struct KArgs {
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
+// Clears `words` 32-bit words (used instead of memset nodes inside graphs).
+int launch_zero(uint32_t* p, uint64_t words, hipStream_t s);
 
 }  // namespace pm

@@ -226,15 +226,26 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     s.s_qq = s_qq;
     s.s_qd = s_qd;
     s.s_dd = sd2;
-    G->items = build_items(nrp, n, item_budget, item_split, 256);
+    {
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](const void* p, size_t len) {
+            const unsigned char* c = (const unsigned char*)p;
+            for (size_t i = 0; i < len; ++i) h = (h ^ c[i]) * 1099511628211ull;
+        };
+        mix(&n, sizeof(n));
+        mix(nrp.data(), 4ull * (n + 1));
+        mix(ncol.data(), 4ull * nnz);
+        if (labels) mix(nlab.data(), n);
+        G->hash = h;
+    }
 
     uint64_t need_rp = 4ull * (n + 1), need_col = 4ull * std::max<uint64_t>(nnz, 1),
-             need_lab = labels ? n : 0, need_items = sizeof(KItem) * G->items.size();
+             need_lab = labels ? n : 0, need_items = 0;
     G->off_rp = arena.alloc(need_rp);
     G->off_col = arena.alloc(need_col);
     G->off_split = arena.alloc(4ull * n);
     G->off_lab = labels ? arena.alloc(need_lab) : UINT64_MAX - 1;
-    G->off_items = arena.alloc(need_items);
+    G->off_items = UINT64_MAX - 1;
     if (G->off_rp == UINT64_MAX || G->off_col == UINT64_MAX || G->off_lab == UINT64_MAX ||
         G->off_items == UINT64_MAX || G->off_split == UINT64_MAX) {
         for (uint64_t o : {G->off_rp, G->off_col, G->off_split, G->off_lab, G->off_items})
@@ -247,8 +258,8 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     HIPCHK(hipMemcpyAsync(dptr(G->off_col), ncol.data(), 4ull * nnz, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dptr(G->off_split), nsplit.data(), 4ull * n, hipMemcpyHostToDevice, stream));
     if (labels) HIPCHK(hipMemcpyAsync(dptr(G->off_lab), nlab.data(), n, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(dptr(G->off_items), G->items.data(), need_items, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
+    G->host_rp = std::move(nrp);
     std::lock_guard<std::mutex> g(mu);
     uint32_t gid = next_gid++;
     graphs[gid] = std::move(G);
@@ -264,6 +275,8 @@ int Ctx_::graph_unload(uint32_t gid) {
     GraphRes& G = *it->second;
     for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items})
         if (o < UINT64_MAX - 1) arena.release(o);
+    for (auto& is : G.itemsets) arena.release(is.second.off);
+    for (auto& ls : G.launches) free_launchset(ls.second.get());
     graphs.erase(it);
     return PM_OK;
 }
@@ -305,8 +318,6 @@ static int to_pat(const pm_pattern& q, Pat* out, std::string* err) {
     return PM_OK;
 }
 
-uint64_t Ctx_::waves() const { return (uint64_t)grid_blocks() * (block / 64); }
-int Ctx_::grid_blocks() const { return num_cus * blocks_per_cu; }
 
 const PlanInfo& Ctx_::plan_for(GraphRes& G, const Pat& p, int* rc) {
     std::lock_guard<std::mutex> g(plan_mu);
@@ -349,8 +360,8 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     return PM_OK;
 }
 
-uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, uint64_t* scratch_stride,
-                         bool* any_agg) const {
+uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg,
+                         uint64_t* scratch_stride, bool* any_agg) const {
     uint64_t stride = 1;
     bool agg = false;
     for (const PlanInfo& p : plans) {
@@ -371,28 +382,287 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     *any_agg = agg;
     uint64_t b = 0;
     b += sizeof(DPlan) * plans.size() + 16 * plans.size() + 256 * 3;
-    b += waves() * (uint64_t)KMAX * stride * 4;
+    b += waves(cfg) * (uint64_t)KMAX * stride * 4;
     return b;
 }
 
-int Ctx_::ensure_agg(uint32_t n) {
-    uint64_t need = agg_waves() * (uint64_t)n * 4;
-    if (agg_off != UINT64_MAX && agg_n >= n) return PM_OK;
+int Ctx_::ensure_agg(uint32_t n, const LaunchCfg& cfg) {
+    uint64_t w = agg_waves(cfg);
+    if (agg_off != UINT64_MAX && agg_n >= n && agg_w >= w) return PM_OK;
     if (agg_off != UINT64_MAX) {
         arena.release(agg_off);
         arena.release(agg_touch_off);
         agg_off = agg_touch_off = UINT64_MAX;
     }
+    uint64_t need = w * (uint64_t)n * 4;
     agg_off = arena.alloc(need);
     agg_touch_off = arena.alloc(need);
     if (agg_off == UINT64_MAX || agg_touch_off == UINT64_MAX) {
         if (agg_off != UINT64_MAX) arena.release(agg_off);
+        if (agg_touch_off != UINT64_MAX) arena.release(agg_touch_off);
         agg_off = agg_touch_off = UINT64_MAX;
         return fail(PM_E_NOMEM, "arena too small for the aggregation counters");
     }
     agg_n = n;
-    HIPCHK(hipMemsetAsync(dptr(agg_off), 0, need, stream));
+    agg_w = w;
+    // the kernel returns every counter it touches to zero, so this runs once
+    if (launch_zero((uint32_t*)dptr(agg_off), need / 4, stream)) return fail(PM_E_DEVICE, "zero-fill failed");
+    HIPCHK(hipStreamSynchronize(stream));
     return PM_OK;
+}
+
+std::string Ctx_::closure_key(const GraphRes& G, const std::vector<Pat>& closure) const {
+    std::string k = std::to_string(G.hash) + "|";
+    for (const Pat& p : closure) {
+        k += std::to_string(p.k) + ":" + std::to_string(p.em) + ":" + (p.vi ? "V" : "E");
+        for (int i = 0; i < p.k; ++i) k += "," + std::to_string((int)p.lab[i]);
+        k += ";";
+    }
+    return k;
+}
+
+LaunchCfg Ctx_::cfg_for(const GraphRes& G, const std::vector<Pat>& closure) const {
+    auto it = tune_cache.find(closure_key(G, closure));
+    if (it != tune_cache.end()) return it->second.first;
+    return default_cfg();
+}
+
+int Ctx_::get_items(GraphRes& G, const LaunchCfg& c, ItemSet** out) {
+    auto key = std::make_pair(c.item_budget, c.item_split);
+    auto it = G.itemsets.find(key);
+    if (it != G.itemsets.end()) {
+        *out = &it->second;
+        return PM_OK;
+    }
+    std::vector<KItem> items = build_items(G.host_rp, G.n, c.item_budget, c.item_split, 256);
+    ItemSet is;
+    is.count = (uint32_t)items.size();
+    is.off = arena.alloc(sizeof(KItem) * items.size());
+    if (is.off == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the work items");
+    HIPCHK(hipMemcpyAsync(dptr(is.off), items.data(), sizeof(KItem) * items.size(), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *out = &(G.itemsets[key] = is);
+    return PM_OK;
+}
+
+void Ctx_::free_launchset(LaunchSet* ls) {
+    if (!ls) return;
+    if (ls->exec) hipGraphExecDestroy(ls->exec);
+    if (ls->graph) hipGraphDestroy(ls->graph);
+    if (ls->host) hipHostFree(ls->host);
+    if (ls->off_mem != UINT64_MAX) arena.release(ls->off_mem);
+    ls->exec = nullptr;
+    ls->graph = nullptr;
+    ls->host = nullptr;
+    ls->off_mem = UINT64_MAX;
+}
+
+int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg, LaunchSet* ls) {
+    const size_t np = plans.size();
+    ls->np = np;
+    ls->cfg = cfg;
+    uint64_t need = footprint(G, plans, cfg, &ls->stride, &ls->any_agg);
+    HIPCHK(hipSetDevice(device));
+    if (ls->any_agg) {
+        int rc = ensure_agg(G.n, cfg);
+        if (rc) return rc;
+    }
+    ItemSet* is;
+    int rc = get_items(G, cfg, &is);
+    if (rc) return rc;
+    ls->off_mem = arena.alloc(need);
+    if (ls->off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
+    char* base = (char*)dptr(ls->off_mem);
+    uint64_t o = 0;
+    auto carve = [&](uint64_t bytes) {
+        char* p = base + o;
+        o += (bytes + 255) & ~uint64_t(255);
+        return p;
+    };
+    ls->dplans = (DPlan*)carve(sizeof(DPlan) * np);
+    char* zb = carve(16 * np + 256 + 256);
+    ls->zero_base = (uint32_t*)zb;
+    ls->zero_words = (16 * np + 512) / 4;
+    ls->counters = (uint64_t*)zb;
+    ls->heads = (uint32_t*)(zb + 16 * np);
+    ls->bytes = (uint64_t*)(zb + 16 * np + 256);
+    ls->scratch = (uint32_t*)carve(waves(cfg) * (uint64_t)KMAX * ls->stride * 4);
+    std::vector<DPlan> hp(np);
+    for (size_t i = 0; i < np; ++i) hp[i] = plans[i].d;
+    HIPCHK(hipMemcpyAsync(ls->dplans, hp.data(), sizeof(DPlan) * np, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    HIPCHK(hipHostMalloc((void**)&ls->host, 16 * np + 64, hipHostMallocDefault));
+    KArgs& a = ls->base;
+    memset(&a, 0, sizeof(a));
+    a.g.rp = (const uint32_t*)dptr(G.off_rp);
+    a.g.col = (const uint32_t*)dptr(G.off_col);
+    a.g.split = (const uint32_t*)dptr(G.off_split);
+    a.g.lab = G.labeled ? (const uint8_t*)dptr(G.off_lab) : nullptr;
+    a.g.n = G.n;
+    a.items = (const KItem*)dptr(is->off);
+    a.nitems = is->count;
+    a.scratch = ls->scratch;
+    a.buf_stride = ls->stride;
+    a.bytes = ls->bytes;
+    a.cancel = nullptr;
+    if (ls->any_agg) {
+        a.aggcnt = (uint32_t*)dptr(agg_off);
+        a.aggtouch = (uint32_t*)dptr(agg_touch_off);
+    }
+    ls->runs.clear();
+    ls->run_agg.clear();
+    int i = 0;
+    while (i < (int)np) {
+        int grp = plans[i].d.agg_last ? 1 : 0;
+        int j = i;
+        while (j < (int)np && (plans[j].d.agg_last ? 1 : 0) == grp) ++j;
+        ls->runs.push_back({i, j});
+        ls->run_agg.push_back(grp);
+        i = j;
+    }
+    return PM_OK;
+}
+
+// [zero-fill -> match launches -> copy-back]; with bytes_pass the same
+// launches run in the byte-counting build and only the tally is copied
+// (host slot 2*np+1), outside any timed region.
+int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
+    const LaunchCfg& cfg = ls.cfg;
+    if (launch_zero(ls.zero_base, ls.zero_words, s)) return fail(PM_E_DEVICE, "zero-fill launch failed");
+    for (size_t r = 0; r < ls.runs.size(); ++r) {
+        KArgs b = ls.base;
+        b.plans = ls.dplans + ls.runs[r].first;
+        b.nplans = ls.runs[r].second - ls.runs[r].first;
+        b.counters = ls.counters + 2 * ls.runs[r].first;
+        b.head = ls.heads + r;
+        int gb = ls.run_agg[r] ? (int)std::max<uint64_t>(1, agg_waves(cfg) / (block / 64)) : grid_blocks(cfg);
+        if (launch_match(b, gb, block, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+    }
+    if (bytes_pass) {
+        HIPCHK(hipMemcpyAsync(ls.host + 2 * ls.np + 1, ls.bytes, 8, hipMemcpyDeviceToHost, s));
+        return PM_OK;
+    }
+    HIPCHK(hipMemcpyAsync(ls.host, ls.counters, 16 * ls.np, hipMemcpyDeviceToHost, s));
+    return PM_OK;
+}
+
+int Ctx_::run_eager_ms(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, double* ms) {
+    LaunchSet ls;
+    int rc = make_launchset(G, plans, c, &ls);
+    if (rc) {
+        free_launchset(&ls);
+        return rc;
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventRecord(e0, stream);
+    rc = enqueue(ls, stream, false);
+    hipEventRecord(e1, stream);
+    hipError_t he = hipEventSynchronize(e1);
+    float f = 0;
+    hipEventElapsedTime(&f, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    free_launchset(&ls);
+    if (he != hipSuccess) return fail(PM_E_DEVICE, std::string("tuning run failed: ") + hipGetErrorString(he));
+    *ms = f;
+    return rc;
+}
+
+int Ctx_::autotune(uint32_t gid, const pm_pattern* pats, uint32_t npat, int morph, int64_t* out_cfg,
+                   double* out_ms) {
+    GraphRes* G;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = graphs.find(gid);
+        if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+        G = it->second.get();
+    }
+    std::vector<Pat> ps(npat);
+    for (uint32_t i = 0; i < npat; ++i) {
+        std::string err;
+        int rc = to_pat(pats[i], &ps[i], &err);
+        if (rc) return fail(rc, err);
+    }
+    MorphPlan mp;
+    std::string err;
+    int rc = morph_plan_count(ps, morph, &mp, &err);
+    if (rc) return fail(rc, err);
+    std::vector<Pat> closure;
+    std::vector<PlanInfo> plans;
+    rc = plan_closure(*G, mp.alt, &closure, &plans);
+    if (rc) return fail(rc, g_err);
+    std::string key = closure_key(*G, closure);
+    auto hit = tune_cache.find(key);
+    if (hit == tune_cache.end()) {
+        // coordinate descent over the launch parameters, timed on the graph
+        LaunchCfg best = default_cfg();
+        double best_ms;
+        rc = run_eager_ms(*G, plans, best, &best_ms);
+        if (rc) return rc;
+        const int bpcs[] = {1, 2, 4, 8};
+        const uint64_t budgets[] = {1024, 4096, 16384, 65536};
+        const uint32_t splits[] = {512, 2048, 8192};
+        for (int stage = 0; stage < 3; ++stage) {
+            int nvals = stage == 0 ? 4 : (stage == 1 ? 4 : 3);
+            for (int v = 0; v < nvals; ++v) {
+                LaunchCfg c = best;
+                if (stage == 0) c.blocks_per_cu = bpcs[v];
+                if (stage == 1) c.item_budget = budgets[v];
+                if (stage == 2) c.item_split = splits[v];
+                if (c.blocks_per_cu == best.blocks_per_cu && c.item_budget == best.item_budget &&
+                    c.item_split == best.item_split)
+                    continue;
+                double ms;
+                rc = run_eager_ms(*G, plans, c, &ms);
+                if (rc == PM_E_NOMEM) continue;
+                if (rc) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+        hit = tune_cache.emplace(key, std::make_pair(best, best_ms)).first;
+        if (!tune_file.empty()) {
+            FILE* f = fopen(tune_file.c_str(), "a");
+            if (f) {
+                fprintf(f, "%d %llu %u %.6f %s\n", best.blocks_per_cu, (unsigned long long)best.item_budget,
+                        best.item_split, best_ms, key.c_str());
+                fclose(f);
+            }
+        }
+    }
+    if (out_cfg) {
+        out_cfg[0] = hit->second.first.blocks_per_cu;
+        out_cfg[1] = (int64_t)hit->second.first.item_budget;
+        out_cfg[2] = hit->second.first.item_split;
+    }
+    if (out_ms) *out_ms = hit->second.second;
+    return PM_OK;
+}
+
+void Ctx_::load_tune_file() {
+    const char* env = getenv("PM_AUTOTUNE_CACHE");
+    if (!env || !*env) return;
+    tune_file = env;
+    FILE* f = fopen(env, "r");
+    if (!f) return;
+    char line[65536];
+    while (fgets(line, sizeof(line), f)) {
+        int bpc;
+        unsigned long long bud;
+        unsigned spl;
+        double ms;
+        int off = 0;
+        if (sscanf(line, "%d %llu %u %lf %n", &bpc, &bud, &spl, &ms, &off) != 4) continue;
+        std::string key(line + off);
+        while (!key.empty() && (key.back() == '\n' || key.back() == '\r')) key.pop_back();
+        if (bpc < 1 || bpc > 64 || bud < 1 || spl < 64) continue;
+        tune_cache[key] = {LaunchCfg{bpc, (uint64_t)bud, (uint32_t)spl}, ms};
+    }
+    fclose(f);
 }
 
 int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph,
@@ -439,106 +709,77 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
 }
 
 int Ctx_::launch(GraphRes& G, Query& Q) {
-    const size_t np = Q.plans.size();
-    uint64_t stride;
-    bool any_agg;
-    uint64_t need = footprint(G, Q.plans, &stride, &any_agg);
+    const LaunchCfg cfg = cfg_for(G, Q.closure);
     HIPCHK(hipSetDevice(device));
-    if (any_agg) {
-        int rc = ensure_agg(G.n);
-        if (rc) return rc;
+    LaunchSet* ls = nullptr;
+    bool replay = use_graphs && !count_bytes;
+    std::string key = closure_key(G, Q.closure) + "#" + std::to_string(cfg.blocks_per_cu) + "," +
+                      std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split);
+    if (replay) {
+        auto it = G.launches.find(key);
+        if (it != G.launches.end() && !it->second->busy) {
+            ls = it->second.get();
+        } else if (it == G.launches.end()) {
+            auto nls = std::make_unique<LaunchSet>();
+            int rc = make_launchset(G, Q.plans, cfg, nls.get());
+            if (rc) {
+                free_launchset(nls.get());
+                return rc;
+            }
+            // capture [zero-fill -> launches -> copy-back] once; replay later
+            if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
+            int erc = enqueue(*nls, cap_stream, false);
+            hipGraph_t graph = nullptr;
+            hipError_t ce = hipStreamEndCapture(cap_stream, &graph);
+            if (erc || ce != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                free_launchset(nls.get());
+                return erc ? erc : fail(PM_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
+            }
+            nls->graph = graph;
+            hipError_t ie = hipGraphInstantiate(&nls->exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                free_launchset(nls.get());
+                return fail(PM_E_DEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(ie));
+            }
+            ls = nls.get();
+            G.launches[key] = std::move(nls);
+        }
     }
-    Q.off_mem = arena.alloc(need);
-    if (Q.off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
-    char* base = (char*)dptr(Q.off_mem);
-    uint64_t o = 0;
-    auto carve = [&](uint64_t bytes) {
-        char* p = base + o;
-        o += (bytes + 255) & ~uint64_t(255);
-        return p;
-    };
-    DPlan* dplans = (DPlan*)carve(sizeof(DPlan) * np);
-    uint64_t* counters = (uint64_t*)carve(16 * np);
-    uint32_t* heads = (uint32_t*)carve(256);
-    uint64_t* bytes = (uint64_t*)carve(256);
-    uint32_t* scratch = (uint32_t*)carve(waves() * (uint64_t)KMAX * stride * 4);
-    std::vector<DPlan> hp(np);
-    for (size_t i = 0; i < np; ++i) hp[i] = Q.plans[i].d;
-    HIPCHK(hipMemcpyAsync(dplans, hp.data(), sizeof(DPlan) * np, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemsetAsync(counters, 0, 16 * np, stream));
-    HIPCHK(hipMemsetAsync(heads, 0, 256, stream));
-    HIPCHK(hipMemsetAsync(bytes, 0, 256, stream));
-
-    KArgs a;
-    memset(&a, 0, sizeof(a));
-    a.g.rp = (const uint32_t*)dptr(G.off_rp);
-    a.g.col = (const uint32_t*)dptr(G.off_col);
-    a.g.split = (const uint32_t*)dptr(G.off_split);
-    a.g.lab = G.labeled ? (const uint8_t*)dptr(G.off_lab) : nullptr;
-    a.g.n = G.n;
-    a.items = (const KItem*)dptr(G.off_items);
-    a.nitems = (uint32_t)G.items.size();
-    a.scratch = scratch;
-    a.buf_stride = stride;
-    a.bytes = bytes;
-    a.cancel = nullptr;
-    if (any_agg) {
-        a.aggcnt = (uint32_t*)dptr(agg_off);
-        a.aggtouch = (uint32_t*)dptr(agg_touch_off);
+    if (!ls) {
+        Q.own = std::make_unique<LaunchSet>();
+        int rc = make_launchset(G, Q.plans, cfg, Q.own.get());
+        if (rc) {
+            free_launchset(Q.own.get());
+            Q.own.reset();
+            return rc;
+        }
     }
-    // plans without aggregation in one launch, aggregation plans in another
-    // (their grid is bounded by the dense counter arrays)
-    std::vector<int> groups[2];
-    for (size_t i = 0; i < np; ++i) groups[Q.plans[i].d.agg_last ? 1 : 0].push_back((int)i);
-    // the launch needs contiguous plans: we launch per contiguous run
     if (!Q.ev_start) {
         HIPCHK(hipEventCreate(&Q.ev_start));
         HIPCHK(hipEventCreate(&Q.ev_stop));
+        HIPCHK(hipEventCreate(&Q.ev_done));
     }
-    if (count_bytes) {
-        // untimed counting pass (same kernel, byte tally enabled)
-        for (int grp = 0; grp < 2; ++grp) {
-            for (int pi : groups[grp]) {
-                KArgs b = a;
-                b.plans = dplans + pi;
-                b.nplans = 1;
-                b.counters = counters + 2 * pi;
-                b.head = heads + 1 + pi % 60;
-                HIPCHK(hipMemsetAsync(b.head, 0, 4, stream));
-                int gb = grp ? (int)std::max<uint64_t>(1, agg_waves() / (block / 64)) : grid_blocks();
-                if (launch_match(b, gb, block, true, stream)) return fail(PM_E_DEVICE, "kernel launch failed");
-            }
-        }
-        HIPCHK(hipMemsetAsync(counters, 0, 16 * np, stream));
+    Q.counted_bytes = !ls && count_bytes;
+    if (Q.counted_bytes) {
+        int rc = enqueue(*Q.own, stream, true);
+        if (rc) return rc;
     }
     HIPCHK(hipEventRecord(Q.ev_start, stream));
-    Q.stats.launches = 0;
-    // group 0: one multi-plan launch when the plans are contiguous
-    {
-        int i = 0;
-        while (i < (int)np) {
-            int grp = Q.plans[i].d.agg_last ? 1 : 0;
-            int j = i;
-            while (j < (int)np && (Q.plans[j].d.agg_last ? 1 : 0) == grp) ++j;
-            KArgs b = a;
-            b.plans = dplans + i;
-            b.nplans = j - i;
-            b.counters = counters + 2 * i;
-            b.head = heads + (Q.stats.launches % 60) + 1;
-            HIPCHK(hipMemsetAsync(b.head, 0, 4, stream));
-            int gb = grp ? (int)std::max<uint64_t>(1, agg_waves() / (block / 64)) : grid_blocks();
-            if (launch_match(b, gb, block, false, stream)) return fail(PM_E_DEVICE, "kernel launch failed");
-            Q.stats.launches++;
-            i = j;
-        }
+    if (ls) {
+        ls->busy = true;
+        Q.ls = ls;
+        HIPCHK(hipGraphLaunch(ls->exec, stream));
+    } else {
+        int rc = enqueue(*Q.own, stream, false);
+        if (rc) return rc;
     }
     HIPCHK(hipEventRecord(Q.ev_stop, stream));
-    Q.host_counters.resize(2 * np + 1);
-    HIPCHK(hipMemcpyAsync(Q.host_counters.data(), counters, 16 * np, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(&Q.host_counters[2 * np], bytes, 8, hipMemcpyDeviceToHost, stream));
-    if (!Q.ev_done) HIPCHK(hipEventCreate(&Q.ev_done));
     HIPCHK(hipEventRecord(Q.ev_done, stream));
-    Q.stats.work_items = (uint64_t)G.items.size() * np;
+    LaunchSet& L = ls ? *ls : *Q.own;
+    Q.stats.launches = (uint32_t)L.runs.size();
+    Q.stats.work_items = (uint64_t)L.base.nitems * L.np;
     return PM_OK;
 }
 
@@ -565,6 +806,7 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
     hipEventElapsedTime(&kms, Q->ev_start, Q->ev_stop);
     Q->stats.kernel_ms = kms;
     size_t np = Q->plans.size();
+    const uint64_t* host = Q->ls ? Q->ls->host : Q->own->host;
     // closure counts, smallest patterns first (quotient plans need them)
     std::vector<__int128> cnt(np, -1);
     std::vector<size_t> order(np);
@@ -575,7 +817,7 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
     for (size_t oi = 0; oi < np && rc == PM_OK; ++oi) {
         size_t i = order[oi];
         const PlanInfo& pi = Q->plans[i];
-        unsigned __int128 v = ((unsigned __int128)Q->host_counters[2 * i + 1] << 64) | Q->host_counters[2 * i];
+        unsigned __int128 v = ((unsigned __int128)host[2 * i + 1] << 64) | host[2 * i];
         if (v >> 120) {
             rc = fail(PM_E_OVERFLOW, "match total exceeds 120 bits");
             break;
@@ -623,13 +865,14 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
         if (rc) fail(rc, err);
     }
     if (rc == PM_OK && out) memcpy(out, res.data(), sizeof(int64_t) * Q->npat);
-    Q->stats.alg_bytes = Q->host_counters[2 * np];
+    Q->stats.alg_bytes = Q->counted_bytes ? host[2 * np + 1] : 0;
     Q->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - Q->t_submit).count();
     last_stats = Q->stats;
     last_alt = alt;
     // release
     std::lock_guard<std::mutex> g(mu);
-    arena.release(Q->off_mem);
+    if (Q->ls) Q->ls->busy = false;
+    if (Q->own) free_launchset(Q->own.get());
     hipEventDestroy(Q->ev_start);
     hipEventDestroy(Q->ev_stop);
     hipEventDestroy(Q->ev_done);
@@ -664,6 +907,7 @@ pm_status pm_create(void* dev_arena, uint64_t arena_bytes, void* hip_stream, int
     c->c.arena.size = arena_bytes;
     c->c.arena.free_[0] = arena_bytes & ~uint64_t(255);
     c->c.num_cus = prop.multiProcessorCount;
+    c->c.load_tune_file();
     *out = c;
     return PM_OK;
 }
@@ -671,6 +915,9 @@ pm_status pm_create(void* dev_arena, uint64_t arena_bytes, void* hip_stream, int
 pm_status pm_destroy(pm_ctx* ctx) {
     if (!ctx) return PM_E_INVAL;
     hipStreamSynchronize(ctx->c.stream);
+    for (auto& g : ctx->c.graphs)
+        for (auto& ls : g.second->launches) ctx->c.free_launchset(ls.second.get());
+    if (ctx->c.cap_stream) hipStreamDestroy(ctx->c.cap_stream);
     delete ctx;
     return PM_OK;
 }
@@ -732,7 +979,7 @@ pm_status pm_query_footprint(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, 
     if (rc) return fail(rc, g_err);
     uint64_t stride;
     bool any_agg;
-    *out_bytes = ctx->c.footprint(*G, plans, &stride, &any_agg);
+    *out_bytes = ctx->c.footprint(*G, plans, ctx->c.cfg_for(*G, closure), &stride, &any_agg);
     return PM_OK;
 }
 
@@ -823,6 +1070,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "item_budget" && value >= 1) c.item_budget = (uint64_t)value;
     else if (k == "item_split" && value >= 64) c.item_split = (uint32_t)value;
     else if (k == "agg_waves" && value >= 1) c.agg_waves_opt = (uint64_t)value;
+    else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;
 }
@@ -846,6 +1094,16 @@ pm_status pm_plan_describe(pm_ctx* ctx, uint32_t gid, const pm_pattern* pat, cha
     std::string s = pi.describe();
     snprintf(buf, cap, "%s", s.c_str());
     return PM_OK;
+}
+
+pm_status pm_autotune(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, uint32_t npat, int32_t morph,
+                      int64_t* out_cfg, double* out_ms) {
+    if (!ctx || !pats || npat == 0) return fail(PM_E_INVAL, "null argument");
+    try {
+        return ctx->c.autotune(gid, pats, npat, morph, out_cfg, out_ms);
+    } catch (const std::exception& e) {
+        return fail(PM_E_NOMEM, std::string("host allocation failed: ") + e.what());
+    }
 }
 
 uint64_t pm_fsm_num_slots(uint32_t num_labels) { return 0 * num_labels; }

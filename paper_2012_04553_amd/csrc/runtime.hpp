@@ -31,6 +31,43 @@ struct Arena {
     uint64_t largest_free();
 };
 
+// Work items of one (root budget, hub slice) configuration, on the device.
+struct ItemSet {
+    uint64_t off = UINT64_MAX;
+    uint32_t count = 0;
+};
+
+struct LaunchCfg {
+    int blocks_per_cu = 4;
+    uint64_t item_budget = 4096;
+    uint32_t item_split = 2048;
+};
+
+// Device state of one (graph, plan closure, launch configuration): plans,
+// counters, queue heads, scratch, pinned result buffer, and the captured
+// hipGraph that replays [zero-fill -> match launches -> copy-back].
+struct LaunchSet {
+    uint64_t off_mem = UINT64_MAX;
+    size_t np = 0;
+    DPlan* dplans = nullptr;
+    uint64_t* counters = nullptr;
+    uint32_t* zero_base = nullptr;   // counters + heads + bytes, cleared together
+    uint64_t zero_words = 0;
+    uint32_t* heads = nullptr;
+    uint64_t* bytes = nullptr;
+    uint32_t* scratch = nullptr;
+    uint64_t stride = 0;
+    bool any_agg = false;
+    KArgs base{};
+    std::vector<std::pair<int, int>> runs;   // contiguous plan ranges, one launch each
+    std::vector<int> run_agg;
+    uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool busy = false;
+    LaunchCfg cfg;
+};
+
 struct GraphRes {
     uint32_t n = 0;
     uint64_t m = 0;
@@ -40,8 +77,11 @@ struct GraphRes {
     uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_split = UINT64_MAX, off_lab = UINT64_MAX,
              off_items = UINT64_MAX;
     uint64_t device_bytes = 0;
-    std::vector<KItem> items;
+    std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
+    std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
+    std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
+    uint64_t hash = 0;                       // FNV-1a of the degree-ordered CSR (+labels)
     int inflight = 0;
 };
 
@@ -51,9 +91,10 @@ struct Query {
     MorphPlan mp;
     std::vector<Pat> closure;        // patterns matched on the device
     std::vector<PlanInfo> plans;     // one per closure entry
-    uint64_t off_mem = UINT64_MAX;
+    LaunchSet* ls = nullptr;                 // cached launch set (busy while in flight)
+    std::unique_ptr<LaunchSet> own;          // or one made for this query alone
+    bool counted_bytes = false;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
-    std::vector<uint64_t> host_counters;
     pm_query_stats stats{};
     std::chrono::steady_clock::time_point t_submit;
 };
@@ -69,6 +110,10 @@ struct Ctx_ {
     uint32_t item_split = 2048;
     bool count_bytes = false;
     uint64_t agg_waves_opt = 512;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
+    std::string tune_file;
     std::mutex mu, plan_mu;
     std::map<uint32_t, std::unique_ptr<GraphRes>> graphs;
     std::map<uint64_t, std::unique_ptr<Query>> queries;
@@ -76,13 +121,24 @@ struct Ctx_ {
     uint64_t next_ticket = 1;
     uint64_t agg_off = UINT64_MAX, agg_touch_off = UINT64_MAX;
     uint32_t agg_n = 0;
+    uint64_t agg_w = 0;
     pm_query_stats last_stats{};
     std::vector<int64_t> last_alt;
 
     void* dptr(uint64_t off) const { return (void*)(arena.base + off); }
-    int grid_blocks() const;
-    uint64_t waves() const;
-    uint64_t agg_waves() const { return std::min<uint64_t>(agg_waves_opt, waves()); }
+    int grid_blocks(const LaunchCfg& c) const { return num_cus * c.blocks_per_cu; }
+    uint64_t waves(const LaunchCfg& c) const { return (uint64_t)grid_blocks(c) * (block / 64); }
+    uint64_t agg_waves(const LaunchCfg& c) const { return std::min<uint64_t>(agg_waves_opt, waves(c)); }
+    LaunchCfg default_cfg() const { return LaunchCfg{blocks_per_cu, item_budget, item_split}; }
+    std::string closure_key(const GraphRes& G, const std::vector<Pat>& closure) const;
+    LaunchCfg cfg_for(const GraphRes& G, const std::vector<Pat>& closure) const;
+    int get_items(GraphRes& G, const LaunchCfg& c, ItemSet** out);
+    int make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, LaunchSet* ls);
+    void free_launchset(LaunchSet* ls);
+    int enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass);
+    int run_eager_ms(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, double* ms);
+    int autotune(uint32_t gid, const pm_pattern* pats, uint32_t npat, int morph, int64_t* out_cfg, double* out_ms);
+    void load_tune_file();
     int graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels, uint32_t* gid);
     int graph_unload(uint32_t gid);
     const PlanInfo& plan_for(GraphRes& G, const Pat& p, int* rc);
@@ -90,8 +146,9 @@ struct Ctx_ {
     // aggregation plans last (they run in a launch of their own)
     int plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
                      std::vector<PlanInfo>* plans);
-    uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, uint64_t* stride, bool* any_agg) const;
-    int ensure_agg(uint32_t n);
+    uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c,
+                       uint64_t* stride, bool* any_agg) const;
+    int ensure_agg(uint32_t n, const LaunchCfg& c);
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
     int launch(GraphRes& G, Query& Q);
     int wait(uint64_t ticket, int64_t* out, int64_t timeout_us);

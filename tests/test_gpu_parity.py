@@ -87,8 +87,11 @@ def test_small_rmat_hubs(eng, scale, seed):
             want = _oracle_counts(g, k, induced)
             for morph in (pm.MORPH_NONE, pm.MORPH_NAIVE):
                 assert _gpu_counts(eng, g, k, induced, morph) == want, (k, induced, morph)
-    want5 = _oracle_counts(g, 5, False)
-    assert _gpu_counts(eng, g, 5, False, pm.MORPH_NONE) == want5
+    if scale <= 8:
+        vi5 = oracle.census(g, 5)
+        ei5 = P.edge_induced_from_vertex_induced(5, vi5)
+        assert _gpu_counts(eng, g, 5, False, pm.MORPH_NONE) == [ei5[m] for m in P.connected_classes(5)]
+        assert _gpu_counts(eng, g, 5, True, pm.MORPH_NAIVE) == [vi5[m] for m in P.connected_classes(5)]
 
 
 def test_hub_slicing(eng):
