@@ -58,6 +58,8 @@ def lib():
                                   ctypes.c_uint32, ctypes.c_uint32, ip, u8p, u64p, u64p]
         L.or_census.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_int, u64p]
         L.or_tier_c4.argtypes = [ctypes.c_uint32, u32p, u32p, u64p]
+        L.or_mni_column.argtypes = [ctypes.c_uint32, u32p, u32p, u8p, ctypes.c_int, ip,
+                                    ctypes.c_uint32, ctypes.c_uint32, ip, u64p]
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,7 +232,46 @@ def mni_support(g, k: int, mask: int, induced: bool, plabels=None) -> int:
     return int(dom.sum(axis=1).min()) if k > 0 else 0
 
 
+def _rooted_order(k, mask, v):
+    order = [v]
+    seen = {v}
+    i = 0
+    while i < len(order):
+        x = order[i]
+        i += 1
+        for y in range(k):
+            if y not in seen and P.has_edge(mask, x, y):
+                seen.add(y)
+                order.append(y)
+    assert len(order) == k, "pattern is not connected"
+    return order
+
+
+def mni_column(g, k: int, mask: int, induced: bool, plabels, v: int) -> int:
+    """|D(v)| by rooted existence search (large graphs)."""
+    rp, col = _graph_arrays(g)
+    order = np.array(_rooted_order(k, mask, v), dtype=np.int32)
+    amask = (P.clique_mask(k) & ~mask) if induced else 0
+    pl = np.full(8, -1, dtype=np.int32)
+    if plabels is not None:
+        pl[:k] = np.asarray(plabels, dtype=np.int32)
+    lab = np.ascontiguousarray(g.labels, dtype=np.uint8)
+    out = ctypes.c_uint64()
+    rc = lib().or_mni_column(g.n, _ptr(rp, ctypes.c_uint32), _ptr(col, ctypes.c_uint32),
+                             _ptr(lab, ctypes.c_uint8), k, _ptr(order, ctypes.c_int), mask, amask,
+                             _ptr(pl, ctypes.c_int), ctypes.byref(out))
+    if rc != 0:
+        raise ValueError(f"or_mni_column failed: {rc}")
+    return int(out.value)
+
+
+def mni_support_rooted(g, k: int, mask: int, induced: bool, plabels) -> int:
+    """MNI support as the smallest column, each column by rooted search."""
+    return min(mni_column(g, k, mask, induced, plabels, v) for v in range(k))
+
+
 __all__ = ["P", "build", "lib", "count_maps", "count", "motif_counts", "census",
            "full_census_tiny", "tier_c4", "named_4", "edge_induced_4_from_tier_c",
            "vertex_induced_4_from_tier_c", "mni_domains", "mni_support", "num_threads",
+           "mni_column", "mni_support_rooted",
            "comb", "factorial"]

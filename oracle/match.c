@@ -26,6 +26,8 @@
  *  - or_mni_maps: minimum-node-image domains (Preliminaries, "Frequent
  *    Subgraph Mining": one column per pattern vertex holding m(v) of every
  *    match) by enumerating every match.
+ *  - or_mni_column: the size of one such column on large graphs, by a
+ *    search from every candidate vertex that stops at its first match.
  *
  * Graph: simple undirected CSR, ascending adjacency, uint32 ids.
  * Pattern edge (i<j) is bit j*(j-1)/2+i of a mask.
@@ -433,5 +435,43 @@ int or_tier_c4(uint32_t n, const uint32_t* rp, const uint32_t* col, uint64_t* ou
         out[2 * i] = (uint64_t)tot[i];
         out[2 * i + 1] = (uint64_t)(tot[i] >> 64);
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* MNI column size by rooted existence                                  */
+/* ------------------------------------------------------------------ */
+
+static int exists_from(const mapctx* c, uint32_t* img, int j) {
+    if (j == c->k) return 1;
+    uint32_t a = img[c->anchor[j]];
+    for (uint32_t e = c->rp[a]; e < c->rp[a + 1]; ++e) {
+        uint32_t x = c->col[e];
+        if (!step_ok(c, img, j, x)) continue;
+        img[j] = x;
+        if (exists_from(c, img, j + 1)) return 1;
+    }
+    return 0;
+}
+
+/* |D(v)| for the pattern vertex order[0]: the number of data vertices x for
+ * which some match maps order[0] to x (a depth-first search from x that
+ * stops at the first match).  `order` must start at the column vertex and
+ * be connected. */
+int or_mni_column(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* lab,
+                  int k, const int* order, uint32_t emask, uint32_t amask, const int* plab,
+                  uint64_t* out) {
+    mapctx c;
+    int rc = setup_ctx(&c, n, rp, col, lab, k, order, emask, amask, plab);
+    if (rc) return rc;
+    uint64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total)
+    for (int64_t r = 0; r < (int64_t)n; ++r) {
+        uint32_t img[8];
+        if (!step_ok(&c, img, 0, (uint32_t)r)) continue;
+        img[0] = (uint32_t)r;
+        if (exists_from(&c, img, 1)) total += 1;
+    }
+    *out = total;
     return 0;
 }

@@ -14,5 +14,7 @@ from .binding import (  # noqa: F401
     PMError,
     lib,
     make_pattern,
+    fsm_num_slots,
+    fsm_slot,
     morph_plan,
 )

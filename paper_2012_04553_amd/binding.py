@@ -130,6 +130,17 @@ def pattern_array(pats) -> ctypes.Array:
     return arr
 
 
+def fsm_slot(num_labels: int, slot: int):
+    """Pattern (k, edge_mask, labels) of an FSM slot (host-only)."""
+    p = pm_pattern()
+    check(lib().pm_fsm_slot(num_labels, slot, ctypes.byref(p)))
+    return p.k, p.edge_mask, [p.label[i] for i in range(p.k)]
+
+
+def fsm_num_slots(num_labels: int) -> int:
+    return int(lib().pm_fsm_num_slots(num_labels))
+
+
 def morph_plan(pats, morph: int = MORPH_NAIVE):
     """Host-only: alternative pattern set and conversion matrix."""
     arr = pattern_array(pats)
@@ -227,6 +238,16 @@ class Engine:
         ms = ctypes.c_double()
         check(lib().pm_autotune(self.ctx, gid, arr, len(pats), morph, cfg, ctypes.byref(ms)))
         return {"blocks_per_cu": cfg[0], "item_budget": cfg[1], "item_split": cfg[2], "ms": ms.value}
+
+    def fsm(self, gid, num_labels: int, threshold: int, morph=MORPH_NONE):
+        """MNI support of every labeled 3-edge pattern (dense slot order) and
+        the frequent flags (support >= threshold)."""
+        ns = int(lib().pm_fsm_num_slots(num_labels))
+        sup = np.zeros(ns, dtype=np.int64)
+        freq = np.zeros(ns, dtype=np.uint8)
+        check(lib().pm_fsm(self.ctx, gid, num_labels, threshold, morph,
+                           sup.ctypes.data_as(_i64p), freq.ctypes.data_as(_u8p), ns))
+        return sup, freq
 
     def plan_describe(self, gid, pat) -> str:
         buf = ctypes.create_string_buffer(8192)

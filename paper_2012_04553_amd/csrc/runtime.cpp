@@ -21,6 +21,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "fsm.hpp"
 #include "runtime.hpp"
 
 namespace pm {
@@ -179,14 +180,19 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
         }
     });
     std::vector<uint8_t> nlab;
+    uint32_t max_label = 0;
     if (labels) {
         nlab.resize(n);
-        for (uint32_t r = 0; r < n; ++r) nlab[r] = labels[order[r]];
+        for (uint32_t r = 0; r < n; ++r) {
+            nlab[r] = labels[order[r]];
+            max_label = std::max<uint32_t>(max_label, nlab[r]);
+        }
     }
     auto G = std::make_unique<GraphRes>();
     G->n = n;
     G->m = nnz / 2;
     G->labeled = labels != nullptr;
+    G->max_label = max_label;
     double sd2 = 0, so2 = 0, s_pq = 0, s_pd = 0, s_qq = 0, s_qd = 0;
     uint32_t maxd = 0, maxo = 0;
     for (uint32_t r = 0; r < n; ++r) {
@@ -1106,10 +1112,202 @@ pm_status pm_autotune(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, uint32_
     }
 }
 
-uint64_t pm_fsm_num_slots(uint32_t num_labels) { return 0 * num_labels; }
-pm_status pm_fsm_slot(uint32_t, uint64_t, pm_pattern*) { return fail(PM_E_UNSUPPORTED, "FSM not built yet"); }
-pm_status pm_fsm(pm_ctx*, uint32_t, uint32_t, int64_t, int32_t, int64_t*, uint8_t*, uint64_t) {
-    return fail(PM_E_UNSUPPORTED, "FSM not built yet");
+// ---- labeled 3-edge FSM: dense slot order --------------------------------
+// [triangles: sorted label triples] [3-edge paths: label 4-tuples up to
+// reversal, the lexicographically smaller orientation] [3-stars: centre
+// label, sorted leaf triple]; each block in lexicographic order.
+static uint64_t fsm_tri(uint32_t L) { return (uint64_t)L * (L + 1) * (L + 2) / 6; }
+static uint64_t fsm_p4(uint32_t L) { return ((uint64_t)L * L * L * L + (uint64_t)L * L) / 2; }
+
+struct FsmTables {
+    uint32_t L = 0;
+    std::vector<int32_t> tricode, p4code, s3code;
+    std::vector<std::array<int, 5>> slots;  // kind (0 tri, 1 path, 2 star), labels
+};
+
+static void fsm_tables(uint32_t L, FsmTables* t) {
+    t->L = L;
+    t->tricode.assign((size_t)L * L * L, -1);
+    t->p4code.assign((size_t)L * L * L * L, -1);
+    t->s3code.assign((size_t)L * L * L * L, -1);
+    t->slots.clear();
+    for (uint32_t a = 0; a < L; ++a)
+        for (uint32_t b = a; b < L; ++b)
+            for (uint32_t c = b; c < L; ++c) {
+                t->tricode[(a * L + b) * L + c] = (int32_t)t->slots.size();
+                t->slots.push_back({0, (int)a, (int)b, (int)c, -1});
+            }
+    for (uint32_t a = 0; a < L; ++a)
+        for (uint32_t b = 0; b < L; ++b)
+            for (uint32_t c = 0; c < L; ++c)
+                for (uint32_t d = 0; d < L; ++d) {
+                    std::array<uint32_t, 4> f{a, b, c, d}, r{d, c, b, a};
+                    if (r < f) continue;  // not canonical
+                    int32_t slot = (int32_t)t->slots.size();
+                    t->slots.push_back({1, (int)a, (int)b, (int)c, (int)d});
+                    int pal = (f == r) ? 1 : 0;
+                    t->p4code[((a * L + b) * L + c) * L + d] = slot << 2 | pal;
+                    t->p4code[((d * L + c) * L + b) * L + a] = slot << 2 | (pal ? 0 : 2) | pal;
+                }
+    for (uint32_t c = 0; c < L; ++c)
+        for (uint32_t x = 0; x < L; ++x)
+            for (uint32_t y = x; y < L; ++y)
+                for (uint32_t z = y; z < L; ++z) {
+                    t->s3code[((c * L + x) * L + y) * L + z] = (int32_t)t->slots.size();
+                    t->slots.push_back({2, (int)c, (int)x, (int)y, (int)z});
+                }
+}
+
+uint64_t pm_fsm_num_slots(uint32_t num_labels) {
+    if (num_labels == 0 || num_labels > (uint32_t)FSM_LMAX) return 0;
+    return fsm_tri(num_labels) + fsm_p4(num_labels) + (uint64_t)num_labels * fsm_tri(num_labels);
+}
+
+pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out) {
+    if (!out || num_labels == 0 || num_labels > (uint32_t)FSM_LMAX) return fail(PM_E_INVAL, "bad label count");
+    if (slot >= pm_fsm_num_slots(num_labels)) return fail(PM_E_INVAL, "slot out of range");
+    FsmTables t;
+    fsm_tables(num_labels, &t);
+    const auto& s = t.slots[slot];
+    for (int i = 0; i < 8; ++i) out->label[i] = -1;
+    out->induce = PM_EDGE_INDUCED;
+    if (s[0] == 0) {  // triangle 0-1-2
+        out->k = 3;
+        out->edge_mask = 0x7;
+        for (int i = 0; i < 3; ++i) out->label[i] = s[1 + i];
+    } else if (s[0] == 1) {  // path 0-1-2-3: edges (0,1) (1,2) (2,3)
+        out->k = 4;
+        out->edge_mask = (1u << pair_bit(0, 1)) | (1u << pair_bit(1, 2)) | (1u << pair_bit(2, 3));
+        for (int i = 0; i < 4; ++i) out->label[i] = s[1 + i];
+    } else {  // star centred at 0
+        out->k = 4;
+        out->edge_mask = (1u << pair_bit(0, 1)) | (1u << pair_bit(0, 2)) | (1u << pair_bit(0, 3));
+        for (int i = 0; i < 4; ++i) out->label[i] = s[1 + i];
+    }
+    return PM_OK;
+}
+
+pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t threshold, int32_t morph,
+                 int64_t* out_support, uint8_t* out_frequent, uint64_t nslots) {
+    if (!ctx || !out_support) return fail(PM_E_INVAL, "null argument");
+    if (num_labels == 0 || num_labels > (uint32_t)FSM_LMAX)
+        return fail(PM_E_UNSUPPORTED, "pm_fsm supports 1..16 labels");
+    if (nslots != pm_fsm_num_slots(num_labels)) return fail(PM_E_INVAL, "nslots must equal pm_fsm_num_slots");
+    if (morph != PM_MORPH_NONE)
+        return fail(PM_E_UNSUPPORTED, "pm_fsm computes edge-induced supports directly (PM_MORPH_NONE)");
+    Ctx_& c = ctx->c;
+    GraphRes* G;
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.graphs.find(gid);
+        if (it == c.graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
+        G = it->second.get();
+    }
+    if (!G->labeled) return fail(PM_E_INVAL, "pm_fsm needs a labeled graph");
+    if (G->max_label >= num_labels) return fail(PM_E_INVAL, "graph label outside 0..num_labels-1");
+    auto t0 = std::chrono::steady_clock::now();
+    FsmTables T;
+    fsm_tables(num_labels, &T);
+    const uint64_t n = G->n;
+    const int grid = std::max(1, c.num_cus * 4);
+    const uint64_t threads = (uint64_t)grid * 256;
+    const uint64_t LL = (uint64_t)FSM_LMAX * FSM_LMAX;
+    uint64_t sz_hist = n * FSM_LMAX * 4, sz_pres = n * 3 * 4, sz_b = n * LL, sz_bm = n * FSM_LMAX * 4;
+    uint64_t sz_tab = 4 * (T.tricode.size() + T.p4code.size() + T.s3code.size());
+    uint64_t sz_cnt = nslots * 16, sz_scr = threads * FSM_SCRATCH_WORDS * 8;
+    uint64_t need = 0;
+    for (uint64_t x : {sz_hist, sz_pres, sz_b, sz_b, sz_bm, sz_tab, sz_cnt, sz_scr}) need += (x + 255) & ~uint64_t(255);
+    uint64_t off = c.arena.alloc(need);
+    if (off == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for FSM tables");
+    char* base = (char*)c.dptr(off);
+    uint64_t o = 0;
+    auto carve = [&](uint64_t bytes) {
+        char* p = base + o;
+        o += (bytes + 255) & ~uint64_t(255);
+        return p;
+    };
+    FsmArgs a;
+    a.rp = (const uint32_t*)c.dptr(G->off_rp);
+    a.col = (const uint32_t*)c.dptr(G->off_col);
+    a.lab = (const uint8_t*)c.dptr(G->off_lab);
+    a.n = G->n;
+    a.L = (int)num_labels;
+    a.hist = (uint32_t*)carve(sz_hist);
+    a.pres = (uint32_t*)carve(sz_pres);
+    a.bcnt = (uint8_t*)carve(sz_b);
+    a.bfrag = (uint8_t*)carve(sz_b);
+    a.bmask = (uint32_t*)carve(sz_bm);
+    char* tab = carve(sz_tab);
+    a.tricode = (const int32_t*)tab;
+    a.p4code = a.tricode + T.tricode.size();
+    a.s3code = a.p4code + T.p4code.size();
+    a.counts = (uint32_t*)carve(sz_cnt);
+    a.scratch = (uint64_t*)carve(sz_scr);
+    std::vector<int32_t> tabs;
+    tabs.insert(tabs.end(), T.tricode.begin(), T.tricode.end());
+    tabs.insert(tabs.end(), T.p4code.begin(), T.p4code.end());
+    tabs.insert(tabs.end(), T.s3code.begin(), T.s3code.end());
+    int rc = PM_OK;
+    std::vector<uint32_t> counts(nslots * 4);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        if (hipMemcpyAsync(tab, tabs.data(), 4 * tabs.size(), hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+            launch_zero(a.counts, nslots * 4, c.stream)) {
+            rc = fail(PM_E_DEVICE, "FSM setup failed");
+            break;
+        }
+        hipEventCreate(&e0);
+        hipEventCreate(&e1);
+        hipEventRecord(e0, c.stream);
+        if (launch_fsm(a, grid, c.stream)) {
+            rc = fail(PM_E_DEVICE, "FSM kernel launch failed");
+            break;
+        }
+        hipEventRecord(e1, c.stream);
+        if (hipMemcpyAsync(counts.data(), a.counts, sz_cnt, hipMemcpyDeviceToHost, c.stream) != hipSuccess) {
+            rc = fail(PM_E_DEVICE, "FSM copy-back failed");
+            break;
+        }
+        hipError_t se = hipStreamSynchronize(c.stream);
+        if (se != hipSuccess) {
+            rc = fail(PM_E_DEVICE, std::string("FSM kernels failed: ") + hipGetErrorString(se));
+            break;
+        }
+    } while (0);
+    float kms = 0;
+    if (e0 && e1 && rc == PM_OK) hipEventElapsedTime(&kms, e0, e1);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    c.arena.release(off);
+    if (rc) return rc;
+    // support = smallest domain over the distinct (non-automorphic) columns
+    for (uint64_t s = 0; s < nslots; ++s) {
+        const auto& sl = T.slots[s];
+        const uint32_t* cc = &counts[s * 4];
+        uint32_t sup;
+        if (sl[0] == 0) {
+            sup = cc[0];
+            if (sl[2] != sl[1]) sup = std::min(sup, cc[1]);
+            if (sl[3] != sl[2]) sup = std::min(sup, cc[2]);
+        } else if (sl[0] == 1) {
+            bool pal = sl[1] == sl[4] && sl[2] == sl[3];
+            sup = std::min(cc[0], cc[1]);
+            if (!pal) sup = std::min(sup, std::min(cc[2], cc[3]));
+        } else {
+            sup = std::min(cc[0], cc[1]);
+            if (sl[3] != sl[2]) sup = std::min(sup, cc[2]);
+            if (sl[4] != sl[3]) sup = std::min(sup, cc[3]);
+        }
+        out_support[s] = sup;
+        if (out_frequent) out_frequent[s] = (int64_t)sup >= threshold ? 1 : 0;
+    }
+    pm_query_stats st{};
+    st.kernel_ms = kms;
+    st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.launches = 3;
+    st.num_alt = (uint32_t)nslots;
+    c.last_stats = st;
+    return PM_OK;
 }
 
 }  // extern "C"

@@ -72,6 +72,7 @@ struct GraphRes {
     uint32_t n = 0;
     uint64_t m = 0;
     bool labeled = false;
+    uint32_t max_label = 0;
     uint32_t max_deg = 0, max_out = 0;
     GraphStats st;
     uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_split = UINT64_MAX, off_lab = UINT64_MAX,

@@ -260,3 +260,17 @@ def test_planted_mistake_is_caught():
     bad[names["cycle4"]] = ei[names["cycle4"]] - good[names["diamond"]]  # drop 3*K4
     if vi[names["clique4"]]:
         assert bad != vi
+
+
+def test_mni_rooted_search_equals_full_enumeration():
+    """The rooted-existence column sizes equal the domains of the full
+    match enumeration (two independent routes to the same definition)."""
+    g = gen.erdos_renyi(30, 0.15, 12).with_labels(gen.zipf_labels(30, 3, 1.2, 13))
+    rng = np.random.default_rng(2)
+    for k in (3, 4):
+        for m in P.connected_classes(k):
+            labs = [int(x) for x in rng.integers(0, 3, size=k)]
+            dom = oracle.mni_domains(g, k, m, False, labs)
+            for v in range(k):
+                assert oracle.mni_column(g, k, m, False, labs, v) == int(dom[v].sum())
+            assert oracle.mni_support_rooted(g, k, m, False, labs) == oracle.mni_support(g, k, m, False, labs)
