@@ -19,3 +19,4 @@ from .graphs import (  # noqa: F401
     graph_from_mask,
     sha256_of,
 )
+from .queries import Query, connected_masks, query_stream  # noqa: F401

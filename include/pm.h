@@ -66,8 +66,12 @@ enum { PM_AGG_COUNT = 0, PM_AGG_MNI = 1 };
 /* Morph mode: NONE matches the query patterns as given ("No PMR",
  * Section 4.2); NAIVE matches the alternative set of Section 4.2's "Naive
  * PMR": vertex-induced patterns become their same-size edge-induced
- * superpatterns plus the clique, converted back by Corollary 3.1. */
-enum { PM_MORPH_NONE = 0, PM_MORPH_NAIVE = 1 };
+ * superpatterns plus the clique, converted back by Corollary 3.1; COST
+ * morphs a vertex-induced pattern only when the engine's cost model (plan
+ * work estimated from the graph's degree statistics, Section 4.1's three
+ * factors) rates its superpatterns cheaper than the pattern itself.
+ * pm_morph_plan has no graph and treats COST as NAIVE. */
+enum { PM_MORPH_NONE = 0, PM_MORPH_NAIVE = 1, PM_MORPH_COST = 2 };
 
 typedef struct {
     uint32_t k;          /* number of pattern vertices, 2..5                 */
@@ -147,7 +151,9 @@ pm_status pm_wait(pm_ctx* ctx, uint64_t ticket, int64_t* out_values,
 /* Optional statistics of the last pm_wait'ed query (call before the next). */
 pm_status pm_last_query_stats(pm_ctx* ctx, pm_query_stats* out);
 
-/* Request cancellation; the kernel drains its remaining work items. */
+/* Request cancellation: the query's kernels stop taking work items (a
+ * host-visible flag polled once per item) and the later pm_wait returns
+ * PM_E_CANCELLED.  PM_E_NOTFOUND for an unknown ticket. */
 pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket);
 
 /* Host-only morph planning (Section 4.1 (a); Section 4.2 "Naive PMR").
@@ -204,6 +210,58 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value);
  * Errors: as pm_submit. */
 pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
                       uint32_t npat, int32_t morph, int64_t* out_cfg, double* out_ms);
+
+/* ---- serving ----------------------------------------------------------
+ * A request loop over resident graphs (continuous batching).  pm_serve
+ * replays a request trace in real time: request i becomes visible at
+ * arrival_s seconds after the call starts.  Pending requests are admitted
+ * in arrival order into up to max_slots slots, each with its own HIP
+ * stream: the requests pending on the same graph as the oldest one (up to
+ * max_batch) form one batch whose patterns are matched in a single
+ * multi-pattern launch; a batch is admitted only while the arena bytes of
+ * all in-flight batches stay within budget_bytes.  Batches run
+ * concurrently on the device, and a finished slot is refilled at once.
+ * Latency of a request = completion time - scheduled arrival (queueing
+ * included).  Not to be called concurrently with other calls on the same
+ * context.  Results are identical to pm_submit/pm_wait of the same
+ * request alone. */
+#define PM_SERVE_MAX_PATTERNS 8
+typedef struct {
+    double arrival_s;       /* scheduled arrival, seconds from the start  */
+    uint32_t graph_id;
+    uint32_t npat;          /* 1 .. PM_SERVE_MAX_PATTERNS                 */
+    int32_t morph;          /* PM_MORPH_*                                 */
+    pm_pattern pats[PM_SERVE_MAX_PATTERNS];
+} pm_serve_request;
+
+typedef struct {
+    double latency_s;       /* completion - scheduled arrival             */
+    double queue_s;         /* admission - scheduled arrival              */
+    int32_t status;         /* PM_OK or the error of this request         */
+    uint32_t batch_size;    /* requests in the batch it ran in            */
+    int64_t values[PM_SERVE_MAX_PATTERNS];
+} pm_serve_result;
+
+typedef struct {
+    uint32_t max_slots;     /* batches in flight (>= 1)                   */
+    uint32_t max_batch;     /* requests merged into one batch (>= 1)      */
+    uint64_t budget_bytes;  /* arena bytes for in-flight batches          */
+    double deadline_s;      /* > 0: a batch still running this long after
+                               admission is cancelled and its requests end
+                               with PM_E_TIMEOUT; 0 = no deadline          */
+} pm_serve_config;
+
+typedef struct {
+    double p50_s, p99_s, mean_s, max_s;  /* latency, nearest rank        */
+    double makespan_s;                   /* first arrival to last done    */
+    double matches_per_s;                /* sum of all values / makespan  */
+    double mean_inflight;                /* batches in flight at admissions */
+    uint64_t batches, completed, failed, timeouts;
+} pm_serve_stats;
+
+pm_status pm_serve(pm_ctx* ctx, const pm_serve_request* reqs, uint32_t nreq,
+                   const pm_serve_config* cfg, pm_serve_result* out_results,
+                   pm_serve_stats* out_stats);
 
 /* Writes a NUL-terminated description of the matching plan the engine
  * compiles for `pat` on graph `graph_id` (core order, per-level set

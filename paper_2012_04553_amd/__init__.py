@@ -7,6 +7,7 @@ from .binding import (  # noqa: F401
     AGG_COUNT,
     AGG_MNI,
     EDGE_INDUCED,
+    MORPH_COST,
     MORPH_NAIVE,
     MORPH_NONE,
     VERTEX_INDUCED,

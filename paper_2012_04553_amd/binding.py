@@ -21,7 +21,7 @@ STATUS = {0: "PM_OK", -1: "PM_E_INVAL", -2: "PM_E_NOMEM", -3: "PM_E_OVERFLOW",
           -8: "PM_E_CANCELLED", -9: "PM_E_NOTFOUND"}
 EDGE_INDUCED, VERTEX_INDUCED = 0, 1
 AGG_COUNT, AGG_MNI = 0, 1
-MORPH_NONE, MORPH_NAIVE = 0, 1
+MORPH_NONE, MORPH_NAIVE, MORPH_COST = 0, 1, 2
 
 
 class PMError(RuntimeError):
@@ -46,6 +46,34 @@ class pm_query_stats(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64),
                 ("work_items", ctypes.c_uint64), ("num_alt", ctypes.c_uint32),
                 ("launches", ctypes.c_uint32)]
+
+
+SERVE_MAX_PATTERNS = 8
+
+
+class pm_serve_request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("graph_id", ctypes.c_uint32),
+                ("npat", ctypes.c_uint32), ("morph", ctypes.c_int32),
+                ("pats", pm_pattern * SERVE_MAX_PATTERNS)]
+
+
+class pm_serve_result(ctypes.Structure):
+    _fields_ = [("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double),
+                ("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32),
+                ("values", ctypes.c_int64 * SERVE_MAX_PATTERNS)]
+
+
+class pm_serve_config(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_uint64), ("deadline_s", ctypes.c_double)]
+
+
+class pm_serve_stats(ctypes.Structure):
+    _fields_ = [("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("max_s", ctypes.c_double), ("makespan_s", ctypes.c_double),
+                ("matches_per_s", ctypes.c_double), ("mean_inflight", ctypes.c_double),
+                ("batches", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("timeouts", ctypes.c_uint64)]
 
 
 # name -> (restype, argtypes) for every function declared in include/pm.h
@@ -79,6 +107,9 @@ SIGNATURES = {
                                      _i64p, ctypes.POINTER(ctypes.c_double)]),
     "pm_plan_describe": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_char_p,
                                           ctypes.c_uint64]),
+    "pm_serve": (ctypes.c_int32, [_P, ctypes.POINTER(pm_serve_request), ctypes.c_uint32,
+                                  ctypes.POINTER(pm_serve_config), ctypes.POINTER(pm_serve_result),
+                                  ctypes.POINTER(pm_serve_stats)]),
     "pm_last_error": (ctypes.c_char_p, []),
     "pm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
 }
@@ -248,6 +279,40 @@ class Engine:
         check(lib().pm_fsm(self.ctx, gid, num_labels, threshold, morph,
                            sup.ctypes.data_as(_i64p), freq.ctypes.data_as(_u8p), ns))
         return sup, freq
+
+    def cancel(self, ticket: int):
+        check(lib().pm_cancel(self.ctx, ticket))
+
+    def serve(self, requests, max_slots=8, max_batch=8, budget_bytes=None, deadline_s=0.0):
+        """Replay a request trace through the serving loop.
+
+        requests: [(arrival_s, graph_id, [(k, mask, induced, labels), ...], morph)]
+        Returns (per-request dicts, stats dict)."""
+        n = len(requests)
+        arr = (pm_serve_request * n)()
+        for i, (t, gid, pats, morph) in enumerate(requests):
+            r = arr[i]
+            r.arrival_s = float(t)
+            r.graph_id = gid
+            r.npat = len(pats)
+            r.morph = morph
+            for j, p in enumerate(pats):
+                r.pats[j] = p if isinstance(p, pm_pattern) else make_pattern(*p)
+        cfg = pm_serve_config()
+        cfg.max_slots = max_slots
+        cfg.max_batch = max_batch
+        cfg.budget_bytes = budget_bytes if budget_bytes is not None else self.arena.numel() // 2
+        cfg.deadline_s = deadline_s
+        res = (pm_serve_result * n)()
+        st = pm_serve_stats()
+        check(lib().pm_serve(self.ctx, arr, n, ctypes.byref(cfg), res, ctypes.byref(st)))
+        out = []
+        for i in range(n):
+            R = res[i]
+            out.append({"latency_s": R.latency_s, "queue_s": R.queue_s, "status": R.status,
+                        "batch_size": R.batch_size,
+                        "values": [int(R.values[j]) for j in range(arr[i].npat)]})
+        return out, {f: getattr(st, f) for f, _ in pm_serve_stats._fields_}
 
     def plan_describe(self, gid, pat) -> str:
         buf = ctypes.create_string_buffer(8192)

@@ -10,6 +10,7 @@
 // "Naive PMR": vertex-induced queries are answered from edge-induced counts
 // of their superpatterns (and the clique).
 #include <algorithm>
+#include <functional>
 #include <map>
 
 #include "internal.hpp"
@@ -129,7 +130,8 @@ static std::vector<Pat> superpatterns(const Pat& p) {
     return out;
 }
 
-int morph_plan_count(const std::vector<Pat>& qs, int morph, MorphPlan* out, std::string* err) {
+int morph_plan_count(const std::vector<Pat>& qs, int morph, MorphPlan* out, std::string* err,
+                     const std::function<double(const Pat&)>& cost) {
     out->alt.clear();
     out->matrix.clear();
     std::vector<std::vector<std::pair<Pat, int64_t>>> rows(qs.size());
@@ -142,6 +144,17 @@ int morph_plan_count(const std::vector<Pat>& qs, int morph, MorphPlan* out, std:
         }
         // lattice over the edge-induced superpatterns, most edges first
         std::vector<Pat> L = superpatterns(p);
+        if (morph == PM_MORPH_COST) {
+            // Section 4.1 cost-based choice: morph only when matching the
+            // edge-induced superpatterns is estimated cheaper than matching
+            // the vertex-induced pattern itself
+            double plain = cost ? cost(p) : 0.0, morphed = 0.0;
+            for (const Pat& q : L) morphed += cost ? cost(q) : 0.0;
+            if (cost && plain <= morphed) {
+                rows[i].push_back({p, 1});
+                continue;
+            }
+        }
         std::sort(L.begin(), L.end(), [](const Pat& a, const Pat& b) {
             int ea = popc(a.em), eb = popc(b.em);
             if (ea != eb) return ea > eb;

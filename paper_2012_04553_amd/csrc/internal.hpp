@@ -2,6 +2,7 @@
 #pragma once
 #include <array>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -53,7 +54,8 @@ struct MorphPlan {
     std::vector<Pat> alt;
     std::vector<int64_t> matrix;   // row-major npat x alt.size()
 };
-int morph_plan_count(const std::vector<Pat>& q, int morph, MorphPlan* out, std::string* err);
+int morph_plan_count(const std::vector<Pat>& q, int morph, MorphPlan* out, std::string* err,
+                     const std::function<double(const Pat&)>& cost = nullptr);
 // combine alternative counts: out[i] = sum_j matrix[i][j]*alt[j]; checked int64
 int unmorph(const MorphPlan& mp, size_t npat, const std::vector<int64_t>& alt_counts,
             std::vector<int64_t>* out, std::string* err);

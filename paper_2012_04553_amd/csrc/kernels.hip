@@ -499,6 +499,16 @@ __device__ __forceinline__ void lanes_finish(Ctx& c, int j, uint32_t b, uint32_t
     }
 }
 
+// Cancellation: the host sets a coherent flag; lane 0 reads it every 16th
+// call (root or level-1 step), so an abandoned item ends within a few of its
+// iterations.  Wave-uniform.
+__device__ __forceinline__ bool should_stop(const KArgs& a, uint32_t& tick) {
+    if (!a.cancel || ((++tick) & 15u)) return false;
+    uint32_t stop = 0;
+    if (wave_lane() == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
+    return bcast(stop) != 0;
+}
+
 template <bool BYTES>
 __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     __shared__ uint32_t s_touch[4];
@@ -512,13 +522,21 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     c.bytes = 0;
     int cur = -1;
     u128 acc = 0;
+    uint32_t tick = 0;
+    bool stopped = false;
     const uint64_t total = (uint64_t)a.nplans * a.nitems;
     for (;;) {
+        if (stopped) break;
         uint32_t it = 0;
         if (lane == 0) it = atomicAdd(a.head, 1u);
         it = bcast(it);
         if (it >= total) break;
-        if (a.cancel && *(volatile const int*)a.cancel) break;
+        if (a.cancel) {
+            // host-visible flag: one read per work item, by one lane
+            uint32_t stop = 0;
+            if (lane == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
+            if (bcast(stop)) break;
+        }
         const int pi = (int)(it / a.nitems);
         const KItem item = a.items[it % a.nitems];
         if (pi != cur) {
@@ -543,6 +561,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             continue;
         }
         for (uint32_t r = item.r0; r < item.r1; ++r) {
+            if (stopped || should_stop(a, tick)) {
+                stopped = true;
+                break;
+            }
             if (rl >= 0 && a.g.lab[r] != (uint8_t)rl) continue;
             c.v[0] = r;
             if (P->local) {
@@ -578,6 +600,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             if (pen == 1) {
                 if (P->agg_last) {
                     for (uint32_t q = pos[1]; q < end[1]; ++q) {
+                        if (should_stop(a, tick)) {
+                            stopped = true;
+                            break;
+                        }
                         c.v[1] = c.buf[c.stride + q];
                         agg_level<BYTES>(c, 2, wid, my_touch, a, acc);
                     }
@@ -591,6 +617,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                 if (pos[j] >= end[j]) {
                     --j;
                     continue;
+                }
+                if (j == 1 && should_stop(a, tick)) {
+                    stopped = true;
+                    break;
                 }
                 c.v[j] = c.buf[(uint64_t)j * c.stride + pos[j]];
                 ++pos[j];

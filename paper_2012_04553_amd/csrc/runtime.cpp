@@ -33,11 +33,6 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
-#define HIPCHK(x)                                                                          \
-    do {                                                                                   \
-        hipError_t e_ = (x);                                                               \
-        if (e_ != hipSuccess) return fail(PM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 // ---------------------------------------------------------------- arena
 
@@ -289,7 +284,7 @@ int Ctx_::graph_unload(uint32_t gid) {
 
 // ---------------------------------------------------------------- queries
 
-static int to_pat(const pm_pattern& q, Pat* out, std::string* err) {
+int to_pat(const pm_pattern& q, Pat* out, std::string* err) {
     if (q.k < 2 || q.k > (uint32_t)KMAX) {
         *err = "pattern size must be 2..5";
         return PM_E_UNSUPPORTED;
@@ -338,6 +333,14 @@ const PlanInfo& Ctx_::plan_for(GraphRes& G, const Pat& p, int* rc) {
     if (*rc) g_err = err;
     G.plan_cache.push_back({p, pi});
     return G.plan_cache.back().second;
+}
+
+std::function<double(const Pat&)> Ctx_::cost_fn(GraphRes& G) {
+    return [this, &G](const Pat& p) {
+        int rc;
+        const PlanInfo& pi = plan_for(G, p, &rc);
+        return rc ? 1e300 : pi.total_cost;
+    };
 }
 
 int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
@@ -455,7 +458,10 @@ void Ctx_::free_launchset(LaunchSet* ls) {
     if (!ls) return;
     if (ls->exec) hipGraphExecDestroy(ls->exec);
     if (ls->graph) hipGraphDestroy(ls->graph);
-    if (ls->host) hipHostFree(ls->host);
+    if (ls->host && !ls->borrowed_host) hipHostFree(ls->host);
+    if (ls->cancel_host && !ls->borrowed_host) hipHostFree(ls->cancel_host);
+    ls->cancel_host = nullptr;
+    ls->cancel_dev = nullptr;
     if (ls->off_mem != UINT64_MAX) arena.release(ls->off_mem);
     ls->exec = nullptr;
     ls->graph = nullptr;
@@ -463,16 +469,19 @@ void Ctx_::free_launchset(LaunchSet* ls) {
     ls->off_mem = UINT64_MAX;
 }
 
-int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg, LaunchSet* ls) {
+int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg, LaunchSet* ls,
+                         hipStream_t st, const AggArrays* agg) {
     const size_t np = plans.size();
+    if (!st) st = stream;
     ls->np = np;
     ls->cfg = cfg;
     uint64_t need = footprint(G, plans, cfg, &ls->stride, &ls->any_agg);
     HIPCHK(hipSetDevice(device));
-    if (ls->any_agg) {
+    if (ls->any_agg && !agg) {
         int rc = ensure_agg(G.n, cfg);
         if (rc) return rc;
     }
+    if (ls->any_agg && agg && agg->n < G.n) return fail(PM_E_NOMEM, "slot aggregation arrays too small");
     ItemSet* is;
     int rc = get_items(G, cfg, &is);
     if (rc) return rc;
@@ -495,9 +504,29 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->scratch = (uint32_t*)carve(waves(cfg) * (uint64_t)KMAX * ls->stride * 4);
     std::vector<DPlan> hp(np);
     for (size_t i = 0; i < np; ++i) hp[i] = plans[i].d;
-    HIPCHK(hipMemcpyAsync(ls->dplans, hp.data(), sizeof(DPlan) * np, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    HIPCHK(hipHostMalloc((void**)&ls->host, 16 * np + 64, hipHostMallocDefault));
+    if (agg && agg->stage) {
+        // pinned staging: a pageable upload could wait for other streams
+        if (agg->stage_bytes < sizeof(DPlan) * np) return fail(PM_E_NOMEM, "slot staging buffer too small");
+        // no synchronisation: the slot's stream orders the upload before the
+        // launches, and the slot reuses the staging only after its event
+        memcpy(agg->stage, hp.data(), sizeof(DPlan) * np);
+        HIPCHK(hipMemcpyAsync(ls->dplans, agg->stage, sizeof(DPlan) * np, hipMemcpyHostToDevice, st));
+    } else {
+        HIPCHK(hipMemcpyAsync(ls->dplans, hp.data(), sizeof(DPlan) * np, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (agg && agg->host) {
+        if (agg->host_words < 2 * np + 8) return fail(PM_E_NOMEM, "slot result buffer too small");
+        ls->host = agg->host;
+        ls->cancel_host = agg->cancel_host;
+        ls->cancel_dev = agg->cancel_dev;
+        ls->borrowed_host = true;
+    } else {
+        HIPCHK(hipHostMalloc((void**)&ls->host, 16 * np + 64, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&ls->cancel_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer((void**)&ls->cancel_dev, ls->cancel_host, 0));
+    }
+    __atomic_store_n(ls->cancel_host, 0, __ATOMIC_SEQ_CST);
     KArgs& a = ls->base;
     memset(&a, 0, sizeof(a));
     a.g.rp = (const uint32_t*)dptr(G.off_rp);
@@ -510,10 +539,17 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     a.scratch = ls->scratch;
     a.buf_stride = ls->stride;
     a.bytes = ls->bytes;
-    a.cancel = nullptr;
+    a.cancel = ls->cancel_dev;
     if (ls->any_agg) {
-        a.aggcnt = (uint32_t*)dptr(agg_off);
-        a.aggtouch = (uint32_t*)dptr(agg_touch_off);
+        if (agg) {
+            a.aggcnt = agg->cnt;
+            a.aggtouch = agg->touch;
+            ls->agg_w = agg->waves;
+        } else {
+            a.aggcnt = (uint32_t*)dptr(agg_off);
+            a.aggtouch = (uint32_t*)dptr(agg_touch_off);
+            ls->agg_w = agg_waves(cfg);
+        }
     }
     ls->runs.clear();
     ls->run_agg.clear();
@@ -541,7 +577,7 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         b.nplans = ls.runs[r].second - ls.runs[r].first;
         b.counters = ls.counters + 2 * ls.runs[r].first;
         b.head = ls.heads + r;
-        int gb = ls.run_agg[r] ? (int)std::max<uint64_t>(1, agg_waves(cfg) / (block / 64)) : grid_blocks(cfg);
+        int gb = ls.run_agg[r] ? (int)std::max<uint64_t>(1, ls.agg_w / (block / 64)) : grid_blocks(cfg);
         if (launch_match(b, gb, block, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
     }
     if (bytes_pass) {
@@ -593,7 +629,7 @@ int Ctx_::autotune(uint32_t gid, const pm_pattern* pats, uint32_t npat, int morp
     }
     MorphPlan mp;
     std::string err;
-    int rc = morph_plan_count(ps, morph, &mp, &err);
+    int rc = morph_plan_count(ps, morph, &mp, &err, cost_fn(*G));
     if (rc) return fail(rc, err);
     std::vector<Pat> closure;
     std::vector<PlanInfo> plans;
@@ -676,7 +712,8 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
     auto t0 = std::chrono::steady_clock::now();
     if (!pats || !ticket || npat == 0) return fail(PM_E_INVAL, "null patterns or ticket");
     if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "pm_submit supports PM_AGG_COUNT; use pm_fsm for MNI");
-    if (morph != PM_MORPH_NONE && morph != PM_MORPH_NAIVE) return fail(PM_E_INVAL, "unknown morph mode");
+    if (morph != PM_MORPH_NONE && morph != PM_MORPH_NAIVE && morph != PM_MORPH_COST)
+        return fail(PM_E_INVAL, "unknown morph mode");
     GraphRes* G;
     {
         std::lock_guard<std::mutex> g(mu);
@@ -696,7 +733,7 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
             if (ps[i].lab[v] >= 0 && !G->labeled) return fail(PM_E_INVAL, "labeled pattern on an unlabeled graph");
     }
     std::string err;
-    int rc = morph_plan_count(ps, morph, &Q->mp, &err);
+    int rc = morph_plan_count(ps, morph, &Q->mp, &err, cost_fn(*G));
     if (rc) return fail(rc, err);
     rc = plan_closure(*G, Q->mp.alt, &Q->closure, &Q->plans);
     if (rc) return fail(rc, g_err);
@@ -776,6 +813,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     if (ls) {
         ls->busy = true;
         Q.ls = ls;
+        *(volatile int*)ls->cancel_host = 0;
         HIPCHK(hipGraphLaunch(ls->exec, stream));
     } else {
         int rc = enqueue(*Q.own, stream, false);
@@ -865,6 +903,7 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
             alt[j] = (int64_t)cnt[i];
         }
     std::vector<int64_t> res;
+    if (rc == PM_OK && Q->cancelled) rc = fail(PM_E_CANCELLED, "query cancelled");
     if (rc == PM_OK) {
         std::string err;
         rc = unmorph(Q->mp, Q->npat, alt, &res, &err);
@@ -977,7 +1016,7 @@ pm_status pm_query_footprint(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, 
     }
     MorphPlan mp;
     std::string err;
-    int rc = morph_plan_count(ps, morph, &mp, &err);
+    int rc = morph_plan_count(ps, morph, &mp, &err, ctx->c.cost_fn(*G));
     if (rc) return fail(rc, err);
     std::vector<PlanInfo> plans;
     std::vector<Pat> closure;
@@ -1013,8 +1052,13 @@ pm_status pm_last_query_stats(pm_ctx* ctx, pm_query_stats* out) {
 pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket) {
     if (!ctx) return fail(PM_E_INVAL, "null ctx");
     std::lock_guard<std::mutex> g(ctx->c.mu);
-    if (!ctx->c.queries.count(ticket)) return fail(PM_E_NOTFOUND, "unknown ticket");
-    return fail(PM_E_UNSUPPORTED, "cancellation is not supported for batch queries");
+    auto it = ctx->c.queries.find(ticket);
+    if (it == ctx->c.queries.end()) return fail(PM_E_NOTFOUND, "unknown ticket");
+    Query& Q = *it->second;
+    LaunchSet* ls = Q.ls ? Q.ls : Q.own.get();
+    if (ls && ls->cancel_host) __atomic_store_n(ls->cancel_host, 1, __ATOMIC_SEQ_CST);
+    Q.cancelled = true;
+    return PM_OK;
 }
 
 pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg, int32_t morph, pm_pattern* out_alt,
@@ -1100,6 +1144,16 @@ pm_status pm_plan_describe(pm_ctx* ctx, uint32_t gid, const pm_pattern* pat, cha
     std::string s = pi.describe();
     snprintf(buf, cap, "%s", s.c_str());
     return PM_OK;
+}
+
+pm_status pm_serve(pm_ctx* ctx, const pm_serve_request* reqs, uint32_t nreq, const pm_serve_config* cfg,
+                   pm_serve_result* out_results, pm_serve_stats* out_stats) {
+    if (!ctx) return fail(PM_E_INVAL, "null ctx");
+    try {
+        return ctx->c.serve(reqs, nreq, cfg, out_results, out_stats);
+    } catch (const std::exception& e) {
+        return fail(PM_E_NOMEM, std::string("host allocation failed: ") + e.what());
+    }
 }
 
 pm_status pm_autotune(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, uint32_t npat, int32_t morph,

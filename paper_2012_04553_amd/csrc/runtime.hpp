@@ -19,6 +19,14 @@ namespace pm {
 extern thread_local std::string g_err;
 int fail(int code, const std::string& msg);
 
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(PM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int to_pat(const pm_pattern& q, Pat* out, std::string* err);
+
 // First-fit sub-allocator over the caller's device arena (offsets).
 struct Arena {
     uintptr_t base = 0;
@@ -41,6 +49,7 @@ struct LaunchCfg {
     int blocks_per_cu = 4;
     uint64_t item_budget = 4096;
     uint32_t item_split = 2048;
+    int grid_override = 0;   // > 0: blocks of the match launch (a GPU share)
 };
 
 // Device state of one (graph, plan closure, launch configuration): plans,
@@ -62,6 +71,10 @@ struct LaunchSet {
     std::vector<std::pair<int, int>> runs;   // contiguous plan ranges, one launch each
     std::vector<int> run_agg;
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
+    uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
+    int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
+    int* cancel_dev = nullptr;
+    bool borrowed_host = false;              // host/cancel buffers owned by a serving slot
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool busy = false;
@@ -95,6 +108,7 @@ struct Query {
     LaunchSet* ls = nullptr;                 // cached launch set (busy while in flight)
     std::unique_ptr<LaunchSet> own;          // or one made for this query alone
     bool counted_bytes = false;
+    bool cancelled = false;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
     pm_query_stats stats{};
     std::chrono::steady_clock::time_point t_submit;
@@ -127,14 +141,36 @@ struct Ctx_ {
     std::vector<int64_t> last_alt;
 
     void* dptr(uint64_t off) const { return (void*)(arena.base + off); }
-    int grid_blocks(const LaunchCfg& c) const { return num_cus * c.blocks_per_cu; }
+    int grid_blocks(const LaunchCfg& c) const {
+        return c.grid_override > 0 ? c.grid_override : num_cus * c.blocks_per_cu;
+    }
     uint64_t waves(const LaunchCfg& c) const { return (uint64_t)grid_blocks(c) * (block / 64); }
     uint64_t agg_waves(const LaunchCfg& c) const { return std::min<uint64_t>(agg_waves_opt, waves(c)); }
     LaunchCfg default_cfg() const { return LaunchCfg{blocks_per_cu, item_budget, item_split}; }
     std::string closure_key(const GraphRes& G, const std::vector<Pat>& closure) const;
     LaunchCfg cfg_for(const GraphRes& G, const std::vector<Pat>& closure) const;
     int get_items(GraphRes& G, const LaunchCfg& c, ItemSet** out);
-    int make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, LaunchSet* ls);
+    // agg: per-wave dense counter arrays (aggcnt, aggtouch, waves) for the
+    // aggregation launches, or null to use the context's shared ones
+    struct AggArrays {
+        uint32_t* cnt = nullptr;
+        uint32_t* touch = nullptr;
+        uint64_t waves = 0;
+        uint32_t n = 0;
+        // optional pinned buffers reused across launch sets (pinned host
+        // allocation and release synchronise the device)
+        uint64_t* host = nullptr;
+        uint64_t host_words = 0;
+        int* cancel_host = nullptr;
+        int* cancel_dev = nullptr;
+        void* stage = nullptr;         // pinned staging for the plan upload
+        uint64_t stage_bytes = 0;
+    };
+    int make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, LaunchSet* ls,
+                       hipStream_t s = nullptr, const AggArrays* agg = nullptr);
+    std::function<double(const Pat&)> cost_fn(GraphRes& G);
+    int serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_config* cfg, pm_serve_result* res,
+              pm_serve_stats* stats);
     void free_launchset(LaunchSet* ls);
     int enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass);
     int run_eager_ms(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, double* ms);

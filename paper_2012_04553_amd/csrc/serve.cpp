@@ -1,0 +1,412 @@
+// Serving loop: continuous batching of pattern-set queries over resident
+// graphs (host side of pm_serve).
+//
+// One host thread runs the loop.  Each iteration (1) makes visible the
+// requests whose scheduled arrival has passed, (2) retires finished slots
+// (event query), converting the batch's closure counts into every request's
+// values with that request's own morph plan, and (3) admits new batches:
+// the oldest pending request and the other pending requests on the same
+// graph (up to max_batch) are planned together, and the batch is admitted
+// when a slot is free and its footprint fits the remaining byte budget.
+// Every slot owns a HIP stream (default priority) and dense two-hop
+// counter arrays, so batches in different slots run concurrently on the
+// device without sharing mutable memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "runtime.hpp"
+
+namespace pm {
+
+namespace {
+
+struct Batch {
+    std::vector<uint32_t> reqs;
+    std::vector<MorphPlan> mps;       // per request
+    std::vector<Pat> closure;
+    std::vector<PlanInfo> plans;
+    LaunchSet ls;
+    uint64_t bytes = 0;
+    double admitted = 0;
+    bool cancelled = false;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    uint64_t agg_off = UINT64_MAX, agg_touch_off = UINT64_MAX;
+    uint64_t* host = nullptr;     // pinned result words, reused by every batch
+    int* cancel_host = nullptr;   // pinned coherent cancel flag
+    int* cancel_dev = nullptr;
+    hipEvent_t done = nullptr;
+    void* stage = nullptr;        // pinned plan staging
+    std::unique_ptr<Batch> batch;
+};
+
+constexpr uint64_t SLOT_STAGE_BYTES = 1024 * sizeof(DPlan);
+
+constexpr uint64_t SLOT_HOST_WORDS = 2 * 1024 + 8;
+
+using Clock = std::chrono::steady_clock;
+
+// closure counts -> per-request values (quotient plans first: by k)
+int batch_values(const Batch& B, std::vector<std::vector<int64_t>>* out, std::string* err) {
+    const size_t np = B.plans.size();
+    std::vector<__int128> cnt(np, -1);
+    std::vector<size_t> order(np);
+    for (size_t i = 0; i < np; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return B.closure[a].k < B.closure[b].k; });
+    for (size_t i : order) {
+        const PlanInfo& pi = B.plans[i];
+        unsigned __int128 v = ((unsigned __int128)B.ls.host[2 * i + 1] << 64) | B.ls.host[2 * i];
+        __int128 c;
+        if (pi.rewrite) {
+            __int128 acc = (__int128)pi.hmult * (__int128)v;
+            for (auto& sq : pi.subs) {
+                size_t j = std::find(B.closure.begin(), B.closure.end(), sq.first) - B.closure.begin();
+                if (j >= np || cnt[j] < 0) {
+                    *err = "internal: quotient sub-pattern missing";
+                    return PM_E_DEVICE;
+                }
+                acc -= (__int128)sq.second * cnt[j];
+            }
+            if (acc < 0 || acc % pi.autp) {
+                *err = "internal: quotient combination not exact";
+                return PM_E_DEVICE;
+            }
+            c = acc / pi.autp;
+        } else {
+            if (v % (unsigned __int128)pi.divisor) {
+                *err = "internal: match total not divisible by the plan divisor";
+                return PM_E_DEVICE;
+            }
+            c = (__int128)(v / (unsigned __int128)pi.divisor);
+        }
+        if (c > (__int128)INT64_MAX) {
+            *err = "count exceeds int64";
+            return PM_E_OVERFLOW;
+        }
+        cnt[i] = c;
+    }
+    out->assign(B.reqs.size(), {});
+    for (size_t r = 0; r < B.reqs.size(); ++r) {
+        const MorphPlan& mp = B.mps[r];
+        std::vector<int64_t> alt(mp.alt.size());
+        for (size_t j = 0; j < alt.size(); ++j) {
+            size_t i = std::find(B.closure.begin(), B.closure.end(), mp.alt[j]) - B.closure.begin();
+            alt[j] = (int64_t)cnt[i];
+        }
+        size_t npat = mp.alt.empty() ? 0 : mp.matrix.size() / mp.alt.size();
+        int rc = unmorph(mp, npat, alt, &(*out)[r], err);
+        if (rc) return rc;
+    }
+    return PM_OK;
+}
+
+}  // namespace
+
+int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_config* cfg, pm_serve_result* res,
+                pm_serve_stats* stats) {
+    if (!reqs || !cfg || !res || nreq == 0) return fail(PM_E_INVAL, "null argument");
+    if (cfg->max_slots < 1 || cfg->max_batch < 1) return fail(PM_E_INVAL, "max_slots and max_batch must be >= 1");
+    HIPCHK(hipSetDevice(device));
+    // validate requests and resolve graphs
+    uint32_t maxn = 0;
+    std::vector<GraphRes*> gr(nreq, nullptr);
+    std::vector<std::vector<Pat>> pats(nreq);
+    for (uint32_t i = 0; i < nreq; ++i) {
+        memset(&res[i], 0, sizeof(res[i]));
+        const pm_serve_request& q = reqs[i];
+        if (q.npat < 1 || q.npat > PM_SERVE_MAX_PATTERNS) return fail(PM_E_INVAL, "request npat out of range");
+        if (i && q.arrival_s < reqs[i - 1].arrival_s) return fail(PM_E_INVAL, "arrivals must be non-decreasing");
+        auto it = graphs.find(q.graph_id);
+        if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id in request");
+        gr[i] = it->second.get();
+        maxn = std::max(maxn, gr[i]->n);
+        pats[i].resize(q.npat);
+        for (uint32_t k = 0; k < q.npat; ++k) {
+            std::string err;
+            int rc = to_pat(q.pats[k], &pats[i][k], &err);
+            if (rc) {
+                res[i].status = rc;
+                break;
+            }
+            for (int v = 0; v < pats[i][k].k; ++v)
+                if (pats[i][k].lab[v] >= 0 && !gr[i]->labeled) res[i].status = PM_E_INVAL;
+        }
+    }
+    // work items of every graph built up front (their upload synchronises)
+    for (uint32_t i = 0; i < nreq; ++i) {
+        ItemSet* is;
+        int irc = get_items(*gr[i], default_cfg(), &is);
+        if (irc) return irc;
+    }
+    // slots: stream + two-hop counter arrays sized for the largest graph
+    const uint64_t slot_agg_waves = 64;
+    std::vector<Slot> slots(cfg->max_slots);
+    int rc = PM_OK;
+    for (Slot& s : slots) {
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
+            rc = fail(PM_E_DEVICE, "stream creation failed");
+            break;
+        }
+        uint64_t need = slot_agg_waves * (uint64_t)maxn * 4;
+        s.agg_off = arena.alloc(need);
+        s.agg_touch_off = arena.alloc(need);
+        if (s.agg_off == UINT64_MAX || s.agg_touch_off == UINT64_MAX) {
+            rc = fail(PM_E_NOMEM, "arena too small for the serving slots");
+            break;
+        }
+        if (launch_zero((uint32_t*)dptr(s.agg_off), need / 4, s.stream)) {
+            rc = fail(PM_E_DEVICE, "zero-fill failed");
+            break;
+        }
+        if (hipHostMalloc((void**)&s.host, 8 * SLOT_HOST_WORDS, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&s.cancel_host, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&s.cancel_dev, s.cancel_host, 0) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(&s.stage, SLOT_STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
+            rc = fail(PM_E_DEVICE, "slot setup failed");
+            break;
+        }
+        HIPCHK(hipStreamSynchronize(s.stream));
+    }
+    auto cleanup = [&]() {
+        for (Slot& s : slots) {
+            if (s.batch) {
+                if (s.cancel_host) __atomic_store_n(s.cancel_host, 1, __ATOMIC_SEQ_CST);
+                hipStreamSynchronize(s.stream);
+                free_launchset(&s.batch->ls);
+            }
+        }
+        for (Slot& s : slots) {
+            if (s.agg_off != UINT64_MAX) arena.release(s.agg_off);
+            if (s.agg_touch_off != UINT64_MAX) arena.release(s.agg_touch_off);
+            if (s.done) hipEventDestroy(s.done);
+            if (s.host) hipHostFree(s.host);
+            if (s.cancel_host) hipHostFree(s.cancel_host);
+            if (s.stage) hipHostFree(s.stage);
+            if (s.stream) hipStreamDestroy(s.stream);
+        }
+    };
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+
+    std::deque<uint32_t> pending;
+    uint32_t next = 0, finished = 0;
+    uint64_t used = 0, batches = 0;
+    double inflight_sum = 0;
+    uint64_t admissions = 0;
+    const Clock::time_point t0 = Clock::now();
+    auto now_s = [&]() { return std::chrono::duration<double>(Clock::now() - t0).count(); };
+    // requests already failed at validation
+    for (uint32_t i = 0; i < nreq; ++i)
+        if (res[i].status) {
+            res[i].latency_s = 0;
+            ++finished;
+        }
+    double last_done = 0;
+    while (finished < nreq && rc == PM_OK) {
+        const double t = now_s();
+        while (next < nreq && reqs[next].arrival_s <= t) {
+            if (!res[next].status) pending.push_back(next);
+            ++next;
+        }
+        bool progressed = false;
+        // retire finished batches; cancel those past the deadline
+        for (Slot& s : slots) {
+            if (!s.batch) continue;
+            hipError_t e = hipEventQuery(s.done);
+            if (e == hipErrorNotReady) {
+                if (cfg->deadline_s > 0 && !s.batch->cancelled && t - s.batch->admitted > cfg->deadline_s) {
+                    __atomic_store_n(s.batch->ls.cancel_host, 1, __ATOMIC_SEQ_CST);
+                    s.batch->cancelled = true;
+                }
+                continue;
+            }
+            Batch& B = *s.batch;
+            const double tdone = now_s();
+            std::vector<std::vector<int64_t>> vals;
+            std::string err;
+            int brc = e == hipSuccess ? (B.cancelled ? PM_E_TIMEOUT : batch_values(B, &vals, &err)) : PM_E_DEVICE;
+            for (size_t r = 0; r < B.reqs.size(); ++r) {
+                pm_serve_result& R = res[B.reqs[r]];
+                R.status = brc;
+                R.latency_s = tdone - reqs[B.reqs[r]].arrival_s;
+                R.batch_size = (uint32_t)B.reqs.size();
+                if (brc == PM_OK)
+                    for (size_t k = 0; k < vals[r].size(); ++k) R.values[k] = vals[r][k];
+                ++finished;
+            }
+            last_done = std::max(last_done, tdone);
+            used -= B.bytes;
+            free_launchset(&B.ls);
+            s.batch.reset();
+            progressed = true;
+            if (e != hipSuccess) {
+                rc = fail(PM_E_DEVICE, std::string("serving batch failed: ") + hipGetErrorString(e));
+                break;
+            }
+        }
+        // admit batches while a slot is free and the budget allows
+        while (!pending.empty() && rc == PM_OK) {
+            Slot* free_slot = nullptr;
+            int busy = 0;
+            for (Slot& s : slots) {
+                if (s.batch) ++busy;
+                else if (!free_slot) free_slot = &s;
+            }
+            if (!free_slot) break;
+            const uint32_t head = pending.front();
+            GraphRes& G = *gr[head];
+            auto B = std::make_unique<Batch>();
+            for (auto it = pending.begin(); it != pending.end() && B->reqs.size() < cfg->max_batch; ++it)
+                if (gr[*it] == &G) B->reqs.push_back(*it);
+            // plan every request, union the closures
+            bool bad = false;
+            std::vector<Pat> alts;
+            for (uint32_t r : B->reqs) {
+                MorphPlan mp;
+                std::string err;
+                int prc = morph_plan_count(pats[r], reqs[r].morph, &mp, &err, cost_fn(G));
+                if (prc) {
+                    res[r].status = prc;
+                    bad = true;
+                }
+                B->mps.push_back(mp);
+                for (const Pat& a : mp.alt)
+                    if (std::find(alts.begin(), alts.end(), a) == alts.end()) alts.push_back(a);
+            }
+            if (bad) {
+                // drop the failed requests from the pending queue, try again
+                for (uint32_t r : B->reqs)
+                    if (res[r].status) {
+                        pending.erase(std::find(pending.begin(), pending.end(), r));
+                        res[r].latency_s = now_s() - reqs[r].arrival_s;
+                        ++finished;
+                    }
+                continue;
+            }
+            int prc = plan_closure(G, alts, &B->closure, &B->plans);
+            if (prc) {
+                rc = prc;
+                break;
+            }
+            LaunchCfg lc = cfg_for(G, B->closure);
+            // a persistent launch holds its CUs until its queue drains: give
+            // each slot a share of the GPU so batches really run side by side
+            lc.grid_override = std::max(1, (int)(num_cus * 2 / cfg->max_slots));
+            uint64_t stride;
+            bool any_agg;
+            B->bytes = footprint(G, B->plans, lc, &stride, &any_agg);
+            if (B->bytes > cfg->budget_bytes) {
+                for (uint32_t r : B->reqs) {
+                    res[r].status = PM_E_NOMEM;
+                    res[r].latency_s = now_s() - reqs[r].arrival_s;
+                    pending.erase(std::find(pending.begin(), pending.end(), r));
+                    ++finished;
+                }
+                continue;
+            }
+            if (used + B->bytes > cfg->budget_bytes) break;  // wait for memory
+            AggArrays ag;
+            ag.cnt = (uint32_t*)dptr(free_slot->agg_off);
+            ag.touch = (uint32_t*)dptr(free_slot->agg_touch_off);
+            ag.waves = slot_agg_waves;
+            ag.n = maxn;
+            ag.host = free_slot->host;
+            ag.host_words = SLOT_HOST_WORDS;
+            ag.cancel_host = free_slot->cancel_host;
+            ag.cancel_dev = free_slot->cancel_dev;
+            ag.stage = free_slot->stage;
+            ag.stage_bytes = SLOT_STAGE_BYTES;
+            int mrc = make_launchset(G, B->plans, lc, &B->ls, free_slot->stream, &ag);
+            if (mrc == PM_E_NOMEM) {
+                free_launchset(&B->ls);
+                if (busy == 0) {
+                    rc = mrc;
+                    break;
+                }
+                break;  // wait for in-flight batches to release memory
+            }
+            if (mrc) {
+                free_launchset(&B->ls);
+                rc = mrc;
+                break;
+            }
+            if (enqueue(B->ls, free_slot->stream, false) ||
+                hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess) {
+                free_launchset(&B->ls);
+                rc = fail(PM_E_DEVICE, "serving launch failed");
+                break;
+            }
+            const double ta = now_s();
+            B->admitted = ta;
+            for (uint32_t r : B->reqs) {
+                res[r].queue_s = ta - reqs[r].arrival_s;
+                pending.erase(std::find(pending.begin(), pending.end(), r));
+            }
+            used += B->bytes;
+            ++batches;
+            inflight_sum += busy + 1;
+            ++admissions;
+            free_slot->batch = std::move(B);
+            progressed = true;
+        }
+        if (!progressed) {
+            // nothing to do: sleep until the next arrival or a short poll
+            double wait = 50e-6;
+            if (next < nreq) wait = std::min(wait, std::max(0.0, reqs[next].arrival_s - now_s()));
+            if (wait > 2e-6) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+        }
+    }
+    cleanup();
+    if (rc) return rc;
+    // statistics
+    std::vector<double> lat;
+    double total_matches = 0;
+    uint64_t failed = 0, timeouts = 0;
+    for (uint32_t i = 0; i < nreq; ++i) {
+        if (res[i].status) {
+            ++failed;
+            if (res[i].status == PM_E_TIMEOUT) ++timeouts;
+            continue;
+        }
+        lat.push_back(res[i].latency_s);
+        for (uint32_t k = 0; k < reqs[i].npat; ++k) total_matches += (double)res[i].values[k];
+    }
+    std::sort(lat.begin(), lat.end());
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        auto rank = [&](double q) {
+            if (lat.empty()) return 0.0;
+            size_t k = (size_t)std::ceil(q * lat.size());
+            if (k < 1) k = 1;
+            return lat[std::min(k, lat.size()) - 1];
+        };
+        stats->p50_s = rank(0.50);
+        stats->p99_s = rank(0.99);
+        double sum = 0;
+        for (double x : lat) sum += x;
+        stats->mean_s = lat.empty() ? 0 : sum / lat.size();
+        stats->max_s = lat.empty() ? 0 : lat.back();
+        stats->makespan_s = last_done - reqs[0].arrival_s;
+        stats->matches_per_s = stats->makespan_s > 0 ? total_matches / stats->makespan_s : 0;
+        stats->mean_inflight = admissions ? inflight_sum / admissions : 0;
+        stats->batches = batches;
+        stats->completed = nreq - failed;
+        stats->failed = failed;
+        stats->timeouts = timeouts;
+    }
+    return PM_OK;
+}
+
+}  // namespace pm
+

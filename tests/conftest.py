@@ -4,6 +4,9 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# Serving overlaps batches on several HIP streams; give the process enough
+# hardware queues that they do not share one (set before HIP initialises).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
