@@ -174,8 +174,10 @@ pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg,
  * `num_labels` labels, in the dense slot order documented with
  * pm_fsm_slot(); `out_support` (host, nslots int64) receives the supports;
  * `out_frequent` (host, nslots bytes, may be NULL) receives support >=
- * threshold.  morph = PM_MORPH_NAIVE takes the vertex-induced route
- * (Theorem 3.2 with union as the join). */
+ * threshold.  Only morph = PM_MORPH_NONE is implemented: supports are
+ * computed from the edge-induced patterns directly; any other value
+ * returns PM_E_UNSUPPORTED.  Errors: PM_E_INVAL (unlabeled graph, a label
+ * >= num_labels, nslots != pm_fsm_num_slots), PM_E_NOMEM (arena). */
 pm_status pm_fsm(pm_ctx* ctx, uint32_t graph_id, uint32_t num_labels,
                  int64_t threshold, int32_t morph, int64_t* out_support,
                  uint8_t* out_frequent, uint64_t nslots);
