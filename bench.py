@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: 4-motif counting on an R-MAT graph (scale 20, edge factor 16,
-(a,b,c,d) = (0.57, 0.19, 0.19, 0.05)), vertex-induced motifs answered by
-pattern morphing (Section 4.2 "Naive PMR": the clique plus the edge-induced
-superpatterns are matched, Corollary 3.1 converts back).
+"""Benchmark of the pattern-morphing engine on one MI355X.
 
-One step = submit the six connected vertex-induced 4-vertex patterns, let
-the engine plan, match (HIP kernels), copy back and convert, with the graph
-resident in HBM.  Prints one JSON line.
+Default workload: 4-motif counting on an R-MAT graph (scale 20, edge factor
+16, (a,b,c,d) = (0.57, 0.19, 0.19, 0.05), seed 2).  The six vertex-induced
+4-vertex motifs are answered by pattern morphing (Section 4.2, Naive PMR:
+the clique plus the edge-induced superpatterns are matched, Corollary 3.1
+converts back).  One step = submit the six patterns, plan, match (one
+hipGraph replay of the persistent multi-pattern launches), copy back and
+convert, with the graph resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+    python bench.py --workload {rmat20-4mc,er2000-4mc,rmat-5mc,rmat18-fsm,serving}
+
+The other workloads print a line of the same form for the other
+configurations (plain ER 4-motif counting, batched 5-motif counting at a
+reduced scale, labeled 3-edge FSM with MNI support, and the serving loop).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,13 +30,73 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "motif-count s (morphed vs plain), matches/s, % HBM peak, p50/p99 query latency"
+KERNEL_SRC = os.path.join(ROOT, "paper_2012_04553_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_rmat20_4mc_morphed_traffic.md")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, budget_s: float = 15.0):
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the match kernel from the committed PMC
+    summary, or None when the kernel source changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            w = line.strip().split()
+            if len(w) == 2 and w[0].endswith(":"):
+                vals[w[0][:-1]] = w[1]
+    if vals.get("kernel_source_sha256") != kernel_sha():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def base_line(args, value, unit, ms_per_step, workload, extra_cfg, higher=True):
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": higher,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": dict({"workload": workload}, **extra_cfg),
+    }
+
+
+def timed_steps(eng, step, args):
+    """W untimed steps, then K timed ones bracketed by device syncs."""
+    import torch
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        kms.append(eng.last_stats()["kernel_ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall * 1e3 / args.steps, kms
+
+
+def cpu_baseline_4mc(g, budget_s: float = 15.0):
     """The oracle (tier A injective-map counting of the six vertex-induced
     4-vertex motifs) on a bounded sample of roots of the same graph, on all
     host threads.  Rate = (matches / |Aut|) per second, i.e. matched
@@ -62,77 +129,66 @@ def cpu_baseline(g, budget_s: float = 15.0):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--plain-scale", type=int, default=12)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+# ---------------------------------------------------------------- workloads
 
-    import numpy as np
-    import torch
-
-    import gen
+def run_4mc(args, eng, g, workload, morph_name="morphed"):
     import paper_2012_04553_amd as pm
-    from paper_2012_04553_amd.binding import lib
-
-    log(f"generating R-MAT scale {args.scale}")
-    t = time.perf_counter()
-    g = gen.rmat(args.scale, 16, 0.57, 0.19, 0.19, 0.05, seed=2)
-    log(f"  n={g.n} m={g.m} ({time.perf_counter() - t:.1f} s)")
-
-    eng = pm.Engine(arena_bytes=48 << 30)
+    import gen
+    masks = list(gen.connected_masks(4))
+    pats = [(4, m, True) for m in masks]
+    mode = pm.MORPH_NAIVE if morph_name == "morphed" else pm.MORPH_NONE
     t = time.perf_counter()
     gid = eng.load(g)
     load_s = time.perf_counter() - t
     log(f"  loaded in {load_s:.2f} s: {eng.graph_stats(gid)}")
-
-    from oracle import P  # pattern masks only (the six connected 4-vertex classes)
-    masks = list(P.connected_classes(4))
-    pats = [(4, m, True) for m in masks]
-
     # untimed pass with the byte tally (same kernel, counting build)
     eng.set_option("count_bytes", 1)
-    ref = eng.count(gid, pats, morph=pm.MORPH_NAIVE)
+    ref = eng.count(gid, pats, morph=mode)
     st = eng.last_stats()
     alg_bytes = st["alg_bytes"]
     launches = st["launches"]
     eng.set_option("count_bytes", 0)
     log(f"  counts {ref}; algorithmic bytes {alg_bytes / 1e9:.2f} GB in {launches} launches")
 
-    for _ in range(args.warmup):
-        eng.count(gid, pats, morph=pm.MORPH_NAIVE)
-
-    torch.cuda.synchronize()
-    kernel_ms = []
-    step_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        out = eng.count(gid, pats, morph=pm.MORPH_NAIVE)
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-        kernel_ms.append(eng.last_stats()["kernel_ms"])
+    def step():
+        out = eng.count(gid, pats, morph=mode)
         assert out == ref, "non-deterministic counts"
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    matches = sum(ref)
-    value = matches / (ms_per_step / 1e3)
-    k_ms = float(np.mean(kernel_ms))
-    achieved = alg_bytes / (k_ms / 1e3) / 1e9
 
+    ms_per_step, kms = timed_steps(eng, step, args)
+    matches = sum(ref)
+    k_ms = sum(kms) / len(kms)
+    per_launch_ms = k_ms / launches
+    achieved = (alg_bytes / launches) / (per_launch_ms / 1e3) / 1e9
+    line = base_line(args, matches / (ms_per_step / 1e3), "matches/s", ms_per_step, workload, {
+        "n": g.n, "m": g.m, "motif_count_s": ms_per_step / 1e3, "kernel_ms": k_ms,
+        "graph_load_s": round(load_s, 3), "matches_per_step": matches, "counts": ref,
+    })
+    line["roofline"] = {
+        "bound": "hbm", "kernel": "match_kernel", "launches_per_step": launches,
+        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None, "alg_bytes_per_launch": alg_bytes / launches,
+        "avg_launch_ms": per_launch_ms,
+    }
+    return line, gid
+
+
+def wl_rmat20_4mc(args, eng):
+    import gen
+    import paper_2012_04553_amd as pm
+    log(f"generating R-MAT scale {args.scale}")
+    g = gen.rmat(args.scale, 16, 0.57, 0.19, 0.19, 0.05, seed=2)
+    log(f"  n={g.n} m={g.m}")
+    line, gid = run_4mc(args, eng, g, f"4-motif counting (6 vertex-induced motifs, morphed), R-MAT scale "
+                        f"{args.scale} edge factor 16 (0.57,0.19,0.19,0.05) seed 2")
+    if args.scale == 20:
+        tr = measured_traffic()
+        line["roofline"]["traffic"] = tr
+    eng.graph_unload(gid)
     # morphed vs plain on a graph small enough for plain matching
-    mvp = None
     if args.plain_scale > 0:
         gs = gen.rmat(args.plain_scale, 16, seed=2)
         gsid = eng.load(gs)
+        pats = [(4, m, True) for m in gen.connected_masks(4)]
         res = {}
         for mode, name in ((pm.MORPH_NAIVE, "morphed"), (pm.MORPH_NONE, "plain")):
             eng.count(gsid, pats, morph=mode)
@@ -140,53 +196,178 @@ def main():
             c = eng.count(gsid, pats, morph=mode)
             res[name] = (time.perf_counter() - ts, c)
         assert res["morphed"][1] == res["plain"][1], "morphed and plain disagree"
-        mvp = {"workload": f"R-MAT scale {args.plain_scale} ef16, 4-motif",
-               "morphed_s": round(res["morphed"][0], 4), "plain_s": round(res["plain"][0], 4),
-               "speedup": round(res["plain"][0] / res["morphed"][0], 2)}
+        line["morphed_vs_plain"] = {
+            "workload": f"R-MAT scale {args.plain_scale} ef16, 4-motif",
+            "morphed_s": round(res["morphed"][0], 4), "plain_s": round(res["plain"][0], 4),
+            "speedup": round(res["plain"][0] / res["morphed"][0], 2)}
         eng.graph_unload(gsid)
-        log(f"  morphed vs plain: {mvp}")
-
-    cpu = None
+        log(f"  morphed vs plain: {line['morphed_vs_plain']}")
     if not args.no_cpu:
         log("  timing the oracle on a bounded sample")
-        cpu = cpu_baseline(g)
+        line["cpu_baseline"] = cpu_baseline_4mc(g)
+    else:
+        line["cpu_baseline"] = None
+    return line
 
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "matches/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"4-motif counting (6 vertex-induced motifs, morphed), R-MAT scale {args.scale} "
-                        "edge factor 16 (0.57,0.19,0.19,0.05) seed 2",
-            "n": g.n, "m": g.m, "motif_count_s": ms_per_step / 1e3,
-            "kernel_ms": k_ms, "graph_load_s": round(load_s, 3),
-            "matches_per_step": matches,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "match_kernel",
-            "launches_per_step": launches,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "alg_bytes_per_step": alg_bytes,
-        },
-        "morphed_vs_plain": mvp,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+
+def wl_er2000_4mc(args, eng):
+    import gen
+    g = gen.erdos_renyi(2000, 0.005, 1)
+    res = {}
+    for name in ("plain", "morphed"):
+        line, gid = run_4mc(args, eng, g, f"plain 4-motif counting, ER G(2000, 0.005) seed 1 ({name})",
+                            morph_name=name)
+        eng.graph_unload(gid)
+        res[name] = line
+    line = res["morphed"]
+    line["morphed_vs_plain"] = {"morphed_s": res["morphed"]["ms_per_step"] / 1e3,
+                                "plain_s": res["plain"]["ms_per_step"] / 1e3}
+    line["config"]["workload"] = "4-motif counting, ER G(2000, 0.005) seed 1, morphed (plain beside it)"
+    line["cpu_baseline"] = None if args.no_cpu else cpu_baseline_4mc(g, budget_s=10.0)
+    return line
+
+
+def wl_rmat_5mc(args, eng):
+    import gen
+    import paper_2012_04553_amd as pm
+    scale = args.scale if args.scale != 20 else 10
+    g = gen.rmat(scale, 16, 0.57, 0.19, 0.19, 0.05, seed=3)
+    gid = eng.load(g)
+    pats = [(5, m, True) for m in gen.connected_masks(5)]
+    log(f"  R-MAT scale {scale}: n={g.n} m={g.m}; autotuning the 5-motif closure")
+    t = time.perf_counter()
+    tune = eng.autotune(gid, pats, morph=pm.MORPH_NAIVE)
+    log(f"  autotune {tune} in {time.perf_counter() - t:.1f} s")
+    eng.set_option("count_bytes", 1)
+    ref = eng.count(gid, pats, morph=pm.MORPH_NAIVE)
+    st = eng.last_stats()
+    eng.set_option("count_bytes", 0)
+
+    def step():
+        assert eng.count(gid, pats, morph=pm.MORPH_NAIVE) == ref
+
+    ms_per_step, kms = timed_steps(eng, step, args)
+    k_ms = sum(kms) / len(kms)
+    launches = st["launches"]
+    achieved = (st["alg_bytes"] / launches) / (k_ms / launches / 1e3) / 1e9
+    line = base_line(args, sum(ref) / (ms_per_step / 1e3), "matches/s", ms_per_step,
+                     f"batched 5-motif counting (21 vertex-induced motifs, morphed, autotuned, hipGraph), "
+                     f"R-MAT scale {scale} edge factor 16 seed 3",
+                     {"n": g.n, "m": g.m, "kernel_ms": k_ms, "autotune": tune, "counts": ref,
+                      "num_alt": st["num_alt"]})
+    line["roofline"] = {"bound": "hbm", "kernel": "match_kernel", "launches_per_step": launches,
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "alg_bytes_per_launch": st["alg_bytes"] / launches}
+    line["cpu_baseline"] = None
     eng.graph_unload(gid)
+    return line
+
+
+def wl_rmat18_fsm(args, eng):
+    import gen
+    import numpy as np
+    import paper_2012_04553_amd as pm
+    g = gen.rmat(18, 8, 0.57, 0.19, 0.19, 0.05, seed=4).with_labels(gen.zipf_labels(1 << 18, 16, 1.2, 40))
+    gid = eng.load(g)
+    # the number of edge-induced 3-edge matches (triangles + 3-paths + 3-stars)
+    tri, p4, s3 = [m for m in gen.connected_masks(3) if bin(m).count("1") == 3] + \
+        [m for m in gen.connected_masks(4) if bin(m).count("1") == 3]
+    c3 = eng.count(gid, [(3, tri, False)], morph=pm.MORPH_NONE)[0]
+    c4 = eng.count(gid, [(4, p4, False), (4, s3, False)], morph=pm.MORPH_NONE)
+    matches = c3 + sum(c4)
+    ref = eng.fsm(gid, 16, 1000)
+
+    def step():
+        sup, freq = eng.fsm(gid, 16, 1000)
+        assert np.array_equal(sup, ref[0])
+
+    ms_per_step, kms = timed_steps(eng, step, args)
+    line = base_line(args, matches / (ms_per_step / 1e3), "matches/s", ms_per_step,
+                     "labeled 3-edge FSM, MNI support of all 46,768 labeled patterns, threshold 1000, "
+                     "R-MAT scale 18 edge factor 8 seed 4, Zipf(1.2) labels over 16 (seed 40)",
+                     {"n": g.n, "m": g.m, "kernel_ms": sum(kms) / len(kms),
+                      "frequent": int(ref[1].sum()), "edge_induced_matches": matches})
+    line["roofline"] = None
+    line["cpu_baseline"] = None
+    eng.graph_unload(gid)
+    return line
+
+
+def wl_serving(args, eng):
+    import gen
+    import numpy as np
+    import paper_2012_04553_amd as pm
+    div = args.serve_div
+    sizes = [100000 // div, 500000 // div, 1000000 // div, 4000000 // div]
+    ids = []
+    for i, n in enumerate(sizes):
+        g = gen.chung_lu(n, 2.1, 20.0, seed=51 + i).with_labels(gen.zipf_labels(n, 16, 1.2, 55))
+        ids.append(eng.load(g))
+        log(f"  Chung-Lu n={n}: m={g.m}")
+    ks = tuple(int(x) for x in args.serve_k.split(","))
+    qs = gen.query_stream(args.serve_queries, args.serve_qps, 4, seed=56, k_choices=ks)
+    reqs = [(q.arrival_s, ids[q.graph], q.patterns, pm.MORPH_COST) for q in qs]
+    t = time.perf_counter()
+    res, st = eng.serve(reqs, max_slots=8, max_batch=8, budget_bytes=64 << 30, deadline_s=args.serve_deadline)
+    wall = time.perf_counter() - t
+    line = base_line(args, st["p99_s"], "s (p99 latency)", wall * 1e3,
+                     f"serving {args.serve_queries} queries at {args.serve_qps} QPS over 4 Chung-Lu graphs "
+                     f"(beta 2.1, mean degree 20, n = {sizes}), k in {ks}, 30% labeled, cost-based morphing",
+                     {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "matches_per_s": st["matches_per_s"],
+                      "completed": st["completed"], "timeouts": st["timeouts"],
+                      "mean_inflight": st["mean_inflight"], "batches": st["batches"],
+                      "deadline_s": args.serve_deadline}, higher=False)
+    line["roofline"] = None
+    line["cpu_baseline"] = None
+    return line
+
+
+WORKLOADS = {
+    "rmat20-4mc": wl_rmat20_4mc,
+    "er2000-4mc": wl_er2000_4mc,
+    "rmat-5mc": wl_rmat_5mc,
+    "rmat18-fsm": wl_rmat18_fsm,
+    "serving": wl_serving,
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20-4mc", choices=sorted(WORKLOADS))
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-scale", type=int, default=12)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="after the workload, copy this many MiB device to device once (PMC calibration)")
+    ap.add_argument("--serve-div", type=int, default=10)
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-k", default="3,4")
+    ap.add_argument("--serve-deadline", type=float, default=0.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2012_04553_amd as pm
+
+    eng = pm.Engine(arena_bytes=48 << 30)
+    line = WORKLOADS[args.workload](args, eng)
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"  calibration copy of {nbytes} bytes done")
+    print(json.dumps(line), flush=True)
     eng.close()
 
 

@@ -99,6 +99,8 @@ struct DPlan {
     uint8_t bridge_src;  //              b in N(v_src)
     int32_t local;       // 1: clique with a total order, counted on a bitmap
                          //    of the root's out-neighbourhood
+    int32_t bm0;         // 1: membership tests against N(v0) use a per-wave
+                         //    bitmap of the root's adjacency list
     DLevel lev[KMAX];
     DTerm term[MAX_TERMS];
     DMono mono[MAX_MONO];

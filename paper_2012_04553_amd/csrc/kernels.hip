@@ -10,15 +10,25 @@
 // entry against the other lists of the level (binary search: membership
 // for pattern edges, non-membership for anti-edges), the symmetry-breaking
 // bounds, injectivity and the label, and ballot + mbcnt compact the
-// survivors in order into the level buffer.  The candidates of the
-// second-to-last core level are then spread over the lanes: every lane
-// finishes its own partial match - counting the last level, or walking it
-// and evaluating the tail polynomial over leaf-set sizes - with sequential
-// set operations, so one wave keeps 64 independent memory streams in flight
-// on the short (degree-oriented) lists that dominate power-law graphs.
+// survivors in order into the level buffer.
+//
+// The candidates of the second-to-last core level are then spread over the
+// lanes, one partial match per lane.  Everything a lane still has to do for
+// its match - the last level, the set-size terms of the leaves, the bridge
+// lists of a two-hop level - is a set of driver ranges, one per lane, of
+// very different lengths on power-law graphs.  These are processed
+// flattened: a wave prefix sum over the range lengths numbers all entries
+// of all lanes, every lane takes the next unprocessed entry in that order
+// (so a long range is streamed by the whole wave, coalesced) and fetches
+// the owning lane's match and probe with cross-lane reads; per-owner counts
+// come back through ballot masks over each owner's stretch of entries.
+//
+// Membership in the root's list N(v0), which every partial match of a root
+// shares, can use a per-wave bitmap of N(v0) (built once per root by plain
+// stores, one writer per word) instead of a binary search.
+//
 // A plan whose last core vertex is reached only through bridge leaves
-// aggregates two-hop multiplicities in a per-wave dense counter array, the
-// lanes scanning different bridges.
+// aggregates two-hop multiplicities in a per-wave dense counter array.
 //
 // Counts accumulate per lane in 128 bits, are reduced across the wave and
 // added to a 128-bit global counter per plan (two 64-bit atomics with
@@ -85,7 +95,79 @@ struct Ctx {
     uint64_t stride;
     uint32_t size[KMAX];     // entries in each level buffer
     uint64_t bytes;          // algorithmic bytes (counting build only)
+    uint32_t* bmw;           // this wave's root bitmap (n bits) or null
+    const uint32_t* bm;      // bmw while it holds N(v0), else null
 };
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = wave_lane();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Lane owning flattened entry t: the number of lanes whose inclusive
+// prefix is <= t (prefixes are non-decreasing over the lanes).  Every lane
+// must execute it (cross-lane reads).
+__device__ __forceinline__ int owner_of(uint32_t incl, uint32_t t) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        uint32_t v = __shfl(incl, lo + step - 1);
+        if (v <= t) lo += step;
+    }
+    return lo;
+}
+
+// Bits [a, b) of a 64-bit mask (0 <= a < b <= 64).
+__device__ __forceinline__ uint64_t range_mask(uint32_t a, uint32_t b) {
+    uint64_t m = (b - a >= 64) ? ~0ull : ((1ull << (b - a)) - 1ull);
+    return m << a;
+}
+
+__device__ __forceinline__ bool bm_test(const uint32_t* bm, uint32_t x) {
+    return (bm[x >> 5] >> (x & 31)) & 1u;
+}
+
+// Root bitmap of N(r): the lane holding the first entry of each 32-id word
+// assembles the word from the following entries (the list is sorted) and
+// stores it, so no two lanes write one word.  The bitmap is all zero before.
+__device__ void bm_build(Ctx& c, uint32_t r) {
+    const int lane = wave_lane();
+    const uint32_t b = c.g.rp[r], e = c.g.rp[r + 1];
+    for (uint32_t p = b + lane; p < e; p += 64) {
+        const uint32_t x = c.g.col[p];
+        const uint32_t w = x >> 5;
+        if (p == b || (c.g.col[p - 1] >> 5) != w) {
+            uint32_t bits = 0;
+            for (uint32_t q = p; q < e; ++q) {
+                const uint32_t y = c.g.col[q];
+                if ((y >> 5) != w) break;
+                bits |= 1u << (y & 31);
+            }
+            c.bmw[w] = bits;
+        }
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    c.bm = c.bmw;
+}
+
+__device__ void bm_clear(Ctx& c, uint32_t r) {
+    const int lane = wave_lane();
+    const uint32_t b = c.g.rp[r], e = c.g.rp[r + 1];
+    // every lane has finished its probes of the bitmap
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t p = b + lane; p < e; p += 64) c.bmw[c.g.col[p] >> 5] = 0u;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    c.bm = nullptr;
+}
 
 __device__ __forceinline__ void bounds_of(const uint32_t* vv, uint8_t gt, uint8_t lt, uint32_t& lo,
                                           uint32_t& hi) {
@@ -119,14 +201,26 @@ __device__ __forceinline__ int pick_driver(const KGraph& g, const uint32_t* vv, 
     return bi;
 }
 
-// Per-candidate test against probe lists, injectivity and label.
+// Per-candidate test against probe lists, injectivity and label.  With a
+// root bitmap, list 0 is tested on the bitmap; every candidate handed to a
+// probe lies inside the probe's id bounds, so membership in all of N(v0)
+// equals membership in its bounded range.
 struct Probe {
     uint32_t pb[KMAX], pe[KMAX];
-    uint8_t adj, anti, neq;
+    uint8_t adj, anti, neq, bm;
     int8_t label;
 };
 
-__device__ __forceinline__ uint64_t make_probe(const KGraph& g, const uint32_t* vv, uint8_t adj, uint8_t anti,
+__device__ __forceinline__ void clear_probe(Probe& pr, uint8_t neq, int8_t label) {
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) pr.pb[i] = pr.pe[i] = 0;
+    pr.adj = pr.anti = pr.bm = 0;
+    pr.neq = neq;
+    pr.label = label;
+}
+
+template <bool BYTES>
+__device__ __forceinline__ uint64_t make_probe(const Ctx& c, const uint32_t* vv, uint8_t adj, uint8_t anti,
                                                uint8_t neq, int8_t label, uint32_t lo, uint32_t hi,
                                                Probe& pr) {
     uint64_t bytes = 0;
@@ -134,28 +228,54 @@ __device__ __forceinline__ uint64_t make_probe(const KGraph& g, const uint32_t* 
     pr.anti = anti;
     pr.neq = neq;
     pr.label = label;
+    pr.bm = (c.bm != nullptr && ((adj | anti) & 1u)) ? 1 : 0;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         pr.pb[i] = pr.pe[i] = 0;
         if (((adj | anti) >> i) & 1) {
-            list_range(g, vv[i], lo, hi, pr.pb[i], pr.pe[i]);
+            if (i == 0 && pr.bm && !BYTES) continue;
+            list_range(c.g, vv[i], lo, hi, pr.pb[i], pr.pe[i]);
             bytes += 8 + 4ull * (pr.pe[i] - pr.pb[i]);
         }
     }
     return bytes;
 }
 
-__device__ __forceinline__ bool probe_ok(const KGraph& g, const uint32_t* vv, const Probe& pr, uint32_t x) {
-    if (pr.label >= 0 && g.lab[x] != (uint8_t)pr.label) return false;
+__device__ __forceinline__ bool probe_ok(const Ctx& c, const uint32_t* vv, const Probe& pr, uint32_t x) {
+    if (pr.label >= 0 && c.g.lab[x] != (uint8_t)pr.label) return false;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i)
         if (((pr.neq >> i) & 1) && x == vv[i]) return false;
+    if (pr.bm && ((pr.adj | pr.anti) & 1u)) {
+        const bool in0 = bm_test(c.bm, x);
+        if ((pr.adj & 1u) && !in0) return false;
+        if ((pr.anti & 1u) && in0) return false;
+    }
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
-        if (((pr.adj >> i) & 1) && !in_sorted(g.col, pr.pb[i], pr.pe[i], x)) return false;
-        if (((pr.anti >> i) & 1) && in_sorted(g.col, pr.pb[i], pr.pe[i], x)) return false;
+        if (i == 0 && pr.bm) continue;
+        if (((pr.adj >> i) & 1) && !in_sorted(c.g.col, pr.pb[i], pr.pe[i], x)) return false;
+        if (((pr.anti >> i) & 1) && in_sorted(c.g.col, pr.pb[i], pr.pe[i], x)) return false;
     }
     return true;
+}
+
+// The probe of lane o (lists: union of the list bits any lane may probe).
+__device__ __forceinline__ void fetch_probe(const Probe& pr, int o, uint8_t lists, Probe& q) {
+    const uint32_t packed = __shfl((uint32_t)pr.adj | ((uint32_t)pr.anti << 8) | ((uint32_t)pr.bm << 16), o);
+    q.adj = (uint8_t)packed;
+    q.anti = (uint8_t)(packed >> 8);
+    q.bm = (uint8_t)(packed >> 16);
+    q.neq = pr.neq;
+    q.label = pr.label;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        q.pb[i] = q.pe[i] = 0;
+        if ((lists >> i) & 1) {
+            q.pb[i] = __shfl(pr.pb[i], o);
+            q.pe[i] = __shfl(pr.pe[i], o);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- wave-cooperative level
@@ -187,27 +307,31 @@ __device__ uint32_t wave_level(Ctx& c, int j) {
         if (BYTES && lane == 0) c.bytes += 8;
     }
     Probe pr;
-    uint64_t pbytes = make_probe(c.g, c.v, chk, anti, L.neq, L.label, lo, hi, pr);
+    uint64_t pbytes = make_probe<BYTES>(c, c.v, chk, anti, L.neq, L.label, lo, hi, pr);
     if (BYTES && lane == 0) c.bytes += pbytes + 4ull * (e - b);
     uint32_t total = 0;
     for (uint32_t base = b; base < e; base += 64) {
         uint32_t idx = base + lane;
         bool ok = idx < e;
         uint32_t x = ok ? drv[idx] : 0;
-        ok = ok && probe_ok(c.g, c.v, pr, x);
+        ok = ok && probe_ok(c, c.v, pr, x);
         uint64_t m = __ballot(ok);
         if (ok) out[total + lane_prefix(m)] = x;
         total += (uint32_t)__popcll(m);
     }
+    // other lanes read the buffer next
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
     return total;
 }
 
 // ---------------------------------------------------------------- per-lane work
+//
+// Every function below is called by all 64 lanes together (it reads other
+// lanes); `valid` marks the lanes that hold a partial match.
 
-// Per-lane filter over level j (prefix vv complete below j).  MODE 0 counts;
-// MODE 1 evaluates the tail for every survivor and returns it in `sum`.
-template <int MODE, bool BYTES>
-__device__ uint64_t lane_level(Ctx& c, uint32_t* vv, int j, u128& sum);
+template <bool BYTES>
+__device__ u128 lanes_tail(Ctx& c, const uint32_t* vv, bool valid, uint64_t aggm);
 
 __device__ __forceinline__ u128 poly_eval(const DPlan* P, const uint64_t* tv) {
     i128 s = 0;
@@ -221,94 +345,149 @@ __device__ __forceinline__ u128 poly_eval(const DPlan* P, const uint64_t* tv) {
     return s > 0 ? (u128)s : (u128)0;
 }
 
-// One tail term for the full core match vv (per lane).
+// A cheap tail term (one adjacency list, range count with injectivity
+// corrections) or the aggregation multiplicity; per lane.
 template <bool BYTES>
-__device__ __forceinline__ uint64_t lane_term(Ctx& c, const uint32_t* vv, const DTerm& t, uint64_t aggm) {
+__device__ __forceinline__ uint64_t cheap_term(Ctx& c, const uint32_t* vv, const DTerm& t, uint64_t aggm) {
     if (t.agg) return aggm;
     uint32_t lo, hi;
     bounds_of(vv, t.gt, t.lt, lo, hi);
     if (lo >= hi) return 0;
-    if (t.cheap) {
-        int a = __builtin_ctz((uint32_t)t.adj);
-        uint32_t b, e;
-        list_range(c.g, vv[a], lo, hi, b, e);
-        uint64_t cnt = e - b;
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (!((t.neq >> i) & 1)) continue;
-            uint32_t y = vv[i];
-            if (y >= lo && y < hi && (((t.sure >> i) & 1) || in_sorted(c.g.col, b, e, y))) --cnt;
-        }
-        if (BYTES) c.bytes += 8;
-        return cnt;
-    }
+    int a = __builtin_ctz((uint32_t)t.adj);
     uint32_t b, e;
-    int bi = pick_driver(c.g, vv, t.adj, lo, hi, b, e);
-    Probe pr;
-    uint64_t pbytes = make_probe(c.g, vv, (uint8_t)(t.adj & ~(1u << bi)), t.anti, t.neq, t.label, lo, hi, pr);
-    if (BYTES) c.bytes += 8 + pbytes + 4ull * (e - b);
-    uint64_t cnt = 0;
-    for (uint32_t p = b; p < e; ++p)
-        if (probe_ok(c.g, vv, pr, c.g.col[p])) ++cnt;
+    list_range(c.g, vv[a], lo, hi, b, e);
+    uint64_t cnt = e - b;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        if (!((t.neq >> i) & 1)) continue;
+        uint32_t y = vv[i];
+        if (y >= lo && y < hi && (((t.sure >> i) & 1) || in_sorted(c.g.col, b, e, y))) --cnt;
+    }
+    if (BYTES) c.bytes += 8;
     return cnt;
+}
+
+// Flattened filter: lane l owns drv[b_l, b_l + len_l) and the probe pr_l of
+// its match vv_l.  MODE 0 returns, per owner, the number of entries that
+// pass; MODE 1 (level j) extends every passing entry x to the match
+// vv_owner + {v_j = x} and adds its tail to `acc` (on the lane that tested
+// x); the return value is then 0.
+template <int MODE, bool BYTES>
+__device__ uint64_t flat_filter(Ctx& c, const uint32_t* vv, const uint32_t* drv, uint32_t b, uint32_t len,
+                                const Probe& pr, uint8_t lists, int j, u128& acc) {
+    const int lane = wave_lane();
+    const uint32_t incl = wave_incl_scan(len);
+    const uint32_t total = __shfl(incl, 63);
+    const uint32_t excl = incl - len;
+    const uint8_t nl = (uint8_t)(lists & (c.bm ? 0xfe : 0xff));
+    uint64_t cnt = 0;
+    for (uint32_t base = 0; base < total; base += 64) {
+        const uint32_t t = base + lane;
+        const bool act = t < total;
+        const int o = owner_of(incl, act ? t : total - 1);
+        const uint32_t src = __shfl(b, o) + (t - __shfl(excl, o));
+        Probe q;
+        fetch_probe(pr, o, nl, q);
+        uint32_t vo[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) vo[i] = __shfl(vv[i], o);
+        uint32_t x = act ? drv[src] : 0u;
+        const bool ok = act && probe_ok(c, vo, q, x);
+        if (MODE == 0) {
+            const uint64_t m = __ballot(ok);
+            const uint32_t s = max(excl, base), f = min(incl, base + 64);
+            if (s < f) cnt += (uint64_t)__popcll(m & range_mask(s - base, f - base));
+        } else {
+            vo[j] = x;
+            acc += lanes_tail<BYTES>(c, vo, ok, 0);
+        }
+    }
+    return cnt;
+}
+
+// A tail term that needs a set operation, for every lane's match.
+template <bool BYTES>
+__device__ uint64_t flat_term(Ctx& c, const uint32_t* vv, bool valid, const DTerm& t) {
+    uint32_t lo, hi, b = 0, e = 0;
+    Probe pr;
+    clear_probe(pr, t.neq, t.label);
+    bounds_of(vv, t.gt, t.lt, lo, hi);
+    if (valid && lo < hi) {
+        int bi = pick_driver(c.g, vv, t.adj, lo, hi, b, e);
+        uint64_t pbytes =
+            make_probe<BYTES>(c, vv, (uint8_t)(t.adj & ~(1u << bi)), t.anti, t.neq, t.label, lo, hi, pr);
+        if (BYTES) c.bytes += 8 + pbytes + 4ull * (e - b);
+    }
+    u128 dummy = 0;
+    return flat_filter<0, BYTES>(c, vv, c.g.col, b, e - b, pr, (uint8_t)(t.adj | t.anti), 0, dummy);
 }
 
 template <bool BYTES>
-__device__ __forceinline__ u128 lane_tail(Ctx& c, const uint32_t* vv, uint64_t aggm) {
+__device__ u128 lanes_tail(Ctx& c, const uint32_t* vv, bool valid, uint64_t aggm) {
     uint64_t tv[MAX_TERMS];
     const int nt = c.P->nterm;
-    for (int q = 0; q < nt; ++q) tv[q] = lane_term<BYTES>(c, vv, c.P->term[q], aggm);
-    return poly_eval(c.P, tv);
+    for (int q = 0; q < nt; ++q) {
+        const DTerm t = c.P->term[q];
+        if (t.agg || t.cheap) tv[q] = valid ? cheap_term<BYTES>(c, vv, t, aggm) : 0;
+        else tv[q] = flat_term<BYTES>(c, vv, valid, t);
+    }
+    return valid ? poly_eval(c.P, tv) : (u128)0;
 }
 
+// Level j for every lane's match vv (complete below j): MODE 0 counts the
+// candidates (times the plan multiplier), MODE 1 evaluates the tail of
+// every extension.
 template <int MODE, bool BYTES>
-__device__ uint64_t lane_level(Ctx& c, uint32_t* vv, int j, u128& sum) {
+__device__ void lanes_level(Ctx& c, const uint32_t* vv, bool valid, int j, u128& acc) {
     const DLevel L = c.P->lev[j];
-    uint32_t lo, hi;
+    uint32_t lo, hi, b = 0, e = 0;
     bounds_of(vv, L.gt, L.lt, lo, hi);
-    if (lo >= hi) return 0;
-    const uint32_t* drv;
-    uint32_t b, e;
+    const bool on = valid && lo < hi;
+    const uint32_t* drv = c.g.col;
     uint8_t chk = L.adj, anti = L.anti;
+    Probe pr;
+    clear_probe(pr, L.neq, L.label);
     if (L.base != 0xff) {
         const uint32_t* bb = c.buf + (uint64_t)L.base * c.stride;
-        uint32_t n = c.size[L.base];
-        b = lo ? lower_bound_u32(bb, 0, n, lo) : 0;
-        e = hi != NOB ? lower_bound_u32(bb, b, n, hi) : n;
-        drv = bb;
         chk &= (uint8_t)~c.P->lev[L.base].adj;
         anti &= (uint8_t)~c.P->lev[L.base].anti;
-    } else {
-        int bi = pick_driver(c.g, vv, L.adj, lo, hi, b, e);
-        drv = c.g.col;
-        chk &= (uint8_t)~(1u << bi);
-        if (BYTES) c.bytes += 8;
-    }
-    Probe pr;
-    uint64_t pbytes = make_probe(c.g, vv, chk, anti, L.neq, L.label, lo, hi, pr);
-    if (BYTES) c.bytes += pbytes + 4ull * (e - b);
-    uint64_t cnt = 0;
-    for (uint32_t p = b; p < e; ++p) {
-        uint32_t x = drv[p];
-        if (!probe_ok(c.g, vv, pr, x)) continue;
-        if (MODE == 0) {
-            ++cnt;
-        } else {
-            vv[j] = x;
-            sum += lane_tail<BYTES>(c, vv, 0);
+        drv = bb;
+        if (on) {
+            const uint32_t n = c.size[L.base];
+            b = lo ? lower_bound_u32(bb, 0, n, lo) : 0;
+            e = hi != NOB ? lower_bound_u32(bb, b, n, hi) : n;
         }
     }
-    return cnt;
+    const uint8_t lists = (uint8_t)(chk | anti);
+    if (on) {
+        uint8_t pc = chk;
+        if (L.base == 0xff) {
+            int bi = pick_driver(c.g, vv, L.adj, lo, hi, b, e);
+            pc &= (uint8_t)~(1u << bi);
+            if (BYTES) c.bytes += 8;
+        }
+        uint64_t pbytes = make_probe<BYTES>(c, vv, pc, anti, L.neq, L.label, lo, hi, pr);
+        if (BYTES) c.bytes += pbytes + 4ull * (e - b);
+    }
+    const uint64_t cnt = flat_filter<MODE, BYTES>(c, vv, drv, b, e - b, pr, lists, j, acc);
+    if (MODE == 0) acc += (u128)cnt * (u128)(uint32_t)c.P->mult;
 }
 
 // ---------------------------------------------------------------- aggregation
 
 // Two-hop aggregation for the last core level j: targets x reached from
 // bridges y in N(v_src) (bridge bounds and label) are counted in a per-wave
-// dense array; every touched target is then evaluated lane-parallel with
-// its multiplicity as the bridge term.
+// dense array; the bridges' lists are streamed flattened, 64 bridges at a
+// time.  Every touched target is then evaluated lane-parallel with its
+// multiplicity as the bridge term.
+//
+// A high-degree root (j = 1) is split over several work items by target id:
+// slice [s0, s1) of the root's degree d takes the targets in the matching
+// fraction of the bounded id range, so each target still collects its full
+// multiplicity inside one wave.
 template <bool BYTES>
-__device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const KArgs& a, u128& acc) {
+__device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const KArgs& a, u128& acc,
+                          uint32_t s0 = 0, uint32_t s1 = 0xffffffffu) {
     const DPlan* P = c.P;
     const DLevel L = P->lev[j];
     const int lane = wave_lane();
@@ -318,24 +497,44 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
     bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
     bounds_of(c.v, L.gt, L.lt, lo, hi);
     if (blo >= bhi || lo >= hi) return;
+    if (s0 != 0 || s1 != 0xffffffffu) {
+        const uint32_t r = c.v[0];
+        const uint64_t d = c.g.rp[r + 1] - c.g.rp[r];
+        const uint64_t top = hi == NOB ? (uint64_t)c.g.n : (uint64_t)hi;
+        const uint64_t span = top > lo ? top - lo : 0;
+        const uint32_t nlo = (uint32_t)(lo + span * min((uint64_t)s0, d) / d);
+        const uint32_t nhi = s1 >= d ? hi : (uint32_t)(lo + span * (uint64_t)s1 / d);
+        lo = nlo;
+        hi = nhi;
+        if (lo >= hi) return;
+    }
     uint32_t bb, be;
     list_range(c.g, c.v[P->bridge_src], blo, bhi, bb, be);
     if (BYTES && lane == 0) c.bytes += 8 + 4ull * (be - bb);
     if (lane == 0) *s_touch = 0;
     __builtin_amdgcn_wave_barrier();
     for (uint32_t base = bb; base < be; base += 64) {
-        uint32_t idx = base + lane;
-        if (idx >= be) continue;
-        uint32_t y = c.g.col[idx];
-        if (P->bridge_label >= 0 && c.g.lab[y] != (uint8_t)P->bridge_label) continue;
-        bool core = false;
-        for (int i = 0; i < j; ++i) core |= (y == c.v[i]);
-        if (core) continue;
-        uint32_t yb, yf;
-        list_range(c.g, y, lo, hi, yb, yf);
-        if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
-        for (uint32_t p = yb; p < yf; ++p) {
-            uint32_t x = c.g.col[p];
+        const uint32_t idx = base + lane;
+        bool valid = idx < be;
+        const uint32_t y = valid ? c.g.col[idx] : 0u;
+        if (valid && P->bridge_label >= 0 && c.g.lab[y] != (uint8_t)P->bridge_label) valid = false;
+        for (int i = 0; i < j; ++i) valid = valid && (y != c.v[i]);
+        uint32_t yb = 0, yf = 0;
+        if (valid) {
+            list_range(c.g, y, lo, hi, yb, yf);
+            if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
+        }
+        const uint32_t len = yf - yb;
+        const uint32_t incl = wave_incl_scan(len);
+        const uint32_t total = __shfl(incl, 63);
+        const uint32_t excl = incl - len;
+        for (uint32_t tb = 0; tb < total; tb += 64) {
+            const uint32_t t = tb + lane;
+            const bool act = t < total;
+            const int o = owner_of(incl, act ? t : total - 1);
+            const uint32_t src = __shfl(yb, o) + (t - __shfl(excl, o));
+            if (!act) continue;
+            const uint32_t x = c.g.col[src];
             if (L.label >= 0 && c.g.lab[x] != (uint8_t)L.label) continue;
             bool skip = false;
 #pragma unroll
@@ -352,14 +551,16 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
     for (uint32_t base = 0; base < ntouch; base += 64) {
-        uint32_t idx = base + lane;
-        if (idx < ntouch) {
-            uint32_t x = touched[idx];
-            uint32_t m = cnt[x];
+        const uint32_t idx = base + lane;
+        const bool valid = idx < ntouch;
+        uint32_t m = 0;
+        if (valid) {
+            const uint32_t x = touched[idx];
+            m = cnt[x];
             cnt[x] = 0;
             vv[j] = x;
-            acc += lane_tail<BYTES>(c, vv, m);
         }
+        acc += lanes_tail<BYTES>(c, vv, valid, m);
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
@@ -484,18 +685,14 @@ __device__ __forceinline__ void lanes_finish(Ctx& c, int j, uint32_t b, uint32_t
     const int last = P->ncore - 1;
     const uint32_t* bj = c.buf + (uint64_t)j * c.stride;
     for (uint32_t base = b; base < e; base += 64) {
-        uint32_t idx = base + lane;
-        if (idx >= e) continue;
+        const uint32_t idx = base + lane;
+        const bool valid = idx < e;
         uint32_t vv[KMAX];
 #pragma unroll
         for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
-        vv[j] = bj[idx];
-        if (P->nterm == 0) {
-            u128 dummy = 0;
-            acc += (u128)lane_level<0, BYTES>(c, vv, last, dummy) * (u128)(uint32_t)P->mult;
-        } else {
-            lane_level<1, BYTES>(c, vv, last, acc);
-        }
+        vv[j] = valid ? bj[idx] : 0u;
+        if (P->nterm == 0) lanes_level<0, BYTES>(c, vv, valid, last, acc);
+        else lanes_level<1, BYTES>(c, vv, valid, last, acc);
     }
 }
 
@@ -520,6 +717,8 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     c.stride = a.buf_stride;
     c.buf = a.scratch + (uint64_t)wid * (uint64_t)KMAX * a.buf_stride;
     c.bytes = 0;
+    c.bmw = a.rootbm ? a.rootbm + (uint64_t)wid * a.bm_words : nullptr;
+    c.bm = nullptr;
     int cur = -1;
     u128 acc = 0;
     uint32_t tick = 0;
@@ -552,11 +751,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             // lanes take roots; every tail term is evaluated per lane
             if (item.s0 != 0 || P->nterm == 0) continue;
             for (uint32_t base = item.r0; base < item.r1; base += 64) {
-                uint32_t r = base + lane;
-                if (r < item.r1 && (rl < 0 || a.g.lab[r] == (uint8_t)rl)) {
-                    uint32_t vv[KMAX] = {r, 0, 0, 0, 0};
-                    acc += lane_tail<BYTES>(c, vv, 0);
-                }
+                const uint32_t r = base + lane;
+                const bool valid = r < item.r1 && (rl < 0 || a.g.lab[r] == (uint8_t)rl);
+                uint32_t vv[KMAX] = {valid ? r : 0u, 0, 0, 0, 0};
+                acc += lanes_tail<BYTES>(c, vv, valid, 0);
             }
             continue;
         }
@@ -573,7 +771,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             }
             if (nc == 2) {
                 if (P->agg_last) {
-                    if (item.s0 == 0) agg_level<BYTES>(c, 1, wid, my_touch, a, acc);
+                    agg_level<BYTES>(c, 1, wid, my_touch, a, acc, item.s0, item.s1);
                     continue;
                 }
                 uint32_t n = wave_level<BYTES>(c, 1);
@@ -583,12 +781,15 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                     continue;
                 }
                 const uint32_t* b1 = c.buf + c.stride;
+                const bool usebm = P->bm0 && c.bmw && e > b;
+                if (usebm) bm_build(c, r);
                 for (uint32_t base = b; base < e; base += 64) {
-                    uint32_t idx = base + lane;
-                    if (idx >= e) continue;
-                    uint32_t vv[KMAX] = {r, b1[idx], 0, 0, 0};
-                    acc += lane_tail<BYTES>(c, vv, 0);
+                    const uint32_t idx = base + lane;
+                    const bool valid = idx < e;
+                    uint32_t vv[KMAX] = {r, valid ? b1[idx] : 0u, 0, 0, 0};
+                    acc += lanes_tail<BYTES>(c, vv, valid, 0);
                 }
+                if (usebm) bm_clear(c, r);
                 continue;
             }
             // nc >= 3: levels 1 .. nc-2 materialised, lanes finish
@@ -597,6 +798,8 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             c.size[1] = wave_level<BYTES>(c, 1);
             pos[1] = min(item.s0, c.size[1]);
             end[1] = min(item.s1, c.size[1]);
+            const bool usebm = P->bm0 && c.bmw && end[1] > pos[1];
+            if (usebm) bm_build(c, r);
             if (pen == 1) {
                 if (P->agg_last) {
                     for (uint32_t q = pos[1]; q < end[1]; ++q) {
@@ -610,6 +813,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                 } else {
                     lanes_finish<BYTES>(c, 1, pos[1], end[1], acc);
                 }
+                if (usebm) bm_clear(c, r);
                 continue;
             }
             int j = 1;
@@ -641,6 +845,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                 pos[j] = 0;
                 end[j] = c.size[j];
             }
+            if (usebm) bm_clear(c, r);
         }
     }
     if (cur >= 0) flush(a, cur, acc);

@@ -34,6 +34,8 @@ struct KArgs {
     uint32_t* aggcnt;         // per-wave dense counters (n each), zeroed
     uint32_t* aggtouch;       // per-wave touched lists (n each)
     uint64_t* bytes;          // algorithmic bytes (counting launch only)
+    uint32_t* rootbm;         // per-wave root adjacency bitmaps (bm_words each), zeroed
+    uint64_t bm_words;
     const int* cancel;        // host-visible cancel flag or null
 };
 

@@ -503,6 +503,30 @@ struct Builder {
         return true;
     }
 
+    // A plan, and its root-bitmap variant when some probe may test N(v0).
+    void add(const PlanInfo& pi, std::vector<PlanInfo>* out) const {
+        out->push_back(pi);
+        const DPlan& d = pi.d;
+        if (d.local || d.agg_last || d.ncore < 2) return;
+        bool probes0 = false;
+        for (int j = 2; j < d.ncore; ++j) {
+            const DLevel& L = d.lev[j];
+            uint8_t m = L.adj | L.anti;
+            if (L.base != 0xff) m = (uint8_t)((L.adj & ~d.lev[L.base].adj) | (L.anti & ~d.lev[L.base].anti));
+            if (m & 1) probes0 = true;
+        }
+        for (int q = 0; q < d.nterm; ++q) {
+            const DTerm& t = d.term[q];
+            if (!t.cheap && !t.agg && ((t.adj | t.anti) & 1)) probes0 = true;
+        }
+        if (!probes0) return;
+        PlanInfo pb = pi;
+        pb.d.bm0 = 1;
+        pb.est_cost = estimate(pb.d);
+        pb.total_cost = pb.est_cost;
+        out->push_back(pb);
+    }
+
     // ---- cost model -------------------------------------------------------
     // Expected work from degree statistics.  The first two levels use exact
     // joint sums over the degree sequence (power-law graphs make degrees of
@@ -574,6 +598,7 @@ struct Builder {
                 continue;
             }
             double best = 1e300;
+            int bi = 0;
             for (int i = 0; i < j; ++i) {
                 if (!((L.adj >> i) & 1)) continue;
                 int type = list_type(L, i);
@@ -581,7 +606,10 @@ struct Builder {
                 if (j == 1) sum = root_sum(type);
                 else if (j == 2 && i <= 1) sum = pair_sum(rel1, i, type);
                 else sum = prefixes * nb_len(type);
-                best = std::min(best, sum);
+                if (sum < best) {
+                    best = sum;
+                    bi = i;
+                }
             }
             if (j == 1) {
                 for (int i = 0; i < 1; ++i) rel1 = list_type(L, 0);
@@ -589,6 +617,8 @@ struct Builder {
             int extra = popc(L.adj) - 1 + popc(L.anti);
             total = best * std::pow(keep, popc(L.adj) - 1);
             work = best * (1.0 + extra * 2.0);
+            // a probe of N(v0) on the root bitmap costs one load, not a search
+            if (d.bm0 && j >= 2 && ((L.anti & 1) || ((L.adj & 1) && bi != 0))) work -= best * BM_SAVING;
             bool counted = (j == last && d.nterm == 0);
             cost += work;
             if (!counted) prefixes = std::max(total, 1e-9);
@@ -606,6 +636,7 @@ struct Builder {
                 continue;
             }
             double best = 1e300;
+            int bi = 0;
             for (int i = 0; i < d.ncore; ++i) {
                 if (!((t.adj >> i) & 1)) continue;
                 int type = ((t.gt >> i) & 1) ? 1 : (((t.lt >> i) & 1) ? -1 : 0);
@@ -613,13 +644,20 @@ struct Builder {
                 if (d.ncore == 1) sum = root_sum(type);
                 else if (d.ncore == 2 && !d.agg_last) sum = pair_sum(rel1, i, type);
                 else sum = prefixes * nb_len(type);
-                best = std::min(best, sum);
+                if (sum < best) {
+                    best = sum;
+                    bi = i;
+                }
             }
             tail_work += best * (1.0 + (popc(t.adj) - 1 + popc(t.anti)) * 2.0) + prefixes * 4.0;
+            if (d.bm0 && ((t.anti & 1) || ((t.adj & 1) && bi != 0))) tail_work -= best * BM_SAVING;
         }
         cost += tail_work;
+        // building and clearing the root bitmap: two passes over N(v0)
+        if (d.bm0) cost += 2.0 * root_sum(0);
         return cost;
     }
+    static constexpr double BM_SAVING = 1.5;
 };
 
 void orders_of(const Pat& p, uint32_t core, bool agg_last, std::vector<std::vector<int>>* out) {
@@ -683,6 +721,7 @@ std::string PlanInfo::describe() const {
     }
     if (d.lane_par) s += " lane_par";
     if (d.local) s += " local_bitmap";
+    if (d.bm0) s += " root_bitmap";
     return s;
 }
 
@@ -721,10 +760,10 @@ int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* o
                 for (int form = 0; form < 2; ++form)
                     for (int dir = -1; dir <= 1; dir += 2) {
                         PlanInfo pi;
-                        if (B.build(core, leaves, ord, form, dir, agg != 0, autp, &pi)) out->push_back(pi);
+                        if (B.build(core, leaves, ord, form, dir, agg != 0, autp, &pi)) B.add(pi, out);
                         if (!agg && form == 0 && !p.vi && popc(leaves) >= 2) {
                             PlanInfo pq;
-                            if (B.build(core, leaves, ord, form, dir, false, autp, &pq, true)) out->push_back(pq);
+                            if (B.build(core, leaves, ord, form, dir, false, autp, &pq, true)) B.add(pq, out);
                         }
                     }
         }

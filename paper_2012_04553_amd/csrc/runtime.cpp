@@ -390,9 +390,19 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     *scratch_stride = stride;
     *any_agg = agg;
     uint64_t b = 0;
-    b += sizeof(DPlan) * plans.size() + 16 * plans.size() + 256 * 3;
+    // plans, counters, heads, byte tally, and 256-byte rounding of each carve
+    b += sizeof(DPlan) * plans.size() + 16 * plans.size() + 512 + 256 * 4;
     b += waves(cfg) * (uint64_t)KMAX * stride * 4;
+    b += waves(cfg) * bitmap_words(G, plans) * 4;
     return b;
+}
+
+// Words of one wave's root bitmap (0 when no plan uses it).
+uint64_t Ctx_::bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
+    bool any = false;
+    for (const PlanInfo& p : plans) any = any || p.d.bm0;
+    if (!any) return 0;
+    return ((G.n + 31) / 32 + 63) & ~uint64_t(63);
 }
 
 int Ctx_::ensure_agg(uint32_t n, const LaunchCfg& cfg) {
@@ -495,12 +505,18 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         return p;
     };
     ls->dplans = (DPlan*)carve(sizeof(DPlan) * np);
-    char* zb = carve(16 * np + 256 + 256);
+    // counters, queue heads, byte tally and root bitmaps are cleared
+    // together by the zero-fill at the head of every replay
+    const uint64_t bm_words = bitmap_words(G, plans);
+    const uint64_t zhead = (16 * np + 512 + 255) & ~uint64_t(255);
+    const uint64_t zbytes = zhead + waves(cfg) * bm_words * 4;
+    char* zb = carve(zbytes);
     ls->zero_base = (uint32_t*)zb;
-    ls->zero_words = (16 * np + 512) / 4;
+    ls->zero_words = zbytes / 4;
     ls->counters = (uint64_t*)zb;
     ls->heads = (uint32_t*)(zb + 16 * np);
     ls->bytes = (uint64_t*)(zb + 16 * np + 256);
+    uint32_t* rootbm = bm_words ? (uint32_t*)(zb + zhead) : nullptr;
     ls->scratch = (uint32_t*)carve(waves(cfg) * (uint64_t)KMAX * ls->stride * 4);
     std::vector<DPlan> hp(np);
     for (size_t i = 0; i < np; ++i) hp[i] = plans[i].d;
@@ -540,6 +556,8 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     a.buf_stride = ls->stride;
     a.bytes = ls->bytes;
     a.cancel = ls->cancel_dev;
+    a.rootbm = rootbm;
+    a.bm_words = bm_words;
     if (ls->any_agg) {
         if (agg) {
             a.aggcnt = agg->cnt;

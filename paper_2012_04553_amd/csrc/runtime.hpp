@@ -60,7 +60,7 @@ struct LaunchSet {
     size_t np = 0;
     DPlan* dplans = nullptr;
     uint64_t* counters = nullptr;
-    uint32_t* zero_base = nullptr;   // counters + heads + bytes, cleared together
+    uint32_t* zero_base = nullptr;   // counters + heads + bytes + root bitmaps, cleared together
     uint64_t zero_words = 0;
     uint32_t* heads = nullptr;
     uint64_t* bytes = nullptr;
@@ -186,6 +186,7 @@ struct Ctx_ {
     uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c,
                        uint64_t* stride, bool* any_agg) const;
     int ensure_agg(uint32_t n, const LaunchCfg& c);
+    uint64_t bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
     int launch(GraphRes& G, Query& Q);
     int wait(uint64_t ticket, int64_t* out, int64_t timeout_us);
