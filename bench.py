@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "motif-count s (morphed vs plain), matches/s, % HBM peak, p50/p99 query latency"
-KERNEL_SRC = os.path.join(ROOT, "paper_2012_04553_amd", "csrc", "kernels.hip")
+# sources that decide the match kernel's memory traffic (kernel, plans, launch configuration)
+PATH_SRCS = [os.path.join(ROOT, "paper_2012_04553_amd", "csrc", f)
+             for f in ("kernels.hip", "kernels.hpp", "planner.cpp", "runtime.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_rmat20_4mc_morphed_traffic.md")
 
 
@@ -38,14 +40,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def path_sha():
+    h = hashlib.sha256()
+    for p in PATH_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the match kernel from the committed PMC
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel, the planner or the launch defaults
+    changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -54,7 +60,7 @@ def measured_traffic():
             w = line.strip().split()
             if len(w) == 2 and w[0].endswith(":"):
                 vals[w[0][:-1]] = w[1]
-    if vals.get("kernel_source_sha256") != kernel_sha():
+    if vals.get("path_source_sha256") != path_sha():
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -309,7 +315,8 @@ def wl_serving(args, eng):
     qs = gen.query_stream(args.serve_queries, args.serve_qps, 4, seed=56, k_choices=ks)
     reqs = [(q.arrival_s, ids[q.graph], q.patterns, pm.MORPH_COST) for q in qs]
     t = time.perf_counter()
-    res, st = eng.serve(reqs, max_slots=8, max_batch=8, budget_bytes=64 << 30, deadline_s=args.serve_deadline)
+    res, st = eng.serve(reqs, max_slots=8, max_batch=8, budget_bytes=32 << 30, deadline_s=args.serve_deadline,
+                        progress_every=max(1, args.serve_queries // 20))
     wall = time.perf_counter() - t
     line = base_line(args, st["p99_s"], "s (p99 latency)", wall * 1e3,
                      f"serving {args.serve_queries} queries at {args.serve_qps} QPS over 4 Chung-Lu graphs "

@@ -194,7 +194,13 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "item_budget"   adjacency entries per root-range work item (>= 1);
  *   "item_split"    level-1 slice length for high-degree roots (>= 64);
  *                   takes effect for graphs loaded afterwards;
- *   "agg_waves"     wavefronts of two-hop aggregation launches (>= 1);
+ *   "agg_waves"     upper bound on the wavefronts of two-hop aggregation
+ *                   launches (>= 1, default 2048); each such wave holds
+ *                   8 bytes per vertex, and their total is also kept within
+ *                   a quarter of the arena (at most 8 GiB);
+ *   "agg_split"     target-range slices of a high-degree root in two-hop
+ *                   aggregation launches: one slice per this many
+ *                   adjacency entries (>= 64, default 256);
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
  *                   hipGraph on first use and replay it afterwards.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */
@@ -251,6 +257,8 @@ typedef struct {
     double deadline_s;      /* > 0: a batch still running this long after
                                admission is cancelled and its requests end
                                with PM_E_TIMEOUT; 0 = no deadline          */
+    uint32_t progress_every; /* > 0: a line on stderr each time this many
+                               more requests have finished; 0 = silent     */
 } pm_serve_config;
 
 typedef struct {

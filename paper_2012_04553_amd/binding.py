@@ -65,7 +65,8 @@ class pm_serve_result(ctypes.Structure):
 
 class pm_serve_config(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("budget_bytes", ctypes.c_uint64), ("deadline_s", ctypes.c_double)]
+                ("budget_bytes", ctypes.c_uint64), ("deadline_s", ctypes.c_double),
+                ("progress_every", ctypes.c_uint32)]
 
 
 class pm_serve_stats(ctypes.Structure):
@@ -283,7 +284,8 @@ class Engine:
     def cancel(self, ticket: int):
         check(lib().pm_cancel(self.ctx, ticket))
 
-    def serve(self, requests, max_slots=8, max_batch=8, budget_bytes=None, deadline_s=0.0):
+    def serve(self, requests, max_slots=8, max_batch=8, budget_bytes=None, deadline_s=0.0,
+              progress_every=0):
         """Replay a request trace through the serving loop.
 
         requests: [(arrival_s, graph_id, [(k, mask, induced, labels), ...], morph)]
@@ -303,6 +305,7 @@ class Engine:
         cfg.max_batch = max_batch
         cfg.budget_bytes = budget_bytes if budget_bytes is not None else self.arena.numel() // 2
         cfg.deadline_s = deadline_s
+        cfg.progress_every = progress_every
         res = (pm_serve_result * n)()
         st = pm_serve_stats()
         check(lib().pm_serve(self.ctx, arr, n, ctypes.byref(cfg), res, ctypes.byref(st)))

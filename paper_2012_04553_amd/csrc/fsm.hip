@@ -21,7 +21,10 @@
 //     for every (lc, ld), how many such c exist and how many of them have a
 //     single witness, then x subtracts itself and (only when needed) the
 //     witnesses it would take away, found by a sorted-list intersection.
-//   * triangle: x lies on a triangle whose other two labels are (ly, lz).
+//   * triangle: x lies on a triangle whose other two labels are (ly, lz);
+//     a pre-pass lists every triangle once from its lowest vertex in the
+//     degree order (merging two out-lists) and records the label pair at
+//     each corner.
 //
 // Each membership increments a per-(pattern, column) counter once per
 // vertex, so the counters are the domain sizes.
@@ -55,6 +58,7 @@ __global__ void fsm_hist(FsmArgs a) {
             if (h[l] >= 2) pm2 |= 1u << l;
             if (h[l] >= 3) pm3 |= 1u << l;
         }
+        for (int w = 0; w < 4; ++w) a.tri[(uint64_t)x * 4 + w] = 0ull;
         a.pres[(uint64_t)x * 3 + 0] = pm1;
         a.pres[(uint64_t)x * 3 + 1] = pm2;
         a.pres[(uint64_t)x * 3 + 2] = pm3;
@@ -69,6 +73,42 @@ __device__ __forceinline__ uint32_t present_minus(const FsmArgs& a, uint32_t v, 
 __device__ __forceinline__ uint32_t twice_minus(const FsmArgs& a, uint32_t v, int drop) {
     uint32_t p2 = a.pres[(uint64_t)v * 3 + 1], p3 = a.pres[(uint64_t)v * 3 + 2];
     return (p3 >> drop) & 1 ? p2 : (p2 & ~(1u << drop));
+}
+
+// ---- triangle label pairs ---------------------------------------------------
+__device__ __forceinline__ void pair_or(const FsmArgs& a, uint32_t x, int l1, int l2) {
+    if (l1 > l2) { int t = l1; l1 = l2; l2 = t; }
+    const int bit = l1 * FSM_LMAX + l2;
+    atomicOr(&a.tri[(uint64_t)x * 4 + (bit >> 6)], 1ull << (bit & 63));
+}
+
+__global__ void fsm_tri(FsmArgs a) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < a.n; u += gridDim.x * blockDim.x) {
+        const uint32_t ue = a.rp[u + 1];
+        const int lu = a.lab[u];
+        for (uint32_t p = a.split[u]; p < ue; ++p) {
+            const uint32_t v = a.col[p];
+            const int lv = a.lab[v];
+            // w above v in both N+(u) and N+(v)
+            uint32_t i = p + 1, j = a.split[v];
+            const uint32_t je = a.rp[v + 1];
+            while (i < ue && j < je) {
+                const uint32_t x = a.col[i], y = a.col[j];
+                if (x == y) {
+                    const int lw = a.lab[x];
+                    pair_or(a, u, lv, lw);
+                    pair_or(a, v, lu, lw);
+                    pair_or(a, x, lu, lv);
+                    ++i;
+                    ++j;
+                } else if (x < y) {
+                    ++i;
+                } else {
+                    ++j;
+                }
+            }
+        }
+    }
 }
 
 // ---- per vertex b: for every (lc, ld), how many c in N(b) (label lc) have a
@@ -104,19 +144,15 @@ __global__ void fsm_btab(FsmArgs a) {
     }
 }
 
-__device__ __forceinline__ void bump(const FsmArgs& a, int slot, int colidx) {
-    atomicAdd(&a.counts[(uint64_t)slot * 4 + colidx], 1u);
-}
-
 // path slot of the ordered label tuple, and the canonical column of position i
-__device__ __forceinline__ void p4_member(const FsmArgs& a, int la, int lb, int lc, int ld, int pos) {
+__device__ __forceinline__ void p4_where(const FsmArgs& a, int la, int lb, int lc, int ld, int pos, int& slot,
+                                         int& colidx) {
     const int L = a.L;
-    int code = a.p4code[((la * L + lb) * L + lc) * L + ld];
-    int slot = code >> 2;
-    int rev = (code >> 1) & 1, pal = code & 1;
-    int colidx = rev ? 3 - pos : pos;
+    const int code = a.p4code[((la * L + lb) * L + lc) * L + ld];
+    slot = code >> 2;
+    const int rev = (code >> 1) & 1, pal = code & 1;
+    colidx = rev ? 3 - pos : pos;
     if (pal && colidx >= 2) colidx = 3 - colidx;
-    bump(a, slot, colidx);
 }
 
 // column of a vertex of label lx in a sorted label triple: first position
@@ -139,87 +175,142 @@ __device__ uint32_t unique_other(const FsmArgs& a, uint32_t x, int l, uint32_t s
     return a.n;
 }
 
+__device__ __forceinline__ uint64_t wave_or64(uint64_t m) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
+    return m;
+}
+
+// Membership sets of one vertex, as 256-bit sets (4 words) per label:
+//   region 0  U[lc]: 3-star leaf, centre label lc, bit (l2*16 + l3) = the
+//             other two leaf labels (l2 <= l3)
+//   region 1  M[lc]: path inner b = x, bit (la*16 + ld) for the path a-x-c-d
+//   region 2  V[lb]: path end a = x, bit (lc*16 + ld) for the path x-b-c-d
+//   tri:      triangle, bit (l2*16 + l3) = the other two labels (l2 <= l3)
+enum { REG_U = 0, REG_M = 1, REG_V = 2 };
+
+__device__ __forceinline__ void where_of(const FsmArgs& a, int reg, int lab, int bit, int lx, int& slot,
+                                         int& colidx) {
+    const int L = a.L;
+    const int hi = bit / FSM_LMAX, lo = bit % FSM_LMAX;
+    if (reg == REG_U) {
+        int s0 = lx, s1 = hi, s2 = lo;
+        sort3(s0, s1, s2);
+        slot = a.s3code[((lab * L + s0) * L + s1) * L + s2];
+        colidx = 1 + first_pos(s0, s1, s2, lx);
+    } else if (reg == REG_M) {
+        p4_where(a, hi, lx, lab, lo, 1, slot, colidx);
+    } else if (reg == REG_V) {
+        p4_where(a, lx, lab, hi, lo, 0, slot, colidx);
+    } else {
+        int s0 = lx, s1 = hi, s2 = lo;
+        sort3(s0, s1, s2);
+        slot = a.tricode[(s0 * L + s1) * L + s2];
+        colidx = first_pos(s0, s1, s2, lx);
+    }
+}
+
+// Adds one word of every lane's membership set to the domain counters.  In a
+// label-uniform wave the lanes sharing a bit add one popcount with a single
+// atomic; otherwise each lane adds its own bits.  Called by all lanes.
+__device__ __forceinline__ void emit_word(const FsmArgs& a, uint64_t m, bool uniform, int lx, int reg, int lab,
+                                          int w) {
+    if (uniform) {
+        uint64_t u = wave_or64(m);
+        while (u) {
+            const int b = __builtin_ctzll(u);
+            u &= u - 1;
+            const uint64_t who = __ballot((m >> b) & 1ull);
+            if (__lane_id() == 0) {
+                int slot, colidx;
+                where_of(a, reg, lab, (w << 6) + b, lx, slot, colidx);
+                atomicAdd(&a.counts[(uint64_t)slot * 4 + colidx], (uint32_t)__popcll(who));
+            }
+        }
+    } else {
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            int slot, colidx;
+            where_of(a, reg, lab, (w << 6) + b, lx, slot, colidx);
+            atomicAdd(&a.counts[(uint64_t)slot * 4 + colidx], 1u);
+        }
+    }
+}
+
+__device__ __forceinline__ void set_bit(uint64_t* r, int bit) { r[bit >> 6] |= 1ull << (bit & 63); }
+__device__ __forceinline__ bool has_bit(const uint64_t* r, int bit) { return (r[bit >> 6] >> (bit & 63)) & 1ull; }
+
+// Vertices are taken in label order, so most wavefronts hold one label and
+// the domain counters see one atomic per (pattern, column) per wavefront.
 __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
     const int L = a.L;
+    const int lane = __lane_id();
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t* scratch = a.scratch + tid * FSM_SCRATCH_WORDS;
-    for (uint32_t x = (uint32_t)tid; x < a.n; x += gridDim.x * blockDim.x) {
-        const int lx = a.lab[x];
-        const uint32_t xs = a.rp[x], xe = a.rp[x + 1];
-        if (xs == xe) continue;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t* U = a.scratch + tid * FSM_SCRATCH_WORDS;   // FSM_LMAX * 4 words each
+    uint64_t* M = U + FSM_LMAX * 4;
+    uint64_t* V = M + FSM_LMAX * 4;
+    for (uint64_t base = tid - lane; base < a.n; base += stride) {   // wave-uniform trip count
+        const uint64_t i = base + lane;
+        const bool act = i < a.n;
+        const uint32_t x = act ? a.order[i] : 0u;
+        const int lx = act ? (int)a.lab[x] : -1;
+        const uint32_t xs = act ? a.rp[x] : 0u, xe = act ? a.rp[x + 1] : 0u;
+        // label-uniform wave: every active lane has the first lane's label
+        const int lx0 = __shfl(lx, 0);
+        const bool uniform = __ballot(act && lx != lx0) == 0ull;
         const uint32_t* hx = a.hist + (uint64_t)x * FSM_LMAX;
-        // ---- 3-star centre ------------------------------------------------
-        for (int l1 = 0; l1 < L; ++l1)
-            for (int l2 = l1; l2 < L; ++l2)
-                for (int l3 = l2; l3 < L; ++l3) {
-                    uint32_t n1 = hx[l1], n2 = hx[l2], n3 = hx[l3];
-                    bool ok;
-                    if (l1 == l3) ok = n1 >= 3;
-                    else if (l1 == l2) ok = n1 >= 2 && n3 >= 1;
-                    else if (l2 == l3) ok = n1 >= 1 && n2 >= 2;
-                    else ok = n1 >= 1 && n2 >= 1 && n3 >= 1;
-                    if (ok) bump(a, a.s3code[((lx * L + l1) * L + l2) * L + l3], 0);
+        for (int q = 0; q < FSM_LMAX * 12; ++q) U[q] = 0;
+        uint64_t tp[4] = {0, 0, 0, 0};
+        if (act && xs != xe) {
+            // ---- 3-star leaf and path inner, one pass over N(x) -----------
+            uint32_t Pd[FSM_LMAX], T2[FSM_LMAX];
+            for (int q = 0; q < FSM_LMAX; ++q) Pd[q] = T2[q] = 0;
+            for (uint32_t p = xs; p < xe; ++p) {
+                const uint32_t c = a.col[p];
+                const int lc = a.lab[c];
+                const uint32_t pr = present_minus(a, c, lx), tw = twice_minus(a, c, lx);
+                Pd[lc] |= pr;
+                T2[lc] |= tw;
+                // pairs (l2 <= l3) c's other neighbours cover: row l2 holds
+                // the labels above l2 in pr, and l2 itself when twice present
+                uint64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+                uint32_t e2 = pr;
+                while (e2) {
+                    const int l2 = __builtin_ctz(e2);
+                    e2 &= e2 - 1;
+                    const uint32_t row = (pr & ~((2u << l2) - 1u)) | (tw & (1u << l2));
+                    const uint64_t sh = (uint64_t)row << ((l2 & 3) * 16);
+                    const int wd = l2 >> 2;
+                    f0 |= wd == 0 ? sh : 0ull;
+                    f1 |= wd == 1 ? sh : 0ull;
+                    f2 |= wd == 2 ? sh : 0ull;
+                    f3 |= wd == 3 ? sh : 0ull;
                 }
-        // ---- 3-star leaf: U[lc] = pairs {l2 <= l3} coverable besides x ------
-        // pair index over (l2 <= l3): bit l2*L + l3 in a 256-bit set
-        uint64_t* U = scratch;  // FSM_LMAX * 4 words
-        for (int i = 0; i < FSM_LMAX * 4; ++i) U[i] = 0;
-        // ---- path inner: Pd[lc] = labels of d reachable; T2[lc]: twice ----
-        uint32_t Pd[FSM_LMAX], T2[FSM_LMAX];
-        for (int i = 0; i < FSM_LMAX; ++i) Pd[i] = T2[i] = 0;
-        for (uint32_t p = xs; p < xe; ++p) {
-            const uint32_t c = a.col[p];
-            const int lc = a.lab[c];
-            const uint32_t pr = present_minus(a, c, lx), tw = twice_minus(a, c, lx);
-            Pd[lc] |= pr;
-            T2[lc] |= tw;
-            // pairs coverable by c's other neighbours
-            uint64_t* u = U + lc * 4;
-            uint32_t e2 = pr;
-            while (e2) {
-                int l2 = __builtin_ctz(e2);
-                e2 &= e2 - 1;
-                uint32_t hi = pr & ~((2u << l2) - 1u);  // l3 > l2
-                if ((tw >> l2) & 1) hi |= 1u << l2;     // l3 == l2
-                while (hi) {
-                    int l3 = __builtin_ctz(hi);
-                    hi &= hi - 1;
-                    int bit = l2 * FSM_LMAX + l3;
-                    u[bit >> 6] |= 1ull << (bit & 63);
-                }
+                uint64_t* u = U + lc * 4;
+                if (f0 & ~u[0]) u[0] |= f0;
+                if (f1 & ~u[1]) u[1] |= f1;
+                if (f2 & ~u[2]) u[2] |= f2;
+                if (f3 & ~u[3]) u[3] |= f3;
             }
-        }
-        for (int lc = 0; lc < L; ++lc) {
-            const uint64_t* u = U + lc * 4;
-            for (int w = 0; w < 4; ++w) {
-                uint64_t m = u[w];
-                while (m) {
-                    int bit = (w << 6) + __builtin_ctzll(m);
-                    m &= m - 1;
-                    int l2 = bit / FSM_LMAX, l3 = bit % FSM_LMAX;
-                    int s0 = lx, s1 = l2, s2 = l3;
-                    sort3(s0, s1, s2);
-                    bump(a, a.s3code[((lc * L + s0) * L + s1) * L + s2], 1 + first_pos(s0, s1, s2, lx));
-                }
-            }
-        }
-        for (int lc = 0; lc < L; ++lc) {
-            if (!Pd[lc]) continue;
-            // a: labels of N(x) \ {c} for some c of label lc
-            const uint32_t pa = hx[lc] >= 2 ? a.pres[(uint64_t)x * 3] : (a.pres[(uint64_t)x * 3] & ~(1u << lc));
-            for (int la = 0; la < L; ++la) {
-                if (!((pa >> la) & 1)) continue;
-                uint32_t dset = Pd[lc];
-                while (dset) {
-                    const int ld = __builtin_ctz(dset);
-                    dset &= dset - 1;
-                    bool ok = true;
-                    if (la == ld) {
+            for (int lc = 0; lc < L; ++lc) {
+                if (!Pd[lc]) continue;
+                // a: labels of N(x) \ {c} for some c of label lc
+                const uint32_t pa = hx[lc] >= 2 ? a.pres[(uint64_t)x * 3] : (a.pres[(uint64_t)x * 3] & ~(1u << lc));
+                uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+                uint32_t ea = pa & ((1u << L) - 1u);
+                while (ea) {
+                    const int la = __builtin_ctz(ea);
+                    ea &= ea - 1;
+                    uint32_t row = Pd[lc];   // labels ld of d
+                    if ((row >> la) & 1) {
+                        // ld == la needs a != d
                         const uint32_t na = hx[la] - (lc == la ? 1u : 0u);
                         if (na < 2 && !((T2[lc] >> la) & 1)) {
                             // every candidate c has one witness d; x one witness a:
                             // valid iff some c (label lc) has its witness d != a
-                            ok = false;
+                            bool ok = false;
                             for (uint32_t p = xs; p < xe && !ok; ++p) {
                                 const uint32_t c = a.col[p];
                                 if (a.lab[c] != lc) continue;
@@ -228,119 +319,102 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
                                 if (aa >= a.n) continue;
                                 if (!fsm_has(a.col, a.rp[c], a.rp[c + 1], aa)) ok = true;
                             }
+                            if (!ok) row &= ~(1u << la);
                         }
                     }
-                    if (ok) p4_member(a, la, lx, lc, ld, 1);
+                    const uint64_t sh = (uint64_t)row << ((la & 3) * 16);
+                    const int wd = la >> 2;
+                    m0 |= wd == 0 ? sh : 0ull;
+                    m1 |= wd == 1 ? sh : 0ull;
+                    m2 |= wd == 2 ? sh : 0ull;
+                    m3 |= wd == 3 ? sh : 0ull;
                 }
+                uint64_t* mm = M + lc * 4;
+                mm[0] = m0;
+                mm[1] = m1;
+                mm[2] = m2;
+                mm[3] = m3;
             }
-        }
-        // ---- path end: V[lb] = (lc, ld) reachable from x via b -------------
-        uint64_t* V = scratch + FSM_LMAX * 4;  // FSM_LMAX * 4 words
-        for (int i = 0; i < FSM_LMAX * 4; ++i) V[i] = 0;
-        for (uint32_t p = xs; p < xe; ++p) {
-            const uint32_t b = a.col[p];
-            const int lb = a.lab[b];
-            const uint32_t* wm = a.bmask + (uint64_t)b * FSM_LMAX;
-            const uint8_t* cnt = a.bcnt + (uint64_t)b * FSM_LMAX * FSM_LMAX;
-            const uint8_t* frag = a.bfrag + (uint64_t)b * FSM_LMAX * FSM_LMAX;
-            const uint32_t ex = present_minus(a, x, lb);  // x as a c-candidate of b
-            uint64_t* v = V + lb * 4;
-            for (int lc = 0; lc < L; ++lc) {
-                uint32_t dm = wm[lc];
-                while (dm) {
-                    const int ld = __builtin_ctz(dm);
-                    dm &= dm - 1;
-                    const int bit = lc * FSM_LMAX + ld;
-                    if ((v[bit >> 6] >> (bit & 63)) & 1ull) continue;
-                    const uint32_t cn = cnt[lc * FSM_LMAX + ld];
-                    const uint32_t fr = frag[lc * FSM_LMAX + ld];
-                    const uint32_t self = (lc == lx && ((ex >> ld) & 1)) ? 1u : 0u;
-                    bool ok;
-                    if (cn < 255 && cn < self + 1) ok = false;
-                    else if (cn < 255 && cn >= self + 1 + fr) ok = true;
-                    else if (ld != lx) ok = cn >= self + 1;
-                    else {
-                        // exact: c in N(b) \ {x}, label lc, with a label-ld neighbour
-                        // outside {b, x}
-                        ok = false;
-                        for (uint32_t q = a.rp[b]; q < a.rp[b + 1] && !ok; ++q) {
-                            const uint32_t c = a.col[q];
-                            if (c == x || a.lab[c] != lc) continue;
-                            uint32_t k = a.hist[(uint64_t)c * FSM_LMAX + ld] - (ld == lb ? 1u : 0u);
-                            if (k >= 1 && fsm_has(a.col, a.rp[c], a.rp[c + 1], x)) --k;
-                            if (k >= 1) ok = true;
+            // ---- path end: V[lb] = (lc, ld) reachable from x via b ---------
+            for (uint32_t p = xs; p < xe; ++p) {
+                const uint32_t b = a.col[p];
+                const int lb = a.lab[b];
+                const uint32_t* wm = a.bmask + (uint64_t)b * FSM_LMAX;
+                const uint8_t* cnt = a.bcnt + (uint64_t)b * FSM_LMAX * FSM_LMAX;
+                const uint8_t* frag = a.bfrag + (uint64_t)b * FSM_LMAX * FSM_LMAX;
+                const uint32_t ex = present_minus(a, x, lb);  // x as a c-candidate of b
+                uint64_t* v = V + lb * 4;
+                for (int lc = 0; lc < L; ++lc) {
+                    // only the (lc, ld) not yet known reachable
+                    const uint32_t known = (uint32_t)((v[lc >> 2] >> ((lc & 3) * 16)) & 0xffffu);
+                    uint32_t dm = wm[lc] & ~known;
+                    while (dm) {
+                        const int ld = __builtin_ctz(dm);
+                        dm &= dm - 1;
+                        const int bit = lc * FSM_LMAX + ld;
+                        const uint32_t cn = cnt[bit];
+                        const uint32_t fr = frag[bit];
+                        const uint32_t self = (lc == lx && ((ex >> ld) & 1)) ? 1u : 0u;
+                        bool ok;
+                        if (cn < 255 && cn < self + 1) ok = false;
+                        else if (cn < 255 && cn >= self + 1 + fr) ok = true;
+                        else if (ld != lx) ok = cn >= self + 1;
+                        else {
+                            // exact: c in N(b) \ {x}, label lc, with a label-ld neighbour
+                            // outside {b, x}
+                            ok = false;
+                            for (uint32_t q = a.rp[b]; q < a.rp[b + 1] && !ok; ++q) {
+                                const uint32_t c = a.col[q];
+                                if (c == x || a.lab[c] != lc) continue;
+                                uint32_t k = a.hist[(uint64_t)c * FSM_LMAX + ld] - (ld == lb ? 1u : 0u);
+                                if (k >= 1 && fsm_has(a.col, a.rp[c], a.rp[c + 1], x)) --k;
+                                if (k >= 1) ok = true;
+                            }
                         }
+                        if (ok) set_bit(v, bit);
                     }
-                    if (ok) v[bit >> 6] |= 1ull << (bit & 63);
                 }
             }
+            // ---- triangle: label pairs listed by the pre-pass ---------------
+            for (int w = 0; w < 4; ++w) tp[w] = a.tri[(uint64_t)x * 4 + w];
         }
-        for (int lb = 0; lb < L; ++lb) {
-            const uint64_t* v = V + lb * 4;
+        // ---- 3-star centre: the label histogram covers the leaf multiset --
+        const int lxs = uniform ? lx0 : lx;
+        for (int l1 = 0; l1 < L; ++l1)
+            for (int l2 = l1; l2 < L; ++l2)
+                for (int l3 = l2; l3 < L; ++l3) {
+                    bool ok = false;
+                    if (act && xs != xe) {
+                        const uint32_t n1 = hx[l1], n2 = hx[l2], n3 = hx[l3];
+                        if (l1 == l3) ok = n1 >= 3;
+                        else if (l1 == l2) ok = n1 >= 2 && n3 >= 1;
+                        else if (l2 == l3) ok = n1 >= 1 && n2 >= 2;
+                        else ok = n1 >= 1 && n2 >= 1 && n3 >= 1;
+                    }
+                    if (uniform) {
+                        const uint64_t who = __ballot(ok);
+                        if (lane == 0 && who)
+                            atomicAdd(&a.counts[(uint64_t)a.s3code[((lxs * L + l1) * L + l2) * L + l3] * 4],
+                                      (uint32_t)__popcll(who));
+                    } else if (ok) {
+                        atomicAdd(&a.counts[(uint64_t)a.s3code[((lx * L + l1) * L + l2) * L + l3] * 4], 1u);
+                    }
+                }
+        // ---- emit the membership sets --------------------------------------
+        for (int lab = 0; lab < L; ++lab)
             for (int w = 0; w < 4; ++w) {
-                uint64_t m = v[w];
-                while (m) {
-                    const int bit = (w << 6) + __builtin_ctzll(m);
-                    m &= m - 1;
-                    p4_member(a, lx, lb, bit / FSM_LMAX, bit % FSM_LMAX, 0);
-                }
+                emit_word(a, U[lab * 4 + w], uniform, lxs, REG_U, lab, w);
+                emit_word(a, M[lab * 4 + w], uniform, lxs, REG_M, lab, w);
+                emit_word(a, V[lab * 4 + w], uniform, lxs, REG_V, lab, w);
             }
-        }
-        // ---- triangle: label pairs of the other two vertices ---------------
-        uint64_t tp[4] = {0, 0, 0, 0};
-        for (uint32_t p = xs; p < xe; ++p) {
-            const uint32_t y = a.col[p];
-            const uint32_t ys = a.rp[y], ye = a.rp[y + 1];
-            // z in N(x) with z > y, z in N(y): scan the shorter tail
-            const uint32_t xt = p + 1;
-            uint32_t yt = ys;
-            {
-                uint32_t lo = ys, hi = ye;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (a.col[mid] <= y) lo = mid + 1;
-                    else hi = mid;
-                }
-                yt = lo;
-            }
-            const int ly = a.lab[y];
-            if (xe - xt <= ye - yt) {
-                for (uint32_t q = xt; q < xe; ++q) {
-                    const uint32_t z = a.col[q];
-                    if (fsm_has(a.col, yt, ye, z)) {
-                        int l2 = ly, l3 = a.lab[z];
-                        if (l2 > l3) { int t = l2; l2 = l3; l3 = t; }
-                        const int bit = l2 * FSM_LMAX + l3;
-                        tp[bit >> 6] |= 1ull << (bit & 63);
-                    }
-                }
-            } else {
-                for (uint32_t q = yt; q < ye; ++q) {
-                    const uint32_t z = a.col[q];
-                    if (fsm_has(a.col, xt, xe, z)) {
-                        int l2 = ly, l3 = a.lab[z];
-                        if (l2 > l3) { int t = l2; l2 = l3; l3 = t; }
-                        const int bit = l2 * FSM_LMAX + l3;
-                        tp[bit >> 6] |= 1ull << (bit & 63);
-                    }
-                }
-            }
-        }
-        for (int w = 0; w < 4; ++w) {
-            uint64_t m = tp[w];
-            while (m) {
-                const int bit = (w << 6) + __builtin_ctzll(m);
-                m &= m - 1;
-                int s0 = lx, s1 = bit / FSM_LMAX, s2 = bit % FSM_LMAX;
-                sort3(s0, s1, s2);
-                bump(a, a.tricode[(s0 * L + s1) * L + s2], first_pos(s0, s1, s2, lx));
-            }
-        }
+        for (int w = 0; w < 4; ++w) emit_word(a, tp[w], uniform, lxs, 3, 0, w);
     }
 }
 
 int launch_fsm(const FsmArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(fsm_hist, dim3(grid), dim3(256), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return -1;
+    hipLaunchKernelGGL(fsm_tri, dim3(grid), dim3(256), 0, s, a);
     if (hipGetLastError() != hipSuccess) return -1;
     hipLaunchKernelGGL(fsm_btab, dim3(grid), dim3(256), 0, s, a);
     if (hipGetLastError() != hipSuccess) return -1;

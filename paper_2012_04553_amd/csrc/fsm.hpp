@@ -6,7 +6,7 @@
 namespace pm {
 
 constexpr int FSM_LMAX = 16;                    // labels supported
-constexpr int FSM_SCRATCH_WORDS = FSM_LMAX * 8;  // per-thread 64-bit words
+constexpr int FSM_SCRATCH_WORDS = FSM_LMAX * 12;  // per-thread 64-bit words (three 256-bit sets per label)
 
 struct FsmArgs {
     const uint32_t* rp;
@@ -24,6 +24,9 @@ struct FsmArgs {
     const int32_t* s3code;   // (centre, sorted leaf triple) -> slot
     uint32_t* counts;   // nslots * 4 domain sizes
     uint64_t* scratch;  // per thread FSM_SCRATCH_WORDS
+    const uint32_t* order;  // n vertices sorted by label
+    const uint32_t* split;  // per vertex: index of the first neighbour above it
+    unsigned long long* tri;  // n * 4: label pairs of the triangles at each vertex
 };
 
 int launch_fsm(const FsmArgs& a, int grid, hipStream_t s);

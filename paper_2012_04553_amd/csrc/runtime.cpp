@@ -261,6 +261,15 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     if (labels) HIPCHK(hipMemcpyAsync(dptr(G->off_lab), nlab.data(), n, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
     G->host_rp = std::move(nrp);
+    if (labels) {
+        // vertices by label (stable: degree order within a label), for the
+        // FSM kernel's label-uniform wavefronts
+        std::vector<uint32_t> cnt(257, 0);
+        for (uint32_t r = 0; r < n; ++r) cnt[nlab[r] + 1]++;
+        for (int l = 0; l < 256; ++l) cnt[l + 1] += cnt[l];
+        G->label_order.resize(n);
+        for (uint32_t r = 0; r < n; ++r) G->label_order[cnt[nlab[r]]++] = r;
+    }
     std::lock_guard<std::mutex> g(mu);
     uint32_t gid = next_gid++;
     graphs[gid] = std::move(G);
@@ -406,7 +415,7 @@ uint64_t Ctx_::bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plan
 }
 
 int Ctx_::ensure_agg(uint32_t n, const LaunchCfg& cfg) {
-    uint64_t w = agg_waves(cfg);
+    uint64_t w = agg_waves(cfg, n);
     if (agg_off != UINT64_MAX && agg_n >= n && agg_w >= w) return PM_OK;
     if (agg_off != UINT64_MAX) {
         arena.release(agg_off);
@@ -495,6 +504,17 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ItemSet* is;
     int rc = get_items(G, cfg, &is);
     if (rc) return rc;
+    // two-hop launches slice hub roots by target range; finer slices keep
+    // each wave's window of its counter array cache-resident
+    ItemSet* isa = is;
+    if (ls->any_agg) {
+        LaunchCfg ac = cfg;
+        ac.item_split = agg_split;
+        rc = get_items(G, ac, &isa);
+        if (rc) return rc;
+    }
+    ls->agg_items = (const KItem*)dptr(isa->off);
+    ls->agg_nitems = isa->count;
     ls->off_mem = arena.alloc(need);
     if (ls->off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
     char* base = (char*)dptr(ls->off_mem);
@@ -566,7 +586,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         } else {
             a.aggcnt = (uint32_t*)dptr(agg_off);
             a.aggtouch = (uint32_t*)dptr(agg_touch_off);
-            ls->agg_w = agg_waves(cfg);
+            ls->agg_w = agg_waves(cfg, G.n);
         }
     }
     ls->runs.clear();
@@ -595,6 +615,10 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         b.nplans = ls.runs[r].second - ls.runs[r].first;
         b.counters = ls.counters + 2 * ls.runs[r].first;
         b.head = ls.heads + r;
+        if (ls.run_agg[r]) {
+            b.items = ls.agg_items;
+            b.nitems = ls.agg_nitems;
+        }
         int gb = ls.run_agg[r] ? (int)std::max<uint64_t>(1, ls.agg_w / (block / 64)) : grid_blocks(cfg);
         if (launch_match(b, gb, block, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
     }
@@ -769,13 +793,33 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
     return PM_OK;
 }
 
+// Frees every cached launch set that is not in flight, on every graph.
+int Ctx_::evict_idle() {
+    int k = 0;
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& gr : graphs) {
+        auto& L = gr.second->launches;
+        for (auto it = L.begin(); it != L.end();) {
+            if (!it->second->busy) {
+                free_launchset(it->second.get());
+                it = L.erase(it);
+                ++k;
+            } else {
+                ++it;
+            }
+        }
+    }
+    return k;
+}
+
 int Ctx_::launch(GraphRes& G, Query& Q) {
     const LaunchCfg cfg = cfg_for(G, Q.closure);
     HIPCHK(hipSetDevice(device));
     LaunchSet* ls = nullptr;
     bool replay = use_graphs && !count_bytes;
     std::string key = closure_key(G, Q.closure) + "#" + std::to_string(cfg.blocks_per_cu) + "," +
-                      std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split);
+                      std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
+                      std::to_string(agg_split);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy) {
@@ -783,6 +827,12 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
         } else if (it == G.launches.end()) {
             auto nls = std::make_unique<LaunchSet>();
             int rc = make_launchset(G, Q.plans, cfg, nls.get());
+            if (rc == PM_E_NOMEM) {
+                // make room: drop cached launch sets that are not in flight
+                free_launchset(nls.get());
+                nls = std::make_unique<LaunchSet>();
+                if (evict_idle() > 0) rc = make_launchset(G, Q.plans, cfg, nls.get());
+            }
             if (rc) {
                 free_launchset(nls.get());
                 return rc;
@@ -811,6 +861,11 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     if (!ls) {
         Q.own = std::make_unique<LaunchSet>();
         int rc = make_launchset(G, Q.plans, cfg, Q.own.get());
+        if (rc == PM_E_NOMEM) {
+            free_launchset(Q.own.get());
+            Q.own = std::make_unique<LaunchSet>();
+            if (evict_idle() > 0) rc = make_launchset(G, Q.plans, cfg, Q.own.get());
+        }
         if (rc) {
             free_launchset(Q.own.get());
             Q.own.reset();
@@ -1138,6 +1193,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "item_budget" && value >= 1) c.item_budget = (uint64_t)value;
     else if (k == "item_split" && value >= 64) c.item_split = (uint32_t)value;
     else if (k == "agg_waves" && value >= 1) c.agg_waves_opt = (uint64_t)value;
+    else if (k == "agg_split" && value >= 64 && value <= 0x7fffffff) c.agg_split = (uint32_t)value;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;
@@ -1286,9 +1342,12 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     const uint64_t LL = (uint64_t)FSM_LMAX * FSM_LMAX;
     uint64_t sz_hist = n * FSM_LMAX * 4, sz_pres = n * 3 * 4, sz_b = n * LL, sz_bm = n * FSM_LMAX * 4;
     uint64_t sz_tab = 4 * (T.tricode.size() + T.p4code.size() + T.s3code.size());
+    uint64_t sz_ord = 4 * n;
+    uint64_t sz_tri = 32 * n;
     uint64_t sz_cnt = nslots * 16, sz_scr = threads * FSM_SCRATCH_WORDS * 8;
     uint64_t need = 0;
-    for (uint64_t x : {sz_hist, sz_pres, sz_b, sz_b, sz_bm, sz_tab, sz_cnt, sz_scr}) need += (x + 255) & ~uint64_t(255);
+    for (uint64_t x : {sz_hist, sz_pres, sz_b, sz_b, sz_bm, sz_tab, sz_cnt, sz_scr, sz_ord, sz_tri})
+        need += (x + 255) & ~uint64_t(255);
     uint64_t off = c.arena.alloc(need);
     if (off == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for FSM tables");
     char* base = (char*)c.dptr(off);
@@ -1315,6 +1374,10 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     a.s3code = a.p4code + T.p4code.size();
     a.counts = (uint32_t*)carve(sz_cnt);
     a.scratch = (uint64_t*)carve(sz_scr);
+    uint32_t* ord = (uint32_t*)carve(sz_ord);
+    a.order = ord;
+    a.tri = (unsigned long long*)carve(sz_tri);
+    a.split = (const uint32_t*)c.dptr(G->off_split);
     std::vector<int32_t> tabs;
     tabs.insert(tabs.end(), T.tricode.begin(), T.tricode.end());
     tabs.insert(tabs.end(), T.p4code.begin(), T.p4code.end());
@@ -1324,6 +1387,7 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     hipEvent_t e0 = nullptr, e1 = nullptr;
     do {
         if (hipMemcpyAsync(tab, tabs.data(), 4 * tabs.size(), hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+            hipMemcpyAsync(ord, G->label_order.data(), sz_ord, hipMemcpyHostToDevice, c.stream) != hipSuccess ||
             launch_zero(a.counts, nslots * 4, c.stream)) {
             rc = fail(PM_E_DEVICE, "FSM setup failed");
             break;
@@ -1376,7 +1440,7 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     pm_query_stats st{};
     st.kernel_ms = kms;
     st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    st.launches = 3;
+    st.launches = 4;
     st.num_alt = (uint32_t)nslots;
     c.last_stats = st;
     return PM_OK;

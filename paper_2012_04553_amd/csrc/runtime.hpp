@@ -70,6 +70,8 @@ struct LaunchSet {
     KArgs base{};
     std::vector<std::pair<int, int>> runs;   // contiguous plan ranges, one launch each
     std::vector<int> run_agg;
+    const KItem* agg_items = nullptr;        // work items of the two-hop launches
+    uint32_t agg_nitems = 0;
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
@@ -92,6 +94,7 @@ struct GraphRes {
              off_items = UINT64_MAX;
     uint64_t device_bytes = 0;
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
+    std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
     std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
@@ -124,7 +127,8 @@ struct Ctx_ {
     uint64_t item_budget = 4096;
     uint32_t item_split = 2048;
     bool count_bytes = false;
-    uint64_t agg_waves_opt = 512;
+    uint64_t agg_waves_opt = 2048;
+    uint32_t agg_split = 256;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
@@ -145,7 +149,14 @@ struct Ctx_ {
         return c.grid_override > 0 ? c.grid_override : num_cus * c.blocks_per_cu;
     }
     uint64_t waves(const LaunchCfg& c) const { return (uint64_t)grid_blocks(c) * (block / 64); }
-    uint64_t agg_waves(const LaunchCfg& c) const { return std::min<uint64_t>(agg_waves_opt, waves(c)); }
+    // wavefronts of the two-hop aggregation launches on an n-vertex graph:
+    // each holds two dense u32[n] arrays, so their number follows from a
+    // memory budget (a quarter of the arena, at most 8 GiB)
+    uint64_t agg_waves(const LaunchCfg& c, uint32_t n) const {
+        const uint64_t budget = std::min<uint64_t>(8ull << 30, arena.size / 4);
+        const uint64_t by_mem = std::max<uint64_t>(64, budget / (8ull * std::max<uint32_t>(n, 1)));
+        return std::min<uint64_t>(std::min<uint64_t>(agg_waves_opt, waves(c)), by_mem);
+    }
     LaunchCfg default_cfg() const { return LaunchCfg{blocks_per_cu, item_budget, item_split}; }
     std::string closure_key(const GraphRes& G, const std::vector<Pat>& closure) const;
     LaunchCfg cfg_for(const GraphRes& G, const std::vector<Pat>& closure) const;
@@ -189,6 +200,7 @@ struct Ctx_ {
     uint64_t bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
     int launch(GraphRes& G, Query& Q);
+    int evict_idle();
     int wait(uint64_t ticket, int64_t* out, int64_t timeout_us);
 };
 

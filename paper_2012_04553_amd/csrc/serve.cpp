@@ -20,6 +20,8 @@
 #include <deque>
 #include <thread>
 
+#include <cstdio>
+
 #include "runtime.hpp"
 
 namespace pm {
@@ -246,6 +248,10 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                 ++finished;
             }
             last_done = std::max(last_done, tdone);
+            if (cfg->progress_every && finished / cfg->progress_every !=
+                                           (finished - B.reqs.size()) / cfg->progress_every)
+                fprintf(stderr, "pm_serve: %u of %u requests finished at %.2f s\n", (unsigned)finished,
+                        (unsigned)nreq, tdone);
             used -= B.bytes;
             free_launchset(&B.ls);
             s.batch.reset();
