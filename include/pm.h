@@ -201,6 +201,10 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "agg_split"     target-range slices of a high-degree root in two-hop
  *                   aggregation launches: one slice per this many
  *                   adjacency entries (>= 64, default 256);
+ *   "heavy_roots"   0/1 (default 1): when every two-hop plan of a query
+ *                   aggregates at its first level, the highest-degree roots
+ *                   get one shared counter array each, filled by many
+ *                   waves in one launch and evaluated in the next;
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
  *                   hipGraph on first use and replay it afterwards.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */

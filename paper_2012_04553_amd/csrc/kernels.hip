@@ -475,6 +475,17 @@ __device__ void lanes_level(Ctx& c, const uint32_t* vv, bool valid, int j, u128&
 
 // ---------------------------------------------------------------- aggregation
 
+// A wave's private counter array is touched by that wave only, so its
+// read-modify-writes need workgroup scope: they complete in the L2 of the
+// wave's own XCD instead of travelling to memory as device-scope atomics.
+// Every access to such an array goes through these two.
+__device__ __forceinline__ uint32_t wave_add(uint32_t* p) {
+    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t wave_take(uint32_t* p) {
+    return __hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Two-hop aggregation for the last core level j: targets x reached from
 // bridges y in N(v_src) (bridge bounds and label) are counted in a per-wave
 // dense array; the bridges' lists are streamed flattened, 64 bridges at a
@@ -541,7 +552,7 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
             for (int i = 0; i < KMAX; ++i)
                 if (((L.neq >> i) & 1) && x == c.v[i]) skip = true;
             if (skip) continue;
-            if (atomicAdd(&cnt[x], 1u) == 0u) touched[atomicAdd(s_touch, 1u)] = x;
+            if (wave_add(&cnt[x]) == 0u) touched[atomicAdd(s_touch, 1u)] = x;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -556,14 +567,81 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
         uint32_t m = 0;
         if (valid) {
             const uint32_t x = touched[idx];
-            m = cnt[x];
-            cnt[x] = 0;
+            m = wave_take(&cnt[x]);
             vv[j] = x;
         }
         acc += lanes_tail<BYTES>(c, vv, valid, m);
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
+}
+
+// Heavy roots of a plan whose first level is the aggregation level.  Item
+// (r0 = root, r1 = h, s0..s1 = bridge positions) adds one to the shared
+// counter of every target reached through those bridges; a later launch
+// evaluates the counters of targets [s0, s1).  The checks on bridges and
+// targets are those of agg_level.
+template <bool BYTES>
+__device__ void heavy_accumulate(Ctx& c, const KItem& item, uint32_t* arr) {
+    const DPlan* P = c.P;
+    const DLevel L = P->lev[1];
+    const int lane = wave_lane();
+    c.v[0] = item.r0;
+    uint32_t blo, bhi, lo, hi;
+    bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
+    bounds_of(c.v, L.gt, L.lt, lo, hi);
+    if (blo >= bhi || lo >= hi) return;
+    uint32_t bb, be;
+    list_range(c.g, c.v[0], blo, bhi, bb, be);
+    const uint32_t b0 = bb + min(item.s0, be - bb), b1 = bb + min(item.s1, be - bb);
+    if (b0 >= b1) return;
+    if (BYTES && lane == 0) c.bytes += 4ull * (b1 - b0) + (item.s0 == 0 ? 8 : 0);
+    for (uint32_t base = b0; base < b1; base += 64) {
+        const uint32_t idx = base + lane;
+        bool valid = idx < b1;
+        const uint32_t y = valid ? c.g.col[idx] : 0u;
+        if (valid && P->bridge_label >= 0 && c.g.lab[y] != (uint8_t)P->bridge_label) valid = false;
+        valid = valid && (y != c.v[0]);
+        uint32_t yb = 0, yf = 0;
+        if (valid) {
+            list_range(c.g, y, lo, hi, yb, yf);
+            if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
+        }
+        const uint32_t len = yf - yb;
+        const uint32_t incl = wave_incl_scan(len);
+        const uint32_t total = __shfl(incl, 63);
+        const uint32_t excl = incl - len;
+        for (uint32_t tb = 0; tb < total; tb += 64) {
+            const uint32_t t = tb + lane;
+            const bool act = t < total;
+            const int o = owner_of(incl, act ? t : total - 1);
+            const uint32_t src = __shfl(yb, o) + (t - __shfl(excl, o));
+            if (!act) continue;
+            const uint32_t x = c.g.col[src];
+            if (L.label >= 0 && c.g.lab[x] != (uint8_t)L.label) continue;
+            if (((L.neq & 1) && x == c.v[0])) continue;
+            atomicAdd(&arr[x], 1u);
+        }
+    }
+}
+
+template <bool BYTES>
+__device__ void heavy_evaluate(Ctx& c, const KItem& item, const uint32_t* arr, u128& acc) {
+    const DLevel L = c.P->lev[1];
+    const int lane = wave_lane();
+    c.v[0] = item.r0;
+    uint32_t lo, hi;
+    bounds_of(c.v, L.gt, L.lt, lo, hi);
+    const uint32_t x0 = max(lo, item.s0), x1 = min(hi == NOB ? c.g.n : hi, item.s1);
+    uint32_t vv[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
+    for (uint32_t base = x0; base < x1; base += 64) {
+        const uint32_t x = base + lane;
+        const uint32_t m = x < x1 ? arr[x] : 0u;
+        vv[1] = x;
+        acc += lanes_tail<BYTES>(c, vv, m != 0, m);
+    }
 }
 
 // ---------------------------------------------------------------- bitmap cliques
@@ -747,6 +825,13 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
         c.P = P;
         const int nc = P->ncore;
         const int8_t rl = P->lev[0].label;
+        if (a.agg_mode) {
+            if (rl >= 0 && a.g.lab[item.r0] != (uint8_t)rl) continue;
+            uint32_t* arr = a.heavy + ((uint64_t)pi * a.heavy_k + item.r1) * a.g.n;
+            if (a.agg_mode == 1) heavy_accumulate<BYTES>(c, item, arr);
+            else heavy_evaluate<BYTES>(c, item, arr, acc);
+            continue;
+        }
         if (nc == 1) {
             // lanes take roots; every tail term is evaluated per lane
             if (item.s0 != 0 || P->nterm == 0) continue;
@@ -856,10 +941,15 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     }
 }
 
+// Clears `words` 32-bit words; four at a time (the region is 16-byte
+// aligned), then the tail.
 __global__ void zero_kernel(uint32_t* p, uint64_t words) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
+    const uint64_t quads = words / 4;
+    uint4* q = (uint4*)p;
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = t; i < quads; i += step) q[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (uint64_t i = quads * 4 + t; i < words; i += step) p[i] = 0u;
 }
 
 int launch_zero(uint32_t* p, uint64_t words, hipStream_t s) {

@@ -36,6 +36,13 @@ struct KArgs {
     uint64_t* bytes;          // algorithmic bytes (counting launch only)
     uint32_t* rootbm;         // per-wave root adjacency bitmaps (bm_words each), zeroed
     uint64_t bm_words;
+    // two-hop plans whose aggregation is the first level: the heaviest roots
+    // run in two launches over one shared counter array per (plan, root):
+    // agg_mode 1 adds the paths of a slice of the root's bridges, agg_mode 2
+    // evaluates a range of targets.  0 = every other launch.
+    uint32_t agg_mode;
+    uint32_t heavy_k;         // heavy roots (arrays per plan)
+    uint32_t* heavy;          // (plan * heavy_k + h) * n counters, zeroed
     const int* cancel;        // host-visible cancel flag or null
 };
 

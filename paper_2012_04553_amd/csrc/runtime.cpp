@@ -378,8 +378,44 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     return PM_OK;
 }
 
+// Heavy roots of the two-hop launches: when every aggregation plan
+// aggregates at its first level, the highest-degree roots (degree >= 256)
+// get one shared counter array per (plan, root), as many as a quarter of the
+// arena allows (at most 4 GiB).  Returns their number; *p_agg = plans.
+uint32_t Ctx_::heavy_count(const GraphRes& G, const std::vector<PlanInfo>& plans, uint32_t* p_agg) const {
+    uint32_t pa = 0;
+    *p_agg = 0;
+    for (const PlanInfo& p : plans) {
+        if (!p.d.agg_last) continue;
+        if (p.d.ncore != 2 || p.d.bridge_src != 0) return 0;
+        ++pa;
+    }
+    *p_agg = pa;
+    if (!pa || !heavy_roots_opt) return 0;
+    const uint64_t budget = std::min<uint64_t>(4ull << 30, arena.size / 8);
+    const uint64_t k = budget / (4ull * std::max<uint32_t>(G.n, 1) * pa);
+    uint32_t cnt = 0;
+    for (int64_t r = (int64_t)G.n - 1; r >= 0 && cnt < k; --r) {
+        if (G.host_rp[r + 1] - G.host_rp[r] < 256) break;
+        ++cnt;
+    }
+    return cnt;
+}
+
+// Work items of the heavy-root launches: bridge slices, then target ranges.
+static void heavy_items(const std::vector<uint32_t>& rp, uint32_t n, uint32_t k, std::vector<KItem>* acc,
+                        std::vector<KItem>* ev) {
+    acc->clear();
+    ev->clear();
+    for (uint32_t h = 0; h < k; ++h) {
+        const uint32_t r = n - 1 - h, d = rp[r + 1] - rp[r];
+        for (uint32_t b = 0; b < d; b += 64) acc->push_back({r, h, b, b + 64});
+        for (uint32_t x = 0; x < n; x += 65536) ev->push_back({r, h, x, std::min<uint32_t>(n, x + 65536)});
+    }
+}
+
 uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg,
-                         uint64_t* scratch_stride, bool* any_agg) const {
+                         uint64_t* scratch_stride, bool* any_agg, bool heavy_ok) const {
     uint64_t stride = 1;
     bool agg = false;
     for (const PlanInfo& p : plans) {
@@ -403,6 +439,19 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     b += sizeof(DPlan) * plans.size() + 16 * plans.size() + 512 + 256 * 4;
     b += waves(cfg) * (uint64_t)KMAX * stride * 4;
     b += waves(cfg) * bitmap_words(G, plans) * 4;
+    uint32_t pa = 0;
+    const uint32_t hk = heavy_ok ? heavy_count(G, plans, &pa) : 0;
+    if (hk) {
+        uint64_t items = 0;
+        for (uint32_t h = 0; h < hk; ++h) {
+            const uint32_t r = G.n - 1 - h;
+            items += (G.host_rp[r + 1] - G.host_rp[r] + 63) / 64 + (G.n + 65535) / 65536;
+        }
+        items += G.n;   // light items: at most one per root, plus hub slices
+        for (uint32_t r = 0; r + hk < G.n; ++r) items += (G.host_rp[r + 1] - G.host_rp[r]) / agg_split;
+        b += 16 * items + 3 * 256;
+        b += 4ull * G.n * hk * pa;
+    }
     return b;
 }
 
@@ -494,7 +543,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     if (!st) st = stream;
     ls->np = np;
     ls->cfg = cfg;
-    uint64_t need = footprint(G, plans, cfg, &ls->stride, &ls->any_agg);
+    uint64_t need = footprint(G, plans, cfg, &ls->stride, &ls->any_agg, agg == nullptr);
+    uint32_t p_agg = 0;
+    const uint32_t hk = agg == nullptr ? heavy_count(G, plans, &p_agg) : 0;
     HIPCHK(hipSetDevice(device));
     if (ls->any_agg && !agg) {
         int rc = ensure_agg(G.n, cfg);
@@ -515,6 +566,11 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     }
     ls->agg_items = (const KItem*)dptr(isa->off);
     ls->agg_nitems = isa->count;
+    std::vector<KItem> light, hacc, hev;
+    if (hk) {
+        light = build_items(G.host_rp, G.n - hk, cfg.item_budget, agg_split, 256);
+        heavy_items(G.host_rp, G.n, hk, &hacc, &hev);
+    }
     ls->off_mem = arena.alloc(need);
     if (ls->off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
     char* base = (char*)dptr(ls->off_mem);
@@ -529,8 +585,28 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     // together by the zero-fill at the head of every replay
     const uint64_t bm_words = bitmap_words(G, plans);
     const uint64_t zhead = (16 * np + 512 + 255) & ~uint64_t(255);
-    const uint64_t zbytes = zhead + waves(cfg) * bm_words * 4;
+    const uint64_t zbm = (waves(cfg) * bm_words * 4 + 255) & ~uint64_t(255);
+    const uint64_t zheavy = 4ull * G.n * hk * p_agg;
+    const uint64_t zbytes = zhead + zbm + zheavy;
     char* zb = carve(zbytes);
+    uint32_t* heavy = hk ? (uint32_t*)(zb + zhead + zbm) : nullptr;
+    ls->heavy_k = hk;
+    ls->heavy_acc = ls->heavy_ev = nullptr;
+    ls->heavy_nacc = ls->heavy_nev = 0;
+    if (hk) {
+        KItem* li = (KItem*)carve(16 * light.size());
+        KItem* ai = (KItem*)carve(16 * hacc.size());
+        KItem* ei = (KItem*)carve(16 * hev.size());
+        HIPCHK(hipMemcpyAsync(li, light.data(), 16 * light.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ai, hacc.data(), 16 * hacc.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ei, hev.data(), 16 * hev.size(), hipMemcpyHostToDevice, st));
+        ls->agg_items = li;
+        ls->agg_nitems = (uint32_t)light.size();
+        ls->heavy_acc = ai;
+        ls->heavy_nacc = (uint32_t)hacc.size();
+        ls->heavy_ev = ei;
+        ls->heavy_nev = (uint32_t)hev.size();
+    }
     ls->zero_base = (uint32_t*)zb;
     ls->zero_words = zbytes / 4;
     ls->counters = (uint64_t*)zb;
@@ -578,6 +654,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     a.cancel = ls->cancel_dev;
     a.rootbm = rootbm;
     a.bm_words = bm_words;
+    a.agg_mode = 0;
+    a.heavy_k = hk;
+    a.heavy = heavy;
     if (ls->any_agg) {
         if (agg) {
             a.aggcnt = agg->cnt;
@@ -598,8 +677,16 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         while (j < (int)np && (plans[j].d.agg_last ? 1 : 0) == grp) ++j;
         ls->runs.push_back({i, j});
         ls->run_agg.push_back(grp);
+        if (grp && hk) {
+            // heavy roots: accumulate, then evaluate
+            ls->runs.push_back({i, j});
+            ls->run_agg.push_back(2);
+            ls->runs.push_back({i, j});
+            ls->run_agg.push_back(3);
+        }
         i = j;
     }
+    if (hk) HIPCHK(hipStreamSynchronize(st));
     return PM_OK;
 }
 
@@ -615,11 +702,17 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         b.nplans = ls.runs[r].second - ls.runs[r].first;
         b.counters = ls.counters + 2 * ls.runs[r].first;
         b.head = ls.heads + r;
-        if (ls.run_agg[r]) {
+        int gb = grid_blocks(cfg);
+        if (ls.run_agg[r] == 1) {
             b.items = ls.agg_items;
             b.nitems = ls.agg_nitems;
+            gb = (int)std::max<uint64_t>(1, ls.agg_w / (block / 64));
+        } else if (ls.run_agg[r] >= 2) {
+            b.agg_mode = ls.run_agg[r] - 1;
+            b.items = ls.run_agg[r] == 2 ? ls.heavy_acc : ls.heavy_ev;
+            b.nitems = ls.run_agg[r] == 2 ? ls.heavy_nacc : ls.heavy_nev;
         }
-        int gb = ls.run_agg[r] ? (int)std::max<uint64_t>(1, ls.agg_w / (block / 64)) : grid_blocks(cfg);
+        if (b.nitems == 0) continue;
         if (launch_match(b, gb, block, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
     }
     if (bytes_pass) {
@@ -1194,6 +1287,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "item_split" && value >= 64) c.item_split = (uint32_t)value;
     else if (k == "agg_waves" && value >= 1) c.agg_waves_opt = (uint64_t)value;
     else if (k == "agg_split" && value >= 64 && value <= 0x7fffffff) c.agg_split = (uint32_t)value;
+    else if (k == "heavy_roots" && (value == 0 || value == 1)) c.heavy_roots_opt = value != 0;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;

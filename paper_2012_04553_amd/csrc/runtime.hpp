@@ -69,9 +69,13 @@ struct LaunchSet {
     bool any_agg = false;
     KArgs base{};
     std::vector<std::pair<int, int>> runs;   // contiguous plan ranges, one launch each
-    std::vector<int> run_agg;
+    std::vector<int> run_agg;                // 0 plain, 1 two-hop, 2/3 heavy-root accumulate/evaluate
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
+    uint32_t heavy_k = 0;                    // heavy roots (shared counter arrays)
+    const KItem* heavy_acc = nullptr;        // their accumulate items
+    const KItem* heavy_ev = nullptr;         // their evaluate items
+    uint32_t heavy_nacc = 0, heavy_nev = 0;
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
@@ -129,6 +133,7 @@ struct Ctx_ {
     bool count_bytes = false;
     uint64_t agg_waves_opt = 2048;
     uint32_t agg_split = 256;
+    bool heavy_roots_opt = true;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
@@ -195,7 +200,8 @@ struct Ctx_ {
     int plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
                      std::vector<PlanInfo>* plans);
     uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c,
-                       uint64_t* stride, bool* any_agg) const;
+                       uint64_t* stride, bool* any_agg, bool heavy_ok = true) const;
+    uint32_t heavy_count(const GraphRes& G, const std::vector<PlanInfo>& plans, uint32_t* p_agg) const;
     int ensure_agg(uint32_t n, const LaunchCfg& c);
     uint64_t bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);

@@ -311,7 +311,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             lc.grid_override = std::max(1, (int)(num_cus * 2 / cfg->max_slots));
             uint64_t stride;
             bool any_agg;
-            B->bytes = footprint(G, B->plans, lc, &stride, &any_agg);
+            B->bytes = footprint(G, B->plans, lc, &stride, &any_agg, false);
             if (B->bytes > cfg->budget_bytes) {
                 for (uint32_t r : B->reqs) {
                     res[r].status = PM_E_NOMEM;
