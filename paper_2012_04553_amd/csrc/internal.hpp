@@ -106,6 +106,23 @@ struct DPlan {
     DMono mono[MAX_MONO];
 };
 
+// Edge-core plans whose set-size terms all intersect N(v0) and N(v1): the
+// heavy roots of such plans can run in edge_window_kernel.
+constexpr uint32_t EW_TERMS = 4;
+inline bool edge_window_ok(const DPlan& d) {
+    if (d.ncore != 2 || d.agg_last || d.local || d.nterm == 0) return false;
+    const DLevel& L = d.lev[1];
+    if (L.adj != 1 || L.anti != 0 || L.base != 0xff) return false;
+    uint32_t heavy_terms = 0;
+    for (int q = 0; q < d.nterm; ++q) {
+        const DTerm& t = d.term[q];
+        if (t.cheap || t.agg) continue;
+        if (t.adj != 3 || t.anti != 0 || ((t.gt | t.lt | t.neq) & ~3u)) return false;
+        ++heavy_terms;
+    }
+    return heavy_terms >= 1 && heavy_terms <= EW_TERMS;
+}
+
 struct PlanInfo {
     DPlan d;
     Pat pat;

@@ -576,74 +576,6 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
     __builtin_amdgcn_wave_barrier();
 }
 
-// Heavy roots of a plan whose first level is the aggregation level.  Item
-// (r0 = root, r1 = h, s0..s1 = bridge positions) adds one to the shared
-// counter of every target reached through those bridges; a later launch
-// evaluates the counters of targets [s0, s1).  The checks on bridges and
-// targets are those of agg_level.
-template <bool BYTES>
-__device__ void heavy_accumulate(Ctx& c, const KItem& item, uint32_t* arr) {
-    const DPlan* P = c.P;
-    const DLevel L = P->lev[1];
-    const int lane = wave_lane();
-    c.v[0] = item.r0;
-    uint32_t blo, bhi, lo, hi;
-    bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
-    bounds_of(c.v, L.gt, L.lt, lo, hi);
-    if (blo >= bhi || lo >= hi) return;
-    uint32_t bb, be;
-    list_range(c.g, c.v[0], blo, bhi, bb, be);
-    const uint32_t b0 = bb + min(item.s0, be - bb), b1 = bb + min(item.s1, be - bb);
-    if (b0 >= b1) return;
-    if (BYTES && lane == 0) c.bytes += 4ull * (b1 - b0) + (item.s0 == 0 ? 8 : 0);
-    for (uint32_t base = b0; base < b1; base += 64) {
-        const uint32_t idx = base + lane;
-        bool valid = idx < b1;
-        const uint32_t y = valid ? c.g.col[idx] : 0u;
-        if (valid && P->bridge_label >= 0 && c.g.lab[y] != (uint8_t)P->bridge_label) valid = false;
-        valid = valid && (y != c.v[0]);
-        uint32_t yb = 0, yf = 0;
-        if (valid) {
-            list_range(c.g, y, lo, hi, yb, yf);
-            if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
-        }
-        const uint32_t len = yf - yb;
-        const uint32_t incl = wave_incl_scan(len);
-        const uint32_t total = __shfl(incl, 63);
-        const uint32_t excl = incl - len;
-        for (uint32_t tb = 0; tb < total; tb += 64) {
-            const uint32_t t = tb + lane;
-            const bool act = t < total;
-            const int o = owner_of(incl, act ? t : total - 1);
-            const uint32_t src = __shfl(yb, o) + (t - __shfl(excl, o));
-            if (!act) continue;
-            const uint32_t x = c.g.col[src];
-            if (L.label >= 0 && c.g.lab[x] != (uint8_t)L.label) continue;
-            if (((L.neq & 1) && x == c.v[0])) continue;
-            atomicAdd(&arr[x], 1u);
-        }
-    }
-}
-
-template <bool BYTES>
-__device__ void heavy_evaluate(Ctx& c, const KItem& item, const uint32_t* arr, u128& acc) {
-    const DLevel L = c.P->lev[1];
-    const int lane = wave_lane();
-    c.v[0] = item.r0;
-    uint32_t lo, hi;
-    bounds_of(c.v, L.gt, L.lt, lo, hi);
-    const uint32_t x0 = max(lo, item.s0), x1 = min(hi == NOB ? c.g.n : hi, item.s1);
-    uint32_t vv[KMAX];
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
-    for (uint32_t base = x0; base < x1; base += 64) {
-        const uint32_t x = base + lane;
-        const uint32_t m = x < x1 ? arr[x] : 0u;
-        vv[1] = x;
-        acc += lanes_tail<BYTES>(c, vv, m != 0, m);
-    }
-}
-
 // ---------------------------------------------------------------- bitmap cliques
 
 // Cliques with a total order live in the out-neighbourhood C of the root:
@@ -825,13 +757,6 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
         c.P = P;
         const int nc = P->ncore;
         const int8_t rl = P->lev[0].label;
-        if (a.agg_mode) {
-            if (rl >= 0 && a.g.lab[item.r0] != (uint8_t)rl) continue;
-            uint32_t* arr = a.heavy + ((uint64_t)pi * a.heavy_k + item.r1) * a.g.n;
-            if (a.agg_mode == 1) heavy_accumulate<BYTES>(c, item, arr);
-            else heavy_evaluate<BYTES>(c, item, arr, acc);
-            continue;
-        }
         if (nc == 1) {
             // lanes take roots; every tail term is evaluated per lane
             if (item.s0 != 0 || P->nterm == 0) continue;
@@ -941,6 +866,280 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- heavy two-hop roots
+
+// Roots of a plan whose first level is the aggregation level and whose
+// two-hop mass is large: one workgroup takes one root and counts the paths
+// to each target in an LDS window of WIN_IDS consecutive target ids.
+// Device-scope atomics are executed in memory on this GPU, LDS atomics in
+// the CU, so the sweep is bounded by reading the bridges' lists.  Every
+// thread owns some of the root's bridges and keeps one cursor per bridge
+// (in scratch only it touches); each window starts at the smallest pending
+// target, so empty id ranges are never visited.  After a window is filled
+// the four waves evaluate its counters and clear them.
+constexpr uint32_t WIN_IDS = 8192;
+
+template <bool BYTES>
+__global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
+    __shared__ uint32_t win[WIN_IDS];
+    __shared__ uint32_t s_item, s_next;
+    const int lane = wave_lane();
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    Ctx c;
+    c.g = a.g;
+    c.stride = a.buf_stride;
+    c.buf = a.scratch + (uint64_t)wid * (uint64_t)KMAX * a.buf_stride;
+    c.bytes = 0;
+    c.bmw = nullptr;
+    c.bm = nullptr;
+    uint32_t* cur = a.wscr + (uint64_t)blockIdx.x * 2 * a.wscr_stride;  // cursor, end per bridge
+    uint32_t* fin = cur + a.wscr_stride;
+    for (uint32_t i = tid; i < WIN_IDS; i += blockDim.x) win[i] = 0;
+    int curp = -1;
+    u128 acc = 0;
+    const uint64_t total = (uint64_t)a.nplans * a.nitems;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t it = atomicAdd(a.head, 1u);
+            if (a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) it = 0xffffffffu;
+            s_item = it;
+        }
+        __syncthreads();
+        const uint32_t it = s_item;
+        if (it >= total) break;
+        const int pi = (int)(it / a.nitems);
+        const KItem item = a.items[it % a.nitems];
+        if (pi != curp) {
+            if (curp >= 0) flush(a, curp, acc);
+            acc = 0;
+            curp = pi;
+        }
+        const DPlan* P = a.plans + pi;
+        c.P = P;
+        const DLevel L = P->lev[1];
+        const uint32_t r = item.r0;
+        if (P->lev[0].label >= 0 && a.g.lab[r] != (uint8_t)P->lev[0].label) continue;
+        c.v[0] = r;
+        uint32_t blo, bhi, lo, hi;
+        bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
+        bounds_of(c.v, L.gt, L.lt, lo, hi);
+        if (blo >= bhi || lo >= hi) continue;
+        const uint32_t top = hi == NOB ? a.g.n : hi;
+        uint32_t bb, be;
+        list_range(c.g, r, blo, bhi, bb, be);
+        const uint32_t nb = be - bb;
+        if (BYTES && tid == 0) c.bytes += 8 + 4ull * nb;
+        // cursors of the owned bridges
+        for (uint32_t k = tid; k < nb; k += blockDim.x) {
+            const uint32_t y = c.g.col[bb + k];
+            uint32_t yb = 0, yf = 0;
+            const bool ok = y != r && (P->bridge_label < 0 || c.g.lab[y] == (uint8_t)P->bridge_label);
+            if (ok) {
+                list_range(c.g, y, lo, hi, yb, yf);
+                if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
+            }
+            cur[k] = yb;
+            fin[k] = yf;
+        }
+        uint32_t wlo = lo;
+        for (;;) {
+            // smallest pending target over all bridges
+            if (tid == 0) s_next = 0xffffffffu;
+            __syncthreads();
+            uint32_t mine = 0xffffffffu;
+            for (uint32_t k = tid; k < nb; k += blockDim.x)
+                if (cur[k] < fin[k]) mine = min(mine, c.g.col[cur[k]]);
+            if (mine != 0xffffffffu) atomicMin(&s_next, mine);
+            __syncthreads();
+            const uint32_t nx = s_next;
+            if (nx == 0xffffffffu || nx >= top) break;
+            wlo = max(wlo, nx);
+            const uint32_t whi = (uint32_t)min((uint64_t)top, (uint64_t)wlo + WIN_IDS);
+            // fill: every owned bridge advances through the window
+            for (uint32_t k = tid; k < nb; k += blockDim.x) {
+                uint32_t q = cur[k];
+                const uint32_t qe = fin[k];
+                while (q < qe) {
+                    const uint32_t x = c.g.col[q];
+                    if (x >= whi) break;
+                    ++q;
+                    if (L.label >= 0 && c.g.lab[x] != (uint8_t)L.label) continue;
+                    if ((L.neq & 1) && x == r) continue;
+                    atomicAdd(&win[x - wlo], 1u);
+                }
+                cur[k] = q;
+            }
+            __syncthreads();
+            // evaluate and clear: wave w takes a quarter of the window
+            uint32_t vv[KMAX];
+#pragma unroll
+            for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
+            const uint32_t span = whi - wlo;
+            const uint32_t part = WIN_IDS / 4, w0 = (tid >> 6) * part, w1 = min(w0 + part, span);
+            for (uint32_t base = w0; base < w1; base += 64) {
+                const uint32_t i = base + lane;
+                uint32_t m = 0;
+                if (i < w1) {
+                    m = win[i];
+                    win[i] = 0;
+                }
+                vv[1] = wlo + i;
+                acc += lanes_tail<BYTES>(c, vv, m != 0, m);
+            }
+            wlo = whi;
+        }
+    }
+    if (curp >= 0) flush(a, curp, acc);
+    if (BYTES) {
+        unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
+// ---------------------------------------------------------------- heavy edge-core roots
+
+// Plans with an edge core (v1 in N(v0)) whose set-size terms all intersect
+// N(v0) and N(v1) (the diamond's t = |N(v0) n N(v1)|).  For a root with a
+// large two-hop mass one workgroup takes the root: threads own level-1
+// candidates v1 and walk N(v1) with a cursor while the workgroup sweeps
+// N(v0) in windows of EW_BITS ids held as an LDS bitmap; every hit is
+// checked against each term's bounds, label and exclusions and counted per
+// candidate.  Each thread then evaluates the tail of its own candidates.
+// Scratch per block: cursor, end and EW_TERMS counters per candidate.
+constexpr uint32_t EW_BITS = 262144;
+constexpr uint32_t EW_WORDS = EW_BITS / 32;
+
+template <bool BYTES>
+__global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
+    __shared__ uint32_t bits[EW_WORDS];
+    __shared__ uint32_t s_item;
+    const int lane = wave_lane();
+    const uint32_t tid = threadIdx.x;
+    Ctx c;
+    c.g = a.g;
+    c.stride = a.buf_stride;
+    c.buf = nullptr;
+    c.bytes = 0;
+    c.bmw = nullptr;
+    c.bm = nullptr;
+    const uint64_t ws = a.wscr_stride;
+    uint32_t* ccur = a.wscr + (uint64_t)blockIdx.x * (2 + EW_TERMS) * ws;
+    uint32_t* cend = ccur + ws;
+    uint32_t* ccnt = cend + ws;   // EW_TERMS * ws, candidate-major
+    for (uint32_t i = tid; i < EW_WORDS; i += blockDim.x) bits[i] = 0;
+    int curp = -1;
+    u128 acc = 0;
+    const uint64_t total = (uint64_t)a.nplans * a.nitems;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t it = atomicAdd(a.head, 1u);
+            if (a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) it = 0xffffffffu;
+            s_item = it;
+        }
+        __syncthreads();
+        const uint32_t it = s_item;
+        if (it >= total) break;
+        const int pi = (int)(it / a.nitems);
+        const KItem item = a.items[it % a.nitems];
+        if (pi != curp) {
+            if (curp >= 0) flush(a, curp, acc);
+            acc = 0;
+            curp = pi;
+        }
+        const DPlan* P = a.plans + pi;
+        c.P = P;
+        const DLevel L1 = P->lev[1];
+        const uint32_t r = item.r0;
+        if (P->lev[0].label >= 0 && a.g.lab[r] != (uint8_t)P->lev[0].label) continue;
+        c.v[0] = r;
+        uint32_t lo1, hi1, cb, ce;
+        bounds_of(c.v, L1.gt, L1.lt, lo1, hi1);
+        if (lo1 >= hi1) continue;
+        list_range(c.g, r, lo1, hi1, cb, ce);
+        const uint32_t nb = ce - cb;
+        // non-cheap terms of the plan, in order (at most EW_TERMS)
+        int tq[EW_TERMS];
+        int nt = 0;
+        for (int q = 0; q < P->nterm; ++q)
+            if (!P->term[q].cheap && !P->term[q].agg && nt < (int)EW_TERMS) tq[nt++] = q;
+        if (BYTES && tid == 0) c.bytes += 8 + 4ull * nb;
+        for (uint32_t k = tid; k < nb; k += blockDim.x) {
+            const uint32_t v1 = c.g.col[cb + k];
+            const bool ok = L1.label < 0 || c.g.lab[v1] == (uint8_t)L1.label;
+            ccur[k] = ok ? c.g.rp[v1] : 0u;
+            cend[k] = ok ? c.g.rp[v1 + 1] : 0u;
+            for (int i = 0; i < nt; ++i) ccnt[(uint64_t)k * EW_TERMS + i] = 0;
+            if (BYTES && ok) c.bytes += (uint64_t)nt * (8 + 4ull * (c.g.rp[v1 + 1] - c.g.rp[v1]) + 4ull * (c.g.rp[r + 1] - c.g.rp[r]));
+        }
+        // windows over N(v0)
+        uint32_t pos = c.g.rp[r];
+        const uint32_t pend_all = c.g.rp[r + 1];
+        while (pos < pend_all) {
+            const uint32_t wlo = c.g.col[pos];
+            const uint32_t whi = (uint32_t)min((uint64_t)c.g.n, (uint64_t)wlo + EW_BITS);
+            const uint32_t pend = lower_bound_u32(c.g.col, pos, pend_all, whi);
+            for (uint32_t i = pos + tid; i < pend; i += blockDim.x) {
+                const uint32_t o = c.g.col[i] - wlo;
+                atomicOr(&bits[o >> 5], 1u << (o & 31));
+            }
+            __syncthreads();
+            for (uint32_t k = tid; k < nb; k += blockDim.x) {
+                uint32_t q = ccur[k];
+                const uint32_t qe = cend[k];
+                if (q >= qe) continue;
+                uint32_t vv[KMAX] = {r, c.g.col[cb + k], 0, 0, 0};
+                uint32_t add[EW_TERMS] = {0, 0, 0, 0};
+                while (q < qe) {
+                    const uint32_t x = c.g.col[q];
+                    if (x >= whi) break;
+                    ++q;
+                    if (x < wlo) continue;
+                    const uint32_t o = x - wlo;
+                    if (!((bits[o >> 5] >> (o & 31)) & 1u)) continue;
+                    for (int i = 0; i < nt; ++i) {
+                        const DTerm t = P->term[tq[i]];
+                        uint32_t lo, hi;
+                        bounds_of(vv, t.gt, t.lt, lo, hi);
+                        if (x < lo || x >= hi) continue;
+                        if (t.label >= 0 && c.g.lab[x] != (uint8_t)t.label) continue;
+                        if (((t.neq & 1) && x == vv[0]) || ((t.neq & 2) && x == vv[1])) continue;
+                        ++add[i];
+                    }
+                }
+                ccur[k] = q;
+                for (int i = 0; i < nt; ++i) ccnt[(uint64_t)k * EW_TERMS + i] += add[i];
+            }
+            __syncthreads();
+            for (uint32_t i = pos + tid; i < pend; i += blockDim.x) bits[(c.g.col[i] - wlo) >> 5] = 0u;
+            __syncthreads();
+            pos = pend;
+        }
+        // tails of the owned candidates
+        for (uint32_t k = tid; k < nb; k += blockDim.x) {
+            if (cend[k] == 0u && ccur[k] == 0u) continue;   // label-filtered candidate
+            uint32_t vv[KMAX] = {r, c.g.col[cb + k], 0, 0, 0};
+            uint64_t tv[MAX_TERMS];
+            int i = 0;
+            for (int q = 0; q < P->nterm; ++q) {
+                const DTerm t = P->term[q];
+                if (!t.cheap && !t.agg && i < nt && tq[i] == q) tv[q] = ccnt[(uint64_t)k * EW_TERMS + i++];
+                else tv[q] = cheap_term<BYTES>(c, vv, t, 0);
+            }
+            acc += poly_eval(P, tv);
+        }
+    }
+    if (curp >= 0) flush(a, curp, acc);
+    if (BYTES) {
+        unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
 // Clears `words` 32-bit words; four at a time (the region is 16-byte
 // aligned), then the tail.
 __global__ void zero_kernel(uint32_t* p, uint64_t words) {
@@ -956,6 +1155,22 @@ int launch_zero(uint32_t* p, uint64_t words, hipStream_t s) {
     int grid = (int)std::min<uint64_t>(1024, (words + 255) / 256);
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(zero_kernel, dim3(grid), dim3(256), 0, s, p, words);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes)
+        hipLaunchKernelGGL(edge_window_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(edge_window_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes)
+        hipLaunchKernelGGL(agg_window_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(agg_window_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -36,17 +36,19 @@ struct KArgs {
     uint64_t* bytes;          // algorithmic bytes (counting launch only)
     uint32_t* rootbm;         // per-wave root adjacency bitmaps (bm_words each), zeroed
     uint64_t bm_words;
-    // two-hop plans whose aggregation is the first level: the heaviest roots
-    // run in two launches over one shared counter array per (plan, root):
-    // agg_mode 1 adds the paths of a slice of the root's bridges, agg_mode 2
-    // evaluates a range of targets.  0 = every other launch.
-    uint32_t agg_mode;
-    uint32_t heavy_k;         // heavy roots (arrays per plan)
-    uint32_t* heavy;          // (plan * heavy_k + h) * n counters, zeroed
+    // heavy two-hop roots (agg_window_kernel): per block, a cursor and an
+    // end position for each bridge of the current root
+    uint32_t* wscr;           // blocks * (2 + EW_TERMS) * wscr_stride
+    uint64_t wscr_stride;
     const int* cancel;        // host-visible cancel flag or null
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
+// Heavy roots of first-level two-hop plans: one workgroup (256 threads) per
+// root, items {root, 0, 0, 0}.
+int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Heavy roots of edge-core plans (edge_window_ok): one workgroup per root.
+int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Clears `words` 32-bit words (used instead of memset nodes inside graphs).
 int launch_zero(uint32_t* p, uint64_t words, hipStream_t s);
 

@@ -260,6 +260,15 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     HIPCHK(hipMemcpyAsync(dptr(G->off_split), nsplit.data(), 4ull * n, hipMemcpyHostToDevice, stream));
     if (labels) HIPCHK(hipMemcpyAsync(dptr(G->off_lab), nlab.data(), n, hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
+    // two-hop mass: summed degrees of the lower neighbours (entries before split)
+    G->two_hop.assign(n, 0);
+    parallel_for(n, [&](uint64_t b, uint64_t e) {
+        for (uint64_t r = b; r < e; ++r) {
+            uint64_t w = 0;
+            for (uint32_t p = nrp[r]; p < nsplit[r]; ++p) w += nrp[ncol[p] + 1] - nrp[ncol[p]];
+            G->two_hop[r] = w;
+        }
+    });
     G->host_rp = std::move(nrp);
     if (labels) {
         // vertices by label (stable: degree order within a label), for the
@@ -366,9 +375,10 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     }
     std::vector<size_t> idx(cl.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
-        return pl[a].d.agg_last < pl[b].d.agg_last;
-    });
+    // plain plans, then edge-core plans, then two-hop plans: each group can
+    // run in launches of its own
+    auto group = [&](size_t a) { return pl[a].d.agg_last ? 2 : (edge_window_ok(pl[a].d) ? 1 : 0); };
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return group(a) < group(b); });
     closure->clear();
     plans->clear();
     for (size_t i : idx) {
@@ -379,39 +389,58 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
 }
 
 // Heavy roots of the two-hop launches: when every aggregation plan
-// aggregates at its first level, the highest-degree roots (degree >= 256)
-// get one shared counter array per (plan, root), as many as a quarter of the
-// arena allows (at most 4 GiB).  Returns their number; *p_agg = plans.
-uint32_t Ctx_::heavy_count(const GraphRes& G, const std::vector<PlanInfo>& plans, uint32_t* p_agg) const {
+// aggregates at its first level, roots whose two-hop mass (the summed
+// degrees of their lower neighbours) is large both absolutely and against
+// the id range a window sweep would cover run in agg_window_kernel, heaviest
+// first.  *p_agg = aggregation plans.
+std::vector<uint32_t> Ctx_::heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans,
+                                        uint32_t* p_agg) const {
+    std::vector<uint32_t> out;
     uint32_t pa = 0;
     *p_agg = 0;
     for (const PlanInfo& p : plans) {
         if (!p.d.agg_last) continue;
-        if (p.d.ncore != 2 || p.d.bridge_src != 0) return 0;
+        if (p.d.ncore != 2 || p.d.bridge_src != 0) return out;
         ++pa;
     }
     *p_agg = pa;
-    if (!pa || !heavy_roots_opt) return 0;
-    const uint64_t budget = std::min<uint64_t>(4ull << 30, arena.size / 8);
-    const uint64_t k = budget / (4ull * std::max<uint32_t>(G.n, 1) * pa);
-    uint32_t cnt = 0;
-    for (int64_t r = (int64_t)G.n - 1; r >= 0 && cnt < k; --r) {
-        if (G.host_rp[r + 1] - G.host_rp[r] < 256) break;
-        ++cnt;
+    if (!pa || !heavy_roots_opt) return out;
+    for (uint32_t r = 0; r < G.n; ++r) {
+        const uint64_t w = G.two_hop[r];
+        if (w >= 16384 && w * 8 >= r) out.push_back(r);
     }
-    return cnt;
+    std::stable_sort(out.begin(), out.end(),
+                     [&](uint32_t x, uint32_t y) { return G.two_hop[x] > G.two_hop[y]; });
+    return out;
 }
 
-// Work items of the heavy-root launches: bridge slices, then target ranges.
-static void heavy_items(const std::vector<uint32_t>& rp, uint32_t n, uint32_t k, std::vector<KItem>* acc,
-                        std::vector<KItem>* ev) {
-    acc->clear();
-    ev->clear();
-    for (uint32_t h = 0; h < k; ++h) {
-        const uint32_t r = n - 1 - h, d = rp[r + 1] - rp[r];
-        for (uint32_t b = 0; b < d; b += 64) acc->push_back({r, h, b, b + 64});
-        for (uint32_t x = 0; x < n; x += 65536) ev->push_back({r, h, x, std::min<uint32_t>(n, x + 65536)});
+// Heavy roots of edge-core plans: roots whose lower neighbours have a large
+// summed degree, heaviest first (none when no such plan is present).
+std::vector<uint32_t> Ctx_::edge_heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
+    std::vector<uint32_t> out;
+    bool any = false;
+    for (const PlanInfo& p : plans) any = any || (!p.d.agg_last && edge_window_ok(p.d));
+    if (!any || !heavy_roots_opt) return out;
+    for (uint32_t r = 0; r < G.n; ++r)
+        if (G.two_hop[r] >= 16384) out.push_back(r);
+    std::stable_sort(out.begin(), out.end(),
+                     [&](uint32_t x, uint32_t y) { return G.two_hop[x] > G.two_hop[y]; });
+    return out;
+}
+
+// Work items over every root except the heavy ones (ranges split around them).
+static std::vector<KItem> items_without(const std::vector<KItem>& all, const std::vector<uint8_t>& heavy) {
+    std::vector<KItem> out;
+    for (const KItem& it : all) {
+        uint32_t b = it.r0;
+        for (uint32_t r = it.r0; r <= it.r1; ++r) {
+            if (r == it.r1 || heavy[r]) {
+                if (r > b) out.push_back({b, r, it.s0, it.s1});
+                b = r + 1;
+            }
+        }
     }
+    return out;
 }
 
 uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg,
@@ -440,18 +469,22 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     b += waves(cfg) * (uint64_t)KMAX * stride * 4;
     b += waves(cfg) * bitmap_words(G, plans) * 4;
     uint32_t pa = 0;
-    const uint32_t hk = heavy_ok ? heavy_count(G, plans, &pa) : 0;
+    const size_t hk = heavy_ok ? heavy_roots(G, plans, &pa).size() : 0;
+    const size_t ek = heavy_ok ? edge_heavy_roots(G, plans).size() : 0;
+    const uint64_t wstride = ((uint64_t)G.max_deg + 63) & ~uint64_t(63);
     if (hk) {
-        uint64_t items = 0;
-        for (uint32_t h = 0; h < hk; ++h) {
-            const uint32_t r = G.n - 1 - h;
-            items += (G.host_rp[r + 1] - G.host_rp[r] + 63) / 64 + (G.n + 65535) / 65536;
-        }
-        items += G.n;   // light items: at most one per root, plus hub slices
-        for (uint32_t r = 0; r + hk < G.n; ++r) items += (G.host_rp[r + 1] - G.host_rp[r]) / agg_split;
-        b += 16 * items + 3 * 256;
-        b += 4ull * G.n * hk * pa;
+        // light items (at most one per root plus the hub slices), heavy items
+        uint64_t items = G.n + hk;
+        for (uint32_t r = 0; r < G.n; ++r) items += (G.host_rp[r + 1] - G.host_rp[r]) / agg_split;
+        b += 16 * items + 2 * 256;
     }
+    if (ek) {
+        uint64_t items = G.n + ek;
+        for (uint32_t r = 0; r < G.n; ++r) items += (G.host_rp[r + 1] - G.host_rp[r]) / cfg.item_split;
+        b += 16 * items + 2 * 256;
+    }
+    // per block: cursor, end and counter words per bridge or candidate
+    if (hk || ek) b += (uint64_t)grid_blocks(cfg) * (2 + EW_TERMS) * wstride * 4 + 256;
     return b;
 }
 
@@ -545,7 +578,10 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->cfg = cfg;
     uint64_t need = footprint(G, plans, cfg, &ls->stride, &ls->any_agg, agg == nullptr);
     uint32_t p_agg = 0;
-    const uint32_t hk = agg == nullptr ? heavy_count(G, plans, &p_agg) : 0;
+    const std::vector<uint32_t> heavy = agg == nullptr ? heavy_roots(G, plans, &p_agg) : std::vector<uint32_t>();
+    const uint32_t hk = (uint32_t)heavy.size();
+    const std::vector<uint32_t> eheavy = agg == nullptr ? edge_heavy_roots(G, plans) : std::vector<uint32_t>();
+    const uint32_t ek = (uint32_t)eheavy.size();
     HIPCHK(hipSetDevice(device));
     if (ls->any_agg && !agg) {
         int rc = ensure_agg(G.n, cfg);
@@ -566,10 +602,23 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     }
     ls->agg_items = (const KItem*)dptr(isa->off);
     ls->agg_nitems = isa->count;
-    std::vector<KItem> light, hacc, hev;
+    std::vector<KItem> light, hitems;
     if (hk) {
-        light = build_items(G.host_rp, G.n - hk, cfg.item_budget, agg_split, 256);
-        heavy_items(G.host_rp, G.n, hk, &hacc, &hev);
+        std::vector<uint8_t> is_heavy(G.n, 0);
+        for (uint32_t r : heavy) {
+            is_heavy[r] = 1;
+            hitems.push_back({r, 0, 0, 0});
+        }
+        light = items_without(build_items(G.host_rp, G.n, cfg.item_budget, agg_split, 256), is_heavy);
+    }
+    std::vector<KItem> elight, eitems;
+    if (ek) {
+        std::vector<uint8_t> is_heavy(G.n, 0);
+        for (uint32_t r : eheavy) {
+            is_heavy[r] = 1;
+            eitems.push_back({r, 0, 0, 0});
+        }
+        elight = items_without(build_items(G.host_rp, G.n, cfg.item_budget, cfg.item_split, 256), is_heavy);
     }
     ls->off_mem = arena.alloc(need);
     if (ls->off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
@@ -586,26 +635,36 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const uint64_t bm_words = bitmap_words(G, plans);
     const uint64_t zhead = (16 * np + 512 + 255) & ~uint64_t(255);
     const uint64_t zbm = (waves(cfg) * bm_words * 4 + 255) & ~uint64_t(255);
-    const uint64_t zheavy = 4ull * G.n * hk * p_agg;
-    const uint64_t zbytes = zhead + zbm + zheavy;
+    const uint64_t zbytes = zhead + zbm;
     char* zb = carve(zbytes);
-    uint32_t* heavy = hk ? (uint32_t*)(zb + zhead + zbm) : nullptr;
-    ls->heavy_k = hk;
-    ls->heavy_acc = ls->heavy_ev = nullptr;
-    ls->heavy_nacc = ls->heavy_nev = 0;
+    ls->heavy_items = nullptr;
+    ls->heavy_nitems = 0;
+    uint32_t* wscr = nullptr;
+    const uint64_t wstride = ((uint64_t)G.max_deg + 63) & ~uint64_t(63);
+    if (hk || ek) wscr = (uint32_t*)carve((uint64_t)grid_blocks(cfg) * (2 + EW_TERMS) * wstride * 4);
+    ls->edge_items = ls->edge_heavy = nullptr;
+    ls->edge_nitems = ls->edge_nheavy = 0;
+    if (ek) {
+        KItem* li = (KItem*)carve(16 * std::max<size_t>(1, elight.size()));
+        KItem* hi = (KItem*)carve(16 * eitems.size());
+        if (!elight.empty())
+            HIPCHK(hipMemcpyAsync(li, elight.data(), 16 * elight.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(hi, eitems.data(), 16 * eitems.size(), hipMemcpyHostToDevice, st));
+        ls->edge_items = li;
+        ls->edge_nitems = (uint32_t)elight.size();
+        ls->edge_heavy = hi;
+        ls->edge_nheavy = ek;
+    }
     if (hk) {
-        KItem* li = (KItem*)carve(16 * light.size());
-        KItem* ai = (KItem*)carve(16 * hacc.size());
-        KItem* ei = (KItem*)carve(16 * hev.size());
-        HIPCHK(hipMemcpyAsync(li, light.data(), 16 * light.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(ai, hacc.data(), 16 * hacc.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(ei, hev.data(), 16 * hev.size(), hipMemcpyHostToDevice, st));
+        KItem* li = (KItem*)carve(16 * std::max<size_t>(1, light.size()));
+        KItem* hi = (KItem*)carve(16 * hitems.size());
+        if (!light.empty())
+            HIPCHK(hipMemcpyAsync(li, light.data(), 16 * light.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(hi, hitems.data(), 16 * hitems.size(), hipMemcpyHostToDevice, st));
         ls->agg_items = li;
         ls->agg_nitems = (uint32_t)light.size();
-        ls->heavy_acc = ai;
-        ls->heavy_nacc = (uint32_t)hacc.size();
-        ls->heavy_ev = ei;
-        ls->heavy_nev = (uint32_t)hev.size();
+        ls->heavy_items = hi;
+        ls->heavy_nitems = hk;
     }
     ls->zero_base = (uint32_t*)zb;
     ls->zero_words = zbytes / 4;
@@ -654,9 +713,8 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     a.cancel = ls->cancel_dev;
     a.rootbm = rootbm;
     a.bm_words = bm_words;
-    a.agg_mode = 0;
-    a.heavy_k = hk;
-    a.heavy = heavy;
+    a.wscr = wscr;
+    a.wscr_stride = wstride;
     if (ls->any_agg) {
         if (agg) {
             a.aggcnt = agg->cnt;
@@ -670,23 +728,36 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     }
     ls->runs.clear();
     ls->run_agg.clear();
+    // runs: plain plans; edge-core plans (light roots, then heavy roots in
+    // LDS windows); two-hop plans (light roots, then heavy roots)
+    auto group = [&](int q) {
+        if (plans[q].d.agg_last) return 2;
+        return (ek && edge_window_ok(plans[q].d)) ? 1 : 0;
+    };
     int i = 0;
     while (i < (int)np) {
-        int grp = plans[i].d.agg_last ? 1 : 0;
+        const int grp = group(i);
         int j = i;
-        while (j < (int)np && (plans[j].d.agg_last ? 1 : 0) == grp) ++j;
-        ls->runs.push_back({i, j});
-        ls->run_agg.push_back(grp);
-        if (grp && hk) {
-            // heavy roots: accumulate, then evaluate
+        while (j < (int)np && group(j) == grp) ++j;
+        if (grp == 0) {
             ls->runs.push_back({i, j});
-            ls->run_agg.push_back(2);
+            ls->run_agg.push_back(0);
+        } else if (grp == 1) {
             ls->runs.push_back({i, j});
             ls->run_agg.push_back(3);
+            ls->runs.push_back({i, j});
+            ls->run_agg.push_back(4);
+        } else {
+            ls->runs.push_back({i, j});
+            ls->run_agg.push_back(1);
+            if (hk) {
+                ls->runs.push_back({i, j});
+                ls->run_agg.push_back(2);
+            }
         }
         i = j;
     }
-    if (hk) HIPCHK(hipStreamSynchronize(st));
+    if (hk || ek) HIPCHK(hipStreamSynchronize(st));
     return PM_OK;
 }
 
@@ -707,10 +778,19 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
             b.items = ls.agg_items;
             b.nitems = ls.agg_nitems;
             gb = (int)std::max<uint64_t>(1, ls.agg_w / (block / 64));
-        } else if (ls.run_agg[r] >= 2) {
-            b.agg_mode = ls.run_agg[r] - 1;
-            b.items = ls.run_agg[r] == 2 ? ls.heavy_acc : ls.heavy_ev;
-            b.nitems = ls.run_agg[r] == 2 ? ls.heavy_nacc : ls.heavy_nev;
+        } else if (ls.run_agg[r] == 2) {
+            b.items = ls.heavy_items;
+            b.nitems = ls.heavy_nitems;
+            if (b.nitems && launch_agg_window(b, gb, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 3) {
+            b.items = ls.edge_items;
+            b.nitems = ls.edge_nitems;
+        } else if (ls.run_agg[r] == 4) {
+            b.items = ls.edge_heavy;
+            b.nitems = ls.edge_nheavy;
+            if (b.nitems && launch_edge_window(b, gb, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
         }
         if (b.nitems == 0) continue;
         if (launch_match(b, gb, block, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");

@@ -69,13 +69,15 @@ struct LaunchSet {
     bool any_agg = false;
     KArgs base{};
     std::vector<std::pair<int, int>> runs;   // contiguous plan ranges, one launch each
-    std::vector<int> run_agg;                // 0 plain, 1 two-hop, 2/3 heavy-root accumulate/evaluate
+    std::vector<int> run_agg;                // 0 plain, 1 two-hop, 2 heavy two-hop roots,
+                                             // 3 edge-core light roots, 4 edge-core heavy roots
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
-    uint32_t heavy_k = 0;                    // heavy roots (shared counter arrays)
-    const KItem* heavy_acc = nullptr;        // their accumulate items
-    const KItem* heavy_ev = nullptr;         // their evaluate items
-    uint32_t heavy_nacc = 0, heavy_nev = 0;
+    const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
+    uint32_t heavy_nitems = 0;
+    const KItem* edge_items = nullptr;       // edge-core plans: light roots
+    const KItem* edge_heavy = nullptr;       //                  heavy roots, one item each
+    uint32_t edge_nitems = 0, edge_nheavy = 0;
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
@@ -99,6 +101,7 @@ struct GraphRes {
     uint64_t device_bytes = 0;
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
+    std::vector<uint64_t> two_hop;           // per vertex: summed degrees of its lower neighbours
     std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
@@ -201,7 +204,9 @@ struct Ctx_ {
                      std::vector<PlanInfo>* plans);
     uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c,
                        uint64_t* stride, bool* any_agg, bool heavy_ok = true) const;
-    uint32_t heavy_count(const GraphRes& G, const std::vector<PlanInfo>& plans, uint32_t* p_agg) const;
+    std::vector<uint32_t> heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans,
+                                      uint32_t* p_agg) const;
+    std::vector<uint32_t> edge_heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     int ensure_agg(uint32_t n, const LaunchCfg& c);
     uint64_t bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
