@@ -57,6 +57,19 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
     return lo;
 }
 
+// First position in a[lo, hi) holding a value >= x, searching outward from
+// lo (cheap when the answer is near lo).
+__device__ __forceinline__ uint32_t gallop_u32(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
+                                               uint32_t x) {
+    uint32_t step = 1, b = lo;
+    while (b < hi && a[b] < x) {
+        lo = b + 1;
+        b = lo + step;
+        step <<= 1;
+    }
+    return lower_bound_u32(a, lo, b < hi ? b : hi, x);
+}
+
 __device__ __forceinline__ bool in_sorted(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
                                           uint32_t x) {
     uint32_t p = lower_bound_u32(a, lo, hi, x);
@@ -873,16 +886,18 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
 // to each target in an LDS window of WIN_IDS consecutive target ids.
 // Device-scope atomics are executed in memory on this GPU, LDS atomics in
 // the CU, so the sweep is bounded by reading the bridges' lists.  Every
-// thread owns some of the root's bridges and keeps one cursor per bridge
-// (in scratch only it touches); each window starts at the smallest pending
-// target, so empty id ranges are never visited.  After a window is filled
-// the four waves evaluate its counters and clear them.
+// thread owns some of the root's bridges and keeps, per bridge, a cursor
+// and the next target (in scratch only it touches): a bridge without a
+// target in the current window costs one read.  Each window starts at the
+// smallest pending target, so empty id ranges are never visited; after a
+// window is filled the four waves evaluate its counters and clear them.
 constexpr uint32_t WIN_IDS = 8192;
 
 template <bool BYTES>
 __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
     __shared__ uint32_t win[WIN_IDS];
-    __shared__ uint32_t s_item, s_next;
+    __shared__ uint16_t used[WIN_IDS];   // touched window offsets, in first-touch order
+    __shared__ uint32_t s_item, s_next[2], s_nused[2];
     const int lane = wave_lane();
     const uint32_t tid = threadIdx.x;
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -893,8 +908,10 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
     c.bytes = 0;
     c.bmw = nullptr;
     c.bm = nullptr;
-    uint32_t* cur = a.wscr + (uint64_t)blockIdx.x * 2 * a.wscr_stride;  // cursor, end per bridge
+    // per owned bridge: cursor, end of its target range, next target
+    uint32_t* cur = a.wscr + (uint64_t)blockIdx.x * (2 + EW_TERMS) * a.wscr_stride;
     uint32_t* fin = cur + a.wscr_stride;
+    uint32_t* nxt = fin + a.wscr_stride;
     for (uint32_t i = tid; i < WIN_IDS; i += blockDim.x) win[i] = 0;
     int curp = -1;
     u128 acc = 0;
@@ -905,6 +922,8 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
             uint32_t it = atomicAdd(a.head, 1u);
             if (a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) it = 0xffffffffu;
             s_item = it;
+            s_next[0] = s_next[1] = 0xffffffffu;
+            s_nused[0] = s_nused[1] = 0;
         }
         __syncthreads();
         const uint32_t it = s_item;
@@ -926,12 +945,20 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
         bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
         bounds_of(c.v, L.gt, L.lt, lo, hi);
         if (blo >= bhi || lo >= hi) continue;
-        const uint32_t top = hi == NOB ? a.g.n : hi;
+        // item slice s0 of s1: the matching fraction of the target id range
+        {
+            const uint64_t t0 = lo, t1 = hi == NOB ? (uint64_t)a.g.n : (uint64_t)hi, span = t1 - t0;
+            const uint64_t ns = max(item.s1, 1u);
+            lo = (uint32_t)(t0 + span * item.s0 / ns);
+            hi = (uint32_t)(t0 + span * (item.s0 + 1) / ns);
+            if (lo >= hi) continue;
+        }
+        const uint32_t top = hi;
         uint32_t bb, be;
         list_range(c.g, r, blo, bhi, bb, be);
         const uint32_t nb = be - bb;
-        if (BYTES && tid == 0) c.bytes += 8 + 4ull * nb;
-        // cursors of the owned bridges
+        if (BYTES && tid == 0 && item.s0 == 0) c.bytes += 8 + 4ull * nb;
+        uint32_t mine = 0xffffffffu;
         for (uint32_t k = tid; k < nb; k += blockDim.x) {
             const uint32_t y = c.g.col[bb + k];
             uint32_t yb = 0, yf = 0;
@@ -940,55 +967,77 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
                 list_range(c.g, y, lo, hi, yb, yf);
                 if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
             }
+            const uint32_t x = yb < yf ? c.g.col[yb] : 0xffffffffu;
             cur[k] = yb;
             fin[k] = yf;
+            nxt[k] = x;
+            mine = min(mine, x);
         }
-        uint32_t wlo = lo;
-        for (;;) {
-            // smallest pending target over all bridges
-            if (tid == 0) s_next = 0xffffffffu;
-            __syncthreads();
-            uint32_t mine = 0xffffffffu;
-            for (uint32_t k = tid; k < nb; k += blockDim.x)
-                if (cur[k] < fin[k]) mine = min(mine, c.g.col[cur[k]]);
-            if (mine != 0xffffffffu) atomicMin(&s_next, mine);
-            __syncthreads();
-            const uint32_t nx = s_next;
-            if (nx == 0xffffffffu || nx >= top) break;
-            wlo = max(wlo, nx);
-            const uint32_t whi = (uint32_t)min((uint64_t)top, (uint64_t)wlo + WIN_IDS);
-            // fill: every owned bridge advances through the window
-            for (uint32_t k = tid; k < nb; k += blockDim.x) {
-                uint32_t q = cur[k];
-                const uint32_t qe = fin[k];
-                while (q < qe) {
-                    const uint32_t x = c.g.col[q];
-                    if (x >= whi) break;
-                    ++q;
-                    if (L.label >= 0 && c.g.lab[x] != (uint8_t)L.label) continue;
-                    if ((L.neq & 1) && x == r) continue;
-                    atomicAdd(&win[x - wlo], 1u);
-                }
-                cur[k] = q;
-            }
-            __syncthreads();
-            // evaluate and clear: wave w takes a quarter of the window
-            uint32_t vv[KMAX];
+        if (mine != 0xffffffffu) atomicMin(&s_next[0], mine);
+        __syncthreads();
+        uint32_t vv[KMAX];
 #pragma unroll
-            for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
-            const uint32_t span = whi - wlo;
-            const uint32_t part = WIN_IDS / 4, w0 = (tid >> 6) * part, w1 = min(w0 + part, span);
-            for (uint32_t base = w0; base < w1; base += 64) {
-                const uint32_t i = base + lane;
-                uint32_t m = 0;
-                if (i < w1) {
+        for (int i = 0; i < KMAX; ++i) vv[i] = c.v[i];
+        int ph = 0;
+        for (;;) {
+            const uint32_t wlo = s_next[ph];
+            if (wlo == 0xffffffffu || wlo >= top) break;
+            const uint32_t whi = (uint32_t)min((uint64_t)top, (uint64_t)wlo + WIN_IDS);
+            // fill: each wave takes 64 bridges at a time; a bridge's targets
+            // inside the window are found by galloping from its cursor and
+            // the wave streams all of them flattened; every bridge offers
+            // its next target for the next window
+            mine = 0xffffffffu;
+            for (uint32_t kb = (tid & ~63u); kb < nb; kb += blockDim.x) {
+                const uint32_t k = kb + lane;
+                const bool valid = k < nb;
+                const uint32_t x0 = valid ? nxt[k] : 0xffffffffu;
+                const uint32_t q = valid ? cur[k] : 0u, qe = valid ? fin[k] : 0u;
+                const uint32_t qend = x0 < whi ? gallop_u32(c.g.col, q, qe, whi) : q;
+                const uint32_t len = qend - q;
+                const uint32_t incl = wave_incl_scan(len);
+                const uint32_t tot = __shfl(incl, 63);
+                const uint32_t excl = incl - len;
+                for (uint32_t tb = 0; tb < tot; tb += 64) {
+                    const uint32_t t = tb + lane;
+                    const bool act = t < tot;
+                    const int o = owner_of(incl, act ? t : tot - 1);
+                    const uint32_t src = __shfl(q, o) + (t - __shfl(excl, o));
+                    if (!act) continue;
+                    const uint32_t x = c.g.col[src];
+                    if ((L.label < 0 || c.g.lab[x] == (uint8_t)L.label) && !((L.neq & 1) && x == r))
+                        if (atomicAdd(&win[x - wlo], 1u) == 0u) used[atomicAdd(&s_nused[ph], 1u)] = (uint16_t)(x - wlo);
+                }
+                if (valid) {
+                    const uint32_t xn = !len ? x0 : (qend < qe ? c.g.col[qend] : 0xffffffffu);
+                    if (len) {
+                        cur[k] = qend;
+                        nxt[k] = xn;
+                    }
+                    mine = min(mine, xn);
+                }
+            }
+            if (mine != 0xffffffffu) atomicMin(&s_next[ph ^ 1], mine);
+            __syncthreads();
+            const uint32_t nu = s_nused[ph];
+            if (tid == 0) {
+                s_next[ph] = 0xffffffffu;   // read by every thread before the barrier
+                s_nused[ph ^ 1] = 0;        // next window's list; last read a window ago
+            }
+            // evaluate and clear the touched counters, 64 per wave at a time
+            for (uint32_t base = (tid & ~63u); base < nu; base += blockDim.x) {
+                const uint32_t idx = base + lane;
+                uint32_t m = 0, i = 0;
+                if (idx < nu) {
+                    i = used[idx];
                     m = win[i];
                     win[i] = 0;
                 }
                 vv[1] = wlo + i;
                 acc += lanes_tail<BYTES>(c, vv, m != 0, m);
             }
-            wlo = whi;
+            __syncthreads();
+            ph ^= 1;
         }
     }
     if (curp >= 0) flush(a, curp, acc);
@@ -1060,6 +1109,10 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
         bounds_of(c.v, L1.gt, L1.lt, lo1, hi1);
         if (lo1 >= hi1) continue;
         list_range(c.g, r, lo1, hi1, cb, ce);
+        // item: candidates [s0, s1) of the root's level-1 range
+        if (item.s0 >= ce - cb) continue;
+        ce = min(ce, cb + item.s1);
+        cb += item.s0;
         const uint32_t nb = ce - cb;
         // non-cheap terms of the plan, in order (at most EW_TERMS)
         int tq[EW_TERMS];
@@ -1087,31 +1140,49 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
                 atomicOr(&bits[o >> 5], 1u << (o & 31));
             }
             __syncthreads();
-            for (uint32_t k = tid; k < nb; k += blockDim.x) {
-                uint32_t q = ccur[k];
-                const uint32_t qe = cend[k];
-                if (q >= qe) continue;
-                uint32_t vv[KMAX] = {r, c.g.col[cb + k], 0, 0, 0};
+            // each wave takes 64 candidates at a time and streams their
+            // entries inside the window flattened; per-owner counts per term
+            // come back through ballot masks
+            for (uint32_t kb = (tid & ~63u); kb < nb; kb += blockDim.x) {
+                const uint32_t k = kb + lane;
+                const uint32_t q = k < nb ? ccur[k] : 0u, qe = k < nb ? cend[k] : 0u;
+                const uint32_t v1 = k < nb ? c.g.col[cb + k] : 0u;
+                const uint32_t qs = q < qe ? gallop_u32(c.g.col, q, qe, wlo) : q;
+                const uint32_t qend = qs < qe ? gallop_u32(c.g.col, qs, qe, whi) : qs;
+                const uint32_t len = qend - qs;
+                const uint32_t incl = wave_incl_scan(len);
+                const uint32_t tot = __shfl(incl, 63);
+                const uint32_t excl = incl - len;
                 uint32_t add[EW_TERMS] = {0, 0, 0, 0};
-                while (q < qe) {
-                    const uint32_t x = c.g.col[q];
-                    if (x >= whi) break;
-                    ++q;
-                    if (x < wlo) continue;
-                    const uint32_t o = x - wlo;
-                    if (!((bits[o >> 5] >> (o & 31)) & 1u)) continue;
+                for (uint32_t tb = 0; tb < tot; tb += 64) {
+                    const uint32_t t = tb + lane;
+                    const bool act = t < tot;
+                    const int o = owner_of(incl, act ? t : tot - 1);
+                    const uint32_t src = __shfl(qs, o) + (t - __shfl(excl, o));
+                    const uint32_t w1 = __shfl(v1, o);
+                    const uint32_t x = act ? c.g.col[src] : 0u;
+                    const uint32_t off = x - wlo;
+                    const bool hit = act && ((bits[off >> 5] >> (off & 31)) & 1u);
+                    const uint32_t vv[KMAX] = {r, w1, 0, 0, 0};
+                    const uint32_t s0 = max(excl, tb), s1 = min(incl, tb + 64);
+                    const uint64_t seg = s0 < s1 ? range_mask(s0 - tb, s1 - tb) : 0ull;
                     for (int i = 0; i < nt; ++i) {
-                        const DTerm t = P->term[tq[i]];
-                        uint32_t lo, hi;
-                        bounds_of(vv, t.gt, t.lt, lo, hi);
-                        if (x < lo || x >= hi) continue;
-                        if (t.label >= 0 && c.g.lab[x] != (uint8_t)t.label) continue;
-                        if (((t.neq & 1) && x == vv[0]) || ((t.neq & 2) && x == vv[1])) continue;
-                        ++add[i];
+                        const DTerm tt = P->term[tq[i]];
+                        bool ok = hit;
+                        if (ok) {
+                            uint32_t lo, hi;
+                            bounds_of(vv, tt.gt, tt.lt, lo, hi);
+                            ok = x >= lo && x < hi && (tt.label < 0 || c.g.lab[x] == (uint8_t)tt.label) &&
+                                 !((tt.neq & 1) && x == r) && !((tt.neq & 2) && x == w1);
+                        }
+                        const uint64_t m = __ballot(ok);
+                        add[i] += (uint32_t)__popcll(m & seg);
                     }
                 }
-                ccur[k] = q;
-                for (int i = 0; i < nt; ++i) ccnt[(uint64_t)k * EW_TERMS + i] += add[i];
+                if (k < nb && q < qe) {
+                    ccur[k] = qend;
+                    for (int i = 0; i < nt; ++i) ccnt[(uint64_t)k * EW_TERMS + i] += add[i];
+                }
             }
             __syncthreads();
             for (uint32_t i = pos + tid; i < pend; i += blockDim.x) bits[(c.g.col[i] - wlo) >> 5] = 0u;

@@ -428,6 +428,23 @@ std::vector<uint32_t> Ctx_::edge_heavy_roots(const GraphRes& G, const std::vecto
     return out;
 }
 
+// Work items of the heavy roots.  Two-hop roots are split by target-id range
+// into about one slice per 2^20 of two-hop mass (items {r, 0, slice, slices});
+// edge-core roots by level-1 candidates, 512 per item (items {r, 0, k0, k1}).
+static std::vector<KItem> heavy_items(const GraphRes& G, const std::vector<uint32_t>& roots, bool two_hop) {
+    std::vector<KItem> out;
+    for (uint32_t r : roots) {
+        if (two_hop) {
+            const uint32_t ns = (uint32_t)std::min<uint64_t>(256, std::max<uint64_t>(1, G.two_hop[r] >> 20));
+            for (uint32_t i = 0; i < ns; ++i) out.push_back({r, 0, i, ns});
+        } else {
+            const uint32_t d = G.host_rp[r + 1] - G.host_rp[r];
+            for (uint32_t k = 0; k < d; k += 512) out.push_back({r, 0, k, k + 512});
+        }
+    }
+    return out;
+}
+
 // Work items over every root except the heavy ones (ranges split around them).
 static std::vector<KItem> items_without(const std::vector<KItem>& all, const std::vector<uint8_t>& heavy) {
     std::vector<KItem> out;
@@ -474,12 +491,12 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     const uint64_t wstride = ((uint64_t)G.max_deg + 63) & ~uint64_t(63);
     if (hk) {
         // light items (at most one per root plus the hub slices), heavy items
-        uint64_t items = G.n + hk;
+        uint64_t items = G.n + heavy_items(G, heavy_roots(G, plans, &pa), true).size();
         for (uint32_t r = 0; r < G.n; ++r) items += (G.host_rp[r + 1] - G.host_rp[r]) / agg_split;
         b += 16 * items + 2 * 256;
     }
     if (ek) {
-        uint64_t items = G.n + ek;
+        uint64_t items = G.n + heavy_items(G, edge_heavy_roots(G, plans), false).size();
         for (uint32_t r = 0; r < G.n; ++r) items += (G.host_rp[r + 1] - G.host_rp[r]) / cfg.item_split;
         b += 16 * items + 2 * 256;
     }
@@ -605,19 +622,15 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     std::vector<KItem> light, hitems;
     if (hk) {
         std::vector<uint8_t> is_heavy(G.n, 0);
-        for (uint32_t r : heavy) {
-            is_heavy[r] = 1;
-            hitems.push_back({r, 0, 0, 0});
-        }
+        for (uint32_t r : heavy) is_heavy[r] = 1;
+        hitems = heavy_items(G, heavy, true);
         light = items_without(build_items(G.host_rp, G.n, cfg.item_budget, agg_split, 256), is_heavy);
     }
     std::vector<KItem> elight, eitems;
     if (ek) {
         std::vector<uint8_t> is_heavy(G.n, 0);
-        for (uint32_t r : eheavy) {
-            is_heavy[r] = 1;
-            eitems.push_back({r, 0, 0, 0});
-        }
+        for (uint32_t r : eheavy) is_heavy[r] = 1;
+        eitems = heavy_items(G, eheavy, false);
         elight = items_without(build_items(G.host_rp, G.n, cfg.item_budget, cfg.item_split, 256), is_heavy);
     }
     ls->off_mem = arena.alloc(need);
@@ -653,7 +666,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         ls->edge_items = li;
         ls->edge_nitems = (uint32_t)elight.size();
         ls->edge_heavy = hi;
-        ls->edge_nheavy = ek;
+        ls->edge_nheavy = (uint32_t)eitems.size();
     }
     if (hk) {
         KItem* li = (KItem*)carve(16 * std::max<size_t>(1, light.size()));
@@ -664,7 +677,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         ls->agg_items = li;
         ls->agg_nitems = (uint32_t)light.size();
         ls->heavy_items = hi;
-        ls->heavy_nitems = hk;
+        ls->heavy_nitems = (uint32_t)hitems.size();
     }
     ls->zero_base = (uint32_t*)zb;
     ls->zero_words = zbytes / 4;
