@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "motif-count s (morphed vs plain), matches/s, % HBM peak, p50/p99 query latency"
 # sources that decide the match kernel's memory traffic (kernel, plans, launch configuration)
 PATH_SRCS = [os.path.join(ROOT, "paper_2012_04553_amd", "csrc", f)
-             for f in ("kernels.hip", "kernels.hpp", "planner.cpp", "runtime.hpp")]
+             for f in ("kernels.hip", "kernels.hpp", "planner.cpp", "runtime.hpp", "runtime.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_rmat20_4mc_morphed_traffic.md")
 
 
@@ -49,8 +49,8 @@ def path_sha():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the match kernel from the committed PMC
-    summary, or None when the kernel, the planner or the launch defaults
+    """HBM bytes per launch of the matching kernels from the committed PMC
+    summary, or None when a kernel, the planner or the launch set-up
     changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -170,8 +170,8 @@ def run_4mc(args, eng, g, workload, morph_name="morphed"):
         "graph_load_s": round(load_s, 3), "matches_per_step": matches, "counts": ref,
     })
     line["roofline"] = {
-        "bound": "hbm", "kernel": "match_kernel", "launches_per_step": launches,
-        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "bound": "hbm", "kernel": "match_kernel + agg_window_kernel + edge_window_kernel",
+        "launches_per_step": launches, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": None, "alg_bytes_per_launch": alg_bytes / launches,
         "avg_launch_ms": per_launch_ms,
     }

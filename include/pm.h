@@ -201,10 +201,13 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "agg_split"     target-range slices of a high-degree root in two-hop
  *                   aggregation launches: one slice per this many
  *                   adjacency entries (>= 64, default 256);
- *   "heavy_roots"   0/1 (default 1): when every two-hop plan of a query
- *                   aggregates at its first level, the highest-degree roots
- *                   get one shared counter array each, filled by many
- *                   waves in one launch and evaluated in the next;
+ *   "heavy_roots"   0/1 (default 1): roots with a large two-hop mass (the
+ *                   summed degrees of their lower neighbours) of two-hop
+ *                   plans that aggregate at their first level, and of
+ *                   edge-core plans whose terms intersect N(v0) and N(v1),
+ *                   are counted by workgroups sweeping LDS windows;
+ *   "heavy_min_mass" two-hop mass from which a root counts as heavy
+ *                   (>= 1, default 16384);
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
  *                   hipGraph on first use and replay it afterwards.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */

@@ -390,9 +390,9 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
 
 // Heavy roots of the two-hop launches: when every aggregation plan
 // aggregates at its first level, roots whose two-hop mass (the summed
-// degrees of their lower neighbours) is large both absolutely and against
-// the id range a window sweep would cover run in agg_window_kernel, heaviest
-// first.  *p_agg = aggregation plans.
+// degrees of their lower neighbours) is at least heavy_min_mass and an
+// eighth of their id (the range a window sweep may cover) run in
+// agg_window_kernel, heaviest first.  *p_agg = aggregation plans.
 std::vector<uint32_t> Ctx_::heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans,
                                         uint32_t* p_agg) const {
     std::vector<uint32_t> out;
@@ -407,22 +407,23 @@ std::vector<uint32_t> Ctx_::heavy_roots(const GraphRes& G, const std::vector<Pla
     if (!pa || !heavy_roots_opt) return out;
     for (uint32_t r = 0; r < G.n; ++r) {
         const uint64_t w = G.two_hop[r];
-        if (w >= 16384 && w * 8 >= r) out.push_back(r);
+        if (w >= heavy_min_mass && w * 8 >= r) out.push_back(r);
     }
     std::stable_sort(out.begin(), out.end(),
                      [&](uint32_t x, uint32_t y) { return G.two_hop[x] > G.two_hop[y]; });
     return out;
 }
 
-// Heavy roots of edge-core plans: roots whose lower neighbours have a large
-// summed degree, heaviest first (none when no such plan is present).
+// Heavy roots of edge-core plans: roots whose lower neighbours have a summed
+// degree of at least heavy_min_mass, heaviest first (none when no such plan
+// is present).
 std::vector<uint32_t> Ctx_::edge_heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
     std::vector<uint32_t> out;
     bool any = false;
     for (const PlanInfo& p : plans) any = any || (!p.d.agg_last && edge_window_ok(p.d));
     if (!any || !heavy_roots_opt) return out;
     for (uint32_t r = 0; r < G.n; ++r)
-        if (G.two_hop[r] >= 16384) out.push_back(r);
+        if (G.two_hop[r] >= heavy_min_mass) out.push_back(r);
     std::stable_sort(out.begin(), out.end(),
                      [&](uint32_t x, uint32_t y) { return G.two_hop[x] > G.two_hop[y]; });
     return out;
@@ -1005,7 +1006,8 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     bool replay = use_graphs && !count_bytes;
     std::string key = closure_key(G, Q.closure) + "#" + std::to_string(cfg.blocks_per_cu) + "," +
                       std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
-                      std::to_string(agg_split);
+                      std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
+                      std::to_string(heavy_min_mass);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy) {
@@ -1381,6 +1383,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "agg_waves" && value >= 1) c.agg_waves_opt = (uint64_t)value;
     else if (k == "agg_split" && value >= 64 && value <= 0x7fffffff) c.agg_split = (uint32_t)value;
     else if (k == "heavy_roots" && (value == 0 || value == 1)) c.heavy_roots_opt = value != 0;
+    else if (k == "heavy_min_mass" && value >= 1) c.heavy_min_mass = (uint64_t)value;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;

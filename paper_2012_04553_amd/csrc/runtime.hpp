@@ -137,6 +137,7 @@ struct Ctx_ {
     uint64_t agg_waves_opt = 2048;
     uint32_t agg_split = 256;
     bool heavy_roots_opt = true;
+    uint64_t heavy_min_mass = 16384;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
