@@ -123,6 +123,73 @@ inline bool edge_window_ok(const DPlan& d) {
     return heavy_terms >= 1 && heavy_terms <= EW_TERMS;
 }
 
+// Triangle-core plans, run by clique_kernel over roots with at most
+// CQ_SMAX out-neighbours, up to CQ_PLANS plans a launch (ids in degree
+// order, no labels, no anti-edges).  The kernel meets every triangle once,
+// at its lowest vertex.  clique_kind returns
+//  1 for a core v0 < v1 < v2 with v1 in N+(v0) and v2 in N+(v0) and N+(v1),
+//    counted or with cheap tail terms only, and for an edge core v0 < v1
+//    with one set-size term |N(v0) cap N(v1)| above v1 (the triangles this
+//    edge closes with its lowest vertex v0): the plan's root is the
+//    triangle's lowest vertex, so roots beyond CQ_SMAX can run elsewhere;
+//  2 for an edge core (either orientation) with one set-size term
+//    |N(v0) cap N(v1)| under any bounds: the sum runs over the triangle's
+//    three edges, so every triangle has to be met in this kernel;
+//  0 otherwise.
+// The tail of an edge-core plan must hold its set-size term in every
+// monomial exactly once (linear in it); other terms must be cheap.
+constexpr uint32_t CQ_SMAX = 1024;
+constexpr int CQ_PLANS = 4;
+constexpr uint32_t CQ_TERMS = 8;
+inline int clique_kind(const DPlan& d) {
+    if (d.ncore < 2 || d.ncore > 3 || d.agg_last || d.nterm > (int)CQ_TERMS) return 0;
+    if (d.local && !(d.ncore == 3 && d.nterm == 0)) return 0;
+    if (d.lev[0].label >= 0) return 0;
+    const DLevel& l1 = d.lev[1];
+    if (l1.adj != 1 || l1.anti || l1.label >= 0 || l1.agg) return 0;
+    const bool up = l1.gt == 1 && l1.lt == 0, down = l1.lt == 1 && l1.gt == 0;
+    if (!up && !(down && d.ncore == 2)) return 0;
+    auto third = [](uint8_t adj, uint8_t anti, int8_t label, uint8_t gt, uint8_t lt, uint8_t neq) {
+        return adj == 3 && !anti && label < 0 && !((gt | lt | neq) & ~3u);
+    };
+    int heavy = -1;
+    for (int q = 0; q < d.nterm; ++q) {
+        const DTerm& t = d.term[q];
+        if (t.agg) return 0;
+        if (t.cheap) continue;
+        if (d.ncore == 3 || heavy >= 0 || !third(t.adj, t.anti, t.label, t.gt, t.lt, t.neq)) return 0;
+        heavy = q;
+    }
+    if (d.ncore == 3) {
+        const DLevel& l2 = d.lev[2];
+        return third(l2.adj, l2.anti, l2.label, l2.gt, l2.lt, l2.neq) && (l2.gt & 2) && !l2.lt ? 1 : 0;
+    }
+    if (heavy < 0) return 0;
+    for (int m = 0; m < d.nmono; ++m) {
+        int k = 0;
+        for (int f = 0; f < d.mono[m].nf; ++f) k += d.mono[m].f[f] == heavy;
+        if (k != 1) return 0;
+    }
+    const DTerm& h = d.term[heavy];
+    return up && (h.gt & 2) && !h.lt ? 1 : 2;
+}
+inline bool clique_ok(const DPlan& d) { return clique_kind(d) != 0; }
+
+// Counted 4-cliques v0 < v1 < v2 < v3 enumerated from N+(v0) (no labels):
+// clique4_kernel counts them from bit rows of the graph induced on N+(v0),
+// roots with up to C4_ROOT_MAX out-neighbours.
+constexpr uint32_t C4_ROOT_MAX = 512;
+inline bool clique4_ok(const DPlan& d) {
+    if (d.ncore != 4 || d.nterm != 0 || d.agg_last || d.lev[0].label >= 0) return false;
+    for (int j = 1; j < 4; ++j) {
+        const DLevel& L = d.lev[j];
+        const uint8_t prev = (uint8_t)((1u << j) - 1);
+        if (L.adj != prev || L.anti || L.label >= 0 || L.lt || L.agg) return false;
+        if (!(L.gt & (1u << (j - 1))) || (L.gt & ~prev)) return false;
+    }
+    return true;
+}
+
 struct PlanInfo {
     DPlan d;
     Pat pat;

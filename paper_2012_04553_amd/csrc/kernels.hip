@@ -1211,6 +1211,439 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- triangle-core plans
+//
+// Plans whose core is a triangle v0 < v1 < v2 (ids in degree order) with v1
+// and v2 taken from the root's out-neighbourhood N+(v0), counted as is or
+// with degree-type tail terms, and edge-core plans that sum a tail linear in
+// the number of triangles closing the edge, run here: every such plan of a
+// launch in one pass over the same triangles.  A wavefront takes a root (or a slice of a
+// hub root's rows), inserts N+(v0) into an open-addressing hash table in its
+// LDS, and streams the rows N+(v1), v1 in N+(v0), flattened over the lanes
+// with CQ_UNROLL reads in flight per lane.  An entry y found in the table
+// closes the triangle (v0, v1, y): y > v1 because it comes from N+(v1), and
+// y is adjacent to v0.  Each triangle is met exactly once, at its lowest
+// vertex.  Lookups cost LDS reads only; the rows are the global traffic.
+constexpr uint32_t CQ_HASH = 2048;   // slots per wavefront; N+(v0) fills at most half
+constexpr uint32_t CQ_EMPTY = 0xffffffffu;
+constexpr int CQ_UNROLL = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Fibonacci hashing onto the 2^11 slots.
+__device__ __forceinline__ uint32_t cq_slot(uint32_t x) { return (x * 0x9E3779B1u) >> 21; }
+
+__device__ __forceinline__ void cq_insert(uint32_t* H, uint32_t x) {
+    uint32_t h = cq_slot(x);
+    while (atomicCAS(&H[h], CQ_EMPTY, x) != CQ_EMPTY) h = (h + 1) & (CQ_HASH - 1);
+}
+
+// The table always holds an empty slot, so a probe for an absent key ends.
+__device__ __forceinline__ bool cq_find(const uint32_t* H, uint32_t x) {
+    uint32_t h = cq_slot(x);
+    for (;;) {
+        const uint32_t k = H[h];
+        if (k == x) return true;
+        if (k == CQ_EMPTY) return false;
+        h = (h + 1) & (CQ_HASH - 1);
+    }
+}
+
+// Removes a key known to be present.  All keys of the table are removed
+// together, so a probe walks past slots other lanes have already emptied.
+__device__ __forceinline__ void cq_erase(uint32_t* H, uint32_t x) {
+    uint32_t h = cq_slot(x);
+    while (H[h] != x) h = (h + 1) & (CQ_HASH - 1);
+    H[h] = CQ_EMPTY;
+}
+
+// Tail of one plan for the core match (v0, v1, v2) with degrees d0, d1, d2.
+// A term over a whole adjacency list whose excluded vertices are all known
+// neighbours of its owner is that owner's degree less their number (the
+// same value as cheap_term computes); other cheap terms go through
+// cheap_term.  The set-size term of an edge-core plan is 1: this triangle's
+// share of it (the tail is linear in it).
+template <bool BYTES>
+__device__ u128 cq_eval(Ctx& c, const DPlan* P, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t d0, uint32_t d1,
+                        uint32_t d2) {
+    uint64_t tv[CQ_TERMS];
+    const uint32_t vv[KMAX] = {v0, v1, v2, 0u, 0u};
+#pragma unroll 1
+    for (int q = 0; q < P->nterm; ++q) {
+        const DTerm t = P->term[q];
+        const int o = __builtin_ctz((uint32_t)t.adj);
+        if (!t.cheap) {
+            tv[q] = 1;
+        } else if ((t.gt | t.lt) == 0 && (t.neq & ~t.sure) == 0) {
+            const uint32_t d = o == 0 ? d0 : (o == 1 ? d1 : d2);
+            tv[q] = (uint64_t)(d - (uint32_t)__builtin_popcount((uint32_t)t.neq));
+            if (BYTES) c.bytes += 8;
+        } else {
+            tv[q] = cheap_term<BYTES>(c, vv, t, 0);
+        }
+    }
+    i128 s = 0;
+    for (int m = 0; m < P->nmono; ++m) {
+        const DMono M = P->mono[m];
+        i128 prod = (i128)M.coef;
+        for (int f = 0; f < M.nf; ++f) prod *= (i128)tv[M.f[f]];
+        s += prod;
+    }
+    return s > 0 ? (u128)s : (u128)0;
+}
+
+// What one plan adds for the triangle a < b < c of this lane, with degrees
+// da, db, dc.  Per lane, no cross-lane reads.  A triangle-core plan
+// takes it as its core match.  An edge-core plan sums over edges (v0, v1)
+// in the orientation of its level 1 the tail of every common neighbour
+// within its set-size term's bounds, so each of the triangle's three edges
+// adds its tail when the opposite vertex is within those bounds.
+template <bool BYTES>
+__device__ __forceinline__ u128 cq_tail(Ctx& c, const DPlan* P, uint32_t a, uint32_t b, uint32_t cc, uint32_t da,
+                                        uint32_t db, uint32_t dc) {
+    if (P->nterm == 0) return (u128)(uint32_t)P->mult;
+    uint8_t hg = 0, hl = 0;
+    for (int q = 0; q < P->nterm; ++q)
+        if (!P->term[q].cheap) {
+            hg = P->term[q].gt;
+            hl = P->term[q].lt;
+        }
+    const bool tri = P->ncore == 3;
+    const bool up = P->lev[1].gt != 0;
+    u128 s = 0;
+#pragma unroll 1
+    for (int e = 0; e < (tri ? 1 : 3); ++e) {
+        // edge (lo, hi) of the triangle and its opposite vertex x (for a
+        // triangle core: the core itself)
+        const uint32_t lo = e == 2 ? b : a, hi = e == 0 ? b : cc, x = e == 0 ? cc : (e == 1 ? b : a);
+        const uint32_t dlo = e == 2 ? db : da, dhi = e == 0 ? db : dc, dx = e == 0 ? dc : (e == 1 ? db : da);
+        const bool fwd = tri || up;
+        const uint32_t v0 = fwd ? lo : hi, v1 = fwd ? hi : lo;
+        const uint32_t d0 = fwd ? dlo : dhi, d1 = fwd ? dhi : dlo;
+        const bool ok = (!(hg & 1) || x > v0) && (!(hg & 2) || x > v1) && (!(hl & 1) || x < v0) &&
+                        (!(hl & 2) || x < v1);
+        if (ok) s += cq_eval<BYTES>(c, P, v0, v1, x, d0, d1, dx);
+    }
+    return s;
+}
+
+// Triangles found by the stream wait in a per-wavefront LDS queue of
+// (v0, v1, v2, deg v1) until 64 are there; then every lane evaluates the
+// tails of one, so the tail code runs with all lanes busy.
+constexpr uint32_t CQ_QCAP = 128;
+
+template <bool BYTES>
+__device__ __forceinline__ void cq_drain(Ctx& c, const KArgs& a, const uint4* Q, uint32_t k, u128* acc) {
+    const uint32_t lane = (uint32_t)wave_lane();
+    if (lane < k) {
+        const uint4 e = Q[lane];
+        const uint32_t d0 = a.g.rp[e.x + 1] - a.g.rp[e.x];
+        const uint32_t d2 = a.g.rp[e.z + 1] - a.g.rp[e.z];
+        if (BYTES) c.bytes += 16;
+#pragma unroll 1
+        for (int p = 0; p < a.nplans; ++p) {
+            const u128 t = cq_tail<BYTES>(c, a.plans + p, e.x, e.y, e.z, d0, e.w, d2);
+#pragma unroll
+            for (int k = 0; k < CQ_PLANS; ++k)
+                if (k == p) acc[k] += t;
+        }
+    }
+}
+
+template <bool BYTES>
+__global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
+    __shared__ uint32_t s_hash[4][CQ_HASH];
+    __shared__ uint4 s_queue[4][CQ_QCAP];
+    const int lane = wave_lane();
+    uint32_t* H = s_hash[threadIdx.x >> 6];
+    uint4* Q = s_queue[threadIdx.x >> 6];
+    uint32_t qn = 0;
+    for (uint32_t i = lane; i < CQ_HASH; i += 64) H[i] = CQ_EMPTY;
+    wave_sync();
+    Ctx c;
+    c.g = a.g;
+    c.P = nullptr;
+    c.buf = nullptr;
+    c.stride = 0;
+    c.bytes = 0;
+    c.bmw = nullptr;
+    c.bm = nullptr;
+    const int np = a.nplans;
+    bool counts_only = true;   // every plan counts its triangles: a tally suffices
+    for (int p = 0; p < np; ++p) counts_only = counts_only && a.plans[p].nterm == 0;
+    u128 acc[CQ_PLANS];
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p) acc[p] = 0;
+    uint64_t tally = 0;
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(a.head, 1u);
+        it = bcast(it);
+        if (it >= a.nitems) break;
+        if (a.cancel) {
+            uint32_t stop = 0;
+            if (lane == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
+            if (bcast(stop)) break;
+        }
+        const KItem item = a.items[it];
+        for (uint32_t r = item.r0; r < item.r1; ++r) {
+            const uint32_t b = a.g.split[r], e = a.g.rp[r + 1];
+            const uint32_t s = e - b;
+            if (s < 2 || s > CQ_SMAX) continue;
+            const uint32_t i0 = item.s0, i1 = min(item.s1, s);
+            if (i0 >= i1) continue;
+            if (BYTES && lane == 0) c.bytes += 12 + 4ull * s;
+            for (uint32_t i = lane; i < s; i += 64) cq_insert(H, a.g.col[b + i]);
+            wave_sync();
+            for (uint32_t base = i0; base < i1; base += 64) {
+                const uint32_t i = base + lane;
+                const bool valid = i < i1;
+                const uint32_t x = valid ? a.g.col[b + i] : 0u;
+                uint32_t pb = 0, len = 0, dx = 0;
+                if (valid) {
+                    pb = a.g.split[x];
+                    const uint32_t xe = a.g.rp[x + 1];
+                    len = xe - pb;
+                    dx = xe - a.g.rp[x];
+                    if (BYTES) c.bytes += 16 + 4ull * len;
+                }
+                const uint32_t incl = wave_incl_scan(len);
+                const uint32_t total = __shfl(incl, 63);
+                const uint32_t excl = incl - len;
+                for (uint32_t t0 = 0; t0 < total; t0 += 64 * CQ_UNROLL) {
+                    uint32_t y[CQ_UNROLL];
+                    int o[CQ_UNROLL];
+                    bool act[CQ_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < CQ_UNROLL; ++u) {
+                        const uint32_t t = t0 + (uint32_t)(u * 64) + lane;
+                        act[u] = t < total;
+                        o[u] = owner_of(incl, act[u] ? t : total - 1);
+                        const uint32_t src = __shfl(pb, o[u]) + (t - __shfl(excl, o[u]));
+                        y[u] = act[u] ? a.g.col[src] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < CQ_UNROLL; ++u) {
+                        const bool hit = act[u] && cq_find(H, y[u]);
+                        if (counts_only) {
+                            tally += hit ? 1u : 0u;
+                            continue;
+                        }
+                        const uint64_t hm = __ballot(hit);
+                        if (hm == 0) continue;
+                        const uint32_t xo = __shfl(x, o[u]);
+                        const uint32_t dxo = __shfl(dx, o[u]);
+                        if (hit) Q[qn + lane_prefix(hm)] = make_uint4(r, xo, y[u], dxo);
+                        qn += (uint32_t)__popcll(hm);
+                        if (qn >= 64) {
+                            wave_sync();
+                            cq_drain<BYTES>(c, a, Q, 64, acc);
+                            const uint32_t rest = qn - 64;
+                            const uint4 t = (uint32_t)lane < rest ? Q[64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+                            wave_sync();
+                            if ((uint32_t)lane < rest) Q[lane] = t;
+                            wave_sync();
+                            qn = rest;
+                        }
+                    }
+                }
+            }
+            wave_sync();
+            for (uint32_t i = lane; i < s; i += 64) cq_erase(H, a.g.col[b + i]);
+            wave_sync();
+        }
+    }
+    if (qn) {
+        wave_sync();
+        cq_drain<BYTES>(c, a, Q, qn, acc);
+    }
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p)
+        if (p < np) flush(a, p, counts_only ? (u128)tally * (u128)(uint32_t)a.plans[p].mult : acc[p]);
+    if (BYTES) {
+        unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
+// ---------------------------------------------------------------- 4-clique plans
+//
+// A 4-clique v0 < v1 < v2 < v3 lies in N+(v0): v1 < v2 < v3 is a triangle of
+// the graph induced on the root's out-neighbourhood.  For each root this
+// kernel builds that graph as bit rows in LDS (row i holds the later
+// out-neighbours j > i adjacent to the i-th, found by streaming N+(x_i)
+// against a hash of N+(v0) that maps an id to its position), then counts
+// its triangles: every bit (i, j) adds the popcount of row i AND row j.
+// Light roots (3 .. C4_LIGHT out-neighbours) take one wavefront each,
+// heavier ones (up to C4_HEAVY) a whole workgroup; larger roots run in the
+// general kernel.
+constexpr uint32_t C4_LIGHT = 256;
+constexpr uint32_t C4_HEAVY = 512;
+constexpr uint32_t C4_LDS_WORDS = 11264;                       // 44 KB a workgroup
+constexpr uint32_t C4_WAVE_WORDS = C4_LDS_WORDS / 4;           // 2816 a wavefront
+
+// LDS layout of one root's table: keys[H], positions (u16)[H], rows[S * W].
+template <int LOGH>
+struct C4Table {
+    uint32_t* keys;
+    uint16_t* pos;
+    uint32_t* rows;
+    __device__ C4Table(uint32_t* base) {
+        keys = base;
+        pos = (uint16_t*)(base + (1u << LOGH));
+        rows = base + (1u << LOGH) + (1u << LOGH) / 2;
+    }
+    __device__ static uint32_t slot(uint32_t x) { return (x * 0x9E3779B1u) >> (32 - LOGH); }
+    __device__ void insert(uint32_t x, uint32_t i) {
+        uint32_t h = slot(x);
+        while (atomicCAS(&keys[h], CQ_EMPTY, x) != CQ_EMPTY) h = (h + 1) & ((1u << LOGH) - 1);
+        pos[h] = (uint16_t)i;
+    }
+    // position of x in N+(v0), or -1; the table always has an empty slot
+    __device__ int find(uint32_t x) const {
+        uint32_t h = slot(x);
+        for (;;) {
+            const uint32_t k = keys[h];
+            if (k == x) return pos[h];
+            if (k == CQ_EMPTY) return -1;
+            h = (h + 1) & ((1u << LOGH) - 1);
+        }
+    }
+};
+
+// One root's 4-cliques by `nthr` cooperating threads (thread `tid`): a
+// wavefront (nthr = 64) or the workgroup (nthr = 256; `sync` is then
+// __syncthreads, otherwise a wavefront barrier).  Returns this thread's share.
+template <int LOGH, bool WG, bool BYTES>
+__device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r, uint32_t b, uint32_t s) {
+    constexpr uint32_t NT = WG ? 256 : 64;
+    const uint32_t tid = WG ? threadIdx.x : (uint32_t)wave_lane();
+    auto sync = [] {
+        if (WG) __syncthreads();
+        else wave_sync();
+    };
+    C4Table<LOGH> T(base);
+    const uint32_t W = (s + 31) >> 5;
+    for (uint32_t i = tid; i < (1u << LOGH); i += NT) T.keys[i] = CQ_EMPTY;
+    for (uint32_t i = tid; i < s * W; i += NT) T.rows[i] = 0;
+    sync();
+    for (uint32_t i = tid; i < s; i += NT) T.insert(g.col[b + i], i);
+    if (BYTES && tid == 0) c.bytes += 12 + 4ull * s;
+    sync();
+    // rows: wavefront w of the group streams row chunks w, w + NT/64, ...
+    const int lane = wave_lane();
+    const uint32_t wv = WG ? (threadIdx.x >> 6) : 0;
+    for (uint32_t base_i = wv * 64; base_i < s; base_i += NT) {
+        const uint32_t i = base_i + lane;
+        const bool valid = i < s;
+        const uint32_t x = valid ? g.col[b + i] : 0u;
+        uint32_t pb = 0, len = 0;
+        if (valid) {
+            pb = g.split[x];
+            len = g.rp[x + 1] - pb;
+            if (BYTES) c.bytes += 12 + 4ull * len;
+        }
+        const uint32_t incl = wave_incl_scan(len);
+        const uint32_t total = __shfl(incl, 63);
+        const uint32_t excl = incl - len;
+        for (uint32_t t0 = 0; t0 < total; t0 += 64 * CQ_UNROLL) {
+            uint32_t y[CQ_UNROLL];
+            int o[CQ_UNROLL];
+            bool act[CQ_UNROLL];
+#pragma unroll
+            for (int u = 0; u < CQ_UNROLL; ++u) {
+                const uint32_t t = t0 + (uint32_t)(u * 64) + lane;
+                act[u] = t < total;
+                o[u] = owner_of(incl, act[u] ? t : total - 1);
+                const uint32_t src = __shfl(pb, o[u]) + (t - __shfl(excl, o[u]));
+                y[u] = act[u] ? g.col[src] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < CQ_UNROLL; ++u) {
+                const int j = act[u] ? T.find(y[u]) : -1;
+                if (j >= 0) {
+                    const uint32_t row = base_i + (uint32_t)o[u];
+                    atomicOr(&T.rows[row * W + ((uint32_t)j >> 5)], 1u << (j & 31));
+                }
+            }
+        }
+    }
+    sync();
+    // triangles of the row graph: task (i, w) takes the bits of word w of row i
+    uint64_t cnt = 0;
+    for (uint32_t t = tid; t < s * W; t += NT) {
+        const uint32_t i = t / W, w = t - i * W;
+        const uint32_t* ri = T.rows + i * W;
+        uint32_t m = ri[w];
+        while (m) {
+            const uint32_t j = (w << 5) + (uint32_t)__builtin_ctz(m);
+            m &= m - 1;
+            const uint32_t* rj = T.rows + j * W;
+            for (uint32_t w2 = j >> 5; w2 < W; ++w2) cnt += (uint32_t)__popc(ri[w2] & rj[w2]);
+        }
+    }
+    sync();
+    return cnt;
+}
+
+template <bool BYTES, bool WG>
+__global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
+    __shared__ uint32_t s_lds[C4_LDS_WORDS];
+    const int lane = wave_lane();
+    uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * C4_WAVE_WORDS;
+    __shared__ uint32_t s_it;
+    Ctx c;
+    c.g = a.g;
+    c.P = nullptr;
+    c.buf = nullptr;
+    c.stride = 0;
+    c.bytes = 0;
+    c.bmw = nullptr;
+    c.bm = nullptr;
+    const int np = a.nplans;
+    uint64_t cnt = 0;
+    for (;;) {
+        uint32_t it = 0;
+        if (WG) {
+            if (threadIdx.x == 0) {
+                uint32_t v = atomicAdd(a.head, 1u);
+                if (v < a.nitems && a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) v = a.nitems;
+                s_it = v;
+            }
+            __syncthreads();
+            it = s_it;
+            __syncthreads();
+        } else {
+            if (lane == 0) {
+                it = atomicAdd(a.head, 1u);
+                if (it < a.nitems && a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) it = a.nitems;
+            }
+            it = bcast(it);
+        }
+        if (it >= a.nitems) break;
+        const KItem item = a.items[it];
+        for (uint32_t r = item.r0; r < item.r1; ++r) {
+            const uint32_t b = a.g.split[r], e = a.g.rp[r + 1];
+            const uint32_t s = e - b;
+            if (s < 3 || s > (WG ? C4_HEAVY : C4_LIGHT)) continue;
+            if (WG) cnt += c4_root<11, true, BYTES>(c, a.g, base, r, b, s);
+            else cnt += c4_root<9, false, BYTES>(c, a.g, base, r, b, s);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p)
+        if (p < np) flush(a, p, (u128)cnt * (u128)(uint32_t)a.plans[p].mult);
+    if (BYTES) {
+        unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
 // Clears `words` 32-bit words; four at a time (the region is 16-byte
 // aligned), then the tail.
 __global__ void zero_kernel(uint32_t* p, uint64_t words) {
@@ -1242,6 +1675,25 @@ int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s)
         hipLaunchKernelGGL(agg_window_kernel<true>, dim3(grid), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(agg_window_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes)
+        hipLaunchKernelGGL(clique_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(clique_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_clique4(const KArgs& a, int grid, bool heavy, bool count_bytes, hipStream_t s) {
+    if (heavy) {
+        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique4_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, false>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique4_kernel<false, false>), dim3(grid), dim3(256), 0, s, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -49,6 +49,14 @@ int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStrea
 int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Heavy roots of edge-core plans (edge_window_ok): one workgroup per root.
 int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Triangle-core plans (clique_ok), at most CQ_PLANS per launch: one
+// wavefront per item {r0, r1, i0, i1} (roots [r0, r1), rows [i0, i1) of
+// N+(r)).
+int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
+// wavefront (heavy = false) or one workgroup (heavy = true) per root of
+// the items {r0, r1, 0, 0}.
+int launch_clique4(const KArgs& a, int grid, bool heavy, bool count_bytes, hipStream_t s);
 // Clears `words` 32-bit words (used instead of memset nodes inside graphs).
 int launch_zero(uint32_t* p, uint64_t words, hipStream_t s);
 

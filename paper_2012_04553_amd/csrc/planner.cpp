@@ -722,6 +722,8 @@ std::string PlanInfo::describe() const {
     if (d.lane_par) s += " lane_par";
     if (d.local) s += " local_bitmap";
     if (d.bm0) s += " root_bitmap";
+    if (clique_ok(d)) s += " triangle_core";
+    if (clique4_ok(d)) s += " clique4";
     return s;
 }
 

@@ -124,6 +124,97 @@ static std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t 
     return items;
 }
 
+
+// Work items of the triangle-core kernel.  A root's stream volume is the
+// summed out-degree of its out-neighbours.  Consecutive roots with 2 ..
+// CQ_SMAX out-neighbours are grouped until their volume reaches CQ_VOL (at
+// most 256 roots an item); a root above CQ_VOL is cut into row slices of
+// about CQ_VOL each (items {r, r+1, i0, i1}).  Roots with more than CQ_SMAX
+// out-neighbours are listed apart for the general kernel.
+static constexpr uint64_t CQ_VOL = 16384;
+static constexpr uint32_t C4_LIGHT_MAX = 256;   // clique4_kernel's wavefront roots
+static void clique_items(GraphRes& G, const std::vector<uint32_t>& rp, const std::vector<uint32_t>& col,
+                         const std::vector<uint32_t>& split) {
+    G.clique_items.clear();
+    G.clique_big.clear();
+    uint32_t gb = 0;
+    uint64_t gv = 0;
+    bool open = false;
+    auto close = [&](uint32_t end) {
+        if (open) G.clique_items.push_back({gb, end, 0, UINT32_MAX});
+        open = false;
+        gv = 0;
+    };
+    for (uint32_t r = 0; r < G.n; ++r) {
+        const uint32_t s = rp[r + 1] - split[r];
+        if (s > CQ_SMAX) {
+            close(r);
+            G.clique_big.push_back(r);
+            continue;
+        }
+        if (s < 2) continue;
+        uint64_t vol = 0;
+        for (uint32_t p = split[r]; p < rp[r + 1]; ++p) vol += rp[col[p] + 1] - split[col[p]];
+        if (vol > CQ_VOL) {
+            close(r);
+            uint64_t acc = 0;
+            uint32_t i0 = 0;
+            for (uint32_t i = 0; i < s; ++i) {
+                const uint32_t x = col[split[r] + i];
+                acc += rp[x + 1] - split[x];
+                if (acc >= CQ_VOL || i + 1 == s) {
+                    G.clique_items.push_back({r, r + 1, i0, i + 1});
+                    i0 = i + 1;
+                    acc = 0;
+                }
+            }
+            continue;
+        }
+        if (!open) {
+            open = true;
+            gb = r;
+        }
+        gv += vol;
+        if (gv >= CQ_VOL || r + 1 - gb >= 256) close(r + 1);
+    }
+    close(G.n);
+    // 4-clique kernel: light roots (3 .. C4_LIGHT_MAX out-neighbours) grouped
+    // up to CQ_VOL of volume, heavier ones (to C4_ROOT_MAX) one an item,
+    // most volume first
+    G.c4_light.clear();
+    G.c4_heavy.clear();
+    G.c4_big.clear();
+    std::vector<std::pair<uint64_t, uint32_t>> hv;
+    open = false;
+    gv = 0;
+    auto close4 = [&](uint32_t end) {
+        if (open) G.c4_light.push_back({gb, end, 0, 0});
+        open = false;
+        gv = 0;
+    };
+    for (uint32_t r = 0; r < G.n; ++r) {
+        const uint32_t s = rp[r + 1] - split[r];
+        if (s < 3) continue;
+        uint64_t vol = 0;
+        for (uint32_t p = split[r]; p < rp[r + 1]; ++p) vol += rp[col[p] + 1] - split[col[p]];
+        if (s > C4_LIGHT_MAX) {
+            close4(r);
+            if (s > C4_ROOT_MAX) G.c4_big.push_back(r);
+            else hv.push_back({vol, r});
+            continue;
+        }
+        if (!open) {
+            open = true;
+            gb = r;
+        }
+        gv += vol;
+        if (gv >= CQ_VOL || r + 1 - gb >= 256) close4(r + 1);
+    }
+    close4(G.n);
+    std::stable_sort(hv.begin(), hv.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& h : hv) G.c4_heavy.push_back({h.second, h.second + 1, 0, 0});
+}
+
 int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels,
                      uint32_t* out_gid) {
     if (!rp || !col || !out_gid) return fail(PM_E_INVAL, "null graph array");
@@ -269,6 +360,7 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
             G->two_hop[r] = w;
         }
     });
+    clique_items(*G, nrp, ncol, nsplit);
     G->host_rp = std::move(nrp);
     if (labels) {
         // vertices by label (stable: degree order within a label), for the
@@ -375,9 +467,13 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     }
     std::vector<size_t> idx(cl.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
-    // plain plans, then edge-core plans, then two-hop plans: each group can
-    // run in launches of its own
-    auto group = [&](size_t a) { return pl[a].d.agg_last ? 2 : (edge_window_ok(pl[a].d) ? 1 : 0); };
+    // plain plans, triangle-core plans, 4-clique plans, edge-core plans, then
+    // two-hop plans:
+    // each group can run in launches of its own
+    auto group = [&](size_t a) {
+        const DPlan& d = pl[a].d;
+        return d.agg_last ? 4 : (clique_ok(d) ? 1 : (clique4_ok(d) ? 2 : (edge_window_ok(d) ? 3 : 0)));
+    };
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return group(a) < group(b); });
     closure->clear();
     plans->clear();
@@ -461,6 +557,47 @@ static std::vector<KItem> items_without(const std::vector<KItem>& all, const std
     return out;
 }
 
+
+// Whether clique_kernel runs this plan on this graph: a plan summed over
+// the edges of every triangle needs all triangles, so no root beyond the
+// kernel's limit.
+static bool clique_runs(const GraphRes& G, const DPlan& d) {
+    const int k = clique_kind(d);
+    return k == 1 || (k == 2 && G.clique_big.empty());
+}
+
+// Whether a launch set runs any plan in clique_kernel.
+bool Ctx_::use_clique(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
+    if (!clique_opt || G.clique_items.empty()) return false;
+    for (const PlanInfo& p : plans)
+        if (clique_runs(G, p.d)) return true;
+    return false;
+}
+
+// Whether a launch set runs any plan in clique4_kernel.
+bool Ctx_::use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
+    if (!clique_opt || (G.c4_light.empty() && G.c4_heavy.empty())) return false;
+    for (const PlanInfo& p : plans)
+        if (clique4_ok(p.d)) return true;
+    return false;
+}
+
+// General-kernel items over the roots clique4_kernel leaves out.
+std::vector<KItem> Ctx_::clique4_big_items(const GraphRes& G, const LaunchCfg& cfg) const {
+    if (G.c4_big.empty()) return {};
+    std::vector<uint8_t> other(G.n, 1);
+    for (uint32_t r : G.c4_big) other[r] = 0;
+    return items_without(build_items(G.host_rp, G.n, cfg.item_budget, cfg.item_split, 256), other);
+}
+
+// Items of the general kernel over the roots clique_kernel leaves out.
+std::vector<KItem> Ctx_::clique_big_items(const GraphRes& G, const LaunchCfg& cfg) const {
+    if (G.clique_big.empty()) return {};
+    std::vector<uint8_t> other(G.n, 1);
+    for (uint32_t r : G.clique_big) other[r] = 0;
+    return items_without(build_items(G.host_rp, G.n, cfg.item_budget, cfg.item_split, 256), other);
+}
+
 uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg,
                          uint64_t* scratch_stride, bool* any_agg, bool heavy_ok) const {
     uint64_t stride = 1;
@@ -503,6 +640,10 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     }
     // per block: cursor, end and counter words per bridge or candidate
     if (hk || ek) b += (uint64_t)grid_blocks(cfg) * (2 + EW_TERMS) * wstride * 4 + 256;
+    if (heavy_ok && use_clique(G, plans))
+        b += 16 * (G.clique_items.size() + clique_big_items(G, cfg).size()) + 2 * 256;
+    if (heavy_ok && use_clique4(G, plans))
+        b += 16 * (G.c4_light.size() + G.c4_heavy.size() + clique4_big_items(G, cfg).size()) + 3 * 256;
     return b;
 }
 
@@ -634,6 +775,10 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         eitems = heavy_items(G, eheavy, false);
         elight = items_without(build_items(G.host_rp, G.n, cfg.item_budget, cfg.item_split, 256), is_heavy);
     }
+    const bool cq = agg == nullptr && use_clique(G, plans);
+    const std::vector<KItem> cq_big = cq ? clique_big_items(G, cfg) : std::vector<KItem>();
+    const bool c4 = agg == nullptr && use_clique4(G, plans);
+    const std::vector<KItem> c4_big = c4 ? clique4_big_items(G, cfg) : std::vector<KItem>();
     ls->off_mem = arena.alloc(need);
     if (ls->off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
     char* base = (char*)dptr(ls->off_mem);
@@ -679,6 +824,33 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         ls->agg_nitems = (uint32_t)light.size();
         ls->heavy_items = hi;
         ls->heavy_nitems = (uint32_t)hitems.size();
+    }
+    ls->cq_items = ls->cq_big = nullptr;
+    ls->cq_nitems = ls->cq_nbig = 0;
+    if (cq) {
+        KItem* ci = (KItem*)carve(16 * G.clique_items.size());
+        KItem* bi = (KItem*)carve(16 * std::max<size_t>(1, cq_big.size()));
+        HIPCHK(hipMemcpyAsync(ci, G.clique_items.data(), 16 * G.clique_items.size(), hipMemcpyHostToDevice, st));
+        if (!cq_big.empty())
+            HIPCHK(hipMemcpyAsync(bi, cq_big.data(), 16 * cq_big.size(), hipMemcpyHostToDevice, st));
+        ls->cq_items = ci;
+        ls->cq_nitems = (uint32_t)G.clique_items.size();
+        ls->cq_big = bi;
+        ls->cq_nbig = (uint32_t)cq_big.size();
+    }
+    ls->c4_light = ls->c4_heavy = ls->c4_big = nullptr;
+    ls->c4_nlight = ls->c4_nheavy = ls->c4_nbig = 0;
+    if (c4) {
+        auto up = [&](const std::vector<KItem>& v, const KItem** dst, uint32_t* cnt) -> int {
+            KItem* d = (KItem*)carve(16 * std::max<size_t>(1, v.size()));
+            if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), 16 * v.size(), hipMemcpyHostToDevice, st));
+            *dst = d;
+            *cnt = (uint32_t)v.size();
+            return PM_OK;
+        };
+        if (up(G.c4_light, &ls->c4_light, &ls->c4_nlight) || up(G.c4_heavy, &ls->c4_heavy, &ls->c4_nheavy) ||
+            up(c4_big, &ls->c4_big, &ls->c4_nbig))
+            return PM_E_DEVICE;
     }
     ls->zero_base = (uint32_t*)zb;
     ls->zero_words = zbytes / 4;
@@ -742,10 +914,14 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     }
     ls->runs.clear();
     ls->run_agg.clear();
-    // runs: plain plans; edge-core plans (light roots, then heavy roots in
-    // LDS windows); two-hop plans (light roots, then heavy roots)
+    // runs: plain plans; triangle-core plans (clique_kernel, CQ_PLANS a
+    // launch, then the general kernel over the roots it leaves out);
+    // edge-core plans (light roots, then heavy roots in LDS windows);
+    // two-hop plans (light roots, then heavy roots)
     auto group = [&](int q) {
         if (plans[q].d.agg_last) return 2;
+        if (cq && clique_runs(G, plans[q].d)) return 3;
+        if (c4 && clique4_ok(plans[q].d)) return 4;
         return (ek && edge_window_ok(plans[q].d)) ? 1 : 0;
     };
     int i = 0;
@@ -756,6 +932,31 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         if (grp == 0) {
             ls->runs.push_back({i, j});
             ls->run_agg.push_back(0);
+        } else if (grp == 3) {
+            for (int k = i; k < j; k += CQ_PLANS) {
+                ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
+                ls->run_agg.push_back(5);
+            }
+            if (!cq_big.empty()) {
+                ls->runs.push_back({i, j});
+                ls->run_agg.push_back(6);
+            }
+        } else if (grp == 4) {
+            for (int k = i; k < j; k += CQ_PLANS) {
+                const std::pair<int, int> rr{k, std::min(j, k + CQ_PLANS)};
+                if (ls->c4_nheavy) {
+                    ls->runs.push_back(rr);
+                    ls->run_agg.push_back(8);
+                }
+                if (ls->c4_nlight) {
+                    ls->runs.push_back(rr);
+                    ls->run_agg.push_back(7);
+                }
+            }
+            if (!c4_big.empty()) {
+                ls->runs.push_back({i, j});
+                ls->run_agg.push_back(9);
+            }
         } else if (grp == 1) {
             ls->runs.push_back({i, j});
             ls->run_agg.push_back(3);
@@ -771,7 +972,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         }
         i = j;
     }
-    if (hk || ek) HIPCHK(hipStreamSynchronize(st));
+    if (hk || ek || cq || c4) HIPCHK(hipStreamSynchronize(st));
     return PM_OK;
 }
 
@@ -800,6 +1001,25 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         } else if (ls.run_agg[r] == 3) {
             b.items = ls.edge_items;
             b.nitems = ls.edge_nitems;
+        } else if (ls.run_agg[r] == 5) {
+            b.items = ls.cq_items;
+            b.nitems = ls.cq_nitems;
+            if (b.nitems && launch_clique(b, clique_blocks(), bytes_pass, s))
+                return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 6) {
+            b.items = ls.cq_big;
+            b.nitems = ls.cq_nbig;
+        } else if (ls.run_agg[r] == 7 || ls.run_agg[r] == 8) {
+            const bool heavy = ls.run_agg[r] == 8;
+            b.items = heavy ? ls.c4_heavy : ls.c4_light;
+            b.nitems = heavy ? ls.c4_nheavy : ls.c4_nlight;
+            if (b.nitems && launch_clique4(b, clique4_blocks(), heavy, bytes_pass, s))
+                return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 9) {
+            b.items = ls.c4_big;
+            b.nitems = ls.c4_nbig;
         } else if (ls.run_agg[r] == 4) {
             b.items = ls.edge_heavy;
             b.nitems = ls.edge_nheavy;
@@ -1007,7 +1227,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     std::string key = closure_key(G, Q.closure) + "#" + std::to_string(cfg.blocks_per_cu) + "," +
                       std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
                       std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
-                      std::to_string(heavy_min_mass);
+                      std::to_string(heavy_min_mass) + "," + std::to_string(clique_opt);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy) {
@@ -1384,6 +1604,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "agg_split" && value >= 64 && value <= 0x7fffffff) c.agg_split = (uint32_t)value;
     else if (k == "heavy_roots" && (value == 0 || value == 1)) c.heavy_roots_opt = value != 0;
     else if (k == "heavy_min_mass" && value >= 1) c.heavy_min_mass = (uint64_t)value;
+    else if (k == "clique_kernel" && (value == 0 || value == 1)) c.clique_opt = value != 0;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;

@@ -70,7 +70,10 @@ struct LaunchSet {
     KArgs base{};
     std::vector<std::pair<int, int>> runs;   // contiguous plan ranges, one launch each
     std::vector<int> run_agg;                // 0 plain, 1 two-hop, 2 heavy two-hop roots,
-                                             // 3 edge-core light roots, 4 edge-core heavy roots
+                                             // 3 edge-core light roots, 4 edge-core heavy roots,
+                                             // 5 triangle-core (clique_kernel), 6 their larger roots,
+                                             // 7/8 4-cliques (clique4_kernel, light/heavy roots),
+                                             // 9 their larger roots
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
     const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
@@ -78,6 +81,13 @@ struct LaunchSet {
     const KItem* edge_items = nullptr;       // edge-core plans: light roots
     const KItem* edge_heavy = nullptr;       //                  heavy roots, one item each
     uint32_t edge_nitems = 0, edge_nheavy = 0;
+    const KItem* cq_items = nullptr;         // triangle-core plans: clique_kernel items
+    const KItem* cq_big = nullptr;           //   and general-kernel items of the larger roots
+    uint32_t cq_nitems = 0, cq_nbig = 0;
+    const KItem* c4_light = nullptr;         // 4-clique plans: wavefront roots,
+    const KItem* c4_heavy = nullptr;         //   workgroup roots,
+    const KItem* c4_big = nullptr;           //   general-kernel items of the larger roots
+    uint32_t c4_nlight = 0, c4_nheavy = 0, c4_nbig = 0;
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
@@ -102,6 +112,10 @@ struct GraphRes {
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
     std::vector<uint64_t> two_hop;           // per vertex: summed degrees of its lower neighbours
+    std::vector<KItem> clique_items;         // triangle-core kernel items
+    std::vector<uint32_t> clique_big;        // roots with more than CQ_SMAX out-neighbours
+    std::vector<KItem> c4_light, c4_heavy;   // 4-clique kernel items
+    std::vector<uint32_t> c4_big;            // roots with more than C4_ROOT_MAX out-neighbours
     std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
@@ -138,6 +152,7 @@ struct Ctx_ {
     uint32_t agg_split = 256;
     bool heavy_roots_opt = true;
     uint64_t heavy_min_mass = 16384;
+    bool clique_opt = true;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
@@ -158,6 +173,10 @@ struct Ctx_ {
         return c.grid_override > 0 ? c.grid_override : num_cus * c.blocks_per_cu;
     }
     uint64_t waves(const LaunchCfg& c) const { return (uint64_t)grid_blocks(c) * (block / 64); }
+    // clique_kernel: 32 KB of LDS a workgroup, five resident a CU
+    int clique_blocks() const { return num_cus * 5; }
+    // clique4_kernel: 44 KB of LDS a workgroup, three resident a CU
+    int clique4_blocks() const { return num_cus * 3; }
     // wavefronts of the two-hop aggregation launches on an n-vertex graph:
     // each holds two dense u32[n] arrays, so their number follows from a
     // memory budget (a quarter of the arena, at most 8 GiB)
@@ -210,6 +229,10 @@ struct Ctx_ {
     std::vector<uint32_t> edge_heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     int ensure_agg(uint32_t n, const LaunchCfg& c);
     uint64_t bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
+    bool use_clique(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
+    std::vector<KItem> clique_big_items(const GraphRes& G, const LaunchCfg& cfg) const;
+    bool use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
+    std::vector<KItem> clique4_big_items(const GraphRes& G, const LaunchCfg& cfg) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
     int launch(GraphRes& G, Query& Q);
     int evict_idle();
