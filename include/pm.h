@@ -208,6 +208,13 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *                   are counted by workgroups sweeping LDS windows;
  *   "heavy_min_mass" two-hop mass from which a root counts as heavy
  *                   (>= 1, default 16384);
+ *   "heavy_span_shift" a two-hop root also needs its mass times
+ *                   2^shift to reach its id, which bounds the id range its
+ *                   window sweep covers (0..32, default 6);
+ *   "clique_kernel" 0/1 (default 1): triangle-core and ordered 4-clique
+ *                   plans run in the LDS hash kernels (roots up to 1024
+ *                   and 512 out-neighbours; larger ones in the general
+ *                   kernel);
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
  *                   hipGraph on first use and replay it afterwards.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */

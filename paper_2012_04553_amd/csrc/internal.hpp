@@ -175,6 +175,30 @@ inline int clique_kind(const DPlan& d) {
 }
 inline bool clique_ok(const DPlan& d) { return clique_kind(d) != 0; }
 
+// Edge-support plans: an edge core (v1 in N(v0), one orientation, no
+// labels) whose one set-size term is the whole common neighbourhood
+// |N(v0) cap N(v1)|, with any tail polynomial in it and cheap terms (the
+// diamond: the sum over edges of t^2 - t).  clique_kernel adds every
+// triangle to the support counter of each of its three edges (a u32 per
+// out-list position: the edge {u < w} at w's place in N+(u)), and
+// support_kernel evaluates the tail per edge from its support.  This needs
+// every triangle, so no root beyond CQ_SMAX.
+inline bool support_ok(const DPlan& d) {
+    if (d.ncore != 2 || d.agg_last || d.local || d.lev[0].label >= 0) return false;
+    const DLevel& l1 = d.lev[1];
+    if (l1.adj != 1 || l1.anti || l1.label >= 0 || l1.agg) return false;
+    if (!((l1.gt == 1 && l1.lt == 0) || (l1.lt == 1 && l1.gt == 0))) return false;
+    int heavy = -1;
+    for (int q = 0; q < d.nterm; ++q) {
+        const DTerm& t = d.term[q];
+        if (t.agg) return false;
+        if (t.cheap) continue;
+        if (heavy >= 0 || t.adj != 3 || t.anti || t.label >= 0 || t.gt || t.lt || (t.neq & ~3u)) return false;
+        heavy = q;
+    }
+    return heavy >= 0;
+}
+
 // Counted 4-cliques v0 < v1 < v2 < v3 enumerated from N+(v0) (no labels):
 // clique4_kernel counts them from bit rows of the graph induced on N+(v0),
 // roots with up to C4_ROOT_MAX out-neighbours.

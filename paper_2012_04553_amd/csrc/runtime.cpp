@@ -486,9 +486,10 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
 
 // Heavy roots of the two-hop launches: when every aggregation plan
 // aggregates at its first level, roots whose two-hop mass (the summed
-// degrees of their lower neighbours) is at least heavy_min_mass and an
-// eighth of their id (the range a window sweep may cover) run in
-// agg_window_kernel, heaviest first.  *p_agg = aggregation plans.
+// degrees of their lower neighbours) is at least heavy_min_mass and at
+// least their id (the range a window sweep may cover) over
+// 2^heavy_span_shift run in agg_window_kernel, heaviest first.
+// *p_agg = aggregation plans.
 std::vector<uint32_t> Ctx_::heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans,
                                         uint32_t* p_agg) const {
     std::vector<uint32_t> out;
@@ -503,7 +504,7 @@ std::vector<uint32_t> Ctx_::heavy_roots(const GraphRes& G, const std::vector<Pla
     if (!pa || !heavy_roots_opt) return out;
     for (uint32_t r = 0; r < G.n; ++r) {
         const uint64_t w = G.two_hop[r];
-        if (w >= heavy_min_mass && w * 8 >= r) out.push_back(r);
+        if (w >= heavy_min_mass && (w << heavy_span_shift) >= r) out.push_back(r);
     }
     std::stable_sort(out.begin(), out.end(),
                      [&](uint32_t x, uint32_t y) { return G.two_hop[x] > G.two_hop[y]; });
@@ -1227,7 +1228,8 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     std::string key = closure_key(G, Q.closure) + "#" + std::to_string(cfg.blocks_per_cu) + "," +
                       std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
                       std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
-                      std::to_string(heavy_min_mass) + "," + std::to_string(clique_opt);
+                      std::to_string(heavy_min_mass) + "," + std::to_string(clique_opt) + "," +
+                      std::to_string(heavy_span_shift);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy) {
@@ -1605,6 +1607,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "heavy_roots" && (value == 0 || value == 1)) c.heavy_roots_opt = value != 0;
     else if (k == "heavy_min_mass" && value >= 1) c.heavy_min_mass = (uint64_t)value;
     else if (k == "clique_kernel" && (value == 0 || value == 1)) c.clique_opt = value != 0;
+    else if (k == "heavy_span_shift" && value >= 0 && value <= 32) c.heavy_span_shift = (uint32_t)value;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;

@@ -153,6 +153,7 @@ struct Ctx_ {
     bool heavy_roots_opt = true;
     uint64_t heavy_min_mass = 16384;
     bool clique_opt = true;
+    uint32_t heavy_span_shift = 6;   // two-hop heavy roots: mass << shift >= id
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
