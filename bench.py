@@ -170,7 +170,7 @@ def run_4mc(args, eng, g, workload, morph_name="morphed"):
         "graph_load_s": round(load_s, 3), "matches_per_step": matches, "counts": ref,
     })
     line["roofline"] = {
-        "bound": "hbm", "kernel": "match_kernel + agg_window_kernel + edge_window_kernel",
+        "bound": "hbm", "kernel": "all matching launches of the step (match, clique, clique4, support, window kernels)",
         "launches_per_step": launches, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": None, "alg_bytes_per_launch": alg_bytes / launches,
         "avg_launch_ms": per_launch_ms,
