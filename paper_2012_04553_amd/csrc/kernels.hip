@@ -1353,15 +1353,36 @@ __device__ __forceinline__ void cq_drain(Ctx& c, const KArgs& a, const uint4* Q,
     }
 }
 
-template <bool BYTES>
+// Slot of a key known to be in the table.
+__device__ __forceinline__ uint32_t cq_slot_of(const uint32_t* H, uint32_t x) {
+    uint32_t h = cq_slot(x);
+    while (H[h] != x) h = (h + 1) & (CQ_HASH - 1);
+    return h;
+}
+
+// With SUP the launch also counts, for every edge {u < w}, the triangles on
+// it (its support, at w's place in N+(u)): the edge (v1, v2) of a triangle
+// found in row v1 by one returning-free global atomic, the edges (v0, v1)
+// and (v0, v2) in LDS (a counter per row of the chunk and a 16-bit counter
+// per hash slot), added to the global array once per row and root.
+template <bool BYTES, bool SUP>
 __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
     __shared__ uint32_t s_hash[4][CQ_HASH];
     __shared__ uint4 s_queue[4][CQ_QCAP];
+    __shared__ uint32_t s_scnt[SUP ? 4 : 1][SUP ? CQ_HASH / 2 : 1];   // two 16-bit counters a word
+    __shared__ uint32_t s_rcnt[SUP ? 4 : 1][64];
     const int lane = wave_lane();
-    uint32_t* H = s_hash[threadIdx.x >> 6];
-    uint4* Q = s_queue[threadIdx.x >> 6];
+    const int wv = threadIdx.x >> 6;
+    uint32_t* H = s_hash[wv];
+    uint4* Q = s_queue[wv];
+    uint32_t* SC = s_scnt[SUP ? wv : 0];
+    uint32_t* RC = s_rcnt[SUP ? wv : 0];
     uint32_t qn = 0;
     for (uint32_t i = lane; i < CQ_HASH; i += 64) H[i] = CQ_EMPTY;
+    if (SUP) {
+        for (uint32_t i = lane; i < CQ_HASH / 2; i += 64) SC[i] = 0;
+        RC[lane] = 0;
+    }
     wave_sync();
     Ctx c;
     c.g = a.g;
@@ -1414,7 +1435,7 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
                 const uint32_t total = __shfl(incl, 63);
                 const uint32_t excl = incl - len;
                 for (uint32_t t0 = 0; t0 < total; t0 += 64 * CQ_UNROLL) {
-                    uint32_t y[CQ_UNROLL];
+                    uint32_t y[CQ_UNROLL], src[CQ_UNROLL];
                     int o[CQ_UNROLL];
                     bool act[CQ_UNROLL];
 #pragma unroll
@@ -1422,12 +1443,18 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
                         const uint32_t t = t0 + (uint32_t)(u * 64) + lane;
                         act[u] = t < total;
                         o[u] = owner_of(incl, act[u] ? t : total - 1);
-                        const uint32_t src = __shfl(pb, o[u]) + (t - __shfl(excl, o[u]));
-                        y[u] = act[u] ? a.g.col[src] : 0u;
+                        src[u] = __shfl(pb, o[u]) + (t - __shfl(excl, o[u]));
+                        y[u] = act[u] ? a.g.col[src[u]] : 0u;
                     }
 #pragma unroll
                     for (int u = 0; u < CQ_UNROLL; ++u) {
                         const bool hit = act[u] && cq_find(H, y[u]);
+                        if (SUP && hit) {
+                            atomicAdd(&a.support[src[u]], 1u);
+                            atomicAdd(&RC[o[u]], 1u);
+                            const uint32_t h = cq_slot_of(H, y[u]);
+                            atomicAdd(&SC[h >> 1], 1u << ((h & 1u) * 16));
+                        }
                         if (counts_only) {
                             tally += hit ? 1u : 0u;
                             continue;
@@ -1450,8 +1477,29 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
                         }
                     }
                 }
+                if (SUP) {
+                    // edges (v0, x) of this chunk's rows
+                    wave_sync();
+                    const uint32_t k = RC[lane];
+                    if (k) {
+                        atomicAdd(&a.support[b + i], k);
+                        RC[lane] = 0;
+                    }
+                    wave_sync();
+                }
             }
             wave_sync();
+            if (SUP) {
+                // edges (v0, y) for the y of N+(v0) closing triangles
+                for (uint32_t i = lane; i < s; i += 64) {
+                    const uint32_t h = cq_slot_of(H, a.g.col[b + i]);
+                    const uint32_t k = (SC[h >> 1] >> ((h & 1u) * 16)) & 0xffffu;
+                    if (k) atomicAdd(&a.support[b + i], k);
+                }
+                wave_sync();
+                for (uint32_t i = lane; i < s; i += 64) SC[cq_slot_of(H, a.g.col[b + i]) >> 1] = 0;
+                wave_sync();
+            }
             for (uint32_t i = lane; i < s; i += 64) cq_erase(H, a.g.col[b + i]);
             wave_sync();
         }
@@ -1467,6 +1515,77 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
         unsigned long long bsum = c.bytes;
         for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
         if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
+// Edge-support plans: one thread per vertex u walks its out-list; each edge
+// {u < w} takes its support t (and returns the counter to zero), orients
+// itself as the plan's level 1 requires, and adds the tail with the
+// set-size term equal to t.
+template <bool BYTES>
+__global__ void __launch_bounds__(256) support_kernel(KArgs a) {
+    const int np = a.nplans;
+    Ctx c;
+    c.g = a.g;
+    c.P = nullptr;
+    c.buf = nullptr;
+    c.stride = 0;
+    c.bytes = 0;
+    c.bmw = nullptr;
+    c.bm = nullptr;
+    u128 acc[CQ_PLANS];
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p) acc[p] = 0;
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < a.g.n; u += step) {
+        const uint32_t pb = a.g.split[u], pe = a.g.rp[u + 1];
+        const uint32_t du = pe - a.g.rp[u];
+        if (BYTES) c.bytes += 12 + 8ull * (pe - pb);
+        for (uint32_t p = pb; p < pe; ++p) {
+            const uint32_t w = a.g.col[p];
+            // an edge on no triangle still adds the tail's terms without t
+            const uint32_t t = a.support[p];
+            if (t) a.support[p] = 0;
+            const uint32_t dw = a.g.rp[w + 1] - a.g.rp[w];
+            if (BYTES) c.bytes += 8;
+#pragma unroll 1
+            for (int q = 0; q < np; ++q) {
+                const DPlan* P = a.plans + q;
+                const bool up = P->lev[1].gt != 0;
+                const uint32_t v0 = up ? u : w, v1 = up ? w : u;
+                const uint32_t d0 = up ? du : dw, d1 = up ? dw : du;
+                uint64_t tv[CQ_TERMS];
+                const uint32_t vv[KMAX] = {v0, v1, 0u, 0u, 0u};
+#pragma unroll 1
+                for (int k = 0; k < P->nterm; ++k) {
+                    const DTerm T = P->term[k];
+                    if (!T.cheap) tv[k] = t;
+                    else if ((T.gt | T.lt) == 0 && (T.neq & ~T.sure) == 0)
+                        tv[k] = (uint64_t)((__builtin_ctz((uint32_t)T.adj) == 0 ? d0 : d1) -
+                                           (uint32_t)__builtin_popcount((uint32_t)T.neq));
+                    else tv[k] = cheap_term<BYTES>(c, vv, T, 0);
+                }
+                i128 sum = 0;
+                for (int m = 0; m < P->nmono; ++m) {
+                    const DMono M = P->mono[m];
+                    i128 prod = (i128)M.coef;
+                    for (int f = 0; f < M.nf; ++f) prod *= (i128)tv[M.f[f]];
+                    sum += prod;
+                }
+                const u128 add = sum > 0 ? (u128)sum : (u128)0;
+#pragma unroll
+                for (int k = 0; k < CQ_PLANS; ++k)
+                    if (k == q) acc[k] += add;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p)
+        if (p < np) flush(a, p, acc[p]);
+    if (BYTES) {
+        unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (wave_lane() == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
     }
 }
 
@@ -1679,10 +1798,19 @@ int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s)
 }
 
 int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
-    if (count_bytes)
-        hipLaunchKernelGGL(clique_kernel<true>, dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(clique_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    if (a.support) {
+        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, false>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique_kernel<false, false>), dim3(grid), dim3(256), 0, s, a);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes) hipLaunchKernelGGL(support_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(support_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

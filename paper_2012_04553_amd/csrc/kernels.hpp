@@ -41,6 +41,7 @@ struct KArgs {
     uint32_t* wscr;           // blocks * (2 + EW_TERMS) * wscr_stride
     uint64_t wscr_stride;
     const int* cancel;        // host-visible cancel flag or null
+    uint32_t* support;        // per out-list position: triangles on that edge, or null
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
@@ -53,6 +54,9 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
 // wavefront per item {r0, r1, i0, i1} (roots [r0, r1), rows [i0, i1) of
 // N+(r)).
 int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Edge-support plans (support_ok) over a support array filled by a
+// launch_clique with a.support set; returns every counter to zero.
+int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
 // wavefront (heavy = false) or one workgroup (heavy = true) per root of
 // the items {r0, r1, 0, 0}.

@@ -724,6 +724,7 @@ std::string PlanInfo::describe() const {
     if (d.bm0) s += " root_bitmap";
     if (clique_ok(d)) s += " triangle_core";
     if (clique4_ok(d)) s += " clique4";
+    if (!clique_ok(d) && support_ok(d)) s += " edge_support";
     return s;
 }
 

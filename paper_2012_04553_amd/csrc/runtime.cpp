@@ -384,7 +384,7 @@ int Ctx_::graph_unload(uint32_t gid) {
     if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
     if (it->second->inflight) return fail(PM_E_BUSY, "queries in flight on this graph");
     GraphRes& G = *it->second;
-    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items})
+    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items, G.off_support})
         if (o < UINT64_MAX - 1) arena.release(o);
     for (auto& is : G.itemsets) arena.release(is.second.off);
     for (auto& ls : G.launches) free_launchset(ls.second.get());
@@ -583,6 +583,27 @@ bool Ctx_::use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) co
     return false;
 }
 
+// Whether a launch set runs its edge-support plans on triangle supports
+// (every triangle has to be met by clique_kernel: no root beyond CQ_SMAX).
+bool Ctx_::use_support(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
+    if (!clique_opt || !support_opt || G.clique_items.empty() || !G.clique_big.empty()) return false;
+    for (const PlanInfo& p : plans)
+        if (!clique_ok(p.d) && support_ok(p.d)) return true;
+    return false;
+}
+
+// The graph's support counters (one u32 per adjacency entry), allocated
+// and cleared on first use; every launch returns them to zero.
+int Ctx_::ensure_support(GraphRes& G) {
+    if (G.off_support != UINT64_MAX) return PM_OK;
+    const uint64_t words = std::max<uint64_t>(1, 2 * G.m);
+    G.off_support = arena.alloc(4 * words);
+    if (G.off_support == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the edge supports");
+    if (launch_zero((uint32_t*)dptr(G.off_support), words, stream)) return fail(PM_E_DEVICE, "zero-fill failed");
+    HIPCHK(hipStreamSynchronize(stream));
+    return PM_OK;
+}
+
 // General-kernel items over the roots clique4_kernel leaves out.
 std::vector<KItem> Ctx_::clique4_big_items(const GraphRes& G, const LaunchCfg& cfg) const {
     if (G.c4_big.empty()) return {};
@@ -641,7 +662,7 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     }
     // per block: cursor, end and counter words per bridge or candidate
     if (hk || ek) b += (uint64_t)grid_blocks(cfg) * (2 + EW_TERMS) * wstride * 4 + 256;
-    if (heavy_ok && use_clique(G, plans))
+    if (heavy_ok && (use_clique(G, plans) || use_support(G, plans)))
         b += 16 * (G.clique_items.size() + clique_big_items(G, cfg).size()) + 2 * 256;
     if (heavy_ok && use_clique4(G, plans))
         b += 16 * (G.c4_light.size() + G.c4_heavy.size() + clique4_big_items(G, cfg).size()) + 3 * 256;
@@ -779,6 +800,12 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const bool cq = agg == nullptr && use_clique(G, plans);
     const std::vector<KItem> cq_big = cq ? clique_big_items(G, cfg) : std::vector<KItem>();
     const bool c4 = agg == nullptr && use_clique4(G, plans);
+    const bool sup = agg == nullptr && use_support(G, plans);
+    if (sup) {
+        int rc2 = ensure_support(G);
+        if (rc2) return rc2;
+    }
+    const bool cqs = cq || sup;
     const std::vector<KItem> c4_big = c4 ? clique4_big_items(G, cfg) : std::vector<KItem>();
     ls->off_mem = arena.alloc(need);
     if (ls->off_mem == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the query scratch");
@@ -828,7 +855,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     }
     ls->cq_items = ls->cq_big = nullptr;
     ls->cq_nitems = ls->cq_nbig = 0;
-    if (cq) {
+    ls->support = sup ? (uint32_t*)dptr(G.off_support) : nullptr;
+    ls->sup_run = -1;
+    if (cqs) {
         KItem* ci = (KItem*)carve(16 * G.clique_items.size());
         KItem* bi = (KItem*)carve(16 * std::max<size_t>(1, cq_big.size()));
         HIPCHK(hipMemcpyAsync(ci, G.clique_items.data(), 16 * G.clique_items.size(), hipMemcpyHostToDevice, st));
@@ -922,6 +951,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     auto group = [&](int q) {
         if (plans[q].d.agg_last) return 2;
         if (cq && clique_runs(G, plans[q].d)) return 3;
+        if (sup && support_ok(plans[q].d)) return 5;
         if (c4 && clique4_ok(plans[q].d)) return 4;
         return (ek && edge_window_ok(plans[q].d)) ? 1 : 0;
     };
@@ -935,12 +965,25 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
             ls->run_agg.push_back(0);
         } else if (grp == 3) {
             for (int k = i; k < j; k += CQ_PLANS) {
+                // the first triangle pass also fills the edge supports
+                if (sup && ls->sup_run < 0) ls->sup_run = (int)ls->runs.size();
                 ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
                 ls->run_agg.push_back(5);
             }
             if (!cq_big.empty()) {
                 ls->runs.push_back({i, j});
                 ls->run_agg.push_back(6);
+            }
+        } else if (grp == 5) {
+            if (ls->sup_run < 0) {
+                // no triangle-core plan: a pass that only fills the supports
+                ls->sup_run = (int)ls->runs.size();
+                ls->runs.push_back({i, i});
+                ls->run_agg.push_back(5);
+            }
+            for (int k = i; k < j; k += CQ_PLANS) {
+                ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
+                ls->run_agg.push_back(10);
             }
         } else if (grp == 4) {
             for (int k = i; k < j; k += CQ_PLANS) {
@@ -973,7 +1016,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         }
         i = j;
     }
-    if (hk || ek || cq || c4) HIPCHK(hipStreamSynchronize(st));
+    if (hk || ek || cqs || c4) HIPCHK(hipStreamSynchronize(st));
     return PM_OK;
 }
 
@@ -1005,8 +1048,13 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         } else if (ls.run_agg[r] == 5) {
             b.items = ls.cq_items;
             b.nitems = ls.cq_nitems;
-            if (b.nitems && launch_clique(b, clique_blocks(), bytes_pass, s))
+            b.support = (int)r == ls.sup_run ? ls.support : nullptr;
+            if (b.nitems && launch_clique(b, clique_blocks(b.support != nullptr), bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 10) {
+            b.support = ls.support;
+            if (launch_support(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 6) {
             b.items = ls.cq_big;
@@ -1229,7 +1277,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
                       std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
                       std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
                       std::to_string(heavy_min_mass) + "," + std::to_string(clique_opt) + "," +
-                      std::to_string(heavy_span_shift);
+                      std::to_string(heavy_span_shift) + "," + std::to_string(support_opt);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy) {
@@ -1607,6 +1655,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "heavy_roots" && (value == 0 || value == 1)) c.heavy_roots_opt = value != 0;
     else if (k == "heavy_min_mass" && value >= 1) c.heavy_min_mass = (uint64_t)value;
     else if (k == "clique_kernel" && (value == 0 || value == 1)) c.clique_opt = value != 0;
+    else if (k == "edge_support" && (value == 0 || value == 1)) c.support_opt = value != 0;
     else if (k == "heavy_span_shift" && value >= 0 && value <= 32) c.heavy_span_shift = (uint32_t)value;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);

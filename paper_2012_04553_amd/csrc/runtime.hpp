@@ -73,7 +73,7 @@ struct LaunchSet {
                                              // 3 edge-core light roots, 4 edge-core heavy roots,
                                              // 5 triangle-core (clique_kernel), 6 their larger roots,
                                              // 7/8 4-cliques (clique4_kernel, light/heavy roots),
-                                             // 9 their larger roots
+                                             // 9 their larger roots, 10 edge-support plans
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
     const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
@@ -88,6 +88,8 @@ struct LaunchSet {
     const KItem* c4_heavy = nullptr;         //   workgroup roots,
     const KItem* c4_big = nullptr;           //   general-kernel items of the larger roots
     uint32_t c4_nlight = 0, c4_nheavy = 0, c4_nbig = 0;
+    uint32_t* support = nullptr;             // edge supports (the graph's), when used
+    int sup_run = -1;                        // the triangle run that fills them
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
@@ -108,6 +110,7 @@ struct GraphRes {
     GraphStats st;
     uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_split = UINT64_MAX, off_lab = UINT64_MAX,
              off_items = UINT64_MAX;
+    uint64_t off_support = UINT64_MAX;       // edge supports, u32 per adjacency entry (on first use)
     uint64_t device_bytes = 0;
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
@@ -154,6 +157,7 @@ struct Ctx_ {
     uint64_t heavy_min_mass = 16384;
     bool clique_opt = true;
     uint32_t heavy_span_shift = 6;   // two-hop heavy roots: mass << shift >= id
+    bool support_opt = true;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
@@ -174,8 +178,10 @@ struct Ctx_ {
         return c.grid_override > 0 ? c.grid_override : num_cus * c.blocks_per_cu;
     }
     uint64_t waves(const LaunchCfg& c) const { return (uint64_t)grid_blocks(c) * (block / 64); }
-    // clique_kernel: 32 KB of LDS a workgroup, five resident a CU
-    int clique_blocks() const { return num_cus * 5; }
+    // clique_kernel: 40 KB of LDS a workgroup, four resident a CU; with
+    // edge supports 65 KB, two
+    int clique_blocks(bool sup = false) const { return num_cus * (sup ? 2 : 4); }
+    int support_blocks() const { return num_cus * 8; }
     // clique4_kernel: 44 KB of LDS a workgroup, three resident a CU
     int clique4_blocks() const { return num_cus * 3; }
     // wavefronts of the two-hop aggregation launches on an n-vertex graph:
@@ -233,6 +239,8 @@ struct Ctx_ {
     bool use_clique(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
     std::vector<KItem> clique_big_items(const GraphRes& G, const LaunchCfg& cfg) const;
     bool use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
+    bool use_support(const GraphRes& G, const std::vector<PlanInfo>& plans) const;
+    int ensure_support(GraphRes& G);
     std::vector<KItem> clique4_big_items(const GraphRes& G, const LaunchCfg& cfg) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
     int launch(GraphRes& G, Query& Q);

@@ -1,6 +1,7 @@
-"""GPU parity of the triangle-core and 4-clique kernels: K3, the tailed
-triangle, the 4-path (which needs K3), K4 and the 4-vertex sets that
-include them, against the oracle's closed-form counts.  The R-MAT graphs
+"""GPU parity of the triangle-core, edge-support and 4-clique kernels: K3,
+the tailed triangle, the 4-path (which needs K3), the diamond (from edge
+supports), K4 and the 4-vertex sets that include them, against the
+oracle's closed-form counts.  The R-MAT graphs
 cut their hub roots into row slices and give the 4-clique kernel roots of
 both its wavefront and workgroup sizes; the clique K_1040 gives roots with
 more out-neighbours than either kernel takes, which run in the general
@@ -54,6 +55,7 @@ def test_clique_kernel_rmat(eng, scale, seed):
         names = oracle.named_4()
         assert "triangle_core" in eng.plan_describe(gid, (4, names["tailed_triangle"], False))
         assert "triangle_core" in eng.plan_describe(gid, (3, 0x7, False))
+        assert "edge_support" in eng.plan_describe(gid, (4, names["diamond"], False))
         for on in (True, False):
             assert _count(eng, gid, [(3, 0x7, False)], pm.MORPH_NONE, on) == [tc["triangles"]]
             assert _count(eng, gid, [(4, m, False) for m in classes], pm.MORPH_NONE, on) == \
@@ -79,5 +81,23 @@ def test_clique_kernel_dense_roots(eng):
         assert eng.graph_stats(gid)["max_out_degree"] > 1024
         for on in (True, False):
             assert _count(eng, gid, pats, pm.MORPH_NONE, on) == want
+    finally:
+        eng.graph_unload(gid)
+
+
+def test_clique_kernels_five_vertex(eng):
+    """Five-vertex edge-induced patterns whose plans have triangle, 4-clique
+    or edge-support cores, with tail monomials that do not hold the set-size
+    term (an edge on no triangle still adds them)."""
+    import paper_2012_04553_amd as pm
+    g = gen.rmat(7, 8, seed=21)
+    vi = oracle.census(g, 5)
+    ei = P.edge_induced_from_vertex_induced(5, vi)
+    classes = list(P.connected_classes(5))
+    gid = eng.load(g)
+    try:
+        for on in (True, False):
+            assert _count(eng, gid, [(5, m, False) for m in classes], pm.MORPH_NONE, on) == \
+                [ei[m] for m in classes]
     finally:
         eng.graph_unload(gid)
