@@ -892,6 +892,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
 // smallest pending target, so empty id ranges are never visited; after a
 // window is filled the four waves evaluate its counters and clear them.
 constexpr uint32_t WIN_IDS = 8192;
+constexpr int AW_UNROLL = 4;
 
 template <bool BYTES>
 __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
@@ -998,15 +999,25 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
                 const uint32_t incl = wave_incl_scan(len);
                 const uint32_t tot = __shfl(incl, 63);
                 const uint32_t excl = incl - len;
-                for (uint32_t tb = 0; tb < tot; tb += 64) {
-                    const uint32_t t = tb + lane;
-                    const bool act = t < tot;
-                    const int o = owner_of(incl, act ? t : tot - 1);
-                    const uint32_t src = __shfl(q, o) + (t - __shfl(excl, o));
-                    if (!act) continue;
-                    const uint32_t x = c.g.col[src];
-                    if ((L.label < 0 || c.g.lab[x] == (uint8_t)L.label) && !((L.neq & 1) && x == r))
-                        if (atomicAdd(&win[x - wlo], 1u) == 0u) used[atomicAdd(&s_nused[ph], 1u)] = (uint16_t)(x - wlo);
+                // AW_UNROLL reads in flight per lane
+                for (uint32_t tb = 0; tb < tot; tb += 64 * AW_UNROLL) {
+                    uint32_t xs[AW_UNROLL];
+                    bool acts[AW_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < AW_UNROLL; ++u) {
+                        const uint32_t t = tb + (uint32_t)(u * 64) + lane;
+                        acts[u] = t < tot;
+                        const int o = owner_of(incl, acts[u] ? t : tot - 1);
+                        const uint32_t src = __shfl(q, o) + (t - __shfl(excl, o));
+                        xs[u] = acts[u] ? c.g.col[src] : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < AW_UNROLL; ++u) {
+                        const uint32_t x = xs[u];
+                        if (acts[u] && (L.label < 0 || c.g.lab[x] == (uint8_t)L.label) && !((L.neq & 1) && x == r))
+                            if (atomicAdd(&win[x - wlo], 1u) == 0u)
+                                used[atomicAdd(&s_nused[ph], 1u)] = (uint16_t)(x - wlo);
+                    }
                 }
                 if (valid) {
                     const uint32_t xn = !len ? x0 : (qend < qe ? c.g.col[qend] : 0xffffffffu);
