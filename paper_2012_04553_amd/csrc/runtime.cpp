@@ -361,6 +361,28 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
         }
     });
     clique_items(*G, nrp, ncol, nsplit);
+    {
+        // the triangle and 4-clique kernels' items stay on the device with
+        // the graph (read-only, shared by every launch set)
+        const size_t nc = G->clique_items.size(), nl = G->c4_light.size(), nh = G->c4_heavy.size();
+        if (nc + nl + nh) {
+            G->off_cq = arena.alloc(16 * (nc + nl + nh));
+            if (G->off_cq == UINT64_MAX) {
+                for (uint64_t o : {G->off_rp, G->off_col, G->off_split, G->off_lab, G->off_items})
+                    if (o < UINT64_MAX - 1) arena.release(o);
+                return fail(PM_E_NOMEM, "arena too small for the graph");
+            }
+            KItem* d = (KItem*)dptr(G->off_cq);
+            if (nc) HIPCHK(hipMemcpyAsync(d, G->clique_items.data(), 16 * nc, hipMemcpyHostToDevice, stream));
+            if (nl) HIPCHK(hipMemcpyAsync(d + nc, G->c4_light.data(), 16 * nl, hipMemcpyHostToDevice, stream));
+            if (nh) HIPCHK(hipMemcpyAsync(d + nc + nl, G->c4_heavy.data(), 16 * nh, hipMemcpyHostToDevice, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            G->d_cq = d;
+            G->d_c4l = d + nc;
+            G->d_c4h = d + nc + nl;
+            G->device_bytes += 16 * (nc + nl + nh);
+        }
+    }
     G->host_rp = std::move(nrp);
     if (labels) {
         // vertices by label (stable: degree order within a label), for the
@@ -384,7 +406,7 @@ int Ctx_::graph_unload(uint32_t gid) {
     if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
     if (it->second->inflight) return fail(PM_E_BUSY, "queries in flight on this graph");
     GraphRes& G = *it->second;
-    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items, G.off_support})
+    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items, G.off_support, G.off_cq})
         if (o < UINT64_MAX - 1) arena.release(o);
     for (auto& is : G.itemsets) arena.release(is.second.off);
     for (auto& ls : G.launches) free_launchset(ls.second.get());
@@ -662,10 +684,10 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     }
     // per block: cursor, end and counter words per bridge or candidate
     if (hk || ek) b += (uint64_t)grid_blocks(cfg) * (2 + EW_TERMS) * wstride * 4 + 256;
-    if (heavy_ok && (use_clique(G, plans) || use_support(G, plans)))
-        b += 16 * (G.clique_items.size() + clique_big_items(G, cfg).size()) + 2 * 256;
-    if (heavy_ok && use_clique4(G, plans))
-        b += 16 * (G.c4_light.size() + G.c4_heavy.size() + clique4_big_items(G, cfg).size()) + 3 * 256;
+    // general-kernel items of the roots the triangle and 4-clique kernels
+    // leave out (their own items live with the graph)
+    if (use_clique(G, plans) || use_support(G, plans)) b += 16 * clique_big_items(G, cfg).size() + 256;
+    if (use_clique4(G, plans)) b += 16 * clique4_big_items(G, cfg).size() + 256;
     return b;
 }
 
@@ -797,9 +819,11 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         eitems = heavy_items(G, eheavy, false);
         elight = items_without(build_items(G.host_rp, G.n, cfg.item_budget, cfg.item_split, 256), is_heavy);
     }
-    const bool cq = agg == nullptr && use_clique(G, plans);
+    // serving slots (agg given) take the triangle and 4-clique kernels only
+    // where no root is left to the general kernel: nothing to upload then
+    const bool cq = use_clique(G, plans) && (agg == nullptr || G.clique_big.empty());
     const std::vector<KItem> cq_big = cq ? clique_big_items(G, cfg) : std::vector<KItem>();
-    const bool c4 = agg == nullptr && use_clique4(G, plans);
+    const bool c4 = use_clique4(G, plans) && (agg == nullptr || G.c4_big.empty());
     const bool sup = agg == nullptr && use_support(G, plans);
     if (sup) {
         int rc2 = ensure_support(G);
@@ -858,29 +882,28 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->support = sup ? (uint32_t*)dptr(G.off_support) : nullptr;
     ls->sup_run = -1;
     if (cqs) {
-        KItem* ci = (KItem*)carve(16 * G.clique_items.size());
-        KItem* bi = (KItem*)carve(16 * std::max<size_t>(1, cq_big.size()));
-        HIPCHK(hipMemcpyAsync(ci, G.clique_items.data(), 16 * G.clique_items.size(), hipMemcpyHostToDevice, st));
-        if (!cq_big.empty())
-            HIPCHK(hipMemcpyAsync(bi, cq_big.data(), 16 * cq_big.size(), hipMemcpyHostToDevice, st));
-        ls->cq_items = ci;
+        ls->cq_items = G.d_cq;
         ls->cq_nitems = (uint32_t)G.clique_items.size();
-        ls->cq_big = bi;
-        ls->cq_nbig = (uint32_t)cq_big.size();
+        if (!cq_big.empty()) {
+            KItem* bi = (KItem*)carve(16 * cq_big.size());
+            HIPCHK(hipMemcpyAsync(bi, cq_big.data(), 16 * cq_big.size(), hipMemcpyHostToDevice, st));
+            ls->cq_big = bi;
+            ls->cq_nbig = (uint32_t)cq_big.size();
+        }
     }
     ls->c4_light = ls->c4_heavy = ls->c4_big = nullptr;
     ls->c4_nlight = ls->c4_nheavy = ls->c4_nbig = 0;
     if (c4) {
-        auto up = [&](const std::vector<KItem>& v, const KItem** dst, uint32_t* cnt) -> int {
-            KItem* d = (KItem*)carve(16 * std::max<size_t>(1, v.size()));
-            if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), 16 * v.size(), hipMemcpyHostToDevice, st));
-            *dst = d;
-            *cnt = (uint32_t)v.size();
-            return PM_OK;
-        };
-        if (up(G.c4_light, &ls->c4_light, &ls->c4_nlight) || up(G.c4_heavy, &ls->c4_heavy, &ls->c4_nheavy) ||
-            up(c4_big, &ls->c4_big, &ls->c4_nbig))
-            return PM_E_DEVICE;
+        ls->c4_light = G.d_c4l;
+        ls->c4_nlight = (uint32_t)G.c4_light.size();
+        ls->c4_heavy = G.d_c4h;
+        ls->c4_nheavy = (uint32_t)G.c4_heavy.size();
+        if (!c4_big.empty()) {
+            KItem* bi = (KItem*)carve(16 * c4_big.size());
+            HIPCHK(hipMemcpyAsync(bi, c4_big.data(), 16 * c4_big.size(), hipMemcpyHostToDevice, st));
+            ls->c4_big = bi;
+            ls->c4_nbig = (uint32_t)c4_big.size();
+        }
     }
     ls->zero_base = (uint32_t*)zb;
     ls->zero_words = zbytes / 4;
@@ -1016,7 +1039,8 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         }
         i = j;
     }
-    if (hk || ek || cqs || c4) HIPCHK(hipStreamSynchronize(st));
+    // pageable uploads above must finish before their host vectors go
+    if (hk || ek || !cq_big.empty() || !c4_big.empty()) HIPCHK(hipStreamSynchronize(st));
     return PM_OK;
 }
 

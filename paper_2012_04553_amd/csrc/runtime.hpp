@@ -111,6 +111,10 @@ struct GraphRes {
     uint64_t off_rp = UINT64_MAX, off_col = UINT64_MAX, off_split = UINT64_MAX, off_lab = UINT64_MAX,
              off_items = UINT64_MAX;
     uint64_t off_support = UINT64_MAX;       // edge supports, u32 per adjacency entry (on first use)
+    uint64_t off_cq = UINT64_MAX;            // device copies of the items below
+    const KItem* d_cq = nullptr;
+    const KItem* d_c4l = nullptr;
+    const KItem* d_c4h = nullptr;
     uint64_t device_bytes = 0;
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
