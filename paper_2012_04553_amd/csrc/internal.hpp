@@ -203,6 +203,7 @@ inline bool support_ok(const DPlan& d) {
 // clique4_kernel counts them from bit rows of the graph induced on N+(v0),
 // roots with up to C4_ROOT_MAX out-neighbours.
 constexpr uint32_t C4_ROOT_MAX = 512;
+constexpr uint32_t C4_LIGHT_MAX = 128;   // roots a wavefront takes; larger ones a workgroup
 inline bool clique4_ok(const DPlan& d) {
     if (d.ncore != 4 || d.nterm != 0 || d.agg_last || d.lev[0].label >= 0) return false;
     for (int j = 1; j < 4; ++j) {

@@ -1611,10 +1611,11 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
 // Light roots (3 .. C4_LIGHT out-neighbours) take one wavefront each,
 // heavier ones (up to C4_HEAVY) a whole workgroup; larger roots run in the
 // general kernel.
-constexpr uint32_t C4_LIGHT = 256;
-constexpr uint32_t C4_HEAVY = 512;
-constexpr uint32_t C4_LDS_WORDS = 11264;                       // 44 KB a workgroup
-constexpr uint32_t C4_WAVE_WORDS = C4_LDS_WORDS / 4;           // 2816 a wavefront
+constexpr uint32_t C4_LIGHT = C4_LIGHT_MAX;
+constexpr uint32_t C4_HEAVY = C4_ROOT_MAX;
+constexpr uint32_t C4_LDS_WORDS = 11264;   // 44 KB: a workgroup's table for up to 512 out-neighbours
+// a wavefront's table for up to 128: 256 keys, 256 positions, 128 rows of 4 words
+constexpr uint32_t C4_WAVE_WORDS = 256 + 128 + 128 * 4;
 
 // LDS layout of one root's table: keys[H], positions (u16)[H], rows[S * W].
 template <int LOGH>
@@ -1722,7 +1723,7 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
 
 template <bool BYTES, bool WG>
 __global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
-    __shared__ uint32_t s_lds[C4_LDS_WORDS];
+    __shared__ uint32_t s_lds[WG ? C4_LDS_WORDS : 4 * C4_WAVE_WORDS];
     const int lane = wave_lane();
     uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * C4_WAVE_WORDS;
     __shared__ uint32_t s_it;
@@ -1761,7 +1762,7 @@ __global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
             const uint32_t s = e - b;
             if (s < 3 || s > (WG ? C4_HEAVY : C4_LIGHT)) continue;
             if (WG) cnt += c4_root<11, true, BYTES>(c, a.g, base, r, b, s);
-            else cnt += c4_root<9, false, BYTES>(c, a.g, base, r, b, s);
+            else cnt += c4_root<8, false, BYTES>(c, a.g, base, r, b, s);
         }
     }
 #pragma unroll

@@ -132,7 +132,6 @@ static std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t 
 // about CQ_VOL each (items {r, r+1, i0, i1}).  Roots with more than CQ_SMAX
 // out-neighbours are listed apart for the general kernel.
 static constexpr uint64_t CQ_VOL = 16384;
-static constexpr uint32_t C4_LIGHT_MAX = 256;   // clique4_kernel's wavefront roots
 static void clique_items(GraphRes& G, const std::vector<uint32_t>& rp, const std::vector<uint32_t>& col,
                          const std::vector<uint32_t>& split) {
     G.clique_items.clear();
@@ -1087,7 +1086,7 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
             const bool heavy = ls.run_agg[r] == 8;
             b.items = heavy ? ls.c4_heavy : ls.c4_light;
             b.nitems = heavy ? ls.c4_nheavy : ls.c4_nlight;
-            if (b.nitems && launch_clique4(b, clique4_blocks(), heavy, bytes_pass, s))
+            if (b.nitems && launch_clique4(b, clique4_blocks(heavy), heavy, bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 9) {

@@ -186,8 +186,9 @@ struct Ctx_ {
     // edge supports 65 KB, two
     int clique_blocks(bool sup = false) const { return num_cus * (sup ? 2 : 4); }
     int support_blocks() const { return num_cus * 8; }
-    // clique4_kernel: 44 KB of LDS a workgroup, three resident a CU
-    int clique4_blocks() const { return num_cus * 3; }
+    // clique4_kernel: workgroup roots 44 KB of LDS a workgroup, three
+    // resident a CU; wavefront roots 14 KB, eight
+    int clique4_blocks(bool heavy) const { return num_cus * (heavy ? 3 : 8); }
     // wavefronts of the two-hop aggregation launches on an n-vertex graph:
     // each holds two dense u32[n] arrays, so their number follows from a
     // memory budget (a quarter of the arena, at most 8 GiB)
