@@ -199,6 +199,19 @@ inline bool support_ok(const DPlan& d) {
     return heavy >= 0;
 }
 
+// Edge-core plans whose terms are all cheap (the 4-path: the sum over edges
+// of (d(v0) - 1)(d(v1) - 1)): support_kernel evaluates them per edge, with
+// no supports needed.
+inline bool edge_cheap_ok(const DPlan& d) {
+    if (d.ncore != 2 || d.agg_last || d.local || d.nterm == 0 || d.lev[0].label >= 0) return false;
+    const DLevel& l1 = d.lev[1];
+    if (l1.adj != 1 || l1.anti || l1.label >= 0 || l1.agg) return false;
+    if (!((l1.gt == 1 && l1.lt == 0) || (l1.lt == 1 && l1.gt == 0))) return false;
+    for (int q = 0; q < d.nterm; ++q)
+        if (!d.term[q].cheap || d.term[q].agg) return false;
+    return true;
+}
+
 // Counted 4-cliques v0 < v1 < v2 < v3 enumerated from N+(v0) (no labels):
 // clique4_kernel counts them from bit rows of the graph induced on N+(v0),
 // roots with up to C4_ROOT_MAX out-neighbours.

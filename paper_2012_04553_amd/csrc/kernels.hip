@@ -1529,9 +1529,10 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
     }
 }
 
-// Edge-support plans: one thread per vertex u walks its out-list; each edge
-// {u < w} takes its support t (and returns the counter to zero), orients
-// itself as the plan's level 1 requires, and adds the tail with the
+// Edge-support plans, and edge-core plans with cheap terms only (then
+// without a support array): one thread per vertex u walks its out-list;
+// each edge {u < w} takes its support t (and returns the counter to zero),
+// orients itself as the plan's level 1 requires, and adds the tail with the
 // set-size term equal to t.
 template <bool BYTES>
 __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
@@ -1555,7 +1556,7 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
         for (uint32_t p = pb; p < pe; ++p) {
             const uint32_t w = a.g.col[p];
             // an edge on no triangle still adds the tail's terms without t
-            const uint32_t t = a.support[p];
+            const uint32_t t = a.support ? a.support[p] : 0u;
             if (t) a.support[p] = 0;
             const uint32_t dw = a.g.rp[w + 1] - a.g.rp[w];
             if (BYTES) c.bytes += 8;

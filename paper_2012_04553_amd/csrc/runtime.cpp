@@ -493,7 +493,8 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     // each group can run in launches of its own
     auto group = [&](size_t a) {
         const DPlan& d = pl[a].d;
-        return d.agg_last ? 4 : (clique_ok(d) ? 1 : (clique4_ok(d) ? 2 : (edge_window_ok(d) ? 3 : 0)));
+        return d.agg_last ? 4
+                          : (clique_ok(d) ? 1 : (clique4_ok(d) ? 2 : (edge_window_ok(d) || edge_cheap_ok(d) ? 3 : 0)));
     };
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return group(a) < group(b); });
     closure->clear();
@@ -973,7 +974,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     auto group = [&](int q) {
         if (plans[q].d.agg_last) return 2;
         if (cq && clique_runs(G, plans[q].d)) return 3;
-        if (sup && support_ok(plans[q].d)) return 5;
+        if ((sup && support_ok(plans[q].d)) || (clique_opt && edge_cheap_ok(plans[q].d))) return 5;
         if (c4 && clique4_ok(plans[q].d)) return 4;
         return (ek && edge_window_ok(plans[q].d)) ? 1 : 0;
     };
@@ -997,7 +998,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                 ls->run_agg.push_back(6);
             }
         } else if (grp == 5) {
-            if (ls->sup_run < 0) {
+            bool need = false;
+            for (int k = i; k < j; ++k) need = need || !edge_cheap_ok(plans[k].d);
+            if (need && ls->sup_run < 0) {
                 // no triangle-core plan: a pass that only fills the supports
                 ls->sup_run = (int)ls->runs.size();
                 ls->runs.push_back({i, i});
