@@ -141,6 +141,9 @@ inline bool edge_window_ok(const DPlan& d) {
 constexpr uint32_t CQ_SMAX = 1024;
 constexpr int CQ_PLANS = 4;
 constexpr uint32_t CQ_TERMS = 8;
+// Graphs up to this many vertices keep the per-slot triangle counters of
+// the support pass inside the hash slots (a smaller LDS footprint).
+constexpr uint32_t CQ_PACK_MAX = 0x3FFFFE;
 inline int clique_kind(const DPlan& d) {
     if (d.ncore < 2 || d.ncore > 3 || d.agg_last || d.nterm > (int)CQ_TERMS) return 0;
     if (d.local && !(d.ncore == 3 && d.nterm == 0)) return 0;

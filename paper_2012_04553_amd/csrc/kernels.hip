@@ -1247,28 +1247,37 @@ __device__ __forceinline__ void wave_sync() {
 // Fibonacci hashing onto the 2^11 slots.
 __device__ __forceinline__ uint32_t cq_slot(uint32_t x) { return (x * 0x9E3779B1u) >> 21; }
 
+// A slot holds a key in its top 32 - KS bits.  With KS = 10 the low bits
+// count the triangles found on the edge (v0, key): at most CQ_SMAX - 1, so
+// they never reach the key, and a key stays below CQ_EMPTY >> KS when
+// n <= CQ_PACK_MAX.
+template <int KS>
 __device__ __forceinline__ void cq_insert(uint32_t* H, uint32_t x) {
     uint32_t h = cq_slot(x);
-    while (atomicCAS(&H[h], CQ_EMPTY, x) != CQ_EMPTY) h = (h + 1) & (CQ_HASH - 1);
+    while (atomicCAS(&H[h], CQ_EMPTY, x << KS) != CQ_EMPTY) h = (h + 1) & (CQ_HASH - 1);
 }
 
-// The table always holds an empty slot, so a probe for an absent key ends.
-__device__ __forceinline__ bool cq_find(const uint32_t* H, uint32_t x) {
+// Slot of x, or -1.  The table always holds an empty slot, so a probe for
+// an absent key ends.
+template <int KS>
+__device__ __forceinline__ int cq_find(const uint32_t* H, uint32_t x) {
     uint32_t h = cq_slot(x);
     for (;;) {
         const uint32_t k = H[h];
-        if (k == x) return true;
-        if (k == CQ_EMPTY) return false;
+        if (k == CQ_EMPTY) return -1;
+        if ((k >> KS) == x) return (int)h;
         h = (h + 1) & (CQ_HASH - 1);
     }
 }
 
-// Removes a key known to be present.  All keys of the table are removed
-// together, so a probe walks past slots other lanes have already emptied.
-__device__ __forceinline__ void cq_erase(uint32_t* H, uint32_t x) {
+// Slot of a key known to be present.  All keys of the table are removed
+// together, so a probe walks past slots other lanes have already emptied
+// (an empty slot never holds a key).
+template <int KS>
+__device__ __forceinline__ uint32_t cq_slot_of(const uint32_t* H, uint32_t x) {
     uint32_t h = cq_slot(x);
-    while (H[h] != x) h = (h + 1) & (CQ_HASH - 1);
-    H[h] = CQ_EMPTY;
+    while ((H[h] >> KS) != x) h = (h + 1) & (CQ_HASH - 1);
+    return h;
 }
 
 // Tail of one plan for the core match (v0, v1, v2) with degrees d0, d1, d2.
@@ -1364,36 +1373,33 @@ __device__ __forceinline__ void cq_drain(Ctx& c, const KArgs& a, const uint4* Q,
     }
 }
 
-// Slot of a key known to be in the table.
-__device__ __forceinline__ uint32_t cq_slot_of(const uint32_t* H, uint32_t x) {
-    uint32_t h = cq_slot(x);
-    while (H[h] != x) h = (h + 1) & (CQ_HASH - 1);
-    return h;
-}
-
-// With SUP the launch also counts, for every edge {u < w}, the triangles on
-// it (its support, at w's place in N+(u)): the edge (v1, v2) of a triangle
-// found in row v1 by one returning-free global atomic, the edges (v0, v1)
-// and (v0, v2) in LDS (a counter per row of the chunk and a 16-bit counter
-// per hash slot), added to the global array once per row and root.
-template <bool BYTES, bool SUP>
+// With supports (MODE 1 or 2) the launch also counts, for every edge
+// {u < w}, the triangles on it (its support, at w's place in N+(u)): the
+// edge (v1, v2) of a triangle found in row v1 by one returning-free global
+// atomic, the edges (v0, v1) and (v0, v2) in LDS (a counter per row of the
+// chunk, and one per hash slot: in the slot's low bits for MODE 2, in a
+// 16-bit array beside the table for MODE 1), added to the global array once
+// per row and root.
+template <bool BYTES, int MODE>
 __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
+    constexpr bool SUP = MODE != 0;
+    constexpr bool SEP = MODE == 1;           // separate slot counters
+    constexpr int KS = MODE == 2 ? 10 : 0;    // key shift in a slot
     __shared__ uint32_t s_hash[4][CQ_HASH];
     __shared__ uint4 s_queue[4][CQ_QCAP];
-    __shared__ uint32_t s_scnt[SUP ? 4 : 1][SUP ? CQ_HASH / 2 : 1];   // two 16-bit counters a word
+    __shared__ uint32_t s_scnt[SEP ? 4 : 1][SEP ? CQ_HASH / 2 : 1];   // two 16-bit counters a word
     __shared__ uint32_t s_rcnt[SUP ? 4 : 1][64];
     const int lane = wave_lane();
     const int wv = threadIdx.x >> 6;
     uint32_t* H = s_hash[wv];
     uint4* Q = s_queue[wv];
-    uint32_t* SC = s_scnt[SUP ? wv : 0];
+    uint32_t* SC = s_scnt[SEP ? wv : 0];
     uint32_t* RC = s_rcnt[SUP ? wv : 0];
     uint32_t qn = 0;
     for (uint32_t i = lane; i < CQ_HASH; i += 64) H[i] = CQ_EMPTY;
-    if (SUP) {
+    if (SEP)
         for (uint32_t i = lane; i < CQ_HASH / 2; i += 64) SC[i] = 0;
-        RC[lane] = 0;
-    }
+    if (SUP) RC[lane] = 0;
     wave_sync();
     Ctx c;
     c.g = a.g;
@@ -1428,7 +1434,7 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
             const uint32_t i0 = item.s0, i1 = min(item.s1, s);
             if (i0 >= i1) continue;
             if (BYTES && lane == 0) c.bytes += 12 + 4ull * s;
-            for (uint32_t i = lane; i < s; i += 64) cq_insert(H, a.g.col[b + i]);
+            for (uint32_t i = lane; i < s; i += 64) cq_insert<KS>(H, a.g.col[b + i]);
             wave_sync();
             for (uint32_t base = i0; base < i1; base += 64) {
                 const uint32_t i = base + lane;
@@ -1459,12 +1465,14 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
                     }
 #pragma unroll
                     for (int u = 0; u < CQ_UNROLL; ++u) {
-                        const bool hit = act[u] && cq_find(H, y[u]);
+                        const int slot = act[u] ? cq_find<KS>(H, y[u]) : -1;
+                        const bool hit = slot >= 0;
                         if (SUP && hit) {
                             atomicAdd(&a.support[src[u]], 1u);
                             atomicAdd(&RC[o[u]], 1u);
-                            const uint32_t h = cq_slot_of(H, y[u]);
-                            atomicAdd(&SC[h >> 1], 1u << ((h & 1u) * 16));
+                            const uint32_t h = (uint32_t)slot;
+                            if (SEP) atomicAdd(&SC[h >> 1], 1u << ((h & 1u) * 16));
+                            else atomicAdd(&H[h], 1u);
                         }
                         if (counts_only) {
                             tally += hit ? 1u : 0u;
@@ -1503,15 +1511,17 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
             if (SUP) {
                 // edges (v0, y) for the y of N+(v0) closing triangles
                 for (uint32_t i = lane; i < s; i += 64) {
-                    const uint32_t h = cq_slot_of(H, a.g.col[b + i]);
-                    const uint32_t k = (SC[h >> 1] >> ((h & 1u) * 16)) & 0xffffu;
+                    const uint32_t h = cq_slot_of<KS>(H, a.g.col[b + i]);
+                    const uint32_t k = SEP ? (SC[h >> 1] >> ((h & 1u) * 16)) & 0xffffu : H[h] & ((1u << KS) - 1);
                     if (k) atomicAdd(&a.support[b + i], k);
                 }
                 wave_sync();
-                for (uint32_t i = lane; i < s; i += 64) SC[cq_slot_of(H, a.g.col[b + i]) >> 1] = 0;
-                wave_sync();
+                if (SEP) {
+                    for (uint32_t i = lane; i < s; i += 64) SC[cq_slot_of<KS>(H, a.g.col[b + i]) >> 1] = 0;
+                    wave_sync();
+                }
             }
-            for (uint32_t i = lane; i < s; i += 64) cq_erase(H, a.g.col[b + i]);
+            for (uint32_t i = lane; i < s; i += 64) H[cq_slot_of<KS>(H, a.g.col[b + i])] = CQ_EMPTY;
             wave_sync();
         }
     }
@@ -1811,12 +1821,15 @@ int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s)
 }
 
 int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
-    if (a.support) {
-        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);
+    if (a.support && a.g.n <= CQ_PACK_MAX) {
+        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, 2>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique_kernel<false, 2>), dim3(grid), dim3(256), 0, s, a);
+    } else if (a.support) {
+        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, 1>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique_kernel<false, 1>), dim3(grid), dim3(256), 0, s, a);
     } else {
-        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, false>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique_kernel<false, false>), dim3(grid), dim3(256), 0, s, a);
+        if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -1075,7 +1075,7 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
             b.items = ls.cq_items;
             b.nitems = ls.cq_nitems;
             b.support = (int)r == ls.sup_run ? ls.support : nullptr;
-            if (b.nitems && launch_clique(b, clique_blocks(b.support != nullptr), bytes_pass, s))
+            if (b.nitems && launch_clique(b, clique_blocks(b.support != nullptr, b.g.n), bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 10) {

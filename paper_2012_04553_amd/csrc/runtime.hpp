@@ -183,8 +183,9 @@ struct Ctx_ {
     }
     uint64_t waves(const LaunchCfg& c) const { return (uint64_t)grid_blocks(c) * (block / 64); }
     // clique_kernel: 40 KB of LDS a workgroup, four resident a CU; with
-    // edge supports 65 KB, two
-    int clique_blocks(bool sup = false) const { return num_cus * (sup ? 2 : 4); }
+    // edge supports 41 KB (counters in the hash slots), three, or 65 KB on
+    // graphs above CQ_PACK_MAX vertices, two
+    int clique_blocks(bool sup, uint32_t n) const { return num_cus * (!sup ? 4 : (n <= CQ_PACK_MAX ? 3 : 2)); }
     int support_blocks() const { return num_cus * 8; }
     // clique4_kernel: workgroup roots 44 KB of LDS a workgroup, three
     // resident a CU; wavefront roots 14 KB, eight
