@@ -101,3 +101,25 @@ def test_clique_kernels_five_vertex(eng):
                 [ei[m] for m in classes]
     finally:
         eng.graph_unload(gid)
+
+
+def test_edge_supports_beyond_packed_ids(eng):
+    """Above 2^22 - 2 vertices the support pass keeps its per-slot counters
+    apart from the hash keys; an R-MAT graph padded with isolated vertices
+    takes that path."""
+    import paper_2012_04553_amd as pm
+    h = gen.rmat(12, 16, seed=8)
+    e = h.edges()
+    n = (1 << 22) + 64
+    g = gen.from_edges(n, e[:, 0] + 64, e[:, 1] + 64)
+    tc = oracle.tier_c4(h)
+    names = oracle.named_4()
+    pats = [(4, names["diamond"], False), (4, names["tailed_triangle"], False), (3, 0x7, False)]
+    want = [tc["diamond"], tc["tailed_triangle"], tc["triangles"]]
+    gid = eng.load(g)
+    try:
+        assert "edge_support" in eng.plan_describe(gid, pats[0])
+        for on in (True, False):
+            assert _count(eng, gid, pats, pm.MORPH_NONE, on) == want
+    finally:
+        eng.graph_unload(gid)
