@@ -214,7 +214,13 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "clique_kernel" 0/1 (default 1): triangle-core and ordered 4-clique
  *                   plans run in the LDS hash kernels (roots up to 1024
  *                   and 512 out-neighbours; larger ones in the general
- *                   kernel);
+ *                   kernel), edge-core plans with cheap terms per edge;
+ *   "edge_support"  0/1 (default 1): edge-core plans whose set-size term
+ *                   is the whole common neighbourhood (the diamond) take
+ *                   it from per-edge triangle counts filled by the
+ *                   triangle pass (needs "clique_kernel" and no root above
+ *                   1024 out-neighbours; one u32 per adjacency entry of
+ *                   the graph, allocated on first use);
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
  *                   hipGraph on first use and replay it afterwards.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */
