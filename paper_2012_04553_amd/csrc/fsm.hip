@@ -23,8 +23,8 @@
 //     witnesses it would take away, found by a sorted-list intersection.
 //   * triangle: x lies on a triangle whose other two labels are (ly, lz);
 //     a pre-pass lists every triangle once from its lowest vertex in the
-//     degree order (merging two out-lists) and records the label pair at
-//     each corner.
+//     degree order (a hash of the root's out-list in LDS, its rows streamed
+//     against it) and records the label pair at each corner.
 //
 // Each membership increments a per-(pattern, column) counter once per
 // vertex, so the counters are the domain sizes.
@@ -82,32 +82,124 @@ __device__ __forceinline__ void pair_or(const FsmArgs& a, uint32_t x, int l1, in
     atomicOr(&a.tri[(uint64_t)x * 4 + (bit >> 6)], 1ull << (bit & 63));
 }
 
-__global__ void fsm_tri(FsmArgs a) {
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < a.n; u += gridDim.x * blockDim.x) {
-        const uint32_t ue = a.rp[u + 1];
-        const int lu = a.lab[u];
-        for (uint32_t p = a.split[u]; p < ue; ++p) {
-            const uint32_t v = a.col[p];
-            const int lv = a.lab[v];
-            // w above v in both N+(u) and N+(v)
-            uint32_t i = p + 1, j = a.split[v];
-            const uint32_t je = a.rp[v + 1];
-            while (i < ue && j < je) {
-                const uint32_t x = a.col[i], y = a.col[j];
-                if (x == y) {
-                    const int lw = a.lab[x];
-                    pair_or(a, u, lv, lw);
-                    pair_or(a, v, lu, lw);
-                    pair_or(a, x, lu, lv);
-                    ++i;
-                    ++j;
-                } else if (x < y) {
-                    ++i;
-                } else {
-                    ++j;
+// ---- triangles, each listed once from its lowest vertex u (degree order).
+// One wavefront per root: N+(u) goes into an open-addressing hash in LDS
+// (Fibonacci hashing, linear probing) and the rows N+(v), v in N+(u), are
+// streamed flattened over the lanes (a prefix sum numbers the row entries,
+// each lane takes one and finds its row by a shuffle search); an entry w
+// found in the table closes (u, v, w).  A root with more than FT_SMAX
+// out-neighbours merges its rows instead, one row per lane.
+constexpr uint32_t FT_HASH = 2048, FT_SMAX = 1024, FT_EMPTY = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t ft_slot(uint32_t x) { return (x * 0x9E3779B1u) >> 21; }
+
+__device__ __forceinline__ void ft_sync() {
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t ft_scan(uint32_t x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// lane whose inclusive prefix range holds entry t (all lanes execute it)
+__device__ __forceinline__ int ft_owner(uint32_t incl, uint32_t t) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t v = __shfl(incl, lo + step - 1);
+        if (v <= t) lo += step;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void ft_found(const FsmArgs& a, uint32_t u, uint32_t v, uint32_t w) {
+    const int lu = a.lab[u], lv = a.lab[v], lw = a.lab[w];
+    pair_or(a, u, lv, lw);
+    pair_or(a, v, lu, lw);
+    pair_or(a, w, lu, lv);
+}
+
+__global__ void __launch_bounds__(256) fsm_tri(FsmArgs a) {
+    __shared__ uint32_t s_hash[4][FT_HASH];
+    const int lane = __lane_id();
+    uint32_t* H = s_hash[threadIdx.x >> 6];
+    for (uint32_t i = lane; i < FT_HASH; i += 64) H[i] = FT_EMPTY;
+    ft_sync();
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t u = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < a.n; u += nw) {
+        const uint32_t b = a.split[u], e = a.rp[u + 1], s = e - b;
+        if (s < 2) continue;
+        if (s > FT_SMAX) {
+            for (uint32_t p = b + lane; p < e; p += 64) {
+                const uint32_t v = a.col[p];
+                uint32_t i = p + 1, j = a.split[v];
+                const uint32_t je = a.rp[v + 1];
+                while (i < e && j < je) {
+                    const uint32_t x = a.col[i], y = a.col[j];
+                    if (x == y) {
+                        ft_found(a, u, v, x);
+                        ++i;
+                        ++j;
+                    } else if (x < y) {
+                        ++i;
+                    } else {
+                        ++j;
+                    }
+                }
+            }
+            continue;
+        }
+        for (uint32_t i = lane; i < s; i += 64) {
+            const uint32_t x = a.col[b + i];
+            uint32_t h = ft_slot(x);
+            while (atomicCAS(&H[h], FT_EMPTY, x) != FT_EMPTY) h = (h + 1) & (FT_HASH - 1);
+        }
+        ft_sync();
+        for (uint32_t base = 0; base < s; base += 64) {
+            const uint32_t i = base + lane;
+            const bool valid = i < s;
+            const uint32_t v = valid ? a.col[b + i] : 0u;
+            const uint32_t pb = valid ? a.split[v] : 0u;
+            const uint32_t len = valid ? a.rp[v + 1] - pb : 0u;
+            const uint32_t incl = ft_scan(len);
+            const uint32_t total = __shfl(incl, 63);
+            const uint32_t excl = incl - len;
+            for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+                const uint32_t t = t0 + lane;
+                const bool act = t < total;
+                const int o = ft_owner(incl, act ? t : total - 1);
+                const uint32_t src = __shfl(pb, o) + (t - __shfl(excl, o));
+                const uint32_t vo = __shfl(v, o);
+                if (!act) continue;
+                const uint32_t w = a.col[src];
+                uint32_t h = ft_slot(w);
+                for (;;) {
+                    const uint32_t k = H[h];
+                    if (k == w) {
+                        ft_found(a, u, vo, w);
+                        break;
+                    }
+                    if (k == FT_EMPTY) break;
+                    h = (h + 1) & (FT_HASH - 1);
                 }
             }
         }
+        ft_sync();
+        // remove the keys (all together: a probe walks past emptied slots)
+        for (uint32_t i = lane; i < s; i += 64) {
+            const uint32_t x = a.col[b + i];
+            uint32_t h = ft_slot(x);
+            while (H[h] != x) h = (h + 1) & (FT_HASH - 1);
+            H[h] = FT_EMPTY;
+        }
+        ft_sync();
     }
 }
 
