@@ -205,8 +205,14 @@ __global__ void __launch_bounds__(256) fsm_tri(FsmArgs a) {
 
 // ---- per vertex b: for every (lc, ld), how many c in N(b) (label lc) have a
 // neighbour of label ld outside {b}, and how many of those have exactly one.
-__global__ void fsm_btab(FsmArgs a) {
+// Vertices up to BT_HEAVY neighbours take one thread; larger ones one
+// wavefront, whose lanes share N(b) and count in LDS (then saturate).
+constexpr uint32_t BT_HEAVY = 256;
+
+__global__ void __launch_bounds__(256) fsm_btab(FsmArgs a) {
+    __shared__ uint32_t s_cnt[4][FSM_LMAX * FSM_LMAX], s_frag[4][FSM_LMAX * FSM_LMAX], s_wm[4][FSM_LMAX];
     for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < a.n; b += gridDim.x * blockDim.x) {
+        if (a.rp[b + 1] - a.rp[b] > BT_HEAVY) continue;
         uint8_t* cnt = a.bcnt + (uint64_t)b * FSM_LMAX * FSM_LMAX;
         uint8_t* frag = a.bfrag + (uint64_t)b * FSM_LMAX * FSM_LMAX;
         uint32_t* wm = a.bmask + (uint64_t)b * FSM_LMAX;
@@ -233,6 +239,51 @@ __global__ void fsm_btab(FsmArgs a) {
                 }
             }
         }
+    }
+    // heavy vertices: a wavefront each
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    uint32_t* C = s_cnt[wv];
+    uint32_t* F = s_frag[wv];
+    uint32_t* WM = s_wm[wv];
+    for (uint32_t i = lane; i < FSM_LMAX * FSM_LMAX; i += 64) {
+        C[i] = 0;
+        F[i] = 0;
+    }
+    if (lane < FSM_LMAX) WM[lane] = 0;
+    ft_sync();
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t b = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < a.n; b += nw) {
+        const uint32_t pb = a.rp[b], pe = a.rp[b + 1];
+        if (pe - pb <= BT_HEAVY) continue;
+        const int lb = a.lab[b];
+        for (uint32_t p = pb + lane; p < pe; p += 64) {
+            const uint32_t c = a.col[p];
+            const int lc = a.lab[c];
+            uint32_t e = present_minus(a, c, lb);
+            if (e) atomicOr(&WM[lc], e);
+            while (e) {
+                const int ld = __builtin_ctz(e);
+                e &= e - 1;
+                const uint32_t k = a.hist[(uint64_t)c * FSM_LMAX + ld] - (ld == lb ? 1u : 0u);
+                atomicAdd(&C[lc * FSM_LMAX + ld], 1u);
+                if (k == 1) atomicAdd(&F[lc * FSM_LMAX + ld], 1u);
+            }
+        }
+        ft_sync();
+        uint8_t* cnt = a.bcnt + (uint64_t)b * FSM_LMAX * FSM_LMAX;
+        uint8_t* frag = a.bfrag + (uint64_t)b * FSM_LMAX * FSM_LMAX;
+        for (uint32_t i = lane; i < FSM_LMAX * FSM_LMAX; i += 64) {
+            cnt[i] = (uint8_t)min(C[i], 255u);
+            frag[i] = (uint8_t)min(F[i], 255u);
+            C[i] = 0;
+            F[i] = 0;
+        }
+        if (lane < FSM_LMAX) {
+            a.bmask[(uint64_t)b * FSM_LMAX + lane] = WM[lane];
+            WM[lane] = 0;
+        }
+        ft_sync();
     }
 }
 
