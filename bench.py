@@ -358,7 +358,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+              "(several GPUs would each take a share of the work items and add their counters)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
