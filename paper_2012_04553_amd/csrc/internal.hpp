@@ -218,8 +218,9 @@ inline bool edge_cheap_ok(const DPlan& d) {
 // Counted 4-cliques v0 < v1 < v2 < v3 enumerated from N+(v0) (no labels):
 // clique4_kernel counts them from bit rows of the graph induced on N+(v0),
 // roots with up to C4_ROOT_MAX out-neighbours.
-constexpr uint32_t C4_ROOT_MAX = 512;
+constexpr uint32_t C4_ROOT_MAX = 1024;
 constexpr uint32_t C4_LIGHT_MAX = 128;   // roots a wavefront takes; larger ones a workgroup
+constexpr uint32_t C4_HEAVY_MAX = 512;   // workgroup roots in 44 KB; larger ones in 152 KB
 inline bool clique4_ok(const DPlan& d) {
     if (d.ncore != 4 || d.nterm != 0 || d.agg_last || d.lev[0].label >= 0) return false;
     for (int j = 1; j < 4; ++j) {

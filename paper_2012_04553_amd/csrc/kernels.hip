@@ -1620,11 +1620,13 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
 // against a hash of N+(v0) that maps an id to its position), then counts
 // its triangles: every bit (i, j) adds the popcount of row i AND row j.
 // Light roots (3 .. C4_LIGHT out-neighbours) take one wavefront each,
-// heavier ones (up to C4_HEAVY) a whole workgroup; larger roots run in the
-// general kernel.
+// heavier ones (up to C4_ROOT_MAX) a whole workgroup, in a 44 KB table up to
+// C4_HEAVY and a 152 KB one above; larger roots run in the general kernel.
 constexpr uint32_t C4_LIGHT = C4_LIGHT_MAX;
-constexpr uint32_t C4_HEAVY = C4_ROOT_MAX;
+constexpr uint32_t C4_HEAVY = C4_HEAVY_MAX;
 constexpr uint32_t C4_LDS_WORDS = 11264;   // 44 KB: a workgroup's table for up to 512 out-neighbours
+// 152 KB: 4096 keys, 4096 positions, 1024 rows of 32 words (one workgroup a CU)
+constexpr uint32_t C4_HUGE_WORDS = 4096 + 2048 + 1024 * 32;
 // a wavefront's table for up to 128: 256 keys, 256 positions, 128 rows of 4 words
 constexpr uint32_t C4_WAVE_WORDS = 256 + 128 + 128 * 4;
 
@@ -1732,9 +1734,12 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
     return cnt;
 }
 
-template <bool BYTES, bool WG>
+// MODE 0: wavefront roots; 1: workgroup roots up to C4_HEAVY; 2: workgroup
+// roots up to C4_ROOT_MAX.
+template <bool BYTES, int MODE>
 __global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
-    __shared__ uint32_t s_lds[WG ? C4_LDS_WORDS : 4 * C4_WAVE_WORDS];
+    constexpr bool WG = MODE != 0;
+    __shared__ uint32_t s_lds[MODE == 2 ? C4_HUGE_WORDS : (WG ? C4_LDS_WORDS : 4 * C4_WAVE_WORDS)];
     const int lane = wave_lane();
     uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * C4_WAVE_WORDS;
     __shared__ uint32_t s_it;
@@ -1771,8 +1776,9 @@ __global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
         for (uint32_t r = item.r0; r < item.r1; ++r) {
             const uint32_t b = a.g.split[r], e = a.g.rp[r + 1];
             const uint32_t s = e - b;
-            if (s < 3 || s > (WG ? C4_HEAVY : C4_LIGHT)) continue;
-            if (WG) cnt += c4_root<11, true, BYTES>(c, a.g, base, r, b, s);
+            if (s < 3 || s > (MODE == 2 ? C4_ROOT_MAX : (WG ? C4_HEAVY : C4_LIGHT))) continue;
+            if (MODE == 2) cnt += c4_root<12, true, BYTES>(c, a.g, base, r, b, s);
+            else if (WG) cnt += c4_root<11, true, BYTES>(c, a.g, base, r, b, s);
             else cnt += c4_root<8, false, BYTES>(c, a.g, base, r, b, s);
         }
     }
@@ -1840,13 +1846,16 @@ int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_clique4(const KArgs& a, int grid, bool heavy, bool count_bytes, hipStream_t s) {
-    if (heavy) {
-        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique4_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);
+int launch_clique4(const KArgs& a, int grid, int mode, bool count_bytes, hipStream_t s) {
+    if (mode == 2) {
+        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 2>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique4_kernel<false, 2>), dim3(grid), dim3(256), 0, s, a);
+    } else if (mode == 1) {
+        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 1>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique4_kernel<false, 1>), dim3(grid), dim3(256), 0, s, a);
     } else {
-        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, false>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique4_kernel<false, false>), dim3(grid), dim3(256), 0, s, a);
+        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((clique4_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

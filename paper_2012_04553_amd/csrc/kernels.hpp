@@ -58,9 +58,10 @@ int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // launch_clique with a.support set; returns every counter to zero.
 int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
-// wavefront (heavy = false) or one workgroup (heavy = true) per root of
-// the items {r0, r1, 0, 0}.
-int launch_clique4(const KArgs& a, int grid, bool heavy, bool count_bytes, hipStream_t s);
+// wavefront (mode 0: up to C4_LIGHT_MAX out-neighbours) or one workgroup
+// (mode 1: up to C4_HEAVY_MAX, mode 2: up to C4_ROOT_MAX) per root of the
+// items {r0, r1, 0, 0}.
+int launch_clique4(const KArgs& a, int grid, int mode, bool count_bytes, hipStream_t s);
 // Clears `words` 32-bit words (used instead of memset nodes inside graphs).
 int launch_zero(uint32_t* p, uint64_t words, hipStream_t s);
 

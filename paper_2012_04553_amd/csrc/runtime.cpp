@@ -178,12 +178,13 @@ static void clique_items(GraphRes& G, const std::vector<uint32_t>& rp, const std
     }
     close(G.n);
     // 4-clique kernel: light roots (3 .. C4_LIGHT_MAX out-neighbours) grouped
-    // up to CQ_VOL of volume, heavier ones (to C4_ROOT_MAX) one an item,
-    // most volume first
+    // up to CQ_VOL of volume, heavier ones one an item, most volume first (to
+    // C4_HEAVY_MAX, and to C4_ROOT_MAX in a launch of their own)
     G.c4_light.clear();
     G.c4_heavy.clear();
+    G.c4_huge.clear();
     G.c4_big.clear();
-    std::vector<std::pair<uint64_t, uint32_t>> hv;
+    std::vector<std::pair<uint64_t, uint32_t>> hv, xv;
     open = false;
     gv = 0;
     auto close4 = [&](uint32_t end) {
@@ -199,6 +200,7 @@ static void clique_items(GraphRes& G, const std::vector<uint32_t>& rp, const std
         if (s > C4_LIGHT_MAX) {
             close4(r);
             if (s > C4_ROOT_MAX) G.c4_big.push_back(r);
+            else if (s > C4_HEAVY_MAX) xv.push_back({vol, r});
             else hv.push_back({vol, r});
             continue;
         }
@@ -210,8 +212,11 @@ static void clique_items(GraphRes& G, const std::vector<uint32_t>& rp, const std
         if (gv >= CQ_VOL || r + 1 - gb >= 256) close4(r + 1);
     }
     close4(G.n);
-    std::stable_sort(hv.begin(), hv.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    auto by_volume = [](const auto& x, const auto& y) { return x.first > y.first; };
+    std::stable_sort(hv.begin(), hv.end(), by_volume);
+    std::stable_sort(xv.begin(), xv.end(), by_volume);
     for (const auto& h : hv) G.c4_heavy.push_back({h.second, h.second + 1, 0, 0});
+    for (const auto& h : xv) G.c4_huge.push_back({h.second, h.second + 1, 0, 0});
 }
 
 int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels,
@@ -363,9 +368,10 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     {
         // the triangle and 4-clique kernels' items stay on the device with
         // the graph (read-only, shared by every launch set)
-        const size_t nc = G->clique_items.size(), nl = G->c4_light.size(), nh = G->c4_heavy.size();
-        if (nc + nl + nh) {
-            G->off_cq = arena.alloc(16 * (nc + nl + nh));
+        const size_t nc = G->clique_items.size(), nl = G->c4_light.size(), nh = G->c4_heavy.size(),
+                     nx = G->c4_huge.size();
+        if (nc + nl + nh + nx) {
+            G->off_cq = arena.alloc(16 * (nc + nl + nh + nx));
             if (G->off_cq == UINT64_MAX) {
                 for (uint64_t o : {G->off_rp, G->off_col, G->off_split, G->off_lab, G->off_items})
                     if (o < UINT64_MAX - 1) arena.release(o);
@@ -375,11 +381,14 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
             if (nc) HIPCHK(hipMemcpyAsync(d, G->clique_items.data(), 16 * nc, hipMemcpyHostToDevice, stream));
             if (nl) HIPCHK(hipMemcpyAsync(d + nc, G->c4_light.data(), 16 * nl, hipMemcpyHostToDevice, stream));
             if (nh) HIPCHK(hipMemcpyAsync(d + nc + nl, G->c4_heavy.data(), 16 * nh, hipMemcpyHostToDevice, stream));
+            if (nx)
+                HIPCHK(hipMemcpyAsync(d + nc + nl + nh, G->c4_huge.data(), 16 * nx, hipMemcpyHostToDevice, stream));
             HIPCHK(hipStreamSynchronize(stream));
             G->d_cq = d;
             G->d_c4l = d + nc;
             G->d_c4h = d + nc + nl;
-            G->device_bytes += 16 * (nc + nl + nh);
+            G->d_c4x = d + nc + nl + nh;
+            G->device_bytes += 16 * (nc + nl + nh + nx);
         }
     }
     G->host_rp = std::move(nrp);
@@ -599,7 +608,7 @@ bool Ctx_::use_clique(const GraphRes& G, const std::vector<PlanInfo>& plans) con
 
 // Whether a launch set runs any plan in clique4_kernel.
 bool Ctx_::use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
-    if (!clique_opt || (G.c4_light.empty() && G.c4_heavy.empty())) return false;
+    if (!clique_opt || (G.c4_light.empty() && G.c4_heavy.empty() && G.c4_huge.empty())) return false;
     for (const PlanInfo& p : plans)
         if (clique4_ok(p.d)) return true;
     return false;
@@ -891,13 +900,15 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
             ls->cq_nbig = (uint32_t)cq_big.size();
         }
     }
-    ls->c4_light = ls->c4_heavy = ls->c4_big = nullptr;
-    ls->c4_nlight = ls->c4_nheavy = ls->c4_nbig = 0;
+    ls->c4_light = ls->c4_heavy = ls->c4_huge = ls->c4_big = nullptr;
+    ls->c4_nlight = ls->c4_nheavy = ls->c4_nhuge = ls->c4_nbig = 0;
     if (c4) {
         ls->c4_light = G.d_c4l;
         ls->c4_nlight = (uint32_t)G.c4_light.size();
         ls->c4_heavy = G.d_c4h;
         ls->c4_nheavy = (uint32_t)G.c4_heavy.size();
+        ls->c4_huge = G.d_c4x;
+        ls->c4_nhuge = (uint32_t)G.c4_huge.size();
         if (!c4_big.empty()) {
             KItem* bi = (KItem*)carve(16 * c4_big.size());
             HIPCHK(hipMemcpyAsync(bi, c4_big.data(), 16 * c4_big.size(), hipMemcpyHostToDevice, st));
@@ -1013,6 +1024,10 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         } else if (grp == 4) {
             for (int k = i; k < j; k += CQ_PLANS) {
                 const std::pair<int, int> rr{k, std::min(j, k + CQ_PLANS)};
+                if (ls->c4_nhuge) {
+                    ls->runs.push_back(rr);
+                    ls->run_agg.push_back(11);
+                }
                 if (ls->c4_nheavy) {
                     ls->runs.push_back(rr);
                     ls->run_agg.push_back(8);
@@ -1085,11 +1100,11 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         } else if (ls.run_agg[r] == 6) {
             b.items = ls.cq_big;
             b.nitems = ls.cq_nbig;
-        } else if (ls.run_agg[r] == 7 || ls.run_agg[r] == 8) {
-            const bool heavy = ls.run_agg[r] == 8;
-            b.items = heavy ? ls.c4_heavy : ls.c4_light;
-            b.nitems = heavy ? ls.c4_nheavy : ls.c4_nlight;
-            if (b.nitems && launch_clique4(b, clique4_blocks(heavy), heavy, bytes_pass, s))
+        } else if (ls.run_agg[r] == 7 || ls.run_agg[r] == 8 || ls.run_agg[r] == 11) {
+            const int mode = ls.run_agg[r] == 7 ? 0 : (ls.run_agg[r] == 8 ? 1 : 2);
+            b.items = mode == 0 ? ls.c4_light : (mode == 1 ? ls.c4_heavy : ls.c4_huge);
+            b.nitems = mode == 0 ? ls.c4_nlight : (mode == 1 ? ls.c4_nheavy : ls.c4_nhuge);
+            if (b.nitems && launch_clique4(b, clique4_blocks(mode), mode, bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 9) {

@@ -73,7 +73,8 @@ struct LaunchSet {
                                              // 3 edge-core light roots, 4 edge-core heavy roots,
                                              // 5 triangle-core (clique_kernel), 6 their larger roots,
                                              // 7/8 4-cliques (clique4_kernel, light/heavy roots),
-                                             // 9 their larger roots, 10 edge-support plans
+                                             // 9 their larger roots, 10 edge-support plans,
+                                             // 11 4-cliques (clique4_kernel, largest roots)
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
     const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
@@ -86,8 +87,9 @@ struct LaunchSet {
     uint32_t cq_nitems = 0, cq_nbig = 0;
     const KItem* c4_light = nullptr;         // 4-clique plans: wavefront roots,
     const KItem* c4_heavy = nullptr;         //   workgroup roots,
+    const KItem* c4_huge = nullptr;          //   workgroup roots above C4_HEAVY_MAX,
     const KItem* c4_big = nullptr;           //   general-kernel items of the larger roots
-    uint32_t c4_nlight = 0, c4_nheavy = 0, c4_nbig = 0;
+    uint32_t c4_nlight = 0, c4_nheavy = 0, c4_nhuge = 0, c4_nbig = 0;
     uint32_t* support = nullptr;             // edge supports (the graph's), when used
     int sup_run = -1;                        // the triangle run that fills them
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
@@ -115,13 +117,14 @@ struct GraphRes {
     const KItem* d_cq = nullptr;
     const KItem* d_c4l = nullptr;
     const KItem* d_c4h = nullptr;
+    const KItem* d_c4x = nullptr;
     uint64_t device_bytes = 0;
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
     std::vector<uint64_t> two_hop;           // per vertex: summed degrees of its lower neighbours
     std::vector<KItem> clique_items;         // triangle-core kernel items
     std::vector<uint32_t> clique_big;        // roots with more than CQ_SMAX out-neighbours
-    std::vector<KItem> c4_light, c4_heavy;   // 4-clique kernel items
+    std::vector<KItem> c4_light, c4_heavy, c4_huge;   // 4-clique kernel items
     std::vector<uint32_t> c4_big;            // roots with more than C4_ROOT_MAX out-neighbours
     std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
@@ -187,9 +190,9 @@ struct Ctx_ {
     // graphs above CQ_PACK_MAX vertices, two
     int clique_blocks(bool sup, uint32_t n) const { return num_cus * (!sup ? 4 : (n <= CQ_PACK_MAX ? 3 : 2)); }
     int support_blocks() const { return num_cus * 8; }
-    // clique4_kernel: workgroup roots 44 KB of LDS a workgroup, three
-    // resident a CU; wavefront roots 14 KB, eight
-    int clique4_blocks(bool heavy) const { return num_cus * (heavy ? 3 : 8); }
+    // clique4_kernel: wavefront roots 14 KB of LDS a workgroup, eight
+    // resident a CU; workgroup roots 44 KB, three; the largest 152 KB, one
+    int clique4_blocks(int mode) const { return num_cus * (mode == 0 ? 8 : (mode == 1 ? 3 : 1)); }
     // wavefronts of the two-hop aggregation launches on an n-vertex graph:
     // each holds two dense u32[n] arrays, so their number follows from a
     // memory budget (a quarter of the arena, at most 8 GiB)
