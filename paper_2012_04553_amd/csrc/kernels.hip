@@ -894,9 +894,13 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
 constexpr uint32_t WIN_IDS = 8192;
 constexpr int AW_UNROLL = 4;
 
-template <bool BYTES>
+// With H16 (a graph whose degrees fit 16 bits, so does every path count)
+// two counters share a word: 16 KB of counters instead of 32 KB, four
+// workgroups a CU instead of three.
+template <bool BYTES, bool H16>
 __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
-    __shared__ uint32_t win[WIN_IDS];
+    constexpr uint32_t WIN_WORDS = H16 ? WIN_IDS / 2 : WIN_IDS;
+    __shared__ uint32_t win[WIN_WORDS];
     __shared__ uint16_t used[WIN_IDS];   // touched window offsets, in first-touch order
     __shared__ uint32_t s_item, s_next[2], s_nused[2];
     const int lane = wave_lane();
@@ -913,7 +917,7 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
     uint32_t* cur = a.wscr + (uint64_t)blockIdx.x * (2 + EW_TERMS) * a.wscr_stride;
     uint32_t* fin = cur + a.wscr_stride;
     uint32_t* nxt = fin + a.wscr_stride;
-    for (uint32_t i = tid; i < WIN_IDS; i += blockDim.x) win[i] = 0;
+    for (uint32_t i = tid; i < WIN_WORDS; i += blockDim.x) win[i] = 0;
     int curp = -1;
     u128 acc = 0;
     const uint64_t total = (uint64_t)a.nplans * a.nitems;
@@ -1014,9 +1018,17 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
 #pragma unroll
                     for (int u = 0; u < AW_UNROLL; ++u) {
                         const uint32_t x = xs[u];
-                        if (acts[u] && (L.label < 0 || c.g.lab[x] == (uint8_t)L.label) && !((L.neq & 1) && x == r))
-                            if (atomicAdd(&win[x - wlo], 1u) == 0u)
-                                used[atomicAdd(&s_nused[ph], 1u)] = (uint16_t)(x - wlo);
+                        if (acts[u] && (L.label < 0 || c.g.lab[x] == (uint8_t)L.label) && !((L.neq & 1) && x == r)) {
+                            const uint32_t off = x - wlo;
+                            bool first;
+                            if (H16) {
+                                const uint32_t sh = (off & 1u) * 16;
+                                first = ((atomicAdd(&win[off >> 1], 1u << sh) >> sh) & 0xffffu) == 0u;
+                            } else {
+                                first = atomicAdd(&win[off], 1u) == 0u;
+                            }
+                            if (first) used[atomicAdd(&s_nused[ph], 1u)] = (uint16_t)off;
+                        }
                     }
                 }
                 if (valid) {
@@ -1041,8 +1053,15 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
                 uint32_t m = 0, i = 0;
                 if (idx < nu) {
                     i = used[idx];
-                    m = win[i];
-                    win[i] = 0;
+                    if (H16) {
+                        // each half is read and cleared by its own lane only
+                        const uint32_t sh = (i & 1u) * 16;
+                        m = (win[i >> 1] >> sh) & 0xffffu;
+                        atomicAnd(&win[i >> 1], ~(0xffffu << sh));
+                    } else {
+                        m = win[i];
+                        win[i] = 0;
+                    }
                 }
                 vv[1] = wlo + i;
                 acc += lanes_tail<BYTES>(c, vv, m != 0, m);
@@ -1819,10 +1838,15 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
 }
 
 int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
-    if (count_bytes)
-        hipLaunchKernelGGL(agg_window_kernel<true>, dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(agg_window_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    // path counts are bounded by the largest degree (the adjacency stride)
+    const bool h16 = a.wscr_stride <= 0xffffu;
+    if (h16) {
+        if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((agg_window_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, false>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((agg_window_kernel<false, false>), dim3(grid), dim3(256), 0, s, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
