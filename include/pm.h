@@ -222,7 +222,10 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *                   1024 out-neighbours; one u32 per adjacency entry of
  *                   the graph, allocated on first use);
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
- *                   hipGraph on first use and replay it afterwards.
+ *                   hipGraph on first use and replay it afterwards;
+ *   "window_counters" 16 or 32 (default 16): counter width of the two-hop
+ *                   window kernel when every degree fits 16 bits (32 is
+ *                   always used otherwise).
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */
 pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value);
 

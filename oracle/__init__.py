@@ -60,6 +60,10 @@ def lib():
         L.or_tier_c4.argtypes = [ctypes.c_uint32, u32p, u32p, u64p]
         L.or_mni_column.argtypes = [ctypes.c_uint32, u32p, u32p, u8p, ctypes.c_int, ip,
                                     ctypes.c_uint32, ctypes.c_uint32, ip, u64p]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.or_mni_labelings.argtypes = [ctypes.c_uint32, u32p, u32p, u8p, ctypes.c_int, ip,
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, i32p,
+                                       ctypes.c_int, u64p]
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -270,8 +274,42 @@ def mni_support_rooted(g, k: int, mask: int, induced: bool, plabels) -> int:
     return min(mni_column(g, k, mask, induced, plabels, v) for v in range(k))
 
 
+def mni_labelings(g, k: int, mask: int, induced: bool, num_labels: int, labelings) -> list[int]:
+    """MNI support of several labelings of one pattern shape at once.
+
+    ``labelings`` is a list of label tuples (label of pattern vertex 0..k-1).
+    Every match of the unlabeled shape is a match of exactly one labeled
+    pattern: the one whose vertex v carries the label of its image
+    (Preliminaries, "Graph Isomorphism" with labels).  All matches are
+    enumerated once and each pattern vertex's image goes into the column of
+    that labeling; the support is the smallest column (Preliminaries, FSM)."""
+    rp, col = _graph_arrays(g)
+    order = np.array(P.connected_order(k, mask), dtype=np.int32)
+    amask = (P.clique_mask(k) & ~mask) if induced else 0
+    lab = np.ascontiguousarray(g.labels, dtype=np.uint8)
+    sel = np.full(num_labels ** k, -1, dtype=np.int32)
+    keys = []
+    for t in labelings:
+        key = 0
+        for v in reversed(range(k)):
+            key = key * num_labels + int(t[v])
+        keys.append(key)
+    uniq = sorted(set(keys))
+    for i, key in enumerate(uniq):
+        sel[key] = i
+    out = np.zeros(len(uniq) * k, dtype=np.uint64)
+    rc = lib().or_mni_labelings(g.n, _ptr(rp, ctypes.c_uint32), _ptr(col, ctypes.c_uint32),
+                                _ptr(lab, ctypes.c_uint8), k, _ptr(order, ctypes.c_int), mask,
+                                amask, num_labels, _ptr(sel, ctypes.c_int32), len(uniq),
+                                _ptr(out, ctypes.c_uint64))
+    if rc != 0:
+        raise ValueError(f"or_mni_labelings failed: {rc}")
+    cols = out.reshape(len(uniq), k)
+    return [int(cols[sel[key]].min()) for key in keys]
+
+
 __all__ = ["P", "build", "lib", "count_maps", "count", "motif_counts", "census",
            "full_census_tiny", "tier_c4", "named_4", "edge_induced_4_from_tier_c",
            "vertex_induced_4_from_tier_c", "mni_domains", "mni_support", "num_threads",
-           "mni_column", "mni_support_rooted",
+           "mni_column", "mni_support_rooted", "mni_labelings",
            "comb", "factorial"]

@@ -28,6 +28,10 @@
  *    match) by enumerating every match.
  *  - or_mni_column: the size of one such column on large graphs, by a
  *    search from every candidate vertex that stops at its first match.
+ *  - or_mni_labelings: the columns of every labeling of one unlabeled
+ *    pattern at once: each match of the unlabeled pattern is a match of
+ *    exactly one labeled pattern, the one whose vertex i carries the label
+ *    of its image.
  *
  * Graph: simple undirected CSR, ascending adjacency, uint32 ids.
  * Pattern edge (i<j) is bit j*(j-1)/2+i of a mask.
@@ -473,5 +477,85 @@ int or_mni_column(uint32_t n, const uint32_t* rp, const uint32_t* col, const uin
         if (exists_from(&c, img, 1)) total += 1;
     }
     *out = total;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* MNI columns of every labeling of one pattern                         */
+/* ------------------------------------------------------------------ */
+
+/* A match m of the unlabeled pattern is a match of the labeled pattern
+ * (same vertices and edges) with vertex i labeled lab[m(i)], and every
+ * match of a labeled pattern arises so.  Enumerate the unlabeled matches
+ * once and file each under the key sum_v lab[m(v)] * L^v of its
+ * labeling (v = pattern vertex).  sel[key] >= 0 picks the labelings to
+ * record; their domains are bitmaps dom[(sel*k + v) * words + x/64].
+ * out[sel*k + v] = |D(v)| of that labeling. */
+typedef struct {
+    mapctx c;
+    int L;
+    const int32_t* sel;
+    uint64_t* dom;
+    size_t words;
+} lblctx;
+
+static void extend_labelings(const lblctx* t, uint32_t* img, int j) {
+    const mapctx* c = &t->c;
+    if (j == c->k) {
+        uint32_t vimg[8];
+        for (int i = 0; i < c->k; ++i) vimg[c->order[i]] = img[i];
+        int64_t key = 0, mul = 1;
+        for (int v = 0; v < c->k; ++v) {
+            key += (int64_t)c->lab[vimg[v]] * mul;
+            mul *= t->L;
+        }
+        int32_t s = t->sel[key];
+        if (s < 0) return;
+        for (int v = 0; v < c->k; ++v) {
+            uint64_t* w = &t->dom[((size_t)s * c->k + v) * t->words + (vimg[v] >> 6)];
+            uint64_t bit = 1ull << (vimg[v] & 63);
+            if (!(*w & bit)) {
+#pragma omp atomic
+                *w |= bit;
+            }
+        }
+        return;
+    }
+    uint32_t a = img[c->anchor[j]];
+    for (uint32_t e = c->rp[a]; e < c->rp[a + 1]; ++e) {
+        uint32_t x = c->col[e];
+        if (!step_ok(c, img, j, x)) continue;
+        img[j] = x;
+        extend_labelings(t, img, j + 1);
+    }
+}
+
+int or_mni_labelings(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* lab,
+                     int k, const int* order, uint32_t emask, uint32_t amask, int L,
+                     const int32_t* sel, int nsel, uint64_t* out) {
+    lblctx t;
+    int rc = setup_ctx(&t.c, n, rp, col, lab, k, order, emask, amask, NULL);
+    if (rc) return rc;
+    if (!lab || L < 1) return -3;
+    for (uint32_t x = 0; x < n; ++x)
+        if (lab[x] >= L) return -4;
+    t.L = L;
+    t.sel = sel;
+    t.words = ((size_t)n + 63) / 64;
+    t.dom = (uint64_t*)calloc((size_t)nsel * k * t.words, sizeof(uint64_t));
+    if (!t.dom) return -5;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < (int64_t)n; ++r) {
+        uint32_t img[8];
+        if (!step_ok(&t.c, img, 0, (uint32_t)r)) continue;
+        img[0] = (uint32_t)r;
+        extend_labelings(&t, img, 1);
+    }
+    for (size_t q = 0; q < (size_t)nsel * k; ++q) {
+        uint64_t cnt = 0;
+        for (size_t w = 0; w < t.words; ++w) cnt += (uint64_t)__builtin_popcountll(t.dom[q * t.words + w]);
+        out[q] = cnt;
+    }
+    free(t.dom);
     return 0;
 }

@@ -1839,7 +1839,7 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
 
 int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
     // path counts are bounded by the largest degree (the adjacency stride)
-    const bool h16 = a.wscr_stride <= 0xffffu;
+    const bool h16 = !a.wide && a.wscr_stride <= 0xffffu;
     if (h16) {
         if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((agg_window_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);

@@ -42,6 +42,8 @@ struct KArgs {
     uint64_t wscr_stride;
     const int* cancel;        // host-visible cancel flag or null
     uint32_t* support;        // per out-list position: triangles on that edge, or null
+    uint32_t wide;            // 1: agg_window_kernel keeps 32-bit counters even
+                              //    when every degree fits 16 bits
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);

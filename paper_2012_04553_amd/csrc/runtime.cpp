@@ -96,8 +96,8 @@ static void parallel_for(uint64_t n, const std::function<void(uint64_t, uint64_t
     for (auto& x : th) x.join();
 }
 
-static std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t n,
-                                      uint64_t budget, uint32_t split, uint32_t max_roots) {
+std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t n, uint64_t budget, uint32_t split,
+                               uint32_t max_roots) {
     std::vector<KItem> items;
     // heaviest roots first (ids ascend with degree)
     int64_t r = (int64_t)n - 1;
@@ -965,6 +965,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     a.bm_words = bm_words;
     a.wscr = wscr;
     a.wscr_stride = wstride;
+    a.wide = window_wide ? 1u : 0u;
     if (ls->any_agg) {
         if (agg) {
             a.aggcnt = agg->cnt;
@@ -1318,7 +1319,8 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
                       std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
                       std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
                       std::to_string(heavy_min_mass) + "," + std::to_string(clique_opt) + "," +
-                      std::to_string(heavy_span_shift) + "," + std::to_string(support_opt);
+                      std::to_string(heavy_span_shift) + "," + std::to_string(support_opt) + "," +
+                      std::to_string(window_wide);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy) {
@@ -1399,6 +1401,75 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     return PM_OK;
 }
 
+// Exact counts of the closure patterns from the 128-bit match totals of
+// their plans (host words 2i, 2i+1), smallest patterns first because
+// quotient plans subtract counts of smaller patterns.  st[i] is PM_OK,
+// PM_E_OVERFLOW (the total exceeds 120 bits, the count exceeds int64, or a
+// count it needs did) or PM_E_DEVICE (an internal inconsistency), with the
+// message in err[i].
+void closure_counts(const std::vector<Pat>& closure, const std::vector<PlanInfo>& plans, const uint64_t* host,
+                    std::vector<__int128>* cnt_out, std::vector<int>* st_out, std::vector<std::string>* err_out) {
+    const size_t np = plans.size();
+    std::vector<__int128>& cnt = *cnt_out;
+    std::vector<int>& st = *st_out;
+    std::vector<std::string>& err = *err_out;
+    cnt.assign(np, -1);
+    st.assign(np, PM_OK);
+    err.assign(np, std::string());
+    std::vector<size_t> order(np);
+    for (size_t i = 0; i < np; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return closure[a].k < closure[b].k; });
+    for (size_t i : order) {
+        const PlanInfo& pi = plans[i];
+        const unsigned __int128 v = ((unsigned __int128)host[2 * i + 1] << 64) | host[2 * i];
+        // below 2^120 every product with a plan multiplier (< 2^7) stays
+        // inside the signed 128-bit range
+        if (v >> 120) {
+            st[i] = PM_E_OVERFLOW;
+            err[i] = "match total exceeds 120 bits";
+            continue;
+        }
+        __int128 c;
+        if (pi.rewrite) {
+            __int128 acc = (__int128)pi.hmult * (__int128)v;
+            for (auto& sq : pi.subs) {
+                size_t j = std::find(closure.begin(), closure.end(), sq.first) - closure.begin();
+                if (j >= np) {
+                    st[i] = PM_E_DEVICE;
+                    err[i] = "internal: quotient sub-pattern missing";
+                    break;
+                }
+                if (st[j]) {
+                    st[i] = st[j];
+                    err[i] = err[j];
+                    break;
+                }
+                acc -= (__int128)sq.second * cnt[j];
+            }
+            if (st[i]) continue;
+            if (acc < 0 || acc % pi.autp) {
+                st[i] = PM_E_DEVICE;
+                err[i] = "internal: quotient combination not exact";
+                continue;
+            }
+            c = acc / pi.autp;
+        } else {
+            if (v % (unsigned __int128)pi.divisor) {
+                st[i] = PM_E_DEVICE;
+                err[i] = "internal: match total not divisible by the plan divisor";
+                continue;
+            }
+            c = (__int128)(v / (unsigned __int128)pi.divisor);
+        }
+        if (c > (__int128)INT64_MAX) {
+            st[i] = PM_E_OVERFLOW;
+            err[i] = "count exceeds int64";
+            continue;
+        }
+        cnt[i] = c;
+    }
+}
+
 int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
     Query* Q;
     {
@@ -1423,51 +1494,13 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
     Q->stats.kernel_ms = kms;
     size_t np = Q->plans.size();
     const uint64_t* host = Q->ls ? Q->ls->host : Q->own->host;
-    // closure counts, smallest patterns first (quotient plans need them)
-    std::vector<__int128> cnt(np, -1);
-    std::vector<size_t> order(np);
-    for (size_t i = 0; i < np; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return Q->closure[a].k < Q->closure[b].k; });
+    std::vector<__int128> cnt;
+    std::vector<int> cst;
+    std::vector<std::string> cerr;
+    closure_counts(Q->closure, Q->plans, host, &cnt, &cst, &cerr);
     int rc = PM_OK;
-    for (size_t oi = 0; oi < np && rc == PM_OK; ++oi) {
-        size_t i = order[oi];
-        const PlanInfo& pi = Q->plans[i];
-        unsigned __int128 v = ((unsigned __int128)host[2 * i + 1] << 64) | host[2 * i];
-        if (v >> 120) {
-            rc = fail(PM_E_OVERFLOW, "match total exceeds 120 bits");
-            break;
-        }
-        __int128 c;
-        if (pi.rewrite) {
-            __int128 acc = (__int128)pi.hmult * (__int128)v;
-            for (auto& sq : pi.subs) {
-                size_t j = std::find(Q->closure.begin(), Q->closure.end(), sq.first) - Q->closure.begin();
-                if (j >= np || cnt[j] < 0) {
-                    rc = fail(PM_E_DEVICE, "internal: quotient sub-pattern missing");
-                    break;
-                }
-                acc -= (__int128)sq.second * cnt[j];
-            }
-            if (rc) break;
-            if (acc < 0 || acc % pi.autp) {
-                rc = fail(PM_E_DEVICE, "internal: quotient combination not exact");
-                break;
-            }
-            c = acc / pi.autp;
-        } else {
-            if (v % (unsigned __int128)pi.divisor) {
-                rc = fail(PM_E_DEVICE, "internal: match total not divisible by the plan divisor");
-                break;
-            }
-            c = (__int128)(v / (unsigned __int128)pi.divisor);
-        }
-        if (c > (__int128)INT64_MAX) {
-            rc = fail(PM_E_OVERFLOW, "count exceeds int64");
-            break;
-        }
-        cnt[i] = c;
-    }
+    for (size_t i = 0; i < np && rc == PM_OK; ++i)
+        if (cst[i]) rc = fail(cst[i], cerr[i]);
     std::vector<int64_t> alt(Q->mp.alt.size(), 0);
     if (rc == PM_OK)
         for (size_t j = 0; j < alt.size(); ++j) {
@@ -1505,9 +1538,6 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
 
 using namespace pm;
 
-struct pm_ctx {
-    Ctx_ c;
-};
 
 extern "C" {
 
@@ -1699,6 +1729,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "edge_support" && (value == 0 || value == 1)) c.support_opt = value != 0;
     else if (k == "heavy_span_shift" && value >= 0 && value <= 32) c.heavy_span_shift = (uint32_t)value;
     else if (k == "hipgraph") c.use_graphs = value != 0;
+    else if (k == "window_counters" && (value == 16 || value == 32)) c.window_wide = value == 32;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;
 }
@@ -1798,9 +1829,20 @@ uint64_t pm_fsm_num_slots(uint32_t num_labels) {
 pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out) {
     if (!out || num_labels == 0 || num_labels > (uint32_t)FSM_LMAX) return fail(PM_E_INVAL, "bad label count");
     if (slot >= pm_fsm_num_slots(num_labels)) return fail(PM_E_INVAL, "slot out of range");
-    FsmTables t;
-    fsm_tables(num_labels, &t);
-    const auto& s = t.slots[slot];
+    // the slot table of each label count is built once per process
+    static std::mutex mu;
+    static std::map<uint32_t, std::unique_ptr<FsmTables>> cache;
+    const FsmTables* t;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto& e = cache[num_labels];
+        if (!e) {
+            e = std::make_unique<FsmTables>();
+            fsm_tables(num_labels, e.get());
+        }
+        t = e.get();
+    }
+    const auto& s = t->slots[slot];
     for (int i = 0; i < 8; ++i) out->label[i] = -1;
     out->induce = PM_EDGE_INDUCED;
     if (s[0] == 0) {  // triangle 0-1-2

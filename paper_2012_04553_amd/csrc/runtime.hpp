@@ -27,6 +27,14 @@ int fail(int code, const std::string& msg);
 
 int to_pat(const pm_pattern& q, Pat* out, std::string* err);
 
+struct PlanInfo;
+// Work items over the roots: consecutive roots of about `budget` adjacency
+// entries (at most max_roots), roots above `split` cut into level-1 slices.
+std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t n, uint64_t budget, uint32_t split,
+                               uint32_t max_roots);
+void closure_counts(const std::vector<Pat>& closure, const std::vector<PlanInfo>& plans, const uint64_t* host,
+                    std::vector<__int128>* cnt, std::vector<int>* st, std::vector<std::string>* err);
+
 // First-fit sub-allocator over the caller's device arena (offsets).
 struct Arena {
     uintptr_t base = 0;
@@ -165,6 +173,7 @@ struct Ctx_ {
     bool clique_opt = true;
     uint32_t heavy_span_shift = 6;   // two-hop heavy roots: mass << shift >= id
     bool support_opt = true;
+    bool window_wide = false;        // agg_window_kernel: 32-bit counters always
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
@@ -258,3 +267,7 @@ struct Ctx_ {
 };
 
 }  // namespace pm
+
+struct pm_ctx {
+    pm::Ctx_ c;
+};

@@ -56,58 +56,36 @@ constexpr uint64_t SLOT_HOST_WORDS = 2 * 1024 + 8;
 
 using Clock = std::chrono::steady_clock;
 
-// closure counts -> per-request values (quotient plans first: by k)
-int batch_values(const Batch& B, std::vector<std::vector<int64_t>>* out, std::string* err) {
-    const size_t np = B.plans.size();
-    std::vector<__int128> cnt(np, -1);
-    std::vector<size_t> order(np);
-    for (size_t i = 0; i < np; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return B.closure[a].k < B.closure[b].k; });
-    for (size_t i : order) {
-        const PlanInfo& pi = B.plans[i];
-        unsigned __int128 v = ((unsigned __int128)B.ls.host[2 * i + 1] << 64) | B.ls.host[2 * i];
-        __int128 c;
-        if (pi.rewrite) {
-            __int128 acc = (__int128)pi.hmult * (__int128)v;
-            for (auto& sq : pi.subs) {
-                size_t j = std::find(B.closure.begin(), B.closure.end(), sq.first) - B.closure.begin();
-                if (j >= np || cnt[j] < 0) {
-                    *err = "internal: quotient sub-pattern missing";
-                    return PM_E_DEVICE;
-                }
-                acc -= (__int128)sq.second * cnt[j];
-            }
-            if (acc < 0 || acc % pi.autp) {
-                *err = "internal: quotient combination not exact";
-                return PM_E_DEVICE;
-            }
-            c = acc / pi.autp;
-        } else {
-            if (v % (unsigned __int128)pi.divisor) {
-                *err = "internal: match total not divisible by the plan divisor";
-                return PM_E_DEVICE;
-            }
-            c = (__int128)(v / (unsigned __int128)pi.divisor);
-        }
-        if (c > (__int128)INT64_MAX) {
-            *err = "count exceeds int64";
-            return PM_E_OVERFLOW;
-        }
-        cnt[i] = c;
-    }
+// closure counts -> per-request values and statuses: a request fails (with
+// PM_E_OVERFLOW, say) only when a count it needs does
+void batch_values(const Batch& B, std::vector<std::vector<int64_t>>* out, std::vector<int>* status,
+                  std::vector<std::string>* errs) {
+    std::vector<__int128> cnt;
+    std::vector<int> st;
+    std::vector<std::string> cerr;
+    closure_counts(B.closure, B.plans, B.ls.host, &cnt, &st, &cerr);
     out->assign(B.reqs.size(), {});
+    status->assign(B.reqs.size(), PM_OK);
+    errs->assign(B.reqs.size(), std::string());
     for (size_t r = 0; r < B.reqs.size(); ++r) {
         const MorphPlan& mp = B.mps[r];
         std::vector<int64_t> alt(mp.alt.size());
-        for (size_t j = 0; j < alt.size(); ++j) {
+        for (size_t j = 0; j < alt.size() && !(*status)[r]; ++j) {
             size_t i = std::find(B.closure.begin(), B.closure.end(), mp.alt[j]) - B.closure.begin();
-            alt[j] = (int64_t)cnt[i];
+            if (i >= cnt.size()) {
+                (*status)[r] = PM_E_DEVICE;
+                (*errs)[r] = "internal: alternative pattern missing from the batch";
+            } else if (st[i]) {
+                (*status)[r] = st[i];
+                (*errs)[r] = cerr[i];
+            } else {
+                alt[j] = (int64_t)cnt[i];
+            }
         }
+        if ((*status)[r]) continue;
         size_t npat = mp.alt.empty() ? 0 : mp.matrix.size() / mp.alt.size();
-        int rc = unmorph(mp, npat, alt, &(*out)[r], err);
-        if (rc) return rc;
+        (*status)[r] = unmorph(mp, npat, alt, &(*out)[r], &(*errs)[r]);
     }
-    return PM_OK;
 }
 
 }  // namespace
@@ -236,14 +214,16 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             Batch& B = *s.batch;
             const double tdone = now_s();
             std::vector<std::vector<int64_t>> vals;
-            std::string err;
-            int brc = e == hipSuccess ? (B.cancelled ? PM_E_TIMEOUT : batch_values(B, &vals, &err)) : PM_E_DEVICE;
+            std::vector<int> rst;
+            std::vector<std::string> rerr;
+            const int brc = e == hipSuccess ? (B.cancelled ? PM_E_TIMEOUT : PM_OK) : PM_E_DEVICE;
+            if (brc == PM_OK) batch_values(B, &vals, &rst, &rerr);
             for (size_t r = 0; r < B.reqs.size(); ++r) {
                 pm_serve_result& R = res[B.reqs[r]];
-                R.status = brc;
+                R.status = brc ? brc : rst[r];
                 R.latency_s = tdone - reqs[B.reqs[r]].arrival_s;
                 R.batch_size = (uint32_t)B.reqs.size();
-                if (brc == PM_OK)
+                if (R.status == PM_OK)
                     for (size_t k = 0; k < vals[r].size(); ++k) R.values[k] = vals[r][k];
                 ++finished;
             }

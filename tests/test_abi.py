@@ -76,3 +76,38 @@ def test_invalid_patterns_rejected_on_host():
         pm.morph_plan([(4, 0b000011, True)])      # disconnected
     with pytest.raises(PMError):
         pm.morph_plan([(6, 0, True)])             # k out of range
+
+
+def _oracle_three_edge_forms(L):
+    """Canonical forms of every labeled connected pattern with 3 edges on L
+    labels (the triangle, the 3-path and the 3-star; any labeling), from the
+    oracle's pattern algebra."""
+    from itertools import product
+    from oracle import P
+    forms = set()
+    for k in (3, 4):
+        for m in P.connected_classes(k):
+            if P.edge_count(m) != 3:
+                continue
+            for labs in product(range(L), repeat=k):
+                forms.add((k,) + P.canonical(k, m, labs))
+    return forms
+
+
+@pytest.mark.parametrize("L", [3, 16])
+def test_fsm_slot_table_complete_and_distinct(L):
+    """pm_fsm_slot enumerates every labeled 3-edge pattern exactly once:
+    the slots' canonical forms are distinct and equal the oracle's set
+    (85 at 3 labels, 46,768 at 16)."""
+    from oracle import P
+    import paper_2012_04553_amd as pm
+    want = _oracle_three_edge_forms(L)
+    ns = pm.fsm_num_slots(L)
+    assert ns == len(want) == {3: 85, 16: 46768}[L]
+    seen = set()
+    for s in range(ns):
+        k, mask, labs = pm.fsm_slot(L, s)
+        assert P.edge_count(mask) == 3 and P.is_connected(k, mask)
+        seen.add((k,) + P.canonical(k, mask, labs))
+    assert len(seen) == ns
+    assert seen == want

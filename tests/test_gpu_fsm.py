@@ -80,9 +80,52 @@ def test_fsm_sixteen_labels_sampled(eng):
         assert sup[s] == want, (s, k, mask, labs)
 
 
+def test_fsm_sixteen_labels_every_slot(eng):
+    """All 46,768 slots at 16 labels on R-MAT graphs small enough for the
+    oracle to enumerate every match of each 3-edge shape once."""
+    import paper_2012_04553_amd as pm
+    L = 16
+    for scale, seed in ((9, 37), (10, 39)):
+        g = gen.rmat(scale, 8, seed=seed)
+        g = g.with_labels(gen.zipf_labels(g.n, L, 1.2, seed + 1))
+        gid = eng.load(g)
+        try:
+            sup, freq = eng.fsm(gid, L, threshold=8)
+        finally:
+            eng.graph_unload(gid)
+        by_shape = {}
+        for s in range(len(sup)):
+            k, mask, labs = _slot_pattern(L, s)
+            by_shape.setdefault((k, mask), []).append((s, labs))
+        assert sum(len(v) for v in by_shape.values()) == 46768
+        nonzero = 0
+        for (k, mask), items in by_shape.items():
+            want = oracle.mni_labelings(g, k, mask, False, L, [labs for _, labs in items])
+            for (s, labs), w in zip(items, want):
+                assert sup[s] == w, (scale, s, k, mask, labs)
+                assert freq[s] == (w >= 8)
+                nonzero += w > 0
+        _say(f"R-MAT {scale}: every slot equal, {nonzero} with nonzero support")
+
+
+def _repeated_label_slots(L, ns, rng, count):
+    """Slots whose pattern repeats a label (where injectivity between
+    same-labeled pattern vertices decides membership)."""
+    out = []
+    for s in rng.permutation(ns):
+        k, mask, labs = _slot_pattern(L, int(s))
+        if len(set(labs)) < k and max(labs) <= 5:
+            out.append(int(s))
+            if len(out) == count:
+                break
+    return out
+
+
 def test_fsm_config_scale_sampled(eng):
-    """R-MAT scale 18, edge factor 8, Zipf(1.2) over 16 labels: a sample of
-    slots (random and highest-support) against the rooted-search oracle."""
+    """R-MAT scale 18, edge factor 8, Zipf(1.2) over 16 labels: 260 slots
+    (random, highest-support, and 200 that repeat a label) against the
+    rooted-search oracle."""
+    import paper_2012_04553_amd as pm
     L = 16
     g = gen.rmat(18, 8, seed=4)
     g = g.with_labels(gen.zipf_labels(g.n, L, 1.2, 40))
@@ -94,11 +137,13 @@ def test_fsm_config_scale_sampled(eng):
     finally:
         eng.graph_unload(gid)
     rng = np.random.default_rng(1)
-    slots = [int(x) for x in rng.choice(len(sup), size=8, replace=False)]
-    slots += [int(i) for i in np.argsort(-sup)[:4]]
+    slots = [int(x) for x in rng.choice(len(sup), size=40, replace=False)]
+    slots += [int(i) for i in np.argsort(-sup)[:20]]
+    slots += _repeated_label_slots(L, len(sup), np.random.default_rng(2), 200)
+    t = time.time()
     for s in slots:
         k, mask, labs = _slot_pattern(L, s)
-        t = time.time()
         want = oracle.mni_support_rooted(g, k, mask, False, labs)
-        _say(f"  slot {s} k={k} labels={labs}: gpu {sup[s]} oracle {want} ({time.time() - t:.1f}s)")
-        assert sup[s] == want
+        assert sup[s] == want, (s, k, mask, labs)
+        assert freq[s] == (want >= 1000)
+    _say(f"  {len(slots)} slots equal the oracle ({time.time() - t:.1f}s)")

@@ -71,3 +71,22 @@ def test_heavy_roots_five_vertex(eng):
     want = oracle.census(g, 5)
     want = [want[m] for m in P.connected_classes(5)]
     assert _counts(eng, g, 5, True, pm.MORPH_NAIVE, True) == want
+
+
+def test_heavy_roots_wide_counters(eng):
+    """The 32-bit-counter variant of the two-hop window kernel (taken on
+    graphs with a degree above 16 bits) forced on small graphs: counts from
+    the oracle's closed forms, and equal to the 16-bit variant."""
+    import paper_2012_04553_amd as pm
+    g = gen.rmat(10, 16, seed=6)
+    want_e = oracle.edge_induced_4_from_tier_c(g)
+    want_e = [want_e[m] for m in P.connected_classes(4)]
+    want_v = oracle.vertex_induced_4_from_tier_c(g)
+    want_v = [want_v[m] for m in P.connected_classes(4)]
+    eng.set_option("window_counters", 32)
+    try:
+        assert _counts(eng, g, 4, False, pm.MORPH_NONE, True) == want_e
+        assert _counts(eng, g, 4, True, pm.MORPH_NAIVE, True) == want_v
+    finally:
+        eng.set_option("window_counters", 16)
+    assert _counts(eng, g, 4, True, pm.MORPH_NAIVE, True) == want_v

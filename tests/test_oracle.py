@@ -274,3 +274,45 @@ def test_mni_rooted_search_equals_full_enumeration():
             for v in range(k):
                 assert oracle.mni_column(g, k, m, False, labs, v) == int(dom[v].sum())
             assert oracle.mni_support_rooted(g, k, m, False, labs) == oracle.mni_support(g, k, m, False, labs)
+
+
+@pytest.mark.parametrize("k,L", [(3, 2), (3, 3), (4, 2), (4, 3), (5, 2)])
+def test_labeled_automorphisms_orbit_count(k, L):
+    """Label-preserving automorphisms, pinned by orbit counting.  The
+    vertex-numbered connected graphs on k vertices with each vertex given
+    one of L labels number L^k times the connected labelled-graph count
+    (4, 38, 728; tests/golden/pattern_pins.txt).  Relabelling the vertices
+    splits them into one orbit per labeled pattern, of size k!/|Aut_L(p)|,
+    so the orbit sizes over the distinct canonical labeled patterns must sum
+    to that number.  A label test missing from the automorphisms (or from
+    the canonical form) breaks the sum."""
+    from itertools import product
+    labelled = {int(r[1]): int(r[2]) for r in _read_golden("pattern_pins.txt")
+                if r[0] == "connected_labelled"}
+    forms = set()
+    for m in P.connected_classes(k):
+        for labs in product(range(L), repeat=k):
+            forms.add(P.canonical(k, m, labs))
+    total = 0
+    for m, labs in forms:
+        aut = P.num_automorphisms(k, m, labs)
+        assert factorial(k) % aut == 0
+        total += factorial(k) // aut
+    assert total == L ** k * labelled[k]
+    # a planted mistake: automorphisms that ignore labels undercount
+    wrong = sum(factorial(k) // P.num_automorphisms(k, m) for m, labs in forms)
+    assert wrong != total
+
+
+def test_mni_labelings_equals_per_pattern_support():
+    """One enumeration of the unlabeled shape, filed by the labels of the
+    images, against the per-pattern support (pinned above) for every
+    labeling of every 3- and 4-vertex shape."""
+    from itertools import product
+    g = gen.erdos_renyi(28, 0.2, 21).with_labels(gen.zipf_labels(28, 3, 1.2, 22))
+    for k in (3, 4):
+        for m in P.connected_classes(k):
+            labs = [list(t) for t in product(range(3), repeat=k)]
+            got = oracle.mni_labelings(g, k, m, False, 3, labs)
+            for t, sup in zip(labs, got):
+                assert sup == oracle.mni_support(g, k, m, False, t), (k, m, t)
