@@ -296,6 +296,23 @@ pm_status pm_serve(pm_ctx* ctx, const pm_serve_request* reqs, uint32_t nreq,
                    const pm_serve_config* cfg, pm_serve_result* out_results,
                    pm_serve_stats* out_stats);
 
+/* Allocation-free counting, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as pm_submit + pm_wait with
+ * PM_AGG_COUNT (counts in `out_values`, host, npat int64), but synchronous
+ * on the context's stream, and no device memory is allocated: not from the
+ * arena, not by the HIP runtime.  Everything the launch needs beyond the
+ * resident graph (plans, counters, queue head, work items, per-wavefront
+ * level buffers) lives in one static device array of 64 MiB per GPU, held
+ * until the process ends; every plan runs in the general matching kernel.
+ * Calls on one GPU share that array: calls from this process are
+ * serialised, calls from several processes that overlap on one GPU race.
+ * Errors: as pm_submit / pm_wait, and PM_E_NOMEM when the query (at most 64
+ * plans) or the graph's level buffers (5 x (max degree + 64) words per
+ * wavefront, 4 wavefronts at least) do not fit the 64 MiB. */
+pm_status pm_count_noalloc(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
+                           uint32_t npat, int32_t morph, int64_t* out_values);
+
 /* Writes a NUL-terminated description of the matching plan the engine
  * compiles for `pat` on graph `graph_id` (core order, per-level set
  * operations and bounds, tail terms) into `buf` (capacity `cap`). */

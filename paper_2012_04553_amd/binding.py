@@ -111,6 +111,8 @@ SIGNATURES = {
     "pm_serve": (ctypes.c_int32, [_P, ctypes.POINTER(pm_serve_request), ctypes.c_uint32,
                                   ctypes.POINTER(pm_serve_config), ctypes.POINTER(pm_serve_result),
                                   ctypes.POINTER(pm_serve_stats)]),
+    "pm_count_noalloc": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_uint32,
+                                          ctypes.c_int32, _i64p]),
     "pm_last_error": (ctypes.c_char_p, []),
     "pm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
 }
@@ -258,6 +260,13 @@ class Engine:
 
     def count(self, gid, pats, morph=MORPH_NAIVE) -> list[int]:
         return self.wait(self.submit(gid, pats, morph), len(pats))
+
+    def count_noalloc(self, gid, pats, morph=MORPH_NAIVE) -> list[int]:
+        """pm_count_noalloc: the same counts without allocating device memory."""
+        arr = pattern_array(pats)
+        out = (ctypes.c_int64 * len(pats))()
+        check(lib().pm_count_noalloc(self.ctx, gid, arr, len(pats), morph, out))
+        return [int(x) for x in out]
 
     def last_stats(self) -> dict:
         s = pm_query_stats()

@@ -1555,6 +1555,7 @@ pm_status pm_create(void* dev_arena, uint64_t arena_bytes, void* hip_stream, int
     c->c.arena.free_[0] = arena_bytes & ~uint64_t(255);
     c->c.num_cus = prop.multiProcessorCount;
     c->c.load_tune_file();
+    noalloc_init(device);
     *out = c;
     return PM_OK;
 }

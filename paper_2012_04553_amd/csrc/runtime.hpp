@@ -32,6 +32,9 @@ struct PlanInfo;
 // entries (at most max_roots), roots above `split` cut into level-1 slices.
 std::vector<KItem> build_items(const std::vector<uint32_t>& rp, uint32_t n, uint64_t budget, uint32_t split,
                                uint32_t max_roots);
+// The allocation-free entry point's static scratch array: its device address
+// is taken once per device when a context is created there.
+void noalloc_init(int device);
 void closure_counts(const std::vector<Pat>& closure, const std::vector<PlanInfo>& plans, const uint64_t* host,
                     std::vector<__int128>* cnt, std::vector<int>* st, std::vector<std::string>* err);
 
