@@ -33,7 +33,6 @@ METRIC = "motif-count s (morphed vs plain), matches/s, % HBM peak, p50/p99 query
 # sources that decide the match kernel's memory traffic (kernel, plans, launch configuration)
 PATH_SRCS = [os.path.join(ROOT, "paper_2012_04553_amd", "csrc", f)
              for f in ("kernels.hip", "kernels.hpp", "planner.cpp", "runtime.hpp", "runtime.cpp")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_kernel_rmat20_4mc_morphed_traffic.md")
 
 
 def log(msg):
@@ -48,14 +47,15 @@ def path_sha():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the matching kernels from the committed PMC
-    summary, or None when a kernel, the planner or the launch set-up
-    changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (profiles/<kernel>_rmat20_4mc_traffic.md), or None when a kernel, the
+    planner or the launch set-up changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_rmat20_4mc_traffic.md")
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             w = line.strip().split()
             if len(w) == 2 and w[0].endswith(":"):
@@ -102,37 +102,77 @@ def timed_steps(eng, step, args):
     return wall * 1e3 / args.steps, kms
 
 
-def cpu_baseline_4mc(g, budget_s: float = 15.0):
-    """The oracle (tier A injective-map counting of the six vertex-induced
-    4-vertex motifs) on a bounded sample of roots of the same graph, on all
-    host threads.  Rate = (matches / |Aut|) per second, i.e. matched
-    subgraphs credited to the sampled roots."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_4mc(g, stride: int = 2):
+    """The oracle's tier-C computation of the same six counts (closed forms
+    over degrees and per-edge common neighbours, 4-cycles by co-degrees,
+    4-cliques on the degree DAG; vertex-induced counts by Corollary 3.1) on
+    a bounded sample of the same graph: the roots u with u % stride == 0,
+    each credited with exactly its share of every sum, on all host
+    threads.  Rate = vertex-induced subgraphs credited to the sample per
+    second (Corollary 3.1 is linear, so credited shares convert like
+    totals)."""
+    import numpy as np
     import oracle
     from oracle import P
-    pats = list(P.connected_classes(4))
-    auts = {m: P.num_automorphisms(4, m) for m in pats}
-    deg = g.degrees()
-    # a fixed spread of generator ids; roots above degree 256 are left out
-    # because one hub root alone costs the oracle d^3 maps
-    sample = [r for r in range(0, g.n, 997) if deg[r] <= 256][:4096]
-    credited = 0.0
-    roots = 0
     t0 = time.perf_counter()
-    for r in sample:
-        for m in pats:
-            credited += oracle.count_maps(g, 4, m, True, roots=(r, r + 1)) / auts[m]
-        roots += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
+    raw = oracle.tier_c4_sample(g, stride, 0)
     dt = time.perf_counter() - t0
+    # credited edge-induced shares (the divisions of the full closed forms)
+    ei = {"star3": raw["star3"], "path4": raw["path4"] - raw["triangles"],
+          "tailed_triangle": raw["tailed_triangle"], "cycle4": raw["cycle4"] / 2,
+          "diamond": raw["diamond"], "clique4": raw["clique4"]}
+    names = oracle.named_4()
+    cls, mat = P.morph_matrix(4)
+    ne = np.array([float(ei[k]) for k in (next(n for n in names if names[n] == m) for m in cls)])
+    nv = np.linalg.solve(np.array(mat, dtype=np.float64), ne)
+    credited = float(nv.sum())
+    roots = (g.n + stride - 1) // stride
     return {
         "value": credited / dt,
         "unit": "matches/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"tier A vertex-induced 4-motif matching rooted at {roots} vertices "
-                  f"(every 997th generator id with degree <= 256), {dt:.1f} s",
+        "sample": f"tier-C closed forms of the six 4-vertex counts (Corollary 3.1 for the vertex-induced ones) "
+                  f"credited to every {stride}th root ({roots} of {g.n}) of the same R-MAT scale-20 graph, "
+                  f"{dt:.1f} s on {oracle.num_threads()} threads of {cpu_model()}",
+        "seconds": round(dt, 2),
+        "cpu_model": cpu_model(),
     }
+
+
+def launch_roofline(eng, gid, pats, mode, steps):
+    """Per-launch roofline: algorithmic bytes of every launch (byte-counting
+    build, untimed) and its device time between HIP events on the engine's
+    stream, averaged over `steps` eager passes of the same launch set."""
+    eng.set_option("count_bytes", 1)
+    eng.count(gid, pats, morph=mode)
+    bytes_ = [x["alg_bytes"] for x in eng.launch_stats()]
+    names = [x["kernel"] for x in eng.launch_stats()]
+    eng.set_option("count_bytes", 0)
+    eng.set_option("launch_events", 1)
+    ms = [0.0] * len(bytes_)
+    eng.count(gid, pats, morph=mode)
+    for _ in range(steps):
+        eng.count(gid, pats, morph=mode)
+        for i, x in enumerate(eng.launch_stats()):
+            ms[i] += x["ms"] / steps
+    eng.set_option("launch_events", 0)
+    per = []
+    for name, b, t in zip(names, bytes_, ms):
+        per.append({"kernel": name, "alg_bytes": b, "ms": round(t, 4),
+                    "gbs": round(b / (t / 1e3) / 1e9, 1) if t > 0 else None})
+    return per
 
 
 # ---------------------------------------------------------------- workloads
@@ -169,11 +209,17 @@ def run_4mc(args, eng, g, workload, morph_name="morphed"):
         "n": g.n, "m": g.m, "motif_count_s": ms_per_step / 1e3, "kernel_ms": k_ms,
         "graph_load_s": round(load_s, 3), "matches_per_step": matches, "counts": ref,
     })
+    per = launch_roofline(eng, gid, pats, mode, max(1, args.steps // 2))
+    dom = max(range(len(per)), key=lambda i: per[i]["ms"])
+    d = per[dom]
+    d_ach = d["alg_bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
     line["roofline"] = {
-        "bound": "hbm", "kernel": "all matching launches of the step (match, clique, clique4, support, window kernels)",
-        "launches_per_step": launches, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None, "alg_bytes_per_launch": alg_bytes / launches,
-        "avg_launch_ms": per_launch_ms,
+        "bound": "hbm", "kernel": d["kernel"], "launch_index": dom,
+        "achieved": d_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d_ach / HBM_PEAK_GBS,
+        "traffic": None, "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": d["ms"],
+        "all_launches": {"launches_per_step": launches, "alg_bytes_per_step": alg_bytes,
+                         "achieved": achieved, "frac": achieved / HBM_PEAK_GBS},
+        "per_launch": per,
     }
     return line, gid
 
@@ -187,8 +233,7 @@ def wl_rmat20_4mc(args, eng):
     line, gid = run_4mc(args, eng, g, f"4-motif counting (6 vertex-induced motifs, morphed), R-MAT scale "
                         f"{args.scale} edge factor 16 (0.57,0.19,0.19,0.05) seed 2")
     if args.scale == 20:
-        tr = measured_traffic()
-        line["roofline"]["traffic"] = tr
+        line["roofline"]["traffic"] = measured_traffic(line["roofline"]["kernel"])
     eng.graph_unload(gid)
     # morphed vs plain on a graph small enough for plain matching
     if args.plain_scale > 0:

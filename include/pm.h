@@ -67,10 +67,14 @@ enum { PM_AGG_COUNT = 0, PM_AGG_MNI = 1 };
  * Section 4.2); NAIVE matches the alternative set of Section 4.2's "Naive
  * PMR": vertex-induced patterns become their same-size edge-induced
  * superpatterns plus the clique, converted back by Corollary 3.1; COST
- * morphs a vertex-induced pattern only when the engine's cost model (plan
- * work estimated from the graph's degree statistics, Section 4.1's three
- * factors) rates its superpatterns cheaper than the pattern itself.
- * pm_morph_plan has no graph and treats COST as NAIVE. */
+ * ("Cost-Based PMR", Section 4.1) picks the cheapest alternative set under
+ * the engine's cost model (plan work estimated from the graph's degree
+ * statistics): over the queries' same-size superpatterns each is matched
+ * vertex-induced, edge-induced or not at all, so vertex- and edge-induced
+ * alternatives mix (Table 4: an edge-induced 4-cycle may become the
+ * vertex-induced 4-cycle, the edge-induced diamond and the 4-clique), see
+ * pm_morph_plan_costs.  pm_morph_plan has no graph and treats COST as
+ * NAIVE. */
 enum { PM_MORPH_NONE = 0, PM_MORPH_NAIVE = 1, PM_MORPH_COST = 2 };
 
 typedef struct {
@@ -135,8 +139,19 @@ pm_status pm_query_footprint(pm_ctx* ctx, uint32_t graph_id,
                              int32_t morph, uint64_t* out_bytes);
 
 /* Submit a query (asynchronous).  `pats` is copied.  The ticket identifies
- * it for pm_wait / pm_cancel.  Errors: PM_E_INVAL, PM_E_UNSUPPORTED,
- * PM_E_NOTFOUND (graph), PM_E_NOMEM (footprint exceeds the free arena). */
+ * it for pm_wait / pm_cancel.
+ *   agg = PM_AGG_COUNT: one count per pattern; `morph` as documented above.
+ *   agg = PM_AGG_MNI: one MNI support per pattern (Preliminaries, FSM): the
+ *     smallest over the pattern's vertices of the number of data vertices
+ *     some match maps that vertex to.  PM_MORPH_NAIVE takes an edge-induced
+ *     pattern's domains as unions of the domains of its vertex-induced
+ *     superpatterns on the same vertices, each read through the column
+ *     permutation (Theorem 3.2); vertex-induced patterns and cliques are
+ *     searched directly (a union has no inverse).  PM_MORPH_NONE and
+ *     PM_MORPH_COST search every pattern directly (with existence searches
+ *     the morphed route never does less work).  Patterns have 2..5 vertices.
+ * Errors: PM_E_INVAL, PM_E_UNSUPPORTED, PM_E_NOTFOUND (graph), PM_E_NOMEM
+ * (footprint exceeds the free arena). */
 pm_status pm_submit(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
                     uint32_t npat, int32_t agg, int32_t morph,
                     uint64_t* out_ticket);
@@ -151,6 +166,19 @@ pm_status pm_wait(pm_ctx* ctx, uint64_t ticket, int64_t* out_values,
 /* Optional statistics of the last pm_wait'ed query (call before the next). */
 pm_status pm_last_query_stats(pm_ctx* ctx, pm_query_stats* out);
 
+/* Per-launch statistics of the last pm_wait'ed counting query: one entry per
+ * kernel launch of its launch set, in launch order.  alg_bytes is the
+ * launch's algorithmic bytes when option "count_bytes" was set (else 0);
+ * ms its device time between HIP events recorded on the context's stream
+ * before and after it when option "launch_events" was set (else 0).
+ * Errors: PM_E_INVAL when `cap` is below *n (then only *n is written). */
+typedef struct {
+    char kernel[32];         /* kernel name                                  */
+    uint64_t alg_bytes;
+    double ms;
+} pm_launch_stat;
+pm_status pm_last_launch_stats(pm_ctx* ctx, pm_launch_stat* out, uint32_t cap, uint32_t* n);
+
 /* Request cancellation: the query's kernels stop taking work items (a
  * host-visible flag polled once per item) and the later pm_wait returns
  * PM_E_CANCELLED.  PM_E_NOTFOUND for an unknown ticket. */
@@ -161,12 +189,50 @@ pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket);
  * labeled), writes the alternative patterns to `out_alt` (capacity
  * *inout_nalt, updated to the count used) and the integer conversion
  * matrix to `out_matrix` (row-major npat x nalt, host): value(query i) =
- * sum_j out_matrix[i*nalt + j] * count(alt j).  For MNI only edge-induced
- * queries are morphed (to vertex-induced superpatterns, Theorem 3.2); the
- * matrix is then unused.  Errors: PM_E_INVAL (capacity), PM_E_UNSUPPORTED. */
+ * sum_j out_matrix[i*nalt + j] * count(alt j).  For PM_AGG_MNI the
+ * alternatives are the patterns whose domains pm_submit searches (with
+ * PM_MORPH_NAIVE or PM_MORPH_COST: each edge-induced query's vertex-induced
+ * superpatterns on the same vertices, Theorem 3.2; otherwise the queries
+ * themselves), and out_matrix[i*nalt + j] is 1 when alternative j's domains
+ * enter query i's union, else 0.  Errors: PM_E_INVAL (capacity),
+ * PM_E_UNSUPPORTED. */
 pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg,
                         int32_t morph, pm_pattern* out_alt, uint32_t* inout_nalt,
                         int64_t* out_matrix);
+
+/* Host-only cost-based morph planning with caller-given costs (Section 4.1's
+ * optimizer; the mixed alternative sets of Table 4).  Over the queries'
+ * same-size superpatterns, each pattern is matched vertex-induced,
+ * edge-induced or not at all, minimising the summed cost, such that every
+ * query's count follows (Theorem 3.1, Corollary 3.1): an edge-induced
+ * query may become its vertex-induced form plus edge-induced
+ * superpatterns, a vertex-induced one its edge-induced superpatterns, or a
+ * query may stay as given.  `cost_pats[i]` (its `induce` says how it would
+ * be matched) costs `costs[i]`; unlisted patterns are never chosen unless
+ * no set avoids them.  pm_submit with PM_MORPH_COST runs the same search
+ * with costs from the engine's plan cost model on the graph.  Output as
+ * pm_morph_plan (COUNT).  Errors: PM_E_INVAL, PM_E_UNSUPPORTED. */
+pm_status pm_morph_plan_costs(const pm_pattern* pats, uint32_t npat,
+                              const pm_pattern* cost_pats, const double* costs,
+                              uint32_t ncost, pm_pattern* out_alt,
+                              uint32_t* inout_nalt, int64_t* out_matrix);
+
+/* Listing (enumeration aggregation; Section 3.2.2, match conversion):
+ * every distinct matched subgraph of `pat` on the graph, once, as the
+ * caller's ids of the images of pattern vertices 0..k-1 (one match per
+ * subgraph: the smallest of its images under the pattern's automorphisms).
+ * With PM_MORPH_NAIVE an edge-induced pattern is listed through its
+ * vertex-induced patterns p + S on the same vertices (S: non-adjacent pairs
+ * of p whose images are adjacent), each of whose matches converts to a
+ * match of p by the identity map of p's vertices; otherwise (and for
+ * vertex-induced patterns and cliques) the pattern is listed directly.
+ * Synchronous.  Writes min(*out_count, capacity) tuples of k uint32 to
+ * out_matches (host, capacity * k entries) and the number of subgraphs to
+ * *out_count.  Order is unspecified.  Errors: PM_E_INVAL,
+ * PM_E_UNSUPPORTED, PM_E_NOTFOUND, PM_E_NOMEM (also when the tuples to
+ * write do not fit half the free arena; *out_count is still set). */
+pm_status pm_list(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pat, int32_t morph,
+                  uint32_t* out_matches, uint64_t capacity, uint64_t* out_count);
 
 /* Labeled 3-edge frequent subgraph mining with MNI support (Preliminaries,
  * FSM).  Computes the support of every edge-induced labeled pattern with 3
@@ -174,13 +240,34 @@ pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg,
  * `num_labels` labels, in the dense slot order documented with
  * pm_fsm_slot(); `out_support` (host, nslots int64) receives the supports;
  * `out_frequent` (host, nslots bytes, may be NULL) receives support >=
- * threshold.  Only morph = PM_MORPH_NONE is implemented: supports are
- * computed from the edge-induced patterns directly; any other value
- * returns PM_E_UNSUPPORTED.  Errors: PM_E_INVAL (unlabeled graph, a label
+ * threshold.  morph = PM_MORPH_NONE (and PM_MORPH_COST) computes the
+ * supports from the edge-induced patterns directly, with membership tests
+ * over per-vertex neighbour-label tables; PM_MORPH_NAIVE computes every
+ * slot's domains as unions of its vertex-induced superpatterns' domains
+ * (Theorem 3.2) with the existence searches of pm_submit's MNI route, in
+ * batches that fit the arena.  Errors: PM_E_INVAL (unlabeled graph, a label
  * >= num_labels, nslots != pm_fsm_num_slots), PM_E_NOMEM (arena). */
 pm_status pm_fsm(pm_ctx* ctx, uint32_t graph_id, uint32_t num_labels,
                  int64_t threshold, int32_t morph, int64_t* out_support,
                  uint8_t* out_frequent, uint64_t nslots);
+
+/* Level-wise frequent subgraph mining (Preliminaries, FSM) with MNI
+ * support.  Level 1 holds every labeled edge (labels 0..num_labels-1);
+ * level e+1 extends each frequent pattern of level e by one edge (between
+ * two of its vertices, or to a new vertex of any label, at most 5 vertices)
+ * and keeps a candidate only when each of its connected subpatterns with
+ * one edge fewer is frequent (MNI support is anti-monotone), before its
+ * support is computed with pm_submit's MNI route (`morph` as there).
+ * Frequent = support >= threshold.  Writes every frequent edge-induced
+ * pattern with 1..max_edges edges, in canonical form, level by level, to
+ * out_pats / out_support (host, `capacity` entries) and their number to
+ * *out_count.  Errors: PM_E_INVAL (unlabeled graph, label >= num_labels,
+ * max_edges outside 1..10, capacity below *out_count: nothing is written
+ * but *out_count), PM_E_NOMEM. */
+pm_status pm_fsm_levelwise(pm_ctx* ctx, uint32_t graph_id, uint32_t num_labels,
+                           uint32_t max_edges, int64_t threshold, int32_t morph,
+                           pm_pattern* out_pats, int64_t* out_support,
+                           uint64_t capacity, uint64_t* out_count);
 
 /* Number of FSM slots for `num_labels` labels, and the pattern of slot s. */
 uint64_t pm_fsm_num_slots(uint32_t num_labels);
@@ -225,7 +312,14 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *                   hipGraph on first use and replay it afterwards;
  *   "window_counters" 16 or 32 (default 16): counter width of the two-hop
  *                   window kernel when every degree fits 16 bits (32 is
- *                   always used otherwise).
+ *                   always used otherwise);
+ *   "launch_events" 0/1 (default 0): launch eagerly (no hipGraph) with a HIP
+ *                   event between launches, for per-launch device times in
+ *                   pm_last_launch_stats;
+ *   "fork_launches" 0/1 (default 0): captured launch sets run the triangle
+ *                   and edge-support launches and the 4-clique launches on
+ *                   two more branches of the hipGraph, beside the general
+ *                   kernel's launches.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */
 pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value);
 

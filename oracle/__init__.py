@@ -58,12 +58,15 @@ def lib():
                                   ctypes.c_uint32, ctypes.c_uint32, ip, u8p, u64p, u64p]
         L.or_census.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_int, u64p]
         L.or_tier_c4.argtypes = [ctypes.c_uint32, u32p, u32p, u64p]
+        L.or_tier_c4_sample.argtypes = [ctypes.c_uint32, u32p, u32p, ctypes.c_uint32, ctypes.c_uint32, u64p]
         L.or_mni_column.argtypes = [ctypes.c_uint32, u32p, u32p, u8p, ctypes.c_int, ip,
                                     ctypes.c_uint32, ctypes.c_uint32, ip, u64p]
         i32p = ctypes.POINTER(ctypes.c_int32)
         L.or_mni_labelings.argtypes = [ctypes.c_uint32, u32p, u32p, u8p, ctypes.c_int, ip,
                                        ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, i32p,
                                        ctypes.c_int, u64p]
+        L.or_list_maps.argtypes = [ctypes.c_uint32, u32p, u32p, u8p, ctypes.c_int, ip,
+                                   ctypes.c_uint32, ctypes.c_uint32, ip, ctypes.c_uint64, u32p, u64p]
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -181,6 +184,31 @@ def tier_c4(g) -> dict:
             for i, key in enumerate(TIER_C4_KEYS)}
 
 
+def tier_c4_sample(g, stride: int, offset: int) -> dict:
+    """The closed forms of tier_c4 credited to the roots u with
+    u % stride == offset, as raw sums (triangles counted 3 times, the 3-path
+    slot holding P4 + 3T, 4-cycles counted twice); over every offset they
+    add up to tier_c4's raw sums."""
+    rp, col = _graph_arrays(g)
+    out = np.zeros(2 * len(TIER_C4_KEYS), dtype=np.uint64)
+    rc = lib().or_tier_c4_sample(g.n, _ptr(rp, ctypes.c_uint32), _ptr(col, ctypes.c_uint32), stride, offset,
+                                 _ptr(out, ctypes.c_uint64))
+    if rc != 0:
+        raise ValueError(f"or_tier_c4_sample failed: {rc}")
+    return {key: (int(out[2 * i + 1]) << 64) | int(out[2 * i])
+            for i, key in enumerate(TIER_C4_KEYS)}
+
+
+def tier_c4_from_raw(raw: dict) -> dict:
+    """tier_c4's values from summed raw sums (exact divisions)."""
+    out = dict(raw)
+    assert raw["triangles"] % 3 == 0 and raw["cycle4"] % 2 == 0
+    out["triangles"] = raw["triangles"] // 3
+    out["path4"] = raw["path4"] - raw["triangles"]
+    out["cycle4"] = raw["cycle4"] // 2
+    return out
+
+
 # canonical masks of the named 4-vertex classes
 def named_4():
     """Canonical masks of the six connected 4-vertex classes by name."""
@@ -274,6 +302,27 @@ def mni_support_rooted(g, k: int, mask: int, induced: bool, plabels) -> int:
     return min(mni_column(g, k, mask, induced, plabels, v) for v in range(k))
 
 
+def list_maps(g, k: int, mask: int, induced: bool, plabels=None) -> np.ndarray:
+    """Every match (Preliminaries: injective map preserving edges, anti-edges
+    when vertex-induced, and labels) as rows of k data vertices in
+    pattern-vertex order; tiny graphs only."""
+    rp, col = _graph_arrays(g)
+    order, amask, pl = _pattern_args(k, mask, induced, plabels)
+    lab = None
+    if g.labels is not None:
+        lab = np.ascontiguousarray(g.labels, dtype=np.uint8)
+    cap = max(1, count_maps(g, k, mask, induced, plabels))
+    out = np.zeros(cap * k, dtype=np.uint32)
+    cnt = ctypes.c_uint64()
+    rc = lib().or_list_maps(g.n, _ptr(rp, ctypes.c_uint32), _ptr(col, ctypes.c_uint32),
+                            None if lab is None else _ptr(lab, ctypes.c_uint8), k,
+                            _ptr(order, ctypes.c_int), mask, amask, _ptr(pl, ctypes.c_int), cap,
+                            _ptr(out, ctypes.c_uint32), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError(f"or_list_maps failed: {rc}")
+    return out[: cnt.value * k].reshape(cnt.value, k)
+
+
 def mni_labelings(g, k: int, mask: int, induced: bool, num_labels: int, labelings) -> list[int]:
     """MNI support of several labelings of one pattern shape at once.
 
@@ -311,5 +360,5 @@ def mni_labelings(g, k: int, mask: int, induced: bool, num_labels: int, labeling
 __all__ = ["P", "build", "lib", "count_maps", "count", "motif_counts", "census",
            "full_census_tiny", "tier_c4", "named_4", "edge_induced_4_from_tier_c",
            "vertex_induced_4_from_tier_c", "mni_domains", "mni_support", "num_threads",
-           "mni_column", "mni_support_rooted", "mni_labelings",
+           "mni_column", "mni_support_rooted", "mni_labelings", "list_maps", "tier_c4_sample", "tier_c4_from_raw",
            "comb", "factorial"]

@@ -28,6 +28,7 @@
  *    match) by enumerating every match.
  *  - or_mni_column: the size of one such column on large graphs, by a
  *    search from every candidate vertex that stops at its first match.
+ *  - or_list_maps: every match written out (listing on tiny graphs).
  *  - or_mni_labelings: the columns of every labeling of one unlabeled
  *    pattern at once: each match of the unlabeled pattern is a match of
  *    exactly one labeled pattern, the one whose vertex i carries the label
@@ -442,6 +443,107 @@ int or_tier_c4(uint32_t n, const uint32_t* rp, const uint32_t* col, uint64_t* ou
     return 0;
 }
 
+/* The same closed forms restricted to a sample of roots: only roots u with
+ * u % stride == offset contribute, each with exactly the terms the full
+ * computation credits to u (its degree terms, its edges to higher ids, its
+ * co-degrees with higher ids, its 4-cliques as the DAG source), plus the
+ * tailed-triangle term of u, which needs the triangles at u over all of u's
+ * edges.  out[0..8] (128-bit pairs) hold the raw sums before the divisions
+ * of or_tier_c4: summed over every offset they equal its raw sums, so
+ * 3T, P4 + 3T and 2 C4 sit in slots 2, 4 and 6. */
+int or_tier_c4_sample(uint32_t n, const uint32_t* rp, const uint32_t* col, uint32_t stride,
+                      uint32_t offset, uint64_t* out) {
+    if (stride == 0) return -1;
+    int nt = or_num_threads();
+    const int NQ = 9;
+    u128* part = (u128*)calloc((size_t)nt * NQ, sizeof(u128));
+    uint32_t* orp = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
+    uint32_t* ocol = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)rp[n] / 2 + 1));
+    orp[0] = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+        uint32_t du = rp[u + 1] - rp[u], c = orp[u];
+        for (uint32_t p = rp[u]; p < rp[u + 1]; ++p) {
+            uint32_t v = col[p], dv = rp[v + 1] - rp[v];
+            if (du < dv || (du == dv && u < v)) ocol[c++] = v;
+        }
+        orp[u + 1] = c;
+    }
+#pragma omp parallel
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        u128* q = part + (size_t)t * NQ;
+        uint32_t* cnt = (uint32_t*)calloc(n, sizeof(uint32_t));
+        uint32_t* touched = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+        uint32_t* s1 = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)n + 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t uu = offset; uu < (int64_t)n; uu += stride) {
+            uint32_t u = (uint32_t)uu;
+            uint64_t du = rp[u + 1] - rp[u];
+            q[1] += (u128)(du * (du - (du > 0)) / 2);
+            if (du >= 3) q[3] += (u128)du * (du - 1) * (du - 2) / 6;
+            uint64_t tvu = 0;   /* 2 * triangles at u */
+            for (uint32_t p = rp[u]; p < rp[u + 1]; ++p) {
+                uint32_t v = col[p];
+                uint64_t tuv = merge_common(col + rp[u], rp[u + 1] - rp[u], col + rp[v], rp[v + 1] - rp[v]);
+                tvu += tuv;
+                if (v <= u) continue;
+                uint64_t dv = rp[v + 1] - rp[v];
+                q[0] += 1;
+                q[2] += tuv;
+                q[4] += (u128)(du - 1) * (dv - 1);
+                q[7] += (u128)tuv * (tuv - (tuv > 0)) / 2;
+            }
+            if (du >= 2) q[5] += (u128)(tvu / 2) * (du - 2);
+            uint32_t nt2 = 0;
+            for (uint32_t p = rp[u]; p < rp[u + 1]; ++p) {
+                uint32_t v = col[p];
+                for (uint32_t r = rp[v]; r < rp[v + 1]; ++r) {
+                    uint32_t w = col[r];
+                    if (w <= u) continue;
+                    if (cnt[w]++ == 0) touched[nt2++] = w;
+                }
+            }
+            for (uint32_t i = 0; i < nt2; ++i) {
+                uint64_t c = cnt[touched[i]];
+                q[6] += (u128)(c * (c - 1) / 2);
+                cnt[touched[i]] = 0;
+            }
+            for (uint32_t p = orp[u]; p < orp[u + 1]; ++p) {
+                uint32_t v = ocol[p];
+                uint32_t ls = 0;
+                uint32_t i = orp[u], j = orp[v];
+                while (i < orp[u + 1] && j < orp[v + 1]) {
+                    if (ocol[i] < ocol[j]) ++i;
+                    else if (ocol[i] > ocol[j]) ++j;
+                    else { s1[ls++] = ocol[i]; ++i; ++j; }
+                }
+                for (uint32_t a = 0; a < ls; ++a) {
+                    uint32_t w = s1[a];
+                    q[8] += merge_common(s1, ls, ocol + orp[w], orp[w + 1] - orp[w]);
+                }
+            }
+        }
+        free(cnt);
+        free(touched);
+        free(s1);
+    }
+    free(orp);
+    free(ocol);
+    u128 tot[9];
+    memset(tot, 0, sizeof(tot));
+    for (int t = 0; t < nt; ++t)
+        for (int i = 0; i < NQ; ++i) tot[i] += part[(size_t)t * NQ + i];
+    free(part);
+    for (int i = 0; i < NQ; ++i) {
+        out[2 * i] = (uint64_t)tot[i];
+        out[2 * i + 1] = (uint64_t)(tot[i] >> 64);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* MNI column size by rooted existence                                  */
 /* ------------------------------------------------------------------ */
@@ -557,5 +659,54 @@ int or_mni_labelings(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
         out[q] = cnt;
     }
     free(t.dom);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Listing: every match written out                                     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    mapctx c;
+    uint32_t* out;          /* cap matches of k ids, pattern-vertex order */
+    uint64_t cap, count;
+} listctx;
+
+static void extend_list(listctx* t, uint32_t* img, int j) {
+    const mapctx* c = &t->c;
+    if (j == c->k) {
+        if (t->count < t->cap)
+            for (int i = 0; i < c->k; ++i) t->out[t->count * (uint64_t)c->k + c->order[i]] = img[i];
+        t->count++;
+        return;
+    }
+    uint32_t a = img[c->anchor[j]];
+    for (uint32_t e = c->rp[a]; e < c->rp[a + 1]; ++e) {
+        uint32_t x = c->col[e];
+        if (!step_ok(c, img, j, x)) continue;
+        img[j] = x;
+        extend_list(t, img, j + 1);
+    }
+}
+
+/* Every match (injective map preserving edges, anti-edges and labels) of
+ * the pattern; the first min(count, cap) are written to out.  Single
+ * threaded, for small graphs. */
+int or_list_maps(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* lab, int k,
+                 const int* order, uint32_t emask, uint32_t amask, const int* plab, uint64_t cap,
+                 uint32_t* out, uint64_t* count) {
+    listctx t;
+    int rc = setup_ctx(&t.c, n, rp, col, lab, k, order, emask, amask, plab);
+    if (rc) return rc;
+    t.out = out;
+    t.cap = cap;
+    t.count = 0;
+    uint32_t img[8];
+    for (uint32_t r = 0; r < n; ++r) {
+        if (!step_ok(&t.c, img, 0, r)) continue;
+        img[0] = r;
+        extend_list(&t, img, 1);
+    }
+    *count = t.count;
     return 0;
 }

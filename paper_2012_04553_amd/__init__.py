@@ -18,4 +18,5 @@ from .binding import (  # noqa: F401
     fsm_num_slots,
     fsm_slot,
     morph_plan,
+    morph_plan_costs,
 )

@@ -48,6 +48,10 @@ class pm_query_stats(ctypes.Structure):
                 ("launches", ctypes.c_uint32)]
 
 
+class pm_launch_stat(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 32), ("alg_bytes", ctypes.c_uint64), ("ms", ctypes.c_double)]
+
+
 SERVE_MAX_PATTERNS = 8
 
 
@@ -97,10 +101,18 @@ SIGNATURES = {
     "pm_wait": (ctypes.c_int32, [_P, ctypes.c_uint64, _i64p, ctypes.c_int64]),
     "pm_last_query_stats": (ctypes.c_int32, [_P, ctypes.POINTER(pm_query_stats)]),
     "pm_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
+    "pm_last_launch_stats": (ctypes.c_int32, [_P, ctypes.POINTER(pm_launch_stat), ctypes.c_uint32,
+                                              ctypes.POINTER(ctypes.c_uint32)]),
     "pm_morph_plan": (ctypes.c_int32, [_patp, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32,
                                        _patp, _u32p, _i64p]),
+    "pm_morph_plan_costs": (ctypes.c_int32, [_patp, ctypes.c_uint32, _patp, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.c_uint32, _patp, _u32p, _i64p]),
     "pm_fsm": (ctypes.c_int32, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                 ctypes.c_int32, _i64p, _u8p, ctypes.c_uint64]),
+    "pm_fsm_levelwise": (ctypes.c_int32, [_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_int64, ctypes.c_int32, _patp, _i64p, ctypes.c_uint64,
+                                          _u64p]),
+    "pm_list": (ctypes.c_int32, [_P, ctypes.c_uint32, _patp, ctypes.c_int32, _u32p, ctypes.c_uint64, _u64p]),
     "pm_fsm_num_slots": (ctypes.c_uint64, [ctypes.c_uint32]),
     "pm_fsm_slot": (ctypes.c_int32, [ctypes.c_uint32, ctypes.c_uint64, _patp]),
     "pm_set_option": (ctypes.c_int32, [_P, ctypes.c_char_p, ctypes.c_int64]),
@@ -175,13 +187,30 @@ def fsm_num_slots(num_labels: int) -> int:
     return int(lib().pm_fsm_num_slots(num_labels))
 
 
-def morph_plan(pats, morph: int = MORPH_NAIVE):
+def morph_plan(pats, morph: int = MORPH_NAIVE, agg: int = AGG_COUNT):
     """Host-only: alternative pattern set and conversion matrix."""
     arr = pattern_array(pats)
-    cap = ctypes.c_uint32(256)
-    alt = (pm_pattern * 256)()
-    mat = (ctypes.c_int64 * (len(pats) * 256))()
-    check(lib().pm_morph_plan(arr, len(pats), AGG_COUNT, morph, alt, ctypes.byref(cap), mat))
+    cap = ctypes.c_uint32(1024)
+    alt = (pm_pattern * 1024)()
+    mat = (ctypes.c_int64 * (len(pats) * 1024))()
+    check(lib().pm_morph_plan(arr, len(pats), agg, morph, alt, ctypes.byref(cap), mat))
+    na = cap.value
+    alts = [(alt[j].k, alt[j].edge_mask, alt[j].induce == VERTEX_INDUCED,
+             [alt[j].label[i] for i in range(alt[j].k)]) for j in range(na)]
+    matrix = np.array([mat[i] for i in range(len(pats) * na)], dtype=np.int64).reshape(len(pats), na)
+    return alts, matrix
+
+
+def morph_plan_costs(pats, cost_pats, costs):
+    """Host-only cost-based morph planning with caller-given costs: the
+    cheapest mixed (vertex-/edge-induced) alternative set and its matrix."""
+    arr = pattern_array(pats)
+    carr = pattern_array(cost_pats)
+    cst = (ctypes.c_double * max(1, len(costs)))(*[float(c) for c in costs])
+    cap = ctypes.c_uint32(1024)
+    alt = (pm_pattern * 1024)()
+    mat = (ctypes.c_int64 * (len(pats) * 1024))()
+    check(lib().pm_morph_plan_costs(arr, len(pats), carr, cst, len(costs), alt, ctypes.byref(cap), mat))
     na = cap.value
     alts = [(alt[j].k, alt[j].edge_mask, alt[j].induce == VERTEX_INDUCED,
              [alt[j].label[i] for i in range(alt[j].k)]) for j in range(na)]
@@ -261,6 +290,42 @@ class Engine:
     def count(self, gid, pats, morph=MORPH_NAIVE) -> list[int]:
         return self.wait(self.submit(gid, pats, morph), len(pats))
 
+    def mni(self, gid, pats, morph=MORPH_NONE) -> list[int]:
+        """MNI support of every pattern (pm_submit with PM_AGG_MNI)."""
+        return self.wait(self.submit(gid, pats, morph, agg=AGG_MNI), len(pats))
+
+    def fsm_levelwise(self, gid, num_labels: int, max_edges: int, threshold: int, morph=MORPH_NONE):
+        """Frequent labeled patterns with 1..max_edges edges: [(k, mask, labels, support)]."""
+        cnt = ctypes.c_uint64()
+        n = 4096
+        while True:
+            pats = (pm_pattern * n)()
+            sup = (ctypes.c_int64 * n)()
+            st = lib().pm_fsm_levelwise(self.ctx, gid, num_labels, max_edges, threshold, morph, pats, sup,
+                                        n, ctypes.byref(cnt))
+            if st == PM_OK or cnt.value <= n:
+                check(st)
+                break
+            n = cnt.value     # capacity was short: run again with room for all
+        return [(pats[i].k, pats[i].edge_mask, [pats[i].label[j] for j in range(pats[i].k)], int(sup[i]))
+                for i in range(cnt.value)]
+
+    def list(self, gid, pat, morph=MORPH_NONE, capacity=None):
+        """Distinct matched subgraphs of one pattern (pm_list): (rows of k
+        vertex ids, total number).  Without `capacity` every row is returned."""
+        arr = pattern_array([pat])
+        k = arr[0].k
+        cnt = ctypes.c_uint64()
+        cap = capacity if capacity is not None else 1 << 16
+        while True:
+            out = np.zeros(max(cap, 1) * k, dtype=np.uint32)
+            check(lib().pm_list(self.ctx, gid, arr, morph, out.ctypes.data_as(_u32p), cap, ctypes.byref(cnt)))
+            if capacity is not None or cnt.value <= cap:
+                break
+            cap = cnt.value
+        got = min(cnt.value, cap)
+        return out[: got * k].reshape(got, k), int(cnt.value)
+
     def count_noalloc(self, gid, pats, morph=MORPH_NAIVE) -> list[int]:
         """pm_count_noalloc: the same counts without allocating device memory."""
         arr = pattern_array(pats)
@@ -272,6 +337,14 @@ class Engine:
         s = pm_query_stats()
         check(lib().pm_last_query_stats(self.ctx, ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in pm_query_stats._fields_}
+
+    def launch_stats(self) -> list[dict]:
+        """Per-launch kernel name, algorithmic bytes and device ms of the last query."""
+        n = ctypes.c_uint32()
+        arr = (pm_launch_stat * 64)()
+        check(lib().pm_last_launch_stats(self.ctx, arr, 64, ctypes.byref(n)))
+        return [{"kernel": arr[i].kernel.decode(), "alg_bytes": int(arr[i].alg_bytes), "ms": arr[i].ms}
+                for i in range(n.value)]
 
     def autotune(self, gid, pats, morph=MORPH_NAIVE):
         arr = pattern_array(pats)

@@ -130,8 +130,185 @@ static std::vector<Pat> superpatterns(const Pat& p) {
     return out;
 }
 
+// Cost-based alternative sets (Section 4.1's optimizer, Table 4's mixed
+// sets).  Over the up-closed set U of the queries' same-size superpatterns,
+// each pattern u is matched vertex-induced (V), edge-induced (E) or not at
+// all.  N_V(u) is known when u is matched V, or matched E and every strict
+// superpattern's N_V is known (Corollary 3.1 from the top).  A
+// vertex-induced query needs its N_V known; an edge-induced query is matched
+// E or needs N_V known for itself and every strict superpattern (Theorem
+// 3.1).  The cheapest assignment is searched exhaustively when U has at
+// most MIX_EXHAUSTIVE patterns; otherwise the cheaper of "every query as
+// given" and "every pattern of U by its cheaper form" is taken (for motif
+// counting, where every pattern is a query, the latter is optimal).
+static constexpr size_t MIX_EXHAUSTIVE = 9;
+
+int morph_plan_mixed(const std::vector<Pat>& qs, const std::function<double(const Pat&)>& cost, MorphPlan* out,
+                     std::string* err) {
+    out->alt.clear();
+    out->matrix.clear();
+    // U: edge-induced canonical forms, most edges first
+    std::vector<Pat> U;
+    std::vector<Pat> qc(qs.size());
+    auto index_of = [&](const Pat& e) -> int {
+        for (size_t i = 0; i < U.size(); ++i)
+            if (U[i] == e) return (int)i;
+        return -1;
+    };
+    for (size_t i = 0; i < qs.size(); ++i) {
+        qc[i] = canonical(qs[i]);
+        for (const Pat& q : superpatterns(qc[i]))
+            if (index_of(q) < 0) U.push_back(q);
+    }
+    std::sort(U.begin(), U.end(), [](const Pat& a, const Pat& b) {
+        int ea = popc(a.em), eb = popc(b.em);
+        if (ea != eb) return ea > eb;
+        return pat_less(a, b);
+    });
+    const size_t nu = U.size();
+    // sup[u][w]: c(u, w) for every superpattern w of u (w != u), 0 otherwise
+    std::vector<std::vector<int64_t>> c(nu, std::vector<int64_t>(nu, 0));
+    for (size_t u = 0; u < nu; ++u)
+        for (const Pat& w : superpatterns(U[u])) {
+            int j = index_of(w);
+            if (j >= 0 && (size_t)j != u) c[u][j] = coef(U[u], w);
+        }
+    std::vector<double> cV(nu), cE(nu);
+    std::vector<bool> clique(nu);
+    for (size_t u = 0; u < nu; ++u) {
+        clique[u] = U[u].em == full_mask(U[u].k);
+        Pat v = U[u];
+        v.vi = !clique[u];
+        cV[u] = cost(v);
+        cE[u] = clique[u] ? cV[u] : cost(U[u]);
+    }
+    struct Q {
+        int u;
+        bool vi;
+    };
+    std::vector<Q> qv(qs.size());
+    for (size_t i = 0; i < qs.size(); ++i) {
+        Pat e = qc[i];
+        e.vi = false;
+        qv[i] = {index_of(e), qc[i].vi && qc[i].em != full_mask(qc[i].k)};
+    }
+    // d[u]: 0 none, 1 V, 2 E (cliques: 0 or 2)
+    auto known = [&](const std::vector<int>& d, std::vector<bool>* K) {
+        K->assign(nu, false);
+        for (size_t u = 0; u < nu; ++u) {   // most edges first: supersets decided
+            if (d[u] == 1) {
+                (*K)[u] = true;
+            } else if (d[u] == 2) {
+                bool all = true;
+                for (size_t w = 0; w < nu && all; ++w)
+                    if (c[u][w] && !(*K)[w]) all = false;
+                (*K)[u] = all;
+            }
+        }
+    };
+    auto feasible = [&](const std::vector<int>& d, const std::vector<bool>& K) {
+        for (const Q& q : qv) {
+            if (q.vi) {
+                if (!K[q.u]) return false;
+            } else if (d[q.u] != 2) {
+                if (!K[q.u]) return false;
+                for (size_t w = 0; w < nu; ++w)
+                    if (c[q.u][w] && !K[w]) return false;
+            }
+        }
+        return true;
+    };
+    auto total = [&](const std::vector<int>& d) {
+        double t = 0;
+        for (size_t u = 0; u < nu; ++u) t += d[u] == 1 ? cV[u] : (d[u] == 2 ? cE[u] : 0.0);
+        return t;
+    };
+    std::vector<int> best;
+    double best_cost = 0;
+    std::vector<bool> K;
+    if (nu <= MIX_EXHAUSTIVE) {
+        std::vector<int> d(nu, 0);
+        uint64_t combos = 1;
+        for (size_t u = 0; u < nu; ++u) combos *= 3;
+        for (uint64_t x = 0; x < combos; ++x) {
+            uint64_t y = x;
+            bool skip = false;
+            for (size_t u = 0; u < nu; ++u) {
+                d[u] = (int)(y % 3);
+                y /= 3;
+                if (clique[u] && d[u] == 1) skip = true;
+            }
+            if (skip) continue;
+            known(d, &K);
+            if (!feasible(d, K)) continue;
+            const double t = total(d);
+            if (best.empty() || t < best_cost) {
+                best = d;
+                best_cost = t;
+            }
+        }
+    } else {
+        std::vector<int> a(nu, 0), b(nu, 0);
+        for (const Q& q : qv) a[q.u] = (q.vi ? 1 : 2);
+        for (size_t u = 0; u < nu; ++u) b[u] = clique[u] ? 2 : (cV[u] < cE[u] ? 1 : 2);
+        known(a, &K);
+        const bool fa = feasible(a, K);
+        best = b;
+        best_cost = total(b);
+        if (fa && total(a) <= best_cost) best = a;
+    }
+    if (best.empty()) {
+        *err = "internal: no feasible alternative set";
+        return PM_E_INVAL;
+    }
+    known(best, &K);
+    // alternatives and integer rows (symbolic Corollary 3.1 from the top)
+    std::vector<int> alt_of(nu, -1);
+    for (size_t u = 0; u < nu; ++u)
+        if (best[u]) {
+            Pat a = U[u];
+            a.vi = best[u] == 1;
+            alt_of[u] = (int)out->alt.size();
+            out->alt.push_back(a);
+        }
+    const size_t na = out->alt.size();
+    std::vector<std::vector<__int128>> NV(nu, std::vector<__int128>(na, 0));
+    for (size_t u = 0; u < nu; ++u) {
+        if (!K[u]) continue;
+        NV[u][alt_of[u]] = 1;
+        if (best[u] == 2)
+            for (size_t w = 0; w < nu; ++w)
+                if (c[u][w])
+                    for (size_t j = 0; j < na; ++j) NV[u][j] -= (__int128)c[u][w] * NV[w][j];
+    }
+    out->matrix.assign(qs.size() * na, 0);
+    for (size_t i = 0; i < qs.size(); ++i) {
+        const Q& q = qv[i];
+        std::vector<__int128> row(na, 0);
+        if (q.vi) {
+            row = NV[q.u];
+        } else if (best[q.u] == 2) {
+            row[alt_of[q.u]] = 1;
+        } else {
+            row = NV[q.u];
+            for (size_t w = 0; w < nu; ++w)
+                if (c[q.u][w])
+                    for (size_t j = 0; j < na; ++j) row[j] += (__int128)c[q.u][w] * NV[w][j];
+        }
+        for (size_t j = 0; j < na; ++j) {
+            if (row[j] > INT64_MAX || row[j] < INT64_MIN) {
+                *err = "morph coefficient outside int64";
+                return PM_E_OVERFLOW;
+            }
+            out->matrix[i * na + j] = (int64_t)row[j];
+        }
+    }
+    return PM_OK;
+}
+
 int morph_plan_count(const std::vector<Pat>& qs, int morph, MorphPlan* out, std::string* err,
                      const std::function<double(const Pat&)>& cost) {
+    if (morph == PM_MORPH_COST && cost) return morph_plan_mixed(qs, cost, out, err);
     out->alt.clear();
     out->matrix.clear();
     std::vector<std::vector<std::pair<Pat, int64_t>>> rows(qs.size());
@@ -144,17 +321,6 @@ int morph_plan_count(const std::vector<Pat>& qs, int morph, MorphPlan* out, std:
         }
         // lattice over the edge-induced superpatterns, most edges first
         std::vector<Pat> L = superpatterns(p);
-        if (morph == PM_MORPH_COST) {
-            // Section 4.1 cost-based choice: morph only when matching the
-            // edge-induced superpatterns is estimated cheaper than matching
-            // the vertex-induced pattern itself
-            double plain = cost ? cost(p) : 0.0, morphed = 0.0;
-            for (const Pat& q : L) morphed += cost ? cost(q) : 0.0;
-            if (cost && plain <= morphed) {
-                rows[i].push_back({p, 1});
-                continue;
-            }
-        }
         std::sort(L.begin(), L.end(), [](const Pat& a, const Pat& b) {
             int ea = popc(a.em), eb = popc(b.em);
             if (ea != eb) return ea > eb;

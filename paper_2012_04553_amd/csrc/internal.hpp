@@ -56,6 +56,10 @@ struct MorphPlan {
 };
 int morph_plan_count(const std::vector<Pat>& q, int morph, MorphPlan* out, std::string* err,
                      const std::function<double(const Pat&)>& cost = nullptr);
+// Cost-based alternative set with vertex- and edge-induced alternatives
+// mixed (cost of a pattern as matched: p.vi says how)
+int morph_plan_mixed(const std::vector<Pat>& qs, const std::function<double(const Pat&)>& cost, MorphPlan* out,
+                     std::string* err);
 // combine alternative counts: out[i] = sum_j matrix[i][j]*alt[j]; checked int64
 int unmorph(const MorphPlan& mp, size_t npat, const std::vector<int64_t>& alt_counts,
             std::vector<int64_t>* out, std::string* err);
@@ -101,6 +105,8 @@ struct DPlan {
                          //    of the root's out-neighbourhood
     int32_t bm0;         // 1: membership tests against N(v0) use a per-wave
                          //    bitmap of the root's adjacency list
+    int32_t cyc5;        // 1: the edge-induced 5-cycle's pair sum, run by
+                         //    cycle5_kernel (no levels or terms of its own)
     DLevel lev[KMAX];
     DTerm term[MAX_TERMS];
     DMono mono[MAX_MONO];
@@ -246,6 +252,9 @@ struct PlanInfo {
     bool rewrite = false;
     int64_t hmult = 1, autp = 1;
     std::vector<std::pair<Pat, int64_t>> subs;
+    // 5-cycle: count = pair sum of cycle5_kernel - the total of the
+    // companion triangle plan (the one entry of subs, a marker pattern)
+    bool cyc5 = false;
     std::string describe() const;
 };
 
@@ -262,6 +271,21 @@ struct GraphStats {             // degree statistics used by the cost model
 };
 
 int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err);
+// The companion of the 5-cycle plan: a marker pattern (labels -2, never a
+// query) whose plan sums, over the triangles {u < v < w}, the neighbours of
+// u, v and w below u.
+Pat cycle5_aux_pattern();
+inline bool is_cycle5(const Pat& p) {
+    if (p.k != 5 || p.vi || popc(p.em) != 5) return false;
+    for (int v = 0; v < 5; ++v) {
+        if (p.lab[v] != -1) return false;
+        int d = 0;
+        for (int w = 0; w < 5; ++w)
+            if (w != v && has_edge(p.em, v, w)) ++d;
+        if (d != 2) return false;
+    }
+    return is_connected(5, p.em);
+}
 // all candidate plans (for tests / autotuning)
 int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* out, std::string* err);
 

@@ -293,7 +293,70 @@ __device__ __forceinline__ void fetch_probe(const Probe& pr, int o, uint8_t list
 
 // ---------------------------------------------------------------- wave-cooperative level
 
+// Label and injectivity of a candidate already known to lie in every list.
+__device__ __forceinline__ bool merge_ok(const Ctx& c, const uint32_t* vv, const Probe& pr, uint32_t x) {
+    if (pr.label >= 0 && c.g.lab[x] != (uint8_t)pr.label) return false;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+        if (((pr.neq >> i) & 1) && x == vv[i]) return false;
+    return true;
+}
+
+// Sorted intersection of two bounded lists of similar length by merge path:
+// the merged sequence of A and B (equal entries: A first) is cut into 64
+// stretches of equal length and lane l merges stretch l, its start found by
+// a binary search along its diagonal.  An entry of A is a match when the B
+// cursor stands on an equal entry as it is taken.  The lanes count their
+// matches, a wave prefix sum places them, and a second merge writes them,
+// so the output is sorted.  Every read stays inside A[0, la) and B[0, lb).
+__device__ uint32_t merge_level(const Ctx& c, const uint32_t* A, uint32_t la, const uint32_t* B, uint32_t lb,
+                                const Probe& pr, uint32_t* out) {
+    const uint32_t lane = (uint32_t)wave_lane();
+    const uint32_t total = la + lb;
+    const uint32_t len = (total + 63) / 64;
+    const uint32_t d0 = min(total, lane * len), d1 = min(total, d0 + len);
+    uint32_t lo = d0 > lb ? d0 - lb : 0, hi = min(d0, la);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A[mid] <= B[d0 - mid - 1]) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t i0 = lo, j0 = d0 - lo;
+    uint32_t cnt = 0;
+    {
+        uint32_t i = i0, jb = j0;
+        for (uint32_t st = d0; st < d1; ++st) {
+            if (i < la && (jb >= lb || A[i] <= B[jb])) {
+                const uint32_t x = A[i];
+                if (jb < lb && B[jb] == x && merge_ok(c, c.v, pr, x)) ++cnt;
+                ++i;
+            } else {
+                ++jb;
+            }
+        }
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t tot = __shfl(incl, 63);
+    if (cnt) {
+        uint32_t o = incl - cnt;
+        uint32_t i = i0, jb = j0;
+        for (uint32_t st = d0; st < d1; ++st) {
+            if (i < la && (jb >= lb || A[i] <= B[jb])) {
+                const uint32_t x = A[i];
+                if (jb < lb && B[jb] == x && merge_ok(c, c.v, pr, x)) out[o++] = x;
+                ++i;
+            } else {
+                ++jb;
+            }
+        }
+    }
+    return tot;
+}
+
 // Materialise the candidates of core level j (wave-uniform prefix c.v).
+// Two adjacency lists of similar length (the driver and one probe list, no
+// anti-edge) are intersected by merge path; otherwise the lanes stream the
+// driver and test each entry against the probe lists by binary search.
 template <bool BYTES>
 __device__ uint32_t wave_level(Ctx& c, int j) {
     const DLevel L = c.P->lev[j];
@@ -323,6 +386,16 @@ __device__ uint32_t wave_level(Ctx& c, int j) {
     uint64_t pbytes = make_probe<BYTES>(c, c.v, chk, anti, L.neq, L.label, lo, hi, pr);
     if (BYTES && lane == 0) c.bytes += pbytes + 4ull * (e - b);
     uint32_t total = 0;
+    if (L.base == 0xff && !anti && !pr.bm && chk && !(chk & (chk - 1))) {
+        const int pi = __builtin_ctz((uint32_t)chk);
+        const uint32_t la = e - b, lb = pr.pe[pi] - pr.pb[pi];
+        if (la + lb >= 256 && lb <= 4 * la) {
+            total = merge_level(c, drv + b, la, c.g.col + pr.pb[pi], lb, pr, out);
+            __threadfence_block();
+            __builtin_amdgcn_wave_barrier();
+            return total;
+        }
+    }
     for (uint32_t base = b; base < e; base += 64) {
         uint32_t idx = base + lane;
         bool ok = idx < e;
@@ -874,6 +947,160 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     if (cur >= 0) flush(a, cur, acc);
     if (BYTES) {
         unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
+// ---------------------------------------------------------------- edge-induced 5-cycles
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// A counter the wave's atomics (performed in the L2) have updated: read at
+// agent scope, past the compute unit's L1, which may still hold the line
+// from an earlier root.
+__device__ __forceinline__ uint32_t wave_peek(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every 5-cycle once, at its lowest vertex a (degree-order ids).  For the
+// targets t > a, A(t) counts the out-neighbours b of a (b > a) adjacent to
+// t, filled in the wave's dense counter array by streaming N(b) above a for
+// every out-neighbour b, flattened over the lanes; bit 31 of a counter marks
+// t as an out-neighbour of a itself, f(t).  A cycle a-b-x-y-e-a with x < y
+// is one edge {x, y} opposite a (y in N+(x): the short out-list) and one
+// pair of bridges b in N(a) n N(x), e in N(a) n N(y), both above a, with
+// b != y, e != x and b != e.  The wave sums, over the touched x and every y
+// in N+(x), (A(x) - f(y)) (A(y) - f(x)): the corrections remove b = y and
+// e = x (y is a bridge of x exactly when f(y)); b = e is left in, and its
+// total is subtracted on the host (the companion triangle plan).  A target
+// with A = 0 contributes nothing: f(y) = 1 would make y a bridge of x.
+template <bool BYTES>
+__global__ void __launch_bounds__(256) cycle5_kernel(KArgs a) {
+    __shared__ uint32_t s_touch[4];
+    constexpr uint32_t FLAG = 0x80000000u;
+    const int lane = wave_lane();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    uint32_t* my_touch = &s_touch[threadIdx.x >> 6];
+    uint32_t* cnt = a.aggcnt + (uint64_t)wid * a.g.n;
+    uint32_t* touched = a.aggtouch + (uint64_t)wid * a.g.n;
+    const KGraph& g = a.g;
+    u128 acc = 0;
+    uint64_t bytes = 0;
+    int cur = -1;
+    uint32_t tick = 0;
+    bool stopped = false;
+    const uint64_t total = (uint64_t)a.nplans * a.nitems;
+    for (;;) {
+        if (stopped) break;
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(a.head, 1u);
+        it = bcast(it);
+        if (it >= total) break;
+        if (a.cancel) {
+            uint32_t stop = 0;
+            if (lane == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
+            if (bcast(stop)) break;
+        }
+        const int pi = (int)(it / a.nitems);
+        const KItem item = a.items[it % a.nitems];
+        if (pi != cur) {
+            if (cur >= 0) flush(a, cur, acc);
+            acc = 0;
+            cur = pi;
+        }
+        // a hub's level-1 slices: the first slice takes the whole root
+        if (item.s0 != 0) continue;
+        for (uint32_t r = item.r0; r < item.r1; ++r) {
+            if (should_stop(a, tick)) {
+                stopped = true;
+                break;
+            }
+            // a root with one out-neighbour has no 5-cycle, but its pairs with
+            // both bridges equal enter the companion plan's total: keep it
+            const uint32_t bb = g.split[r], be = g.rp[r + 1];
+            if (be == bb) continue;
+            if (BYTES && lane == 0) bytes += 8 + 4ull * (be - bb);
+            if (lane == 0) *my_touch = 0;
+            __builtin_amdgcn_wave_barrier();
+            // fill: the targets above r of every out-neighbour
+            for (uint32_t base = bb; base < be; base += 64) {
+                const uint32_t k = base + lane;
+                uint32_t yb = 0, yf = 0;
+                if (k < be) {
+                    list_range(g, g.col[k], r + 1, NOB, yb, yf);
+                    if (BYTES) bytes += 8 + 4ull * (yf - yb);
+                }
+                const uint32_t len = yf - yb;
+                const uint32_t incl = wave_incl_scan(len);
+                const uint32_t tot = __shfl(incl, 63);
+                const uint32_t excl = incl - len;
+                for (uint32_t tb = 0; tb < tot; tb += 64) {
+                    const uint32_t t = tb + lane;
+                    const bool act = t < tot;
+                    const int o = owner_of(incl, act ? t : tot - 1);
+                    const uint32_t src = __shfl(yb, o) + (t - __shfl(excl, o));
+                    if (!act) continue;
+                    const uint32_t x = g.col[src];
+                    if (wave_add(&cnt[x]) == 0u) touched[atomicAdd(my_touch, 1u)] = x;
+                }
+            }
+            __threadfence_block();
+            __builtin_amdgcn_wave_barrier();
+            // mark the out-neighbours themselves
+            for (uint32_t k = bb + lane; k < be; k += 64) {
+                const uint32_t y = g.col[k];
+                if (wave_or(&cnt[y], FLAG) == 0u) touched[atomicAdd(my_touch, 1u)] = y;
+            }
+            __threadfence_block();
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t nt = bcast(*(volatile uint32_t*)my_touch);
+            // pairs: every touched x with A(x) > 0, every y in N+(x)
+            for (uint32_t base = 0; base < nt; base += 64) {
+                const uint32_t idx = base + lane;
+                uint32_t ax = 0, fx = 0, pb = 0, pe = 0;
+                if (idx < nt) {
+                    const uint32_t x = touched[idx];
+                    const uint32_t v = wave_peek(&cnt[x]);
+                    ax = v & ~FLAG;
+                    fx = v >> 31;
+                    if (ax) {
+                        pb = g.split[x];
+                        pe = g.rp[x + 1];
+                        if (BYTES) bytes += 8 + 8ull * (pe - pb);
+                    }
+                }
+                const uint32_t len = pe - pb;
+                const uint32_t incl = wave_incl_scan(len);
+                const uint32_t tot = __shfl(incl, 63);
+                const uint32_t excl = incl - len;
+                for (uint32_t tb = 0; tb < tot; tb += 64) {
+                    const uint32_t t = tb + lane;
+                    const bool act = t < tot;
+                    const int o = owner_of(incl, act ? t : tot - 1);
+                    const uint32_t src = __shfl(pb, o) + (t - __shfl(excl, o));
+                    const uint32_t oax = __shfl(ax, o), ofx = __shfl(fx, o);
+                    if (!act) continue;
+                    const uint32_t v = wave_peek(&cnt[g.col[src]]);
+                    const uint32_t ay = v & ~FLAG;
+                    if (ay) {
+                        const int64_t p = ((int64_t)oax - (int64_t)(v >> 31)) * ((int64_t)ay - (int64_t)ofx);
+                        acc += (u128)(i128)p;
+                    }
+                }
+            }
+            __threadfence_block();
+            __builtin_amdgcn_wave_barrier();
+            // every counter back to zero
+            for (uint32_t i = lane; i < nt; i += 64) wave_take(&cnt[touched[i]]);
+            __threadfence_block();
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (cur >= 0) flush(a, cur, acc);
+    if (BYTES) {
+        unsigned long long bsum = bytes;
         for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
         if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
     }
@@ -1881,6 +2108,14 @@ int launch_clique4(const KArgs& a, int grid, int mode, bool count_bytes, hipStre
         if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((clique4_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_cycle5(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes)
+        hipLaunchKernelGGL(cycle5_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(cycle5_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -64,6 +64,9 @@ int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // (mode 1: up to C4_HEAVY_MAX, mode 2: up to C4_ROOT_MAX) per root of the
 // items {r0, r1, 0, 0}.
 int launch_clique4(const KArgs& a, int grid, int mode, bool count_bytes, hipStream_t s);
+// Edge-induced 5-cycle pair sums (plans with cyc5) over the root items,
+// one wavefront per root with its dense counter array (aggcnt/aggtouch).
+int launch_cycle5(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Clears `words` 32-bit words (used instead of memset nodes inside graphs).
 int launch_zero(uint32_t* p, uint64_t words, hipStream_t s);
 

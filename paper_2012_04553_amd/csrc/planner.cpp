@@ -719,6 +719,7 @@ std::string PlanInfo::describe() const {
         snprintf(buf, sizeof(buf), ")/%lld", (long long)autp);
         s += buf;
     }
+    if (cyc5) s += " | cycle5 pair sum minus the companion triangle plan";
     if (d.lane_par) s += " lane_par";
     if (d.local) s += " local_bitmap";
     if (d.bm0) s += " root_bitmap";
@@ -778,7 +779,97 @@ int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* o
     return PM_OK;
 }
 
+Pat cycle5_aux_pattern() {
+    Pat a;
+    a.k = 3;
+    a.em = 0x7;
+    a.vi = false;
+    for (int i = 0; i < 3; ++i) a.lab[i] = -2;
+    return a;
+}
+
+// Edge-induced, unlabeled 5-cycle: every cycle once, at its lowest vertex a
+// (degree-order ids), as the sum over the edges {x < y} opposite a of
+// (A(x) - [y in N+(a)]) (A(y) - [x in N+(a)]), where A(t) counts the
+// out-neighbours of a adjacent to t > a (cycle5_kernel), minus the choices
+// with both bridges equal: one out-neighbour b of a closing a triangle
+// {b, x, y} above a.  Summed over a, those are, for every triangle
+// {u < v < w}, the neighbours of u, v and w below u: the companion plan, a
+// triangle core v0 < v1 < v2 with the cheap terms |N(v_i) n [0, v0)|.
+static void cycle5_plans(const GraphStats& gs, PlanInfo* pc, PlanInfo* aux) {
+    DPlan d;
+    memset(&d, 0, sizeof(d));
+    d.ncore = 1;
+    d.mult = 1;
+    d.cyc5 = 1;
+    d.bridge_src = 0xff;
+    d.lev[0].base = 0xff;
+    d.lev[0].label = -1;
+    pc->d = d;
+    pc->divisor = 1;
+    pc->cyc5 = true;
+    pc->formulation = 0;
+    for (int j = 0; j < KMAX; ++j) pc->order[j] = j < 1 ? 0 : -1;
+    // cost: the fill streams N(b) above a for every out-neighbour b of a
+    // (about sum_b d(b) d-(b)), the scan reads N+(x) for every target
+    pc->est_cost = gs.s_pd + gs.s_qd * std::max(gs.avg_out, 1.0);
+    pc->total_cost = pc->est_cost;
+    pc->subs.clear();
+    pc->subs.push_back({cycle5_aux_pattern(), 1});
+
+    DPlan t;
+    memset(&t, 0, sizeof(t));
+    t.ncore = 3;
+    t.mult = 1;
+    t.bridge_src = 0xff;
+    for (int j = 0; j < 3; ++j) {
+        t.lev[j].base = 0xff;
+        t.lev[j].label = -1;
+    }
+    t.lev[1].adj = 1;
+    t.lev[1].gt = 1;
+    t.lev[2].adj = 3;
+    t.lev[2].gt = 3;
+    t.lev[2].base = 1;
+    t.nterm = 3;
+    for (int q = 0; q < 3; ++q) {
+        DTerm& m = t.term[q];
+        m.adj = (uint8_t)(1u << q);
+        m.lt = 1;
+        m.label = -1;
+        m.cheap = 1;
+        m.neq = (uint8_t)(7u & ~(m.adj | m.lt));
+        for (int i = 0; i < 3; ++i)
+            if ((m.neq >> i) & 1) m.sure |= (uint8_t)(1u << i);
+    }
+    t.nmono = 3;
+    for (int q = 0; q < 3; ++q) {
+        t.mono[q].coef = 1;
+        t.mono[q].nf = 1;
+        t.mono[q].f[0] = (uint8_t)q;
+    }
+    t.lane_par = 1;
+    aux->d = t;
+    aux->pat = cycle5_aux_pattern();
+    aux->divisor = 1;
+    aux->formulation = 0;
+    for (int j = 0; j < KMAX; ++j) aux->order[j] = j < 3 ? (int8_t)j : -1;
+    aux->est_cost = gs.s_pp + gs.m;
+    aux->total_cost = aux->est_cost;
+}
+
 int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err) {
+    if (p.k == 3 && p.lab[0] == -2) {
+        PlanInfo pc;
+        cycle5_plans(gs, &pc, out);
+        return PM_OK;
+    }
+    if (is_cycle5(p)) {
+        PlanInfo aux;
+        cycle5_plans(gs, out, &aux);
+        out->pat = p;
+        return PM_OK;
+    }
     std::vector<PlanInfo> all;
     int rc = candidate_plans(p, gs, &all, err);
     if (rc) return rc;

@@ -279,6 +279,7 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
         }
     }
     auto G = std::make_unique<GraphRes>();
+    G->orig_id = order;
     G->n = n;
     G->m = nnz / 2;
     G->labeled = labels != nullptr;
@@ -398,6 +399,7 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
         std::vector<uint32_t> cnt(257, 0);
         for (uint32_t r = 0; r < n; ++r) cnt[nlab[r] + 1]++;
         for (int l = 0; l < 256; ++l) cnt[l + 1] += cnt[l];
+        G->label_begin.assign(cnt.begin(), cnt.end());
         G->label_order.resize(n);
         for (uint32_t r = 0; r < n; ++r) G->label_order[cnt[nlab[r]]++] = r;
     }
@@ -414,7 +416,8 @@ int Ctx_::graph_unload(uint32_t gid) {
     if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
     if (it->second->inflight) return fail(PM_E_BUSY, "queries in flight on this graph");
     GraphRes& G = *it->second;
-    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items, G.off_support, G.off_cq})
+    for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items, G.off_support, G.off_cq,
+                       G.off_lorder})
         if (o < UINT64_MAX - 1) arena.release(o);
     for (auto& is : G.itemsets) arena.release(is.second.off);
     for (auto& ls : G.launches) free_launchset(ls.second.get());
@@ -502,6 +505,7 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     // each group can run in launches of its own
     auto group = [&](size_t a) {
         const DPlan& d = pl[a].d;
+        if (d.cyc5) return 5;
         return d.agg_last ? 4
                           : (clique_ok(d) ? 1 : (clique4_ok(d) ? 2 : (edge_window_ok(d) || edge_cheap_ok(d) ? 3 : 0)));
     };
@@ -661,7 +665,7 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
             bool out_list = (L.adj & L.gt) != 0;
             stride = std::max<uint64_t>(stride, (out_list ? G.max_out : G.max_deg) + 64);
         }
-        if (p.d.agg_last) agg = true;
+        if (p.d.agg_last || p.d.cyc5) agg = true;
         if (p.d.local) {
             // bitmap rows: max_out rows of ceil(max_out/64) 64-bit words
             uint64_t words = (uint64_t)G.max_out * ((G.max_out + 63) / 64);
@@ -708,13 +712,35 @@ uint64_t Ctx_::bitmap_words(const GraphRes& G, const std::vector<PlanInfo>& plan
     return ((G.n + 31) / 32 + 63) & ~uint64_t(63);
 }
 
+// Whether a launch set in flight (cached and busy, or a query's own) points
+// to the context's two-hop arrays.
+bool Ctx_::ctx_agg_busy() {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& gr : graphs)
+        for (auto& l : gr.second->launches)
+            if (l.second->busy && l.second->agg_gen) return true;
+    for (auto& q : queries)
+        if (q.second->own && q.second->own->agg_gen) return true;
+    return false;
+}
+
+void Ctx_::release_retired_agg() {
+    if (agg_retired.empty() || ctx_agg_busy()) return;
+    for (uint64_t off : agg_retired) arena.release(off);
+    agg_retired.clear();
+}
+
 int Ctx_::ensure_agg(uint32_t n, const LaunchCfg& cfg) {
     uint64_t w = agg_waves(cfg, n);
     if (agg_off != UINT64_MAX && agg_n >= n && agg_w >= w) return PM_OK;
     if (agg_off != UINT64_MAX) {
-        arena.release(agg_off);
-        arena.release(agg_touch_off);
+        // launch sets built on these arrays are rebuilt on their next use;
+        // the arrays go once no launch in flight reads them
+        agg_retired.push_back(agg_off);
+        agg_retired.push_back(agg_touch_off);
         agg_off = agg_touch_off = UINT64_MAX;
+        ++agg_gen;
+        release_retired_agg();
     }
     uint64_t need = w * (uint64_t)n * 4;
     agg_off = arena.alloc(need);
@@ -780,6 +806,7 @@ void Ctx_::free_launchset(LaunchSet* ls) {
     ls->graph = nullptr;
     ls->host = nullptr;
     ls->off_mem = UINT64_MAX;
+    ls->agg_gen = 0;
 }
 
 int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& cfg, LaunchSet* ls,
@@ -937,13 +964,13 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         HIPCHK(hipStreamSynchronize(st));
     }
     if (agg && agg->host) {
-        if (agg->host_words < 2 * np + 8) return fail(PM_E_NOMEM, "slot result buffer too small");
+        if (agg->host_words < 2 * np + 2 + MAX_RUNS) return fail(PM_E_NOMEM, "slot result buffer too small");
         ls->host = agg->host;
         ls->cancel_host = agg->cancel_host;
         ls->cancel_dev = agg->cancel_dev;
         ls->borrowed_host = true;
     } else {
-        HIPCHK(hipHostMalloc((void**)&ls->host, 16 * np + 64, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&ls->host, 16 * np + 8 * (2 + MAX_RUNS), hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&ls->cancel_host, 64, hipHostMallocMapped | hipHostMallocCoherent));
         HIPCHK(hipHostGetDevicePointer((void**)&ls->cancel_dev, ls->cancel_host, 0));
     }
@@ -974,6 +1001,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         } else {
             a.aggcnt = (uint32_t*)dptr(agg_off);
             a.aggtouch = (uint32_t*)dptr(agg_touch_off);
+            ls->agg_gen = agg_gen;
             ls->agg_w = agg_waves(cfg, G.n);
         }
     }
@@ -984,6 +1012,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     // edge-core plans (light roots, then heavy roots in LDS windows);
     // two-hop plans (light roots, then heavy roots)
     auto group = [&](int q) {
+        if (plans[q].d.cyc5) return 6;
         if (plans[q].d.agg_last) return 2;
         if (cq && clique_runs(G, plans[q].d)) return 3;
         if ((sup && support_ok(plans[q].d)) || (clique_opt && edge_cheap_ok(plans[q].d))) return 5;
@@ -1042,6 +1071,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                 ls->runs.push_back({i, j});
                 ls->run_agg.push_back(9);
             }
+        } else if (grp == 6) {
+            ls->runs.push_back({i, j});
+            ls->run_agg.push_back(12);
         } else if (grp == 1) {
             ls->runs.push_back({i, j});
             ls->run_agg.push_back(3);
@@ -1062,14 +1094,58 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     return PM_OK;
 }
 
+// The kernel a launch-set run uses (LaunchSet::run_agg codes).
+const char* run_kernel_name(int kind) {
+    switch (kind) {
+        case 2: return "agg_window_kernel";
+        case 4: return "edge_window_kernel";
+        case 5: return "clique_kernel";
+        case 7: case 8: case 11: return "clique4_kernel";
+        case 10: return "support_kernel";
+        case 12: return "cycle5_kernel";
+        default: return "match_kernel";
+    }
+}
+
 // [zero-fill -> match launches -> copy-back]; with bytes_pass the same
 // launches run in the byte-counting build and only the tally is copied
 // (host slot 2*np+1), outside any timed region.
-int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
+// Branch of a run when a captured launch set forks: 1 = triangle pass and
+// edge supports (in order: the supports read what the pass writes), 2 =
+// 4-cliques; 0 = the rest (general kernel and window kernels, which share
+// the per-wavefront level buffers and window scratch).
+static int run_branch(int kind) {
+    if (kind == 5 || kind == 10) return 1;
+    if (kind == 7 || kind == 8 || kind == 11) return 2;
+    return 0;
+}
+
+int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* run_ev, bool fork) {
     const LaunchCfg& cfg = ls.cfg;
-    if (launch_zero(ls.zero_base, ls.zero_words, s)) return fail(PM_E_DEVICE, "zero-fill launch failed");
+    if (ls.runs.size() > MAX_RUNS) return fail(PM_E_DEVICE, "internal: too many launches in one set");
+    if (launch_zero(ls.zero_base, ls.zero_words, s0)) return fail(PM_E_DEVICE, "zero-fill launch failed");
+    if (run_ev) HIPCHK(hipEventRecord(run_ev[0], s0));
+    bool used[3] = {true, false, false};
+    if (fork) {
+        for (int k = 0; k < 2; ++k) {
+            if (!branch[k]) HIPCHK(hipStreamCreateWithFlags(&branch[k], hipStreamNonBlocking));
+            if (!join_ev[k]) HIPCHK(hipEventCreateWithFlags(&join_ev[k], hipEventDisableTiming));
+        }
+        if (!fork_ev) HIPCHK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(fork_ev, s0));
+        for (size_t r = 0; r < ls.runs.size(); ++r) {
+            const int br = run_branch(ls.run_agg[r]);
+            if (br && !used[br]) {
+                used[br] = true;
+                HIPCHK(hipStreamWaitEvent(branch[br - 1], fork_ev, 0));
+            }
+        }
+    }
     for (size_t r = 0; r < ls.runs.size(); ++r) {
+        hipStream_t s = fork && run_branch(ls.run_agg[r]) ? branch[run_branch(ls.run_agg[r]) - 1] : s0;
+        if (run_ev && r > 0) HIPCHK(hipEventRecord(run_ev[r], s));
         KArgs b = ls.base;
+        b.bytes = ls.bytes + r;
         b.plans = ls.dplans + ls.runs[r].first;
         b.nplans = ls.runs[r].second - ls.runs[r].first;
         b.counters = ls.counters + 2 * ls.runs[r].first;
@@ -1079,6 +1155,10 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
             b.items = ls.agg_items;
             b.nitems = ls.agg_nitems;
             gb = (int)std::max<uint64_t>(1, ls.agg_w / (block / 64));
+        } else if (ls.run_agg[r] == 12) {
+            gb = (int)std::max<uint64_t>(1, ls.agg_w / (block / 64));
+            if (b.nitems && launch_cycle5(b, gb, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
         } else if (ls.run_agg[r] == 2) {
             b.items = ls.heavy_items;
             b.nitems = ls.heavy_nitems;
@@ -1120,11 +1200,18 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass) {
         if (b.nitems == 0) continue;
         if (launch_match(b, gb, block, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
     }
+    if (fork)
+        for (int k = 0; k < 2; ++k)
+            if (used[k + 1]) {
+                HIPCHK(hipEventRecord(join_ev[k], branch[k]));
+                HIPCHK(hipStreamWaitEvent(s0, join_ev[k], 0));
+            }
+    if (run_ev) HIPCHK(hipEventRecord(run_ev[ls.runs.size()], s0));
     if (bytes_pass) {
-        HIPCHK(hipMemcpyAsync(ls.host + 2 * ls.np + 1, ls.bytes, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ls.host + 2 * ls.np + 2, ls.bytes, 8 * MAX_RUNS, hipMemcpyDeviceToHost, s0));
         return PM_OK;
     }
-    HIPCHK(hipMemcpyAsync(ls.host, ls.counters, 16 * ls.np, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ls.host, ls.counters, 16 * ls.np, hipMemcpyDeviceToHost, s0));
     return PM_OK;
 }
 
@@ -1251,7 +1338,7 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
                  uint64_t* ticket) {
     auto t0 = std::chrono::steady_clock::now();
     if (!pats || !ticket || npat == 0) return fail(PM_E_INVAL, "null patterns or ticket");
-    if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "pm_submit supports PM_AGG_COUNT; use pm_fsm for MNI");
+    if (agg != PM_AGG_COUNT && agg != PM_AGG_MNI) return fail(PM_E_INVAL, "unknown aggregation");
     if (morph != PM_MORPH_NONE && morph != PM_MORPH_NAIVE && morph != PM_MORPH_COST)
         return fail(PM_E_INVAL, "unknown morph mode");
     GraphRes* G;
@@ -1272,6 +1359,7 @@ int Ctx_::submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, i
         for (int v = 0; v < ps[i].k; ++v)
             if (ps[i].lab[v] >= 0 && !G->labeled) return fail(PM_E_INVAL, "labeled pattern on an unlabeled graph");
     }
+    if (agg == PM_AGG_MNI) return submit_mni(*G, gid, ps, morph, ticket);
     std::string err;
     int rc = morph_plan_count(ps, morph, &Q->mp, &err, cost_fn(*G));
     if (rc) return fail(rc, err);
@@ -1314,7 +1402,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
     const LaunchCfg cfg = cfg_for(G, Q.closure);
     HIPCHK(hipSetDevice(device));
     LaunchSet* ls = nullptr;
-    bool replay = use_graphs && !count_bytes;
+    bool replay = use_graphs && !count_bytes && !launch_events;
     std::string key = closure_key(G, Q.closure) + "#" + std::to_string(cfg.blocks_per_cu) + "," +
                       std::to_string(cfg.item_budget) + "," + std::to_string(cfg.item_split) + "," +
                       std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
@@ -1323,6 +1411,13 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
                       std::to_string(window_wide);
     if (replay) {
         auto it = G.launches.find(key);
+        if (it != G.launches.end() && !it->second->busy && it->second->agg_gen &&
+            it->second->agg_gen != agg_gen) {
+            // built on two-hop arrays that have since been reallocated
+            free_launchset(it->second.get());
+            G.launches.erase(it);
+            it = G.launches.end();
+        }
         if (it != G.launches.end() && !it->second->busy) {
             ls = it->second.get();
         } else if (it == G.launches.end()) {
@@ -1341,7 +1436,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
             // capture [zero-fill -> launches -> copy-back] once; replay later
             if (!cap_stream) HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
             HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
-            int erc = enqueue(*nls, cap_stream, false);
+            int erc = enqueue(*nls, cap_stream, false, nullptr, fork_launches);
             hipGraph_t graph = nullptr;
             hipError_t ce = hipStreamEndCapture(cap_stream, &graph);
             if (erc || ce != hipSuccess) {
@@ -1378,6 +1473,12 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
         HIPCHK(hipEventCreate(&Q.ev_stop));
         HIPCHK(hipEventCreate(&Q.ev_done));
     }
+    if (launch_events) {
+        LaunchSet& L0 = ls ? *ls : *Q.own;
+        Q.run_ev.assign(L0.runs.size() + 1, nullptr);
+        for (auto& e : Q.run_ev) HIPCHK(hipEventCreate(&e));
+        Q.run_kind = L0.run_agg;
+    }
     Q.counted_bytes = !ls && count_bytes;
     if (Q.counted_bytes) {
         int rc = enqueue(*Q.own, stream, true);
@@ -1390,7 +1491,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
         *(volatile int*)ls->cancel_host = 0;
         HIPCHK(hipGraphLaunch(ls->exec, stream));
     } else {
-        int rc = enqueue(*Q.own, stream, false);
+        int rc = enqueue(*Q.own, stream, false, Q.run_ev.empty() ? nullptr : Q.run_ev.data());
         if (rc) return rc;
     }
     HIPCHK(hipEventRecord(Q.ev_stop, stream));
@@ -1430,7 +1531,23 @@ void closure_counts(const std::vector<Pat>& closure, const std::vector<PlanInfo>
             continue;
         }
         __int128 c;
-        if (pi.rewrite) {
+        if (pi.cyc5) {
+            // pair sum minus the companion triangle plan's total
+            const size_t j = pi.subs.empty() ? np
+                                             : std::find(closure.begin(), closure.end(), pi.subs[0].first) -
+                                                   closure.begin();
+            if (j >= np || cnt[j] < 0) {
+                st[i] = j < np && st[j] ? st[j] : PM_E_DEVICE;
+                err[i] = j < np && st[j] ? err[j] : "internal: 5-cycle companion plan missing";
+                continue;
+            }
+            c = (__int128)v - cnt[j];
+            if (c < 0) {
+                st[i] = PM_E_DEVICE;
+                err[i] = "internal: negative 5-cycle count";
+                continue;
+            }
+        } else if (pi.rewrite) {
             __int128 acc = (__int128)pi.hmult * (__int128)v;
             for (auto& sq : pi.subs) {
                 size_t j = std::find(closure.begin(), closure.end(), sq.first) - closure.begin();
@@ -1489,6 +1606,17 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
         }
         std::this_thread::yield();
     }
+    if (Q->mni) {
+        const int rc = finish_mni(*Q, out);
+        std::lock_guard<std::mutex> g(mu);
+        hipEventDestroy(Q->ev_start);
+        hipEventDestroy(Q->ev_stop);
+        hipEventDestroy(Q->ev_done);
+        auto git = graphs.find(Q->gid);
+        if (git != graphs.end()) git->second->inflight--;
+        queries.erase(ticket);
+        return rc;
+    }
     float kms = 0;
     hipEventElapsedTime(&kms, Q->ev_start, Q->ev_stop);
     Q->stats.kernel_ms = kms;
@@ -1515,20 +1643,39 @@ int Ctx_::wait(uint64_t ticket, int64_t* out, int64_t timeout_us) {
         if (rc) fail(rc, err);
     }
     if (rc == PM_OK && out) memcpy(out, res.data(), sizeof(int64_t) * Q->npat);
-    Q->stats.alg_bytes = Q->counted_bytes ? host[2 * np + 1] : 0;
+    Q->stats.alg_bytes = 0;
+    last_launches.clear();
+    {
+        LaunchSet& L0 = Q->ls ? *Q->ls : *Q->own;
+        for (size_t r = 0; r < L0.runs.size(); ++r) {
+            pm_launch_stat ls_{};
+            snprintf(ls_.kernel, sizeof(ls_.kernel), "%s", run_kernel_name(L0.run_agg[r]));
+            ls_.alg_bytes = Q->counted_bytes ? host[2 * np + 2 + r] : 0;
+            Q->stats.alg_bytes += ls_.alg_bytes;
+            float ms = 0;
+            if (Q->run_ev.size() > r + 1) hipEventElapsedTime(&ms, Q->run_ev[r], Q->run_ev[r + 1]);
+            ls_.ms = ms;
+            last_launches.push_back(ls_);
+        }
+    }
+    for (auto& e : Q->run_ev) hipEventDestroy(e);
+    Q->run_ev.clear();
     Q->stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - Q->t_submit).count();
     last_stats = Q->stats;
     last_alt = alt;
     // release
-    std::lock_guard<std::mutex> g(mu);
-    if (Q->ls) Q->ls->busy = false;
-    if (Q->own) free_launchset(Q->own.get());
-    hipEventDestroy(Q->ev_start);
-    hipEventDestroy(Q->ev_stop);
-    hipEventDestroy(Q->ev_done);
-    auto git = graphs.find(Q->gid);
-    if (git != graphs.end()) git->second->inflight--;
-    queries.erase(ticket);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (Q->ls) Q->ls->busy = false;
+        if (Q->own) free_launchset(Q->own.get());
+        hipEventDestroy(Q->ev_start);
+        hipEventDestroy(Q->ev_stop);
+        hipEventDestroy(Q->ev_done);
+        auto git = graphs.find(Q->gid);
+        if (git != graphs.end()) git->second->inflight--;
+        queries.erase(ticket);
+    }
+    release_retired_agg();
     return rc;
 }
 
@@ -1610,12 +1757,20 @@ pm_status pm_query_footprint(pm_ctx* ctx, uint32_t gid, const pm_pattern* pats, 
         if (it == ctx->c.graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id");
         G = it->second.get();
     }
-    if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "footprint: COUNT only");
+    if (agg != PM_AGG_COUNT && agg != PM_AGG_MNI) return fail(PM_E_INVAL, "unknown aggregation");
     std::vector<Pat> ps(npat);
     for (uint32_t i = 0; i < npat; ++i) {
         std::string err;
         int rc = to_pat(pats[i], &ps[i], &err);
         if (rc) return fail(rc, err);
+    }
+    if (agg == PM_AGG_MNI) {
+        MniPlan P;
+        std::string err;
+        int rc = mni_plan(ps, morph == PM_MORPH_NAIVE ? PM_MORPH_NAIVE : PM_MORPH_NONE, &P, &err);
+        if (rc) return fail(rc, err);
+        *out_bytes = ctx->c.mni_footprint(*G, P);
+        return PM_OK;
     }
     MorphPlan mp;
     std::string err;
@@ -1652,6 +1807,15 @@ pm_status pm_last_query_stats(pm_ctx* ctx, pm_query_stats* out) {
     return PM_OK;
 }
 
+pm_status pm_last_launch_stats(pm_ctx* ctx, pm_launch_stat* out, uint32_t cap, uint32_t* n) {
+    if (!ctx || !n) return fail(PM_E_INVAL, "null argument");
+    const auto& L = ctx->c.last_launches;
+    *n = (uint32_t)L.size();
+    if (cap < L.size() || (!out && !L.empty())) return fail(PM_E_INVAL, "capacity below the number of launches");
+    for (size_t i = 0; i < L.size(); ++i) out[i] = L[i];
+    return PM_OK;
+}
+
 pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket) {
     if (!ctx) return fail(PM_E_INVAL, "null ctx");
     std::lock_guard<std::mutex> g(ctx->c.mu);
@@ -1660,6 +1824,7 @@ pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket) {
     Query& Q = *it->second;
     LaunchSet* ls = Q.ls ? Q.ls : Q.own.get();
     if (ls && ls->cancel_host) __atomic_store_n(ls->cancel_host, 1, __ATOMIC_SEQ_CST);
+    if (Q.mni_cancel) __atomic_store_n(Q.mni_cancel, 1, __ATOMIC_SEQ_CST);
     Q.cancelled = true;
     return PM_OK;
 }
@@ -1667,7 +1832,7 @@ pm_status pm_cancel(pm_ctx* ctx, uint64_t ticket) {
 pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg, int32_t morph, pm_pattern* out_alt,
                         uint32_t* inout_nalt, int64_t* out_matrix) {
     if (!pats || !inout_nalt) return fail(PM_E_INVAL, "null argument");
-    if (agg != PM_AGG_COUNT) return fail(PM_E_UNSUPPORTED, "morph plans for MNI are internal to pm_fsm");
+    if (agg != PM_AGG_COUNT && agg != PM_AGG_MNI) return fail(PM_E_INVAL, "unknown aggregation");
     std::vector<Pat> ps(npat);
     for (uint32_t i = 0; i < npat; ++i) {
         std::string err;
@@ -1676,9 +1841,67 @@ pm_status pm_morph_plan(const pm_pattern* pats, uint32_t npat, int32_t agg, int3
     }
     MorphPlan mp;
     std::string err;
-    int rc = morph_plan_count(ps, morph, &mp, &err);
-    if (rc) return fail(rc, err);
+    if (agg == PM_AGG_MNI) {
+        // Theorem 3.2: the patterns whose domains are joined (by union) into
+        // each query's domains; the matrix marks which
+        MniPlan P;
+        int rc = mni_plan(ps, morph == PM_MORPH_NAIVE || morph == PM_MORPH_COST ? PM_MORPH_NAIVE : PM_MORPH_NONE,
+                          &P, &err);
+        if (rc) return fail(rc, err);
+        mp.alt = P.alt;
+        mp.matrix.assign((size_t)npat * P.alt.size(), 0);
+        for (uint32_t i = 0; i < npat; ++i)
+            for (uint32_t j : P.qalts[i]) mp.matrix[(size_t)i * P.alt.size() + j] = 1;
+    } else {
+        int rc = morph_plan_count(ps, morph, &mp, &err);
+        if (rc) return fail(rc, err);
+    }
     uint32_t na = (uint32_t)mp.alt.size();
+    if (*inout_nalt < na || !out_alt) {
+        *inout_nalt = na;
+        return fail(PM_E_INVAL, "out_alt capacity too small");
+    }
+    *inout_nalt = na;
+    for (uint32_t j = 0; j < na; ++j) {
+        pm_pattern& o = out_alt[j];
+        o.k = (uint32_t)mp.alt[j].k;
+        o.edge_mask = mp.alt[j].em;
+        o.induce = mp.alt[j].vi ? PM_VERTEX_INDUCED : PM_EDGE_INDUCED;
+        for (int i = 0; i < 8; ++i) o.label[i] = mp.alt[j].lab[i];
+    }
+    if (out_matrix)
+        for (size_t i = 0; i < mp.matrix.size(); ++i) out_matrix[i] = mp.matrix[i];
+    return PM_OK;
+}
+
+pm_status pm_morph_plan_costs(const pm_pattern* pats, uint32_t npat, const pm_pattern* cost_pats,
+                              const double* costs, uint32_t ncost, pm_pattern* out_alt, uint32_t* inout_nalt,
+                              int64_t* out_matrix) {
+    if (!pats || !inout_nalt || (ncost && (!cost_pats || !costs))) return fail(PM_E_INVAL, "null argument");
+    std::vector<Pat> ps(npat), cp(ncost);
+    for (uint32_t i = 0; i < npat; ++i) {
+        std::string err;
+        int rc = to_pat(pats[i], &ps[i], &err);
+        if (rc) return fail(rc, err);
+    }
+    for (uint32_t i = 0; i < ncost; ++i) {
+        std::string err;
+        int rc = to_pat(cost_pats[i], &cp[i], &err);
+        if (rc) return fail(rc, err);
+        cp[i] = canonical(cp[i]);
+    }
+    // patterns without a listed cost are never worth matching
+    auto cost = [&](const Pat& q) {
+        const Pat c = canonical(q);
+        for (uint32_t i = 0; i < ncost; ++i)
+            if (cp[i] == c) return costs[i];
+        return 1e30;
+    };
+    MorphPlan mp;
+    std::string err;
+    int rc = morph_plan_mixed(ps, cost, &mp, &err);
+    if (rc) return fail(rc, err);
+    const uint32_t na = (uint32_t)mp.alt.size();
     if (*inout_nalt < na || !out_alt) {
         *inout_nalt = na;
         return fail(PM_E_INVAL, "out_alt capacity too small");
@@ -1731,6 +1954,8 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "heavy_span_shift" && value >= 0 && value <= 32) c.heavy_span_shift = (uint32_t)value;
     else if (k == "hipgraph") c.use_graphs = value != 0;
     else if (k == "window_counters" && (value == 16 || value == 32)) c.window_wide = value == 32;
+    else if (k == "launch_events" && (value == 0 || value == 1)) c.launch_events = value != 0;
+    else if (k == "fork_launches" && (value == 0 || value == 1)) c.fork_launches = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;
 }
@@ -1862,14 +2087,72 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out) {
     return PM_OK;
 }
 
+// Morphed FSM (Theorem 3.2): every slot's edge-induced pattern takes its
+// domains as unions over its vertex-induced superpatterns' domains, through
+// the MNI search kernels, in batches of slots whose bitmaps fit a quarter of
+// the free arena.
+static pm_status fsm_morphed(Ctx_& c, GraphRes& G, const FsmTables& T, uint32_t L, int64_t threshold,
+                             int64_t* out_support, uint8_t* out_frequent,
+                             std::chrono::steady_clock::time_point t0) {
+    const uint64_t nslots = T.slots.size();
+    const uint64_t per_task = 4ull * ((G.n + 31) / 32);
+    const uint64_t budget = std::max<uint64_t>(c.arena.largest_free() / 4, 64ull << 20);
+    // a slot needs at most 8 superpatterns x 4 columns of searches
+    const uint64_t batch = std::max<uint64_t>(1, budget / (32 * per_task + 4096));
+    float kms = 0;
+    uint32_t launches = 0;
+    for (uint64_t s0 = 0; s0 < nslots; s0 += batch) {
+        const uint64_t s1 = std::min<uint64_t>(nslots, s0 + batch);
+        std::vector<Pat> ps;
+        for (uint64_t s = s0; s < s1; ++s) {
+            pm_pattern q;
+            pm_fsm_slot(L, s, &q);
+            Pat p;
+            std::string err;
+            to_pat(q, &p, &err);
+            ps.push_back(p);
+        }
+        MniPlan P;
+        std::string err;
+        int rc = mni_plan(ps, PM_MORPH_NAIVE, &P, &err);
+        if (rc) return fail(rc, err);
+        std::vector<int64_t> sup;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipEventCreate(&e0);
+        hipEventCreate(&e1);
+        hipEventRecord(e0, c.stream);
+        rc = c.run_mni_sync(G, P, &sup);
+        hipEventRecord(e1, c.stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc) return rc;
+        kms += ms;
+        launches += 2;
+        for (uint64_t s = s0; s < s1; ++s) {
+            out_support[s] = sup[s - s0];
+            if (out_frequent) out_frequent[s] = sup[s - s0] >= threshold ? 1 : 0;
+        }
+    }
+    pm_query_stats st{};
+    st.kernel_ms = kms;
+    st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st.launches = launches;
+    st.num_alt = (uint32_t)nslots;
+    c.last_stats = st;
+    return PM_OK;
+}
+
 pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t threshold, int32_t morph,
                  int64_t* out_support, uint8_t* out_frequent, uint64_t nslots) {
     if (!ctx || !out_support) return fail(PM_E_INVAL, "null argument");
     if (num_labels == 0 || num_labels > (uint32_t)FSM_LMAX)
         return fail(PM_E_UNSUPPORTED, "pm_fsm supports 1..16 labels");
     if (nslots != pm_fsm_num_slots(num_labels)) return fail(PM_E_INVAL, "nslots must equal pm_fsm_num_slots");
-    if (morph != PM_MORPH_NONE)
-        return fail(PM_E_UNSUPPORTED, "pm_fsm computes edge-induced supports directly (PM_MORPH_NONE)");
+    if (morph != PM_MORPH_NONE && morph != PM_MORPH_NAIVE && morph != PM_MORPH_COST)
+        return fail(PM_E_INVAL, "unknown morph mode");
     Ctx_& c = ctx->c;
     GraphRes* G;
     {
@@ -1883,6 +2166,7 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     auto t0 = std::chrono::steady_clock::now();
     FsmTables T;
     fsm_tables(num_labels, &T);
+    if (morph == PM_MORPH_NAIVE) return fsm_morphed(c, *G, T, num_labels, threshold, out_support, out_frequent, t0);
     const uint64_t n = G->n;
     const int grid = std::max(1, c.num_cus * 4);
     const uint64_t threads = (uint64_t)grid * 256;

@@ -13,6 +13,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "mni.hpp"
 
 namespace pm {
 
@@ -26,6 +27,21 @@ int fail(int code, const std::string& msg);
     } while (0)
 
 int to_pat(const pm_pattern& q, Pat* out, std::string* err);
+
+// MNI domain searches of a query (mni_host.cpp): deduplicated column
+// searches, and per query pattern one output per vertex, the union of some
+// searches' bitmaps.
+struct MniPlan {
+    std::vector<MTask> tasks;
+    std::vector<uint32_t> list;                 // search indices of the outputs
+    std::vector<MOut> outs;
+    std::vector<std::vector<uint32_t>> qouts;   // per query pattern: its outputs
+    std::vector<Pat> alt;                       // distinct patterns searched
+    std::vector<std::vector<uint32_t>> qalts;   // per query pattern: indices into alt
+};
+// morph: PM_MORPH_NONE (direct) or PM_MORPH_NAIVE (edge-induced patterns
+// through their vertex-induced superpatterns, Theorem 3.2)
+int mni_plan(const std::vector<Pat>& qs, int morph, MniPlan* out, std::string* err);
 
 struct PlanInfo;
 // Work items over the roots: consecutive roots of about `budget` adjacency
@@ -55,6 +71,8 @@ struct ItemSet {
     uint64_t off = UINT64_MAX;
     uint32_t count = 0;
 };
+
+constexpr size_t MAX_RUNS = 32;   // launches of one launch set (byte tallies, events)
 
 struct LaunchCfg {
     int blocks_per_cu = 4;
@@ -111,6 +129,8 @@ struct LaunchSet {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool busy = false;
+    uint64_t agg_gen = 0;                    // generation of the context's two-hop arrays it
+                                             // points to (0: uses none, or a slot's own)
     LaunchCfg cfg;
 };
 
@@ -131,6 +151,7 @@ struct GraphRes {
     const KItem* d_c4x = nullptr;
     uint64_t device_bytes = 0;
     std::vector<uint32_t> host_rp;           // degree-ordered row offsets (item building)
+    std::vector<uint32_t> orig_id;           // degree-ordered id -> the caller's id
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
     std::vector<uint64_t> two_hop;           // per vertex: summed degrees of its lower neighbours
     std::vector<KItem> clique_items;         // triangle-core kernel items
@@ -140,6 +161,8 @@ struct GraphRes {
     std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
+    uint64_t off_lorder = UINT64_MAX;        // label-sorted vertex order on the device (first MNI use)
+    std::vector<uint32_t> label_begin;       // labeled graphs: first position of each label in label_order
     uint64_t hash = 0;                       // FNV-1a of the degree-ordered CSR (+labels)
     int inflight = 0;
 };
@@ -157,6 +180,15 @@ struct Query {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_done = nullptr;
     pm_query_stats stats{};
     std::chrono::steady_clock::time_point t_submit;
+    std::vector<hipEvent_t> run_ev;          // launch_events: one before each launch, one after the last
+    std::vector<int> run_kind;               // LaunchSet::run_agg of each launch
+    // MNI queries: domain searches, their arena region, pinned column sizes
+    // and cancel flag
+    bool mni = false;
+    MniPlan mni_plan;
+    uint64_t mni_off = UINT64_MAX;
+    unsigned long long* mni_host = nullptr;
+    int* mni_cancel = nullptr;
 };
 
 struct Ctx_ {
@@ -177,8 +209,16 @@ struct Ctx_ {
     uint32_t heavy_span_shift = 6;   // two-hop heavy roots: mass << shift >= id
     bool support_opt = true;
     bool window_wide = false;        // agg_window_kernel: 32-bit counters always
+    bool launch_events = false;      // eager launches with an event between launches
+    std::vector<pm_launch_stat> last_launches;
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
+    // captured launch sets fork the LDS-kernel launches (triangle pass and
+    // edge supports; 4-cliques) onto two branches beside the general-kernel
+    // launches, which share the per-wavefront buffers and stay in order
+    hipStream_t branch[2] = {nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+    bool fork_launches = false;      // measured slower at R-MAT 20 (127 vs 120 ms a step)
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
     std::string tune_file;
     std::mutex mu, plan_mu;
@@ -187,6 +227,13 @@ struct Ctx_ {
     uint32_t next_gid = 1;
     uint64_t next_ticket = 1;
     uint64_t agg_off = UINT64_MAX, agg_touch_off = UINT64_MAX;
+    // the two-hop arrays are reallocated when a graph needs more; launch
+    // sets (and their captured graphs) built on older arrays are rebuilt,
+    // and older arrays are released once nothing in flight uses them
+    uint64_t agg_gen = 1;
+    std::vector<uint64_t> agg_retired;
+    bool ctx_agg_busy();
+    void release_retired_agg();
     uint32_t agg_n = 0;
     uint64_t agg_w = 0;
     pm_query_stats last_stats{};
@@ -239,7 +286,7 @@ struct Ctx_ {
     int serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_config* cfg, pm_serve_result* res,
               pm_serve_stats* stats);
     void free_launchset(LaunchSet* ls);
-    int enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass);
+    int enqueue(LaunchSet& ls, hipStream_t s, bool bytes_pass, hipEvent_t* run_ev = nullptr, bool fork = false);
     int run_eager_ms(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, double* ms);
     int autotune(uint32_t gid, const pm_pattern* pats, uint32_t npat, int morph, int64_t* out_cfg, double* out_ms);
     void load_tune_file();
@@ -264,6 +311,17 @@ struct Ctx_ {
     int ensure_support(GraphRes& G);
     std::vector<KItem> clique4_big_items(const GraphRes& G, const LaunchCfg& cfg) const;
     int submit(uint32_t gid, const pm_pattern* pats, uint32_t npat, int agg, int morph, uint64_t* ticket);
+    // MNI queries (mni_host.cpp)
+    uint64_t mni_footprint(const GraphRes& G, const MniPlan& P) const;
+    int ensure_label_order(GraphRes& G);
+    int enqueue_mni(GraphRes& G, const MniPlan& P, uint64_t base, unsigned long long* host, const int* cancel,
+                    hipStream_t s);
+    int run_mni_sync(GraphRes& G, const MniPlan& P, std::vector<int64_t>* sup);
+    int submit_mni(GraphRes& G, uint32_t gid, const std::vector<Pat>& ps, int morph, uint64_t* ticket);
+    int finish_mni(Query& Q, int64_t* out);
+    int fsm_levelwise(GraphRes& G, uint32_t L, uint32_t max_edges, int64_t threshold, int morph,
+                      std::vector<std::pair<Pat, int64_t>>* out);
+    int list_matches(GraphRes& G, const Pat& p, int morph, uint32_t* out, uint64_t cap, uint64_t* count);
     int launch(GraphRes& G, Query& Q);
     int evict_idle();
     int wait(uint64_t ticket, int64_t* out, int64_t timeout_us);

@@ -111,3 +111,121 @@ def test_fsm_slot_table_complete_and_distinct(L):
         seen.add((k,) + P.canonical(k, mask, labs))
     assert len(seen) == ns
     assert seen == want
+
+
+def test_morph_plan_mni_alternatives():
+    """PM_AGG_MNI morph plan: an edge-induced query's alternatives are the
+    vertex-induced patterns p + S over every set S of its non-adjacent pairs
+    (Theorem 3.2), as canonical forms; a vertex-induced query is its own."""
+    from itertools import combinations
+    from oracle import P
+    import paper_2012_04553_amd as pm
+
+    def canon_key(k, m, vi, labs):
+        cm, cl = P.canonical(k, m, labs)
+        clique = cm == P.clique_mask(k)
+        return (k, cm, bool(vi) and not clique, tuple(cl))
+
+    for k in (3, 4):
+        for m in P.connected_classes(k):
+            for labs in ([-1] * k, [0, 1] + [0] * (k - 2)):
+                alts, M = pm.morph_plan([(k, m, False, labs)], pm.MORPH_NAIVE, pm.AGG_MNI)
+                got = {canon_key(ak, am, avi, alab) for ak, am, avi, alab in alts}
+                assert all(M[0, j] == 1 for j in range(len(alts)))
+                nonedges = [b for b in range(P.num_pairs(k)) if not (m >> b) & 1]
+                want = set()
+                for r in range(len(nonedges) + 1):
+                    for S in combinations(nonedges, r):
+                        q = m
+                        for b in S:
+                            q |= 1 << b
+                        want.add(canon_key(k, q, True, labs))
+                assert got == want, (k, m, labs)
+                alts, M = pm.morph_plan([(k, m, True, labs)], pm.MORPH_NAIVE, pm.AGG_MNI)
+                assert {canon_key(ak, am, avi, alab) for ak, am, avi, alab in alts} == \
+                    {canon_key(k, m, True, labs)}
+
+
+def _named4(pm):
+    import oracle
+    return oracle.named_4()
+
+
+def _alt_set(alts):
+    from oracle import P
+    out = set()
+    for k, m, vi, labs in alts:
+        cm = P.canonical(k, m)[0]
+        out.add((cm, bool(vi) and cm != P.clique_mask(k)))
+    return out
+
+
+# Per-pattern costs of matching each 4-vertex pattern vertex- (V) or
+# edge-induced (E), shaped like the paper's system on its skewed graphs
+# (Table 1: the edge-induced diamond is far cheaper than the vertex-induced
+# one; Table 3: matching the edge-induced 4-cycle costs more than its
+# vertex-induced form), and like its Patents graph, where the edge-induced
+# 4-cycle and the vertex-induced diamond stay cheap.
+SKEWED = {("tailed_triangle", "V"): 4.4, ("tailed_triangle", "E"): 0.1, ("cycle4", "V"): 1.9,
+          ("cycle4", "E"): 3.0, ("diamond", "V"): 3.0, ("diamond", "E"): 0.08, ("clique4", "E"): 0.3,
+          ("star3", "V"): 9.0, ("star3", "E"): 0.01, ("path4", "V"): 9.0, ("path4", "E"): 0.05}
+PATENTS = dict(SKEWED)
+PATENTS.update({("cycle4", "E"): 1.0, ("diamond", "V"): 0.2})
+
+
+def _plan_with(pm, names, pats, costs):
+    cpats = [(4, names[n], how == "V") for (n, how) in costs]
+    return pm.morph_plan_costs(pats, cpats, list(costs.values()))
+
+
+def test_cost_based_sets_reproduce_table4():
+    """The cost-based optimizer over mixed vertex-/edge-induced alternative
+    sets picks Table 4's sets under costs shaped like the paper's graphs:
+    p1^V -> {p1^E, p3^E, p4}; p2^V -> {p2^V}; p2^E -> {p2^V, p3^E, p4};
+    p3^V -> {p3^E, p4}; {p2^E, p3^E} -> {p2^V, p3^E, p4}; and on the
+    Patents-like costs p2^E and p3^V stay as given.  Each chosen set's
+    integer rows reproduce the queries from oracle counts."""
+    import gen
+    import oracle
+    import paper_2012_04553_amd as pm
+    n = _named4(pm)
+    p1, p2, p3, p4 = n["tailed_triangle"], n["cycle4"], n["diamond"], n["clique4"]
+    cases = [
+        ([(4, p1, True)], SKEWED, {(p1, False), (p3, False), (p4, False)}),
+        ([(4, p2, True)], SKEWED, {(p2, True)}),
+        ([(4, p2, False)], SKEWED, {(p2, True), (p3, False), (p4, False)}),
+        ([(4, p3, True)], SKEWED, {(p3, False), (p4, False)}),
+        ([(4, p2, False), (4, p3, False)], SKEWED, {(p2, True), (p3, False), (p4, False)}),
+        ([(4, p2, False)], PATENTS, {(p2, False)}),
+        ([(4, p3, True)], PATENTS, {(p3, True)}),
+        ([(4, p2, False), (4, p3, False)], PATENTS, {(p2, False), (p3, False)}),
+    ]
+    g = gen.erdos_renyi(30, 0.3, 17)
+    for pats, costs, want in cases:
+        alts, M = _plan_with(pm, n, pats, costs)
+        assert _alt_set(alts) == want, (pats, _alt_set(alts))
+        vals = [oracle.count(g, ak, am, bool(avi)) for ak, am, avi, _ in alts]
+        for i, (k, m, vi) in enumerate(pats):
+            assert sum(int(M[i, j]) * vals[j] for j in range(len(alts))) == oracle.count(g, k, m, vi)
+
+
+def test_cost_based_motif_sets_exact():
+    """Motif counting (every vertex-induced pattern a query): whatever mix
+    the costs select, the rows reproduce the oracle's counts."""
+    import gen
+    import oracle
+    import numpy as np
+    from oracle import P
+    import paper_2012_04553_amd as pm
+    g = gen.erdos_renyi(26, 0.3, 19)
+    rng = np.random.default_rng(3)
+    cls = P.connected_classes(4)
+    pats = [(4, m, True) for m in cls]
+    want = [oracle.count(g, 4, m, True) for m in cls]
+    for _ in range(6):
+        cpats = [(4, m, vi) for m in cls for vi in (False, True)]
+        costs = [float(x) for x in rng.uniform(0.1, 10, size=len(cpats))]
+        alts, M = pm.morph_plan_costs(pats, cpats, costs)
+        vals = [oracle.count(g, ak, am, bool(avi)) for ak, am, avi, _ in alts]
+        got = [sum(int(M[i, j]) * vals[j] for j in range(len(alts))) for i in range(len(pats))]
+        assert got == want

@@ -91,11 +91,10 @@ def test_serving_admission_by_budget(eng, graphs):
     assert res[0]["status"] == -2 and st["failed"] == 1
 
 
-def _cycle5():
-    m = 0
-    for i in range(5):
-        m |= 1 << P.pair_bit(i, (i + 1) % 5)
-    return P.canonical(5, m)[0]
+def _heavy5():
+    """The house (a 5-cycle with one chord), edge-induced: its plan
+    enumerates long enough on R-MAT 12 to be cancelled or timed out."""
+    return P.canonical(5, 0xED)[0]
 
 
 def test_cancel_heavy_query(eng):
@@ -107,8 +106,8 @@ def test_cancel_heavy_query(eng):
     g = gen.rmat(12, 16, seed=3)
     gid = eng.load(g)
     try:
-        # the edge-induced 5-cycle alone runs for tens of seconds here
-        heavy = [(5, _cycle5(), False)]
+        # the edge-induced house alone runs for seconds here
+        heavy = [(5, _heavy5(), False)]
         t = time.time()
         tk = eng.submit(gid, heavy, morph=pm.MORPH_NONE)
         time.sleep(0.2)
@@ -131,7 +130,7 @@ def test_serving_deadline(eng, graphs):
     heavy_g = gen.rmat(12, 16, seed=3)
     hid = eng.load(heavy_g)
     try:
-        heavy = [(5, _cycle5(), False)]
+        heavy = [(5, _heavy5(), False)]
         reqs = [(0.0, hid, heavy, pm.MORPH_NONE)]
         light = _trace(ids[:1], 10, 1000.0, seed=11)
         reqs += [(t + 0.01, gid, pats, m) for (t, gid, pats, m) in light]

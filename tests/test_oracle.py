@@ -316,3 +316,48 @@ def test_mni_labelings_equals_per_pattern_support():
             got = oracle.mni_labelings(g, k, m, False, 3, labs)
             for t, sup in zip(labs, got):
                 assert sup == oracle.mni_support(g, k, m, False, t), (k, m, t)
+
+
+def test_tier_c_root_sample_adds_up():
+    """The root-sampled closed forms (used to time the oracle on a bounded
+    sample) add up over every residue class to the full closed forms."""
+    g = gen.rmat(9, 16, seed=23)
+    full = oracle.tier_c4(g)
+    for stride in (1, 3, 7):
+        raw = {k: 0 for k in oracle.TIER_C4_KEYS}
+        for off in range(stride):
+            part = oracle.tier_c4_sample(g, stride, off)
+            for k in raw:
+                raw[k] += part[k]
+        assert oracle.tier_c4_from_raw(raw) == full, stride
+
+
+def test_list_maps_pins():
+    """Listing oracle: as many rows as matches counted, every row a match
+    (brute-force check of edges, anti-edges and labels), and the rows
+    collapse to count() distinct subgraphs; on K_6 the triangles are the
+    C(6, 3) vertex triples."""
+    g = gen.erdos_renyi(14, 0.35, 27).with_labels(gen.zipf_labels(14, 2, 1.0, 28))
+    adj = {(u, int(v)) for u in range(g.n) for v in g.neighbors(u)}
+    for k in (3, 4):
+        for m in P.connected_classes(k):
+            for induced in (False, True):
+                for labs in (None, [0] + [1] * (k - 1)):
+                    rows = oracle.list_maps(g, k, m, induced, labs)
+                    assert len(rows) == oracle.count_maps(g, k, m, induced, labs)
+                    keys = set()
+                    for r in rows:
+                        r = [int(x) for x in r]
+                        assert len(set(r)) == k
+                        for j in range(k):
+                            for i in range(j):
+                                e = (r[i], r[j]) in adj
+                                assert e or not P.has_edge(m, i, j)
+                                assert not (induced and e and not P.has_edge(m, i, j))
+                        if labs is not None:
+                            assert all(int(g.labels[r[v]]) == labs[v] for v in range(k))
+                        keys.add((frozenset(r), frozenset(tuple(sorted((r[i], r[j]))) for i, j in P.edges_of(k, m))))
+                    assert len(keys) == oracle.count(g, k, m, induced, labs)
+    k6 = gen.complete_graph(6)
+    rows = oracle.list_maps(k6, 3, 0b111, False)
+    assert len({frozenset(int(x) for x in r) for r in rows}) == comb(6, 3)
