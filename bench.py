@@ -306,12 +306,33 @@ def wl_rmat_5mc(args, eng):
                      f"R-MAT scale {scale} edge factor 16 seed 3",
                      {"n": g.n, "m": g.m, "kernel_ms": k_ms, "autotune": tune, "counts": ref,
                       "num_alt": st["num_alt"]})
-    line["roofline"] = {"bound": "hbm", "kernel": "match_kernel", "launches_per_step": launches,
-                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                        "alg_bytes_per_launch": st["alg_bytes"] / launches}
+    per = launch_roofline(eng, gid, pats, pm.MORPH_NAIVE, max(1, args.steps // 2))
+    dom = max(range(len(per)), key=lambda i: per[i]["ms"])
+    d = per[dom]
+    d_ach = d["alg_bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
+    line["roofline"] = {"bound": "hbm", "kernel": d["kernel"], "launch_index": dom, "achieved": d_ach,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d_ach / HBM_PEAK_GBS, "traffic": None,
+                        "alg_bytes_per_launch": d["alg_bytes"], "avg_launch_ms": d["ms"],
+                        "all_launches": {"launches_per_step": launches, "achieved": achieved,
+                                         "frac": achieved / HBM_PEAK_GBS},
+                        "per_launch": per}
     line["cpu_baseline"] = None
     eng.graph_unload(gid)
+    if args.plain_5mc_scale > 0:
+        gp = gen.rmat(args.plain_5mc_scale, 16, 0.57, 0.19, 0.19, 0.05, seed=3)
+        gpid = eng.load(gp)
+        res = {}
+        for mode, name in ((pm.MORPH_NAIVE, "morphed"), (pm.MORPH_NONE, "plain")):
+            eng.count(gpid, pats, morph=mode)
+            ts = time.perf_counter()
+            c = eng.count(gpid, pats, morph=mode)
+            res[name] = (time.perf_counter() - ts, c)
+        assert res["morphed"][1] == res["plain"][1], "morphed and plain disagree"
+        line["morphed_vs_plain"] = {
+            "workload": f"R-MAT scale {args.plain_5mc_scale} ef16 seed 3, 21 vertex-induced 5-motifs",
+            "morphed_s": round(res["morphed"][0], 4), "plain_s": round(res["plain"][0], 4),
+            "speedup": round(res["plain"][0] / res["morphed"][0], 2)}
+        eng.graph_unload(gpid)
     return line
 
 
@@ -369,7 +390,9 @@ def wl_serving(args, eng):
                      {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "matches_per_s": st["matches_per_s"],
                       "completed": st["completed"], "timeouts": st["timeouts"],
                       "mean_inflight": st["mean_inflight"], "batches": st["batches"],
-                      "deadline_s": args.serve_deadline}, higher=False)
+                      "sustained_qps": st["sustained_qps"], "offered_qps": args.serve_qps,
+                      "mean_setup_s": st["mean_setup_s"], "mean_service_s": st["mean_service_s"],
+                      "makespan_s": st["makespan_s"], "deadline_s": args.serve_deadline}, higher=False)
     line["roofline"] = None
     line["cpu_baseline"] = None
     return line
@@ -395,6 +418,8 @@ def main():
     ap.add_argument("--plain-scale", type=int, default=12)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the workload, copy this many MiB device to device once (PMC calibration)")
+    ap.add_argument("--plain-5mc-scale", type=int, default=9,
+                    help="rmat-5mc: also time plain (unmorphed) 5-motif counting at this scale (0: skip)")
     ap.add_argument("--serve-div", type=int, default=10)
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--serve-qps", type=float, default=200.0)

@@ -365,6 +365,9 @@ typedef struct {
     int32_t status;         /* PM_OK or the error of this request         */
     uint32_t batch_size;    /* requests in the batch it ran in            */
     int64_t values[PM_SERVE_MAX_PATTERNS];
+    double setup_s;         /* host time to plan its batch and build the
+                               launch set, before the batch was enqueued  */
+    double service_s;       /* completion - admission (the batch on the GPU) */
 } pm_serve_result;
 
 typedef struct {
@@ -384,6 +387,8 @@ typedef struct {
     double matches_per_s;                /* sum of all values / makespan  */
     double mean_inflight;                /* batches in flight at admissions */
     uint64_t batches, completed, failed, timeouts;
+    double mean_setup_s, mean_service_s; /* per completed request          */
+    double sustained_qps;                /* completed / makespan          */
 } pm_serve_stats;
 
 pm_status pm_serve(pm_ctx* ctx, const pm_serve_request* reqs, uint32_t nreq,

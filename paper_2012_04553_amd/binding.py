@@ -64,7 +64,8 @@ class pm_serve_request(ctypes.Structure):
 class pm_serve_result(ctypes.Structure):
     _fields_ = [("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double),
                 ("status", ctypes.c_int32), ("batch_size", ctypes.c_uint32),
-                ("values", ctypes.c_int64 * SERVE_MAX_PATTERNS)]
+                ("values", ctypes.c_int64 * SERVE_MAX_PATTERNS), ("setup_s", ctypes.c_double),
+                ("service_s", ctypes.c_double)]
 
 
 class pm_serve_config(ctypes.Structure):
@@ -78,7 +79,9 @@ class pm_serve_stats(ctypes.Structure):
                 ("max_s", ctypes.c_double), ("makespan_s", ctypes.c_double),
                 ("matches_per_s", ctypes.c_double), ("mean_inflight", ctypes.c_double),
                 ("batches", ctypes.c_uint64), ("completed", ctypes.c_uint64),
-                ("failed", ctypes.c_uint64), ("timeouts", ctypes.c_uint64)]
+                ("failed", ctypes.c_uint64), ("timeouts", ctypes.c_uint64),
+                ("mean_setup_s", ctypes.c_double), ("mean_service_s", ctypes.c_double),
+                ("sustained_qps", ctypes.c_double)]
 
 
 # name -> (restype, argtypes) for every function declared in include/pm.h
@@ -395,7 +398,7 @@ class Engine:
         for i in range(n):
             R = res[i]
             out.append({"latency_s": R.latency_s, "queue_s": R.queue_s, "status": R.status,
-                        "batch_size": R.batch_size,
+                        "batch_size": R.batch_size, "setup_s": R.setup_s, "service_s": R.service_s,
                         "values": [int(R.values[j]) for j in range(arr[i].npat)]})
         return out, {f: getattr(st, f) for f, _ in pm_serve_stats._fields_}
 

@@ -222,6 +222,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                 pm_serve_result& R = res[B.reqs[r]];
                 R.status = brc ? brc : rst[r];
                 R.latency_s = tdone - reqs[B.reqs[r]].arrival_s;
+                R.service_s = tdone - B.admitted;
                 R.batch_size = (uint32_t)B.reqs.size();
                 if (R.status == PM_OK)
                     for (size_t k = 0; k < vals[r].size(); ++k) R.values[k] = vals[r][k];
@@ -252,6 +253,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             if (!free_slot) break;
             const uint32_t head = pending.front();
             GraphRes& G = *gr[head];
+            const double t_setup = now_s();
             auto B = std::make_unique<Batch>();
             for (auto it = pending.begin(); it != pending.end() && B->reqs.size() < cfg->max_batch; ++it)
                 if (gr[*it] == &G) B->reqs.push_back(*it);
@@ -337,6 +339,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             B->admitted = ta;
             for (uint32_t r : B->reqs) {
                 res[r].queue_s = ta - reqs[r].arrival_s;
+                res[r].setup_s = ta - t_setup;
                 pending.erase(std::find(pending.begin(), pending.end(), r));
             }
             used += B->bytes;
@@ -357,7 +360,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     if (rc) return rc;
     // statistics
     std::vector<double> lat;
-    double total_matches = 0;
+    double total_matches = 0, setup_sum = 0, service_sum = 0;
     uint64_t failed = 0, timeouts = 0;
     for (uint32_t i = 0; i < nreq; ++i) {
         if (res[i].status) {
@@ -366,6 +369,8 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             continue;
         }
         lat.push_back(res[i].latency_s);
+        setup_sum += res[i].setup_s;
+        service_sum += res[i].service_s;
         for (uint32_t k = 0; k < reqs[i].npat; ++k) total_matches += (double)res[i].values[k];
     }
     std::sort(lat.begin(), lat.end());
@@ -390,6 +395,9 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
         stats->completed = nreq - failed;
         stats->failed = failed;
         stats->timeouts = timeouts;
+        stats->mean_setup_s = lat.empty() ? 0 : setup_sum / lat.size();
+        stats->mean_service_s = lat.empty() ? 0 : service_sum / lat.size();
+        stats->sustained_qps = stats->makespan_s > 0 ? (double)stats->completed / stats->makespan_s : 0;
     }
     return PM_OK;
 }
