@@ -366,6 +366,40 @@ def wl_rmat18_fsm(args, eng):
     return line
 
 
+def service_profile(eng, ids, sizes, ks, per_class, deadline_s):
+    """Where serving time goes: `per_class` queries of every (graph, k) class
+    of the same query distribution, each served alone (one slot, batches of
+    one), with their planning and launch-set set-up time and their service
+    time (admission to completion).  A query still running at the deadline is
+    cancelled and counted as taking the deadline, so the mix estimate below is
+    an upper bound on the queries per second one GPU sustains."""
+    import gen
+    import paper_2012_04553_amd as pm
+    pool = gen.query_stream(400 * len(ids) * len(ks) * max(1, per_class), 1e6, len(ids), seed=57,
+                            k_choices=ks)
+    classes = []
+    for gi, gid in enumerate(ids):
+        for k in ks:
+            qs = [q for q in pool if q.graph == gi and q.patterns[0][0] == k][:per_class]
+            reqs = [(0.0, gid, q.patterns, pm.MORPH_COST) for q in qs]
+            res, _ = eng.serve(reqs, max_slots=1, max_batch=1, deadline_s=deadline_s, progress_every=1)
+            svc = sorted(r["service_s"] if r["status"] == 0 else max(r["service_s"], deadline_s) for r in res)
+            setup = [r["setup_s"] for r in res]
+            done = sum(1 for r in res if r["status"] == 0)
+            row = {"graph_n": sizes[gi], "k": k, "queries": len(res), "completed": done,
+                   "timeouts": sum(1 for r in res if r["status"] == -7),
+                   "median_service_s": svc[len(svc) // 2] if svc else None,
+                   "mean_service_s": sum(svc) / len(svc) if svc else None,
+                   "max_service_s": svc[-1] if svc else None,
+                   "mean_setup_s": sum(setup) / len(setup) if setup else None}
+            log(f"  service profile n={sizes[gi]} k={k}: {row}")
+            classes.append(row)
+    means = [c["mean_service_s"] for c in classes if c["mean_service_s"] is not None]
+    mix = sum(means) / len(means) if means else None
+    return {"per_class": per_class, "deadline_s": deadline_s, "classes": classes,
+            "mix_mean_service_s": mix, "mix_qps_upper_bound": (1.0 / mix) if mix else None}
+
+
 def wl_serving(args, eng):
     import gen
     import numpy as np
@@ -378,6 +412,8 @@ def wl_serving(args, eng):
         ids.append(eng.load(g))
         log(f"  Chung-Lu n={n}: m={g.m}")
     ks = tuple(int(x) for x in args.serve_k.split(","))
+    profile = service_profile(eng, ids, sizes, ks, args.serve_profile, args.serve_deadline) \
+        if args.serve_profile > 0 else None
     qs = gen.query_stream(args.serve_queries, args.serve_qps, 4, seed=56, k_choices=ks)
     reqs = [(q.arrival_s, ids[q.graph], q.patterns, pm.MORPH_COST) for q in qs]
     t = time.perf_counter()
@@ -392,7 +428,8 @@ def wl_serving(args, eng):
                       "mean_inflight": st["mean_inflight"], "batches": st["batches"],
                       "sustained_qps": st["sustained_qps"], "offered_qps": args.serve_qps,
                       "mean_setup_s": st["mean_setup_s"], "mean_service_s": st["mean_service_s"],
-                      "makespan_s": st["makespan_s"], "deadline_s": args.serve_deadline}, higher=False)
+                      "makespan_s": st["makespan_s"], "deadline_s": args.serve_deadline,
+                      "service_profile": profile}, higher=False)
     line["roofline"] = None
     line["cpu_baseline"] = None
     return line
@@ -425,6 +462,8 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-k", default="3,4")
     ap.add_argument("--serve-deadline", type=float, default=0.0)
+    ap.add_argument("--serve-profile", type=int, default=0,
+                    help="serving: time this many queries of every (graph, k) class alone first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -47,8 +47,40 @@ typedef __int128 i128;
 
 constexpr uint32_t NOB = 0xffffffffu;  // "no upper bound"
 
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t lo,
-                                                     uint32_t hi, uint32_t x) {
+// Graph arrays, level buffers and bitmaps live in global memory.  Device
+// code reaches them through pointers typed with the global address space, so
+// loads compile as global (not flat) accesses even inside functions that
+// receive the matching context by reference: a flat load also counts against
+// the LDS wait counter, which would make every LDS or cross-lane wait drain
+// the wave's outstanding memory loads.
+#define PM_GLOBAL __attribute__((address_space(1)))
+template <class T> using gcp = const PM_GLOBAL T*;
+template <class T> using gp = PM_GLOBAL T*;
+
+struct DGraph {
+    gcp<uint32_t> rp, col, split;
+    gcp<uint8_t> lab;
+    uint32_t n;
+};
+
+// Copy of a plan record (plain words) out of global memory.
+template <class T>
+__device__ __forceinline__ T gload(const PM_GLOBAL T* p) {
+    static_assert(sizeof(T) % 4 == 0, "plan records are whole words");
+    T out;
+    uint32_t* o = (uint32_t*)&out;
+    const PM_GLOBAL uint32_t* w = (const PM_GLOBAL uint32_t*)p;
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(T) / 4; ++i) o[i] = w[i];
+    return out;
+}
+
+__device__ __forceinline__ DGraph dgraph(const KGraph& g) {
+    return DGraph{(gcp<uint32_t>)g.rp, (gcp<uint32_t>)g.col, (gcp<uint32_t>)g.split, (gcp<uint8_t>)g.lab, g.n};
+}
+
+template <class P>
+__device__ __forceinline__ uint32_t lower_bound_u32(P a, uint32_t lo, uint32_t hi, uint32_t x) {
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
         if (a[mid] < x) lo = mid + 1;
@@ -59,8 +91,8 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
 
 // First position in a[lo, hi) holding a value >= x, searching outward from
 // lo (cheap when the answer is near lo).
-__device__ __forceinline__ uint32_t gallop_u32(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
-                                               uint32_t x) {
+template <class P>
+__device__ __forceinline__ uint32_t gallop_u32(P a, uint32_t lo, uint32_t hi, uint32_t x) {
     uint32_t step = 1, b = lo;
     while (b < hi && a[b] < x) {
         lo = b + 1;
@@ -70,15 +102,16 @@ __device__ __forceinline__ uint32_t gallop_u32(const uint32_t* __restrict__ a, u
     return lower_bound_u32(a, lo, b < hi ? b : hi, x);
 }
 
-__device__ __forceinline__ bool in_sorted(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi,
-                                          uint32_t x) {
+template <class P>
+__device__ __forceinline__ bool in_sorted(P a, uint32_t lo, uint32_t hi, uint32_t x) {
     uint32_t p = lower_bound_u32(a, lo, hi, x);
     return p < hi && a[p] == x;
 }
 
 // Entries of N(v) within [lo, hi): the split index (first neighbour above
 // v) answers the common bounds lo = v+1 and hi = v without a search.
-__device__ __forceinline__ void list_range(const KGraph& g, uint32_t v, uint32_t lo, uint32_t hi,
+template <class GR>
+__device__ __forceinline__ void list_range(const GR& g, uint32_t v, uint32_t lo, uint32_t hi,
                                            uint32_t& b, uint32_t& e) {
     const uint32_t s = g.rp[v], t = g.rp[v + 1], sp = g.split[v];
     if (lo == 0) b = s;
@@ -101,15 +134,15 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
 }
 
 struct Ctx {
-    KGraph g;
-    const DPlan* P;
+    DGraph g;
+    gcp<DPlan> P;
     uint32_t v[KMAX];        // wave-uniform prefix of the core match
-    uint32_t* buf;           // per-wave level buffers
+    gp<uint32_t> buf;        // per-wave level buffers
     uint64_t stride;
     uint32_t size[KMAX];     // entries in each level buffer
     uint64_t bytes;          // algorithmic bytes (counting build only)
-    uint32_t* bmw;           // this wave's root bitmap (n bits) or null
-    const uint32_t* bm;      // bmw while it holds N(v0), else null
+    gp<uint32_t> bmw;        // this wave's root bitmap (n bits) or null
+    gcp<uint32_t> bm;        // bmw while it holds N(v0), else null
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -143,7 +176,8 @@ __device__ __forceinline__ uint64_t range_mask(uint32_t a, uint32_t b) {
     return m << a;
 }
 
-__device__ __forceinline__ bool bm_test(const uint32_t* bm, uint32_t x) {
+template <class P>
+__device__ __forceinline__ bool bm_test(P bm, uint32_t x) {
     return (bm[x >> 5] >> (x & 31)) & 1u;
 }
 
@@ -194,7 +228,8 @@ __device__ __forceinline__ void bounds_of(const uint32_t* vv, uint8_t gt, uint8_
 }
 
 // Shortest bounded adjacency list among `adj` (per lane when vv differs).
-__device__ __forceinline__ int pick_driver(const KGraph& g, const uint32_t* vv, uint8_t adj, uint32_t lo,
+template <class GR>
+__device__ __forceinline__ int pick_driver(const GR& g, const uint32_t* vv, uint8_t adj, uint32_t lo,
                                            uint32_t hi, uint32_t& b, uint32_t& e) {
     uint32_t best = NOB;
     int bi = 0;
@@ -309,8 +344,8 @@ __device__ __forceinline__ bool merge_ok(const Ctx& c, const uint32_t* vv, const
 // cursor stands on an equal entry as it is taken.  The lanes count their
 // matches, a wave prefix sum places them, and a second merge writes them,
 // so the output is sorted.  Every read stays inside A[0, la) and B[0, lb).
-__device__ uint32_t merge_level(const Ctx& c, const uint32_t* A, uint32_t la, const uint32_t* B, uint32_t lb,
-                                const Probe& pr, uint32_t* out) {
+__device__ uint32_t merge_level(const Ctx& c, gcp<uint32_t> A, uint32_t la, gcp<uint32_t> B, uint32_t lb,
+                                const Probe& pr, gp<uint32_t> out) {
     const uint32_t lane = (uint32_t)wave_lane();
     const uint32_t total = la + lb;
     const uint32_t len = (total + 63) / 64;
@@ -359,17 +394,17 @@ __device__ uint32_t merge_level(const Ctx& c, const uint32_t* A, uint32_t la, co
 // driver and test each entry against the probe lists by binary search.
 template <bool BYTES>
 __device__ uint32_t wave_level(Ctx& c, int j) {
-    const DLevel L = c.P->lev[j];
+    const DLevel L = gload(&c.P->lev[j]);
     const int lane = wave_lane();
     uint32_t lo, hi;
     bounds_of(c.v, L.gt, L.lt, lo, hi);
-    uint32_t* out = c.buf + (uint64_t)j * c.stride;
+    gp<uint32_t> out = c.buf + (uint64_t)j * c.stride;
     if (lo >= hi) return 0;
-    const uint32_t* drv;
+    gcp<uint32_t> drv;
     uint32_t b, e;
     uint8_t chk = L.adj, anti = L.anti;
     if (L.base != 0xff) {
-        const uint32_t* bb = c.buf + (uint64_t)L.base * c.stride;
+        gcp<uint32_t> bb = c.buf + (uint64_t)L.base * c.stride;
         uint32_t n = c.size[L.base];
         b = lo ? lower_bound_u32(bb, 0, n, lo) : 0;
         e = hi != NOB ? lower_bound_u32(bb, b, n, hi) : n;
@@ -416,14 +451,14 @@ __device__ uint32_t wave_level(Ctx& c, int j) {
 // Every function below is called by all 64 lanes together (it reads other
 // lanes); `valid` marks the lanes that hold a partial match.
 
-template <bool BYTES>
+template <bool BYTES, bool SMALL = false>
 __device__ u128 lanes_tail(Ctx& c, const uint32_t* vv, bool valid, uint64_t aggm);
 
-__device__ __forceinline__ u128 poly_eval(const DPlan* P, const uint64_t* tv) {
+__device__ __forceinline__ u128 poly_eval(gcp<DPlan> P, const uint64_t* tv) {
     i128 s = 0;
     const int nm = P->nmono;
     for (int m = 0; m < nm; ++m) {
-        const DMono M = P->mono[m];
+        const DMono M = gload(&P->mono[m]);
         i128 prod = (i128)M.coef;
         for (int f = 0; f < M.nf; ++f) prod *= (i128)tv[M.f[f]];
         s += prod;
@@ -459,7 +494,7 @@ __device__ __forceinline__ uint64_t cheap_term(Ctx& c, const uint32_t* vv, const
 // vv_owner + {v_j = x} and adds its tail to `acc` (on the lane that tested
 // x); the return value is then 0.
 template <int MODE, bool BYTES>
-__device__ uint64_t flat_filter(Ctx& c, const uint32_t* vv, const uint32_t* drv, uint32_t b, uint32_t len,
+__device__ uint64_t flat_filter(Ctx& c, const uint32_t* vv, gcp<uint32_t> drv, uint32_t b, uint32_t len,
                                 const Probe& pr, uint8_t lists, int j, u128& acc) {
     const int lane = wave_lane();
     const uint32_t incl = wave_incl_scan(len);
@@ -508,12 +543,47 @@ __device__ uint64_t flat_term(Ctx& c, const uint32_t* vv, bool valid, const DTer
     return flat_filter<0, BYTES>(c, vv, c.g.col, b, e - b, pr, (uint8_t)(t.adj | t.anti), 0, dummy);
 }
 
+// Tails of at most SMALL_TERMS terms (the common case) keep the term values
+// in registers: a dynamically indexed array would live in per-lane scratch
+// memory, whose traffic goes through the L2 for every evaluated match.
+constexpr int SMALL_TERMS = 4;
+
+__device__ __forceinline__ uint64_t pick4(uint32_t i, uint64_t t0, uint64_t t1, uint64_t t2, uint64_t t3) {
+    return i == 0 ? t0 : (i == 1 ? t1 : (i == 2 ? t2 : t3));
+}
+
 template <bool BYTES>
+__device__ __forceinline__ uint64_t term_value(Ctx& c, const uint32_t* vv, bool valid, const DTerm& t,
+                                               uint64_t aggm) {
+    if (t.agg || t.cheap) return valid ? cheap_term<BYTES>(c, vv, t, aggm) : 0;
+    return flat_term<BYTES>(c, vv, valid, t);
+}
+
+template <bool BYTES, bool SMALL>
 __device__ u128 lanes_tail(Ctx& c, const uint32_t* vv, bool valid, uint64_t aggm) {
-    uint64_t tv[MAX_TERMS];
     const int nt = c.P->nterm;
+    if (SMALL && nt <= SMALL_TERMS) {
+        uint64_t t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        if (nt > 0) t0 = term_value<BYTES>(c, vv, valid, gload(&c.P->term[0]), aggm);
+        if (nt > 1) t1 = term_value<BYTES>(c, vv, valid, gload(&c.P->term[1]), aggm);
+        if (nt > 2) t2 = term_value<BYTES>(c, vv, valid, gload(&c.P->term[2]), aggm);
+        if (nt > 3) t3 = term_value<BYTES>(c, vv, valid, gload(&c.P->term[3]), aggm);
+        if (!valid) return 0;
+        i128 s = 0;
+        const int nm = c.P->nmono;
+        for (int m = 0; m < nm; ++m) {
+            const DMono M = gload(&c.P->mono[m]);
+            i128 prod = (i128)M.coef;
+#pragma unroll
+            for (int f = 0; f < MAX_FAC; ++f)
+                if (f < M.nf) prod *= (i128)pick4(M.f[f], t0, t1, t2, t3);
+            s += prod;
+        }
+        return s > 0 ? (u128)s : (u128)0;
+    }
+    uint64_t tv[MAX_TERMS];
     for (int q = 0; q < nt; ++q) {
-        const DTerm t = c.P->term[q];
+        const DTerm t = gload(&c.P->term[q]);
         if (t.agg || t.cheap) tv[q] = valid ? cheap_term<BYTES>(c, vv, t, aggm) : 0;
         else tv[q] = flat_term<BYTES>(c, vv, valid, t);
     }
@@ -525,16 +595,16 @@ __device__ u128 lanes_tail(Ctx& c, const uint32_t* vv, bool valid, uint64_t aggm
 // every extension.
 template <int MODE, bool BYTES>
 __device__ void lanes_level(Ctx& c, const uint32_t* vv, bool valid, int j, u128& acc) {
-    const DLevel L = c.P->lev[j];
+    const DLevel L = gload(&c.P->lev[j]);
     uint32_t lo, hi, b = 0, e = 0;
     bounds_of(vv, L.gt, L.lt, lo, hi);
     const bool on = valid && lo < hi;
-    const uint32_t* drv = c.g.col;
+    gcp<uint32_t> drv = c.g.col;
     uint8_t chk = L.adj, anti = L.anti;
     Probe pr;
     clear_probe(pr, L.neq, L.label);
     if (L.base != 0xff) {
-        const uint32_t* bb = c.buf + (uint64_t)L.base * c.stride;
+        gcp<uint32_t> bb = c.buf + (uint64_t)L.base * c.stride;
         chk &= (uint8_t)~c.P->lev[L.base].adj;
         anti &= (uint8_t)~c.P->lev[L.base].anti;
         drv = bb;
@@ -585,8 +655,8 @@ __device__ __forceinline__ uint32_t wave_take(uint32_t* p) {
 template <bool BYTES>
 __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const KArgs& a, u128& acc,
                           uint32_t s0 = 0, uint32_t s1 = 0xffffffffu) {
-    const DPlan* P = c.P;
-    const DLevel L = P->lev[j];
+    gcp<DPlan> P = c.P;
+    const DLevel L = gload(&P->lev[j]);
     const int lane = wave_lane();
     uint32_t* cnt = a.aggcnt + (uint64_t)wid * c.g.n;
     uint32_t* touched = a.aggtouch + (uint64_t)wid * c.g.n;
@@ -678,14 +748,14 @@ __device__ void local_clique(Ctx& c, uint32_t s0, uint32_t s1, u128& acc) {
     if (BYTES && lane == 0) c.bytes += 8 + 4ull * s;
     if (s < (uint32_t)(nc - 1) || s0 >= s) return;
     const uint32_t W = (s + 63) >> 6;
-    uint64_t* rows = (uint64_t*)c.buf;
-    const uint32_t* C1 = c.g.col + b;
+    gp<uint64_t> rows = (gp<uint64_t>)c.buf;
+    gcp<uint32_t> C1 = c.g.col + b;
     for (uint32_t i = lane; i < s; i += 64) {
         const uint32_t x = C1[i];
         uint32_t p = c.g.split[x];
         const uint32_t pe = c.g.rp[x + 1];
         if (BYTES) c.bytes += 8 + 4ull * (pe - p) + 4ull * (s - i - 1);
-        uint64_t* row = rows + (uint64_t)i * W;
+        gp<uint64_t> row = rows + (uint64_t)i * W;
         uint32_t q = i + 1;
         uint32_t cw = q >> 6;
         for (uint32_t w = 0; w < cw && w < W; ++w) row[w] = 0;
@@ -710,7 +780,7 @@ __device__ void local_clique(Ctx& c, uint32_t s0, uint32_t s1, u128& acc) {
     __builtin_amdgcn_wave_barrier();
     const uint32_t ie = min(s, s1);
     for (uint32_t i = s0 + lane; i < ie; i += 64) {
-        const uint64_t* ri = rows + (uint64_t)i * W;
+        gcp<uint64_t> ri = rows + (uint64_t)i * W;
         uint64_t cnt = 0;
         if (nc == 3) {
             for (uint32_t w = 0; w < W; ++w) cnt += __popcll(ri[w]);
@@ -720,7 +790,7 @@ __device__ void local_clique(Ctx& c, uint32_t s0, uint32_t s1, u128& acc) {
                 while (m) {
                     const uint32_t j = (w << 6) + __builtin_ctzll(m);
                     m &= m - 1;
-                    const uint64_t* rj = rows + (uint64_t)j * W;
+                    gcp<uint64_t> rj = rows + (uint64_t)j * W;
                     if (nc == 4) {
                         for (uint32_t w2 = j >> 6; w2 < W; ++w2) cnt += __popcll(ri[w2] & rj[w2]);
                     } else {
@@ -729,7 +799,7 @@ __device__ void local_clique(Ctx& c, uint32_t s0, uint32_t s1, u128& acc) {
                             while (t) {
                                 const uint32_t k = (w2 << 6) + __builtin_ctzll(t);
                                 t &= t - 1;
-                                const uint64_t* rk = rows + (uint64_t)k * W;
+                                gcp<uint64_t> rk = rows + (uint64_t)k * W;
                                 for (uint32_t w3 = k >> 6; w3 < W; ++w3) cnt += __popcll(ri[w3] & rj[w3] & rk[w3]);
                             }
                         }
@@ -776,10 +846,10 @@ __device__ __forceinline__ void flush(const KArgs& a, int plan, u128 acc) {
 // the match (j = ncore - 2).
 template <bool BYTES>
 __device__ __forceinline__ void lanes_finish(Ctx& c, int j, uint32_t b, uint32_t e, u128& acc) {
-    const DPlan* P = c.P;
+    gcp<DPlan> P = c.P;
     const int lane = wave_lane();
     const int last = P->ncore - 1;
-    const uint32_t* bj = c.buf + (uint64_t)j * c.stride;
+    gcp<uint32_t> bj = c.buf + (uint64_t)j * c.stride;
     for (uint32_t base = b; base < e; base += 64) {
         const uint32_t idx = base + lane;
         const bool valid = idx < e;
@@ -809,11 +879,11 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     uint32_t* my_touch = &s_touch[threadIdx.x >> 6];
     Ctx c;
-    c.g = a.g;
+    c.g = dgraph(a.g);
     c.stride = a.buf_stride;
-    c.buf = a.scratch + (uint64_t)wid * (uint64_t)KMAX * a.buf_stride;
+    c.buf = (gp<uint32_t>)(a.scratch + (uint64_t)wid * (uint64_t)KMAX * a.buf_stride);
     c.bytes = 0;
-    c.bmw = a.rootbm ? a.rootbm + (uint64_t)wid * a.bm_words : nullptr;
+    c.bmw = a.rootbm ? (gp<uint32_t>)(a.rootbm + (uint64_t)wid * a.bm_words) : nullptr;
     c.bm = nullptr;
     int cur = -1;
     u128 acc = 0;
@@ -839,7 +909,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             acc = 0;
             cur = pi;
         }
-        const DPlan* P = a.plans + pi;
+        gcp<DPlan> P = (gcp<DPlan>)a.plans + pi;
         c.P = P;
         const int nc = P->ncore;
         const int8_t rl = P->lev[0].label;
@@ -876,7 +946,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                     if (lane == 0 && e > b) acc += (u128)(e - b) * (u128)(uint32_t)P->mult;
                     continue;
                 }
-                const uint32_t* b1 = c.buf + c.stride;
+                gcp<uint32_t> b1 = c.buf + c.stride;
                 const bool usebm = P->bm0 && c.bmw && e > b;
                 if (usebm) bm_build(c, r);
                 for (uint32_t base = b; base < e; base += 64) {
@@ -1109,42 +1179,78 @@ __global__ void __launch_bounds__(256) cycle5_kernel(KArgs a) {
 // ---------------------------------------------------------------- heavy two-hop roots
 
 // Roots of a plan whose first level is the aggregation level and whose
-// two-hop mass is large: one workgroup takes one root and counts the paths
-// to each target in an LDS window of WIN_IDS consecutive target ids.
-// Device-scope atomics are executed in memory on this GPU, LDS atomics in
-// the CU, so the sweep is bounded by reading the bridges' lists.  Every
-// thread owns some of the root's bridges and keeps, per bridge, a cursor
-// and the next target (in scratch only it touches): a bridge without a
-// target in the current window costs one read.  Each window starts at the
-// smallest pending target, so empty id ranges are never visited; after a
-// window is filled the four waves evaluate its counters and clear them.
-constexpr uint32_t WIN_IDS = 8192;
-constexpr int AW_UNROLL = 4;
+// two-hop mass is large: one workgroup, alone on its CU, takes one root (or
+// one slice of its target ids) and counts the paths r - y - x to each target
+// x in an LDS window of consecutive target ids.  LDS atomics run in the CU,
+// so the sweep is bounded by reading the bridges' lists; the window is as
+// large as the CU's LDS allows (128 KB of counters), so a bridge's list is
+// cut into few pieces and most of its cache lines are read once.
+//
+// Every bridge keeps a cursor, the end of its list and its next target (in
+// global scratch owned by the workgroup): a bridge without a target in the
+// current window costs one read of that state.  Each window starts at the
+// smallest pending target, so empty id ranges are never visited.  Waves take
+// 64 bridges at a time from a shared counter, find each bridge's targets in
+// the window by galloping from its cursor, and stream them flattened.  The
+// first touch of a target marks its 64-id group; after the window is
+// filled, the waves walk the marked groups, clear their counters, compact
+// the touched targets into a per-wave queue and evaluate the tail 64
+// targets at a time.
+#ifndef PM_AW_THREADS
+#define PM_AW_THREADS 1024
+#endif
+#ifndef PM_AW_WORDS
+#define PM_AW_WORDS 32768
+#endif
+#ifndef PM_AW_UNROLL
+#define PM_AW_UNROLL 4
+#endif
+constexpr uint32_t AW_THREADS = PM_AW_THREADS;
+constexpr uint32_t AW_WAVES = AW_THREADS / 64;
+constexpr uint32_t AW_WORDS = PM_AW_WORDS;   // counter words (128 KB by default)
+constexpr uint32_t AW_QCAP = 128;            // per-wave queue of touched targets
+constexpr int AW_UNROLL = PM_AW_UNROLL;
+#ifndef PM_AW_LONG
+#define PM_AW_LONG 64
+#endif
+constexpr uint32_t AW_LONG = PM_AW_LONG;     // a segment this long is streamed by the whole wave
+// workgroups of this kernel that fit one CU's 160 KB of LDS
+constexpr int AW_CU_BLOCKS = (int)(160u * 1024u / (AW_WORDS * 4u + AW_WAVES * AW_QCAP * 6u + 4096u));
+static_assert(AW_CU_BLOCKS >= 1, "window does not fit the LDS");
 
 // With H16 (a graph whose degrees fit 16 bits, so does every path count)
-// two counters share a word: 16 KB of counters instead of 32 KB, four
-// workgroups a CU instead of three.
+// two counters share a word and the window covers twice as many ids.
 template <bool BYTES, bool H16>
-__global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
-    constexpr uint32_t WIN_WORDS = H16 ? WIN_IDS / 2 : WIN_IDS;
-    __shared__ uint32_t win[WIN_WORDS];
-    __shared__ uint16_t used[WIN_IDS];   // touched window offsets, in first-touch order
-    __shared__ uint32_t s_item, s_next[2], s_nused[2];
+__global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
+    constexpr uint32_t WIN_IDS = H16 ? 2 * AW_WORDS : AW_WORDS;
+    constexpr uint32_t NGROUPS = WIN_IDS / 64;
+    __shared__ uint32_t win[AW_WORDS];
+    __shared__ uint32_t gbits[NGROUPS / 32];
+    __shared__ uint16_t glist[NGROUPS];
+    __shared__ uint16_t qoff[AW_WAVES][AW_QCAP];
+    __shared__ uint32_t qm[AW_WAVES][AW_QCAP];
+    __shared__ uint32_t s_item, s_next[2], s_ng[2], s_batch;
     const int lane = wave_lane();
     const uint32_t tid = threadIdx.x;
-    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t w = tid >> 6;
+    // the sweep reads the graph through this copy, which never leaves
+    // registers, so its loads compile as global (not flat) accesses; the
+    // tail evaluation gets the graph through the context
+    const KGraph G = a.g;
     Ctx c;
-    c.g = a.g;
-    c.stride = a.buf_stride;
-    c.buf = a.scratch + (uint64_t)wid * (uint64_t)KMAX * a.buf_stride;
+    c.g = dgraph(a.g);
+    c.stride = 0;
+    c.buf = nullptr;   // tails need no level buffers
     c.bytes = 0;
     c.bmw = nullptr;
     c.bm = nullptr;
-    // per owned bridge: cursor, end of its target range, next target
+    // per bridge: cursor, end of its list, next target
     uint32_t* cur = a.wscr + (uint64_t)blockIdx.x * (2 + EW_TERMS) * a.wscr_stride;
     uint32_t* fin = cur + a.wscr_stride;
     uint32_t* nxt = fin + a.wscr_stride;
-    for (uint32_t i = tid; i < WIN_WORDS; i += blockDim.x) win[i] = 0;
+    uint32_t* lst = nxt + a.wscr_stride;   // last target of the bridge below `top`
+    for (uint32_t i = tid; i < AW_WORDS; i += AW_THREADS) win[i] = 0;
+    for (uint32_t i = tid; i < NGROUPS / 32; i += AW_THREADS) gbits[i] = 0;
     int curp = -1;
     u128 acc = 0;
     const uint64_t total = (uint64_t)a.nplans * a.nitems;
@@ -1154,8 +1260,9 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
             uint32_t it = atomicAdd(a.head, 1u);
             if (a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) it = 0xffffffffu;
             s_item = it;
-            s_next[0] = s_next[1] = 0xffffffffu;
-            s_nused[0] = s_nused[1] = 0;
+            s_next[0] = s_next[1] = NOB;
+            s_ng[0] = s_ng[1] = 0;
+            s_batch = 0;
         }
         __syncthreads();
         const uint32_t it = s_item;
@@ -1167,11 +1274,11 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
             acc = 0;
             curp = pi;
         }
-        const DPlan* P = a.plans + pi;
+        gcp<DPlan> P = (gcp<DPlan>)a.plans + pi;
         c.P = P;
-        const DLevel L = P->lev[1];
+        const DLevel L = gload(&P->lev[1]);
         const uint32_t r = item.r0;
-        if (P->lev[0].label >= 0 && a.g.lab[r] != (uint8_t)P->lev[0].label) continue;
+        if (P->lev[0].label >= 0 && G.lab[r] != (uint8_t)P->lev[0].label) continue;
         c.v[0] = r;
         uint32_t blo, bhi, lo, hi;
         bounds_of(c.v, P->bridge_gt, P->bridge_lt, blo, bhi);
@@ -1187,25 +1294,36 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
         }
         const uint32_t top = hi;
         uint32_t bb, be;
-        list_range(c.g, r, blo, bhi, bb, be);
+        list_range(G, r, blo, bhi, bb, be);
         const uint32_t nb = be - bb;
         if (BYTES && tid == 0 && item.s0 == 0) c.bytes += 8 + 4ull * nb;
-        uint32_t mine = 0xffffffffu;
-        for (uint32_t k = tid; k < nb; k += blockDim.x) {
-            const uint32_t y = c.g.col[bb + k];
-            uint32_t yb = 0, yf = 0;
-            const bool ok = y != r && (P->bridge_label < 0 || c.g.lab[y] == (uint8_t)P->bridge_label);
+        // bridge set-up: the cursor starts at the first target >= lo; the
+        // end is the end of the list (targets at or above `top` end the
+        // bridge when they come up as its next target)
+        uint32_t mine = NOB;
+        for (uint32_t k = tid; k < nb; k += AW_THREADS) {
+            const uint32_t y = G.col[bb + k];
+            const bool ok = y != r && (P->bridge_label < 0 || G.lab[y] == (uint8_t)P->bridge_label);
+            uint32_t yb = 0, yf = 0, x = NOB, xl = 0;
             if (ok) {
-                list_range(c.g, y, lo, hi, yb, yf);
-                if (BYTES) c.bytes += 8 + 4ull * (yf - yb);
+                const uint32_t s = G.rp[y];
+                yf = G.rp[y + 1];
+                yb = lo == 0 ? s : lower_bound_u32(G.col, s, yf, lo);
+                if (yb < yf) {
+                    x = G.col[yb];
+                    xl = G.col[yf - 1];
+                    if (x >= top) x = NOB;
+                }
+                if (BYTES) c.bytes += 8 + 4ull * (lower_bound_u32(G.col, yb, yf, top) - yb);
             }
-            const uint32_t x = yb < yf ? c.g.col[yb] : 0xffffffffu;
             cur[k] = yb;
             fin[k] = yf;
             nxt[k] = x;
+            lst[k] = xl;
             mine = min(mine, x);
         }
-        if (mine != 0xffffffffu) atomicMin(&s_next[0], mine);
+        for (int off = 32; off >= 1; off >>= 1) mine = min(mine, (uint32_t)__shfl_xor(mine, off));
+        if (lane == 0 && mine != NOB) atomicMin(&s_next[0], mine);
         __syncthreads();
         uint32_t vv[KMAX];
 #pragma unroll
@@ -1213,53 +1331,82 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
         int ph = 0;
         for (;;) {
             const uint32_t wlo = s_next[ph];
-            if (wlo == 0xffffffffu || wlo >= top) break;
+            if (wlo == NOB || wlo >= top) break;
             const uint32_t whi = (uint32_t)min((uint64_t)top, (uint64_t)wlo + WIN_IDS);
-            // fill: each wave takes 64 bridges at a time; a bridge's targets
-            // inside the window are found by galloping from its cursor and
-            // the wave streams all of them flattened; every bridge offers
-            // its next target for the next window
-            mine = 0xffffffffu;
-            for (uint32_t kb = (tid & ~63u); kb < nb; kb += blockDim.x) {
+            // fill
+            mine = NOB;
+            for (;;) {
+                uint32_t kb = 0;
+                if (lane == 0) kb = atomicAdd(&s_batch, 64u);
+                kb = __shfl(kb, 0);
+                if (kb >= nb) break;
                 const uint32_t k = kb + lane;
                 const bool valid = k < nb;
-                const uint32_t x0 = valid ? nxt[k] : 0xffffffffu;
+                const uint32_t x0 = valid ? nxt[k] : NOB;
                 const uint32_t q = valid ? cur[k] : 0u, qe = valid ? fin[k] : 0u;
-                const uint32_t qend = x0 < whi ? gallop_u32(c.g.col, q, qe, whi) : q;
+                // the whole rest of the list lies in the window when its last
+                // entry does; else gallop to the window's end
+                const uint32_t qend = x0 >= whi ? q : (lst[k] < whi ? qe : gallop_u32(G.col, q, qe, whi));
                 const uint32_t len = qend - q;
-                const uint32_t incl = wave_incl_scan(len);
+                // a window target: count it; its first touch marks its group
+                auto take = [&](uint32_t x) {
+                    if ((L.label >= 0 && G.lab[x] != (uint8_t)L.label) || ((L.neq & 1) && x == r)) return;
+                    const uint32_t off = x - wlo;
+                    bool first;
+                    if (H16) {
+                        const uint32_t sh = (off & 1u) * 16;
+                        first = ((atomicAdd(&win[off >> 1], 1u << sh) >> sh) & 0xffffu) == 0u;
+                    } else {
+                        first = atomicAdd(&win[off], 1u) == 0u;
+                    }
+                    if (first) {
+                        const uint32_t g = off >> 6, bit = 1u << (g & 31);
+                        if (!(gbits[g >> 5] & bit) && !(atomicOr(&gbits[g >> 5], bit) & bit))
+                            glist[atomicAdd(&s_ng[ph], 1u)] = (uint16_t)g;
+                    }
+                };
+                // long segments (most of the entries: hub bridges) are
+                // streamed by the whole wave, one after the other, with
+                // coalesced reads and no search for an entry's owner
+                uint64_t longm = __ballot(len >= AW_LONG);
+                while (longm) {
+                    const int o = __builtin_ctzll(longm);
+                    longm &= longm - 1;
+                    const uint32_t qo = __builtin_amdgcn_readlane(q, o), lo_len = __builtin_amdgcn_readlane(len, o);
+                    for (uint32_t tb = 0; tb < lo_len; tb += 64 * AW_UNROLL) {
+                        uint32_t xs[AW_UNROLL];
+#pragma unroll
+                        for (int u = 0; u < AW_UNROLL; ++u) {
+                            const uint32_t t = tb + (uint32_t)(u * 64) + lane;
+                            xs[u] = t < lo_len ? G.col[qo + t] : NOB;
+                        }
+#pragma unroll
+                        for (int u = 0; u < AW_UNROLL; ++u)
+                            if (xs[u] != NOB) take(xs[u]);
+                    }
+                }
+                // short segments: flattened over the lanes
+                const uint32_t slen = len >= AW_LONG ? 0u : len;
+                const uint32_t incl = wave_incl_scan(slen);
                 const uint32_t tot = __shfl(incl, 63);
-                const uint32_t excl = incl - len;
-                // AW_UNROLL reads in flight per lane
+                const uint32_t excl = incl - slen;
                 for (uint32_t tb = 0; tb < tot; tb += 64 * AW_UNROLL) {
                     uint32_t xs[AW_UNROLL];
-                    bool acts[AW_UNROLL];
 #pragma unroll
                     for (int u = 0; u < AW_UNROLL; ++u) {
                         const uint32_t t = tb + (uint32_t)(u * 64) + lane;
-                        acts[u] = t < tot;
-                        const int o = owner_of(incl, acts[u] ? t : tot - 1);
+                        const bool act = t < tot;
+                        const int o = owner_of(incl, act ? t : tot - 1);
                         const uint32_t src = __shfl(q, o) + (t - __shfl(excl, o));
-                        xs[u] = acts[u] ? c.g.col[src] : 0u;
+                        xs[u] = act ? G.col[src] : NOB;
                     }
 #pragma unroll
-                    for (int u = 0; u < AW_UNROLL; ++u) {
-                        const uint32_t x = xs[u];
-                        if (acts[u] && (L.label < 0 || c.g.lab[x] == (uint8_t)L.label) && !((L.neq & 1) && x == r)) {
-                            const uint32_t off = x - wlo;
-                            bool first;
-                            if (H16) {
-                                const uint32_t sh = (off & 1u) * 16;
-                                first = ((atomicAdd(&win[off >> 1], 1u << sh) >> sh) & 0xffffu) == 0u;
-                            } else {
-                                first = atomicAdd(&win[off], 1u) == 0u;
-                            }
-                            if (first) used[atomicAdd(&s_nused[ph], 1u)] = (uint16_t)off;
-                        }
-                    }
+                    for (int u = 0; u < AW_UNROLL; ++u)
+                        if (xs[u] != NOB) take(xs[u]);
                 }
                 if (valid) {
-                    const uint32_t xn = !len ? x0 : (qend < qe ? c.g.col[qend] : 0xffffffffu);
+                    uint32_t xn = !len ? x0 : (qend < qe ? G.col[qend] : NOB);
+                    if (xn >= top) xn = NOB;
                     if (len) {
                         cur[k] = qend;
                         nxt[k] = xn;
@@ -1267,31 +1414,62 @@ __global__ void __launch_bounds__(256) agg_window_kernel(KArgs a) {
                     mine = min(mine, xn);
                 }
             }
-            if (mine != 0xffffffffu) atomicMin(&s_next[ph ^ 1], mine);
+            for (int off = 32; off >= 1; off >>= 1) mine = min(mine, (uint32_t)__shfl_xor(mine, off));
+            if (lane == 0 && mine != NOB) atomicMin(&s_next[ph ^ 1], mine);
             __syncthreads();
-            const uint32_t nu = s_nused[ph];
+            const uint32_t ng = s_ng[ph];
             if (tid == 0) {
-                s_next[ph] = 0xffffffffu;   // read by every thread before the barrier
-                s_nused[ph ^ 1] = 0;        // next window's list; last read a window ago
+                s_next[ph] = NOB;   // read by every thread before the barrier
+                s_ng[ph ^ 1] = 0;   // next window's group count; last read a window ago
+                s_batch = 0;        // every wave has left the fill
             }
-            // evaluate and clear the touched counters, 64 per wave at a time
-            for (uint32_t base = (tid & ~63u); base < nu; base += blockDim.x) {
-                const uint32_t idx = base + lane;
-                uint32_t m = 0, i = 0;
-                if (idx < nu) {
-                    i = used[idx];
-                    if (H16) {
-                        // each half is read and cleared by its own lane only
-                        const uint32_t sh = (i & 1u) * 16;
-                        m = (win[i >> 1] >> sh) & 0xffffu;
-                        atomicAnd(&win[i >> 1], ~(0xffffu << sh));
-                    } else {
-                        m = win[i];
-                        win[i] = 0;
-                    }
+            for (uint32_t i = tid; i < NGROUPS / 32; i += AW_THREADS) gbits[i] = 0;
+            // evaluate: walk the marked groups, clear their counters, queue
+            // the touched targets, evaluate 64 at a time
+            uint32_t qn = 0;
+            for (uint32_t gi = w; gi < ng; gi += AW_WAVES) {
+                const uint32_t off = ((uint32_t)glist[gi] << 6) + (uint32_t)lane;
+                uint32_t m;
+                if (H16) {
+                    m = (win[off >> 1] >> ((off & 1u) * 16)) & 0xffffu;
+                    __builtin_amdgcn_wave_barrier();
+                    if (!(off & 1u)) win[off >> 1] = 0u;
+                } else {
+                    m = win[off];
+                    win[off] = 0u;
                 }
-                vv[1] = wlo + i;
-                acc += lanes_tail<BYTES>(c, vv, m != 0, m);
+                const uint64_t mask = __ballot(m != 0u);
+                if (m) {
+                    const uint32_t pos = qn + lane_prefix(mask);
+                    qoff[w][pos] = (uint16_t)off;
+                    qm[w][pos] = m;
+                }
+                qn += (uint32_t)__popcll(mask);
+                if (qn >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    const uint32_t eo = qoff[w][lane], em = qm[w][lane];
+                    const uint32_t rest = qn - 64;
+                    uint32_t ro = 0, rm = 0;
+                    if ((uint32_t)lane < rest) {
+                        ro = qoff[w][64 + lane];
+                        rm = qm[w][64 + lane];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    if ((uint32_t)lane < rest) {
+                        qoff[w][lane] = (uint16_t)ro;
+                        qm[w][lane] = rm;
+                    }
+                    qn = rest;
+                    vv[1] = wlo + eo;
+                    acc += lanes_tail<BYTES, true>(c, vv, true, em);
+                }
+            }
+            if (qn) {
+                __builtin_amdgcn_wave_barrier();
+                const bool act = (uint32_t)lane < qn;
+                const uint32_t eo = act ? qoff[w][lane] : 0u, em = act ? qm[w][lane] : 0u;
+                vv[1] = wlo + eo;
+                acc += lanes_tail<BYTES, true>(c, vv, act, em);
             }
             __syncthreads();
             ph ^= 1;
@@ -1325,7 +1503,7 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
     const int lane = wave_lane();
     const uint32_t tid = threadIdx.x;
     Ctx c;
-    c.g = a.g;
+    c.g = dgraph(a.g);
     c.stride = a.buf_stride;
     c.buf = nullptr;
     c.bytes = 0;
@@ -1356,9 +1534,9 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
             acc = 0;
             curp = pi;
         }
-        const DPlan* P = a.plans + pi;
+        gcp<DPlan> P = (gcp<DPlan>)a.plans + pi;
         c.P = P;
-        const DLevel L1 = P->lev[1];
+        const DLevel L1 = gload(&P->lev[1]);
         const uint32_t r = item.r0;
         if (P->lev[0].label >= 0 && a.g.lab[r] != (uint8_t)P->lev[0].label) continue;
         c.v[0] = r;
@@ -1424,7 +1602,7 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
                     const uint32_t s0 = max(excl, tb), s1 = min(incl, tb + 64);
                     const uint64_t seg = s0 < s1 ? range_mask(s0 - tb, s1 - tb) : 0ull;
                     for (int i = 0; i < nt; ++i) {
-                        const DTerm tt = P->term[tq[i]];
+                        const DTerm tt = gload(&P->term[tq[i]]);
                         bool ok = hit;
                         if (ok) {
                             uint32_t lo, hi;
@@ -1453,7 +1631,7 @@ __global__ void __launch_bounds__(256) edge_window_kernel(KArgs a) {
             uint64_t tv[MAX_TERMS];
             int i = 0;
             for (int q = 0; q < P->nterm; ++q) {
-                const DTerm t = P->term[q];
+                const DTerm t = gload(&P->term[q]);
                 if (!t.cheap && !t.agg && i < nt && tq[i] == q) tv[q] = ccnt[(uint64_t)k * EW_TERMS + i++];
                 else tv[q] = cheap_term<BYTES>(c, vv, t, 0);
             }
@@ -1533,13 +1711,13 @@ __device__ __forceinline__ uint32_t cq_slot_of(const uint32_t* H, uint32_t x) {
 // cheap_term.  The set-size term of an edge-core plan is 1: this triangle's
 // share of it (the tail is linear in it).
 template <bool BYTES>
-__device__ u128 cq_eval(Ctx& c, const DPlan* P, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t d0, uint32_t d1,
+__device__ u128 cq_eval(Ctx& c, gcp<DPlan> P, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t d0, uint32_t d1,
                         uint32_t d2) {
     uint64_t tv[CQ_TERMS];
     const uint32_t vv[KMAX] = {v0, v1, v2, 0u, 0u};
 #pragma unroll 1
     for (int q = 0; q < P->nterm; ++q) {
-        const DTerm t = P->term[q];
+        const DTerm t = gload(&P->term[q]);
         const int o = __builtin_ctz((uint32_t)t.adj);
         if (!t.cheap) {
             tv[q] = 1;
@@ -1553,7 +1731,7 @@ __device__ u128 cq_eval(Ctx& c, const DPlan* P, uint32_t v0, uint32_t v1, uint32
     }
     i128 s = 0;
     for (int m = 0; m < P->nmono; ++m) {
-        const DMono M = P->mono[m];
+        const DMono M = gload(&P->mono[m]);
         i128 prod = (i128)M.coef;
         for (int f = 0; f < M.nf; ++f) prod *= (i128)tv[M.f[f]];
         s += prod;
@@ -1568,7 +1746,7 @@ __device__ u128 cq_eval(Ctx& c, const DPlan* P, uint32_t v0, uint32_t v1, uint32
 // within its set-size term's bounds, so each of the triangle's three edges
 // adds its tail when the opposite vertex is within those bounds.
 template <bool BYTES>
-__device__ __forceinline__ u128 cq_tail(Ctx& c, const DPlan* P, uint32_t a, uint32_t b, uint32_t cc, uint32_t da,
+__device__ __forceinline__ u128 cq_tail(Ctx& c, gcp<DPlan> P, uint32_t a, uint32_t b, uint32_t cc, uint32_t da,
                                         uint32_t db, uint32_t dc) {
     if (P->nterm == 0) return (u128)(uint32_t)P->mult;
     uint8_t hg = 0, hl = 0;
@@ -1611,7 +1789,7 @@ __device__ __forceinline__ void cq_drain(Ctx& c, const KArgs& a, const uint4* Q,
         if (BYTES) c.bytes += 16;
 #pragma unroll 1
         for (int p = 0; p < a.nplans; ++p) {
-            const u128 t = cq_tail<BYTES>(c, a.plans + p, e.x, e.y, e.z, d0, e.w, d2);
+            const u128 t = cq_tail<BYTES>(c, (gcp<DPlan>)a.plans + p, e.x, e.y, e.z, d0, e.w, d2);
 #pragma unroll
             for (int k = 0; k < CQ_PLANS; ++k)
                 if (k == p) acc[k] += t;
@@ -1648,7 +1826,7 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
     if (SUP) RC[lane] = 0;
     wave_sync();
     Ctx c;
-    c.g = a.g;
+    c.g = dgraph(a.g);
     c.P = nullptr;
     c.buf = nullptr;
     c.stride = 0;
@@ -1794,7 +1972,7 @@ template <bool BYTES>
 __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
     const int np = a.nplans;
     Ctx c;
-    c.g = a.g;
+    c.g = dgraph(a.g);
     c.P = nullptr;
     c.buf = nullptr;
     c.stride = 0;
@@ -1818,7 +1996,7 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
             if (BYTES) c.bytes += 8;
 #pragma unroll 1
             for (int q = 0; q < np; ++q) {
-                const DPlan* P = a.plans + q;
+                gcp<DPlan> P = (gcp<DPlan>)a.plans + q;
                 const bool up = P->lev[1].gt != 0;
                 const uint32_t v0 = up ? u : w, v1 = up ? w : u;
                 const uint32_t d0 = up ? du : dw, d1 = up ? dw : du;
@@ -1826,7 +2004,7 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
                 const uint32_t vv[KMAX] = {v0, v1, 0u, 0u, 0u};
 #pragma unroll 1
                 for (int k = 0; k < P->nterm; ++k) {
-                    const DTerm T = P->term[k];
+                    const DTerm T = gload(&P->term[k]);
                     if (!T.cheap) tv[k] = t;
                     else if ((T.gt | T.lt) == 0 && (T.neq & ~T.sure) == 0)
                         tv[k] = (uint64_t)((__builtin_ctz((uint32_t)T.adj) == 0 ? d0 : d1) -
@@ -1835,7 +2013,7 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
                 }
                 i128 sum = 0;
                 for (int m = 0; m < P->nmono; ++m) {
-                    const DMono M = P->mono[m];
+                    const DMono M = gload(&P->mono[m]);
                     i128 prod = (i128)M.coef;
                     for (int f = 0; f < M.nf; ++f) prod *= (i128)tv[M.f[f]];
                     sum += prod;
@@ -1990,7 +2168,7 @@ __global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
     uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * C4_WAVE_WORDS;
     __shared__ uint32_t s_it;
     Ctx c;
-    c.g = a.g;
+    c.g = dgraph(a.g);
     c.P = nullptr;
     c.buf = nullptr;
     c.stride = 0;
@@ -2064,15 +2242,17 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int agg_window_cu_blocks() { return AW_CU_BLOCKS; }
+
 int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
     // path counts are bounded by the largest degree (the adjacency stride)
     const bool h16 = !a.wide && a.wscr_stride <= 0xffffu;
     if (h16) {
-        if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, true>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((agg_window_kernel<false, true>), dim3(grid), dim3(256), 0, s, a);
+        if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, true>), dim3(grid), dim3(AW_THREADS), 0, s, a);
+        else hipLaunchKernelGGL((agg_window_kernel<false, true>), dim3(grid), dim3(AW_THREADS), 0, s, a);
     } else {
-        if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, false>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((agg_window_kernel<false, false>), dim3(grid), dim3(256), 0, s, a);
+        if (count_bytes) hipLaunchKernelGGL((agg_window_kernel<true, false>), dim3(grid), dim3(AW_THREADS), 0, s, a);
+        else hipLaunchKernelGGL((agg_window_kernel<false, false>), dim3(grid), dim3(AW_THREADS), 0, s, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -47,9 +47,12 @@ struct KArgs {
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
-// Heavy roots of first-level two-hop plans: one workgroup (256 threads) per
-// root, items {root, 0, 0, 0}.
+// Heavy roots of first-level two-hop plans: large workgroups (1024 threads
+// and 142 KB of LDS by default), one root or root slice at a time, items
+// {root, 0, slice, slices}; `grid` should not exceed the CU count times
+// agg_window_cu_blocks(), the workgroups one CU holds.
 int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+int agg_window_cu_blocks();
 // Heavy roots of edge-core plans (edge_window_ok): one workgroup per root.
 int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Triangle-core plans (clique_ok), at most CQ_PLANS per launch: one

@@ -562,13 +562,14 @@ std::vector<uint32_t> Ctx_::edge_heavy_roots(const GraphRes& G, const std::vecto
 }
 
 // Work items of the heavy roots.  Two-hop roots are split by target-id range
-// into about one slice per 2^20 of two-hop mass (items {r, 0, slice, slices});
+// into about one slice per 2^22 of two-hop mass (items {r, 0, slice, slices};
+// their workgroups hold a whole CU each, so a few hundred run at once);
 // edge-core roots by level-1 candidates, 512 per item (items {r, 0, k0, k1}).
 static std::vector<KItem> heavy_items(const GraphRes& G, const std::vector<uint32_t>& roots, bool two_hop) {
     std::vector<KItem> out;
     for (uint32_t r : roots) {
         if (two_hop) {
-            const uint32_t ns = (uint32_t)std::min<uint64_t>(256, std::max<uint64_t>(1, G.two_hop[r] >> 20));
+            const uint32_t ns = (uint32_t)std::min<uint64_t>(256, std::max<uint64_t>(1, G.two_hop[r] >> 22));
             for (uint32_t i = 0; i < ns; ++i) out.push_back({r, 0, i, ns});
         } else {
             const uint32_t d = G.host_rp[r + 1] - G.host_rp[r];
@@ -1162,7 +1163,8 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
         } else if (ls.run_agg[r] == 2) {
             b.items = ls.heavy_items;
             b.nitems = ls.heavy_nitems;
-            if (b.nitems && launch_agg_window(b, gb, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            if (b.nitems && launch_agg_window(b, std::min(gb, num_cus * agg_window_cu_blocks()), bytes_pass, s))
+                return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 3) {
             b.items = ls.edge_items;
