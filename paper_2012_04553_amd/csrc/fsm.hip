@@ -554,14 +554,19 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
     }
 }
 
-int launch_fsm(const FsmArgs& a, int grid, hipStream_t s) {
+int launch_fsm(const FsmArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
+    if (ev) hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(fsm_hist, dim3(grid), dim3(256), 0, s, a);
     if (hipGetLastError() != hipSuccess) return -1;
+    if (ev) hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(fsm_tri, dim3(grid), dim3(256), 0, s, a);
     if (hipGetLastError() != hipSuccess) return -1;
+    if (ev) hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(fsm_btab, dim3(grid), dim3(256), 0, s, a);
     if (hipGetLastError() != hipSuccess) return -1;
+    if (ev) hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(fsm_main, dim3(grid), dim3(256), 0, s, a);
+    if (ev) hipEventRecord(ev[4], s);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

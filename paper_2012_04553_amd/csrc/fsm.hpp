@@ -29,6 +29,8 @@ struct FsmArgs {
     unsigned long long* tri;  // n * 4: label pairs of the triangles at each vertex
 };
 
-int launch_fsm(const FsmArgs& a, int grid, hipStream_t s);
+// The four FSM kernels in order; with `ev` (5 events), ev[i] is recorded
+// before kernel i and ev[4] after the last.
+int launch_fsm(const FsmArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 
 }  // namespace pm

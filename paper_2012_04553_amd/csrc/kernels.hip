@@ -573,10 +573,16 @@ __device__ u128 lanes_tail(Ctx& c, const uint32_t* vv, bool valid, uint64_t aggm
         const int nm = c.P->nmono;
         for (int m = 0; m < nm; ++m) {
             const DMono M = gload(&c.P->mono[m]);
-            i128 prod = (i128)M.coef;
+            // set sizes are below 2^32, so two factors multiply exactly in
+            // 64 bits and the coefficient needs one 64 x 64 -> 128 product
+            const uint64_t f0 = M.nf > 0 ? pick4(M.f[0], t0, t1, t2, t3) : 1u;
+            const uint64_t f1 = M.nf > 1 ? pick4(M.f[1], t0, t1, t2, t3) : 1u;
+            i128 prod = (i128)M.coef * (i128)(f0 * f1);
+            if (M.nf > 2) {
 #pragma unroll
-            for (int f = 0; f < MAX_FAC; ++f)
-                if (f < M.nf) prod *= (i128)pick4(M.f[f], t0, t1, t2, t3);
+                for (int f = 2; f < MAX_FAC; ++f)
+                    if (f < M.nf) prod *= (i128)pick4(M.f[f], t0, t1, t2, t3);
+            }
             s += prod;
         }
         return s > 0 ? (u128)s : (u128)0;
@@ -726,7 +732,7 @@ __device__ void agg_level(Ctx& c, int j, uint32_t wid, uint32_t* s_touch, const 
             m = wave_take(&cnt[x]);
             vv[j] = x;
         }
-        acc += lanes_tail<BYTES>(c, vv, valid, m);
+        acc += lanes_tail<BYTES, true>(c, vv, valid, m);
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
@@ -862,18 +868,27 @@ __device__ __forceinline__ void lanes_finish(Ctx& c, int j, uint32_t b, uint32_t
     }
 }
 
-// Cancellation: the host sets a coherent flag; lane 0 reads it every 16th
-// call (root or level-1 step), so an abandoned item ends within a few of its
-// iterations.  Wave-uniform.
-__device__ __forceinline__ bool should_stop(const KArgs& a, uint32_t& tick) {
-    if (!a.cancel || ((++tick) & 15u)) return false;
+// Cancellation: the host sets a coherent flag; lane 0 reads it once the
+// calls since the last read (a root, a step at any materialised level, a
+// penultimate-level aggregation, a batch of 64 level-1 candidates) weigh 16,
+// a root weighing one plus its degree over 64, so an abandoned item ends
+// within a few of its innermost iterations even on hub roots.  Wave-uniform.
+__device__ __forceinline__ bool should_stop(const KArgs& a, uint32_t& tick, uint32_t weight = 1) {
+    if (!a.cancel) return false;
+    tick += weight;
+    if (tick < 16u) return false;
+    tick = 0;
     uint32_t stop = 0;
     if (wave_lane() == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
     return bcast(stop) != 0;
 }
 
 template <bool BYTES>
+#ifdef PM_MATCH_WPE
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PM_MATCH_WPE))) match_kernel(KArgs a) {
+#else
 __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
+#endif
     __shared__ uint32_t s_touch[4];
     const int lane = wave_lane();
     const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -925,7 +940,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             continue;
         }
         for (uint32_t r = item.r0; r < item.r1; ++r) {
-            if (stopped || should_stop(a, tick)) {
+            if (stopped || should_stop(a, tick, 1u + ((a.g.rp[r + 1] - a.g.rp[r]) >> 6))) {
                 stopped = true;
                 break;
             }
@@ -950,6 +965,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                 const bool usebm = P->bm0 && c.bmw && e > b;
                 if (usebm) bm_build(c, r);
                 for (uint32_t base = b; base < e; base += 64) {
+                    if (should_stop(a, tick)) {
+                        stopped = true;
+                        break;
+                    }
                     const uint32_t idx = base + lane;
                     const bool valid = idx < e;
                     uint32_t vv[KMAX] = {r, valid ? b1[idx] : 0u, 0, 0, 0};
@@ -988,7 +1007,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                     --j;
                     continue;
                 }
-                if (j == 1 && should_stop(a, tick)) {
+                if (should_stop(a, tick)) {
                     stopped = true;
                     break;
                 }
@@ -998,13 +1017,18 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                 c.size[j] = wave_level<BYTES>(c, j);
                 if (j == pen) {
                     if (P->agg_last) {
-                        for (uint32_t q = 0; q < c.size[j]; ++q) {
+                        for (uint32_t q = 0; q < c.size[j] && !stopped; ++q) {
+                            if (should_stop(a, tick)) {
+                                stopped = true;
+                                break;
+                            }
                             c.v[j] = c.buf[(uint64_t)j * c.stride + q];
                             agg_level<BYTES>(c, j + 1, wid, my_touch, a, acc);
                         }
                     } else {
                         lanes_finish<BYTES>(c, j, 0, c.size[j], acc);
                     }
+                    if (stopped) break;
                     --j;
                     continue;
                 }
@@ -1374,15 +1398,15 @@ __global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
                     longm &= longm - 1;
                     const uint32_t qo = __builtin_amdgcn_readlane(q, o), lo_len = __builtin_amdgcn_readlane(len, o);
                     for (uint32_t tb = 0; tb < lo_len; tb += 64 * AW_UNROLL) {
+                        // every lane loads (a clamped index past the end
+                        // re-reads the last entry), so no load is predicated
                         uint32_t xs[AW_UNROLL];
 #pragma unroll
-                        for (int u = 0; u < AW_UNROLL; ++u) {
-                            const uint32_t t = tb + (uint32_t)(u * 64) + lane;
-                            xs[u] = t < lo_len ? G.col[qo + t] : NOB;
-                        }
+                        for (int u = 0; u < AW_UNROLL; ++u)
+                            xs[u] = G.col[qo + min(tb + (uint32_t)(u * 64) + lane, lo_len - 1u)];
 #pragma unroll
                         for (int u = 0; u < AW_UNROLL; ++u)
-                            if (xs[u] != NOB) take(xs[u]);
+                            if (tb + (uint32_t)(u * 64) + lane < lo_len) take(xs[u]);
                     }
                 }
                 // short segments: flattened over the lanes

@@ -2217,7 +2217,7 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     tabs.insert(tabs.end(), T.s3code.begin(), T.s3code.end());
     int rc = PM_OK;
     std::vector<uint32_t> counts(nslots * 4);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     do {
         if (hipMemcpyAsync(tab, tabs.data(), 4 * tabs.size(), hipMemcpyHostToDevice, c.stream) != hipSuccess ||
             hipMemcpyAsync(ord, G->label_order.data(), sz_ord, hipMemcpyHostToDevice, c.stream) != hipSuccess ||
@@ -2225,14 +2225,11 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
             rc = fail(PM_E_DEVICE, "FSM setup failed");
             break;
         }
-        hipEventCreate(&e0);
-        hipEventCreate(&e1);
-        hipEventRecord(e0, c.stream);
-        if (launch_fsm(a, grid, c.stream)) {
+        for (auto& e : ev) hipEventCreate(&e);
+        if (launch_fsm(a, grid, c.stream, ev)) {
             rc = fail(PM_E_DEVICE, "FSM kernel launch failed");
             break;
         }
-        hipEventRecord(e1, c.stream);
         if (hipMemcpyAsync(counts.data(), a.counts, sz_cnt, hipMemcpyDeviceToHost, c.stream) != hipSuccess) {
             rc = fail(PM_E_DEVICE, "FSM copy-back failed");
             break;
@@ -2244,9 +2241,40 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
         }
     } while (0);
     float kms = 0;
-    if (e0 && e1 && rc == PM_OK) hipEventElapsedTime(&kms, e0, e1);
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    c.last_launches.clear();
+    if (rc == PM_OK && ev[0] && ev[4]) {
+        hipEventElapsedTime(&kms, ev[0], ev[4]);
+        // algorithmic bytes per launch: every array a kernel reads or writes,
+        // with the fixed-size per-vertex records of a neighbour counted once
+        // per adjacency entry that reaches them (m2 = adjacency entries)
+        const uint64_t m2 = G->host_rp[n];
+        const uint64_t per[4] = {
+            // hist: row offsets, lists, neighbour labels; writes histogram,
+            // presence masks and the cleared triangle masks
+            n * (8 + 4 * FSM_LMAX + 12 + 32) + m2 * (4 + 1),
+            // tri: out-lists streamed against the root's hashed out-list,
+            // corner label pairs written
+            n * (8 + 4 + 32) + m2 * (4 + 1),
+            // btab: per vertex b, its neighbours' histograms and masks; writes
+            // b's (lc, ld) masks, counts and witness counts
+            n * (8 + 4 * FSM_LMAX + FSM_LMAX * FSM_LMAX * 2) + m2 * (4 + 1 + 4 * FSM_LMAX + 12),
+            // main: per vertex its records; per adjacency entry the
+            // neighbour's label and presence masks in two passes and its
+            // (lc, ld) mask row in the path-end pass
+            n * (4 + 8 + 1 + 4 * FSM_LMAX + 12 + 32) + m2 * (2 * (4 + 1 + 12) + 4 * FSM_LMAX)};
+        static const char* names[4] = {"fsm_hist", "fsm_tri", "fsm_btab", "fsm_main"};
+        for (int i = 0; i < 4; ++i) {
+            pm_launch_stat ls_{};
+            snprintf(ls_.kernel, sizeof(ls_.kernel), "%s", names[i]);
+            ls_.alg_bytes = per[i];
+            float ms = 0;
+            hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            ls_.ms = ms;
+            c.last_launches.push_back(ls_);
+        }
+    }
+    for (auto& e : ev)
+        if (e) hipEventDestroy(e);
     c.arena.release(off);
     if (rc) return rc;
     // support = smallest domain over the distinct (non-automorphic) columns
