@@ -384,6 +384,102 @@ __device__ __forceinline__ void emit_word(const FsmArgs& a, uint64_t m, bool uni
 __device__ __forceinline__ void set_bit(uint64_t* r, int bit) { r[bit >> 6] |= 1ull << (bit & 63); }
 __device__ __forceinline__ bool has_bit(const uint64_t* r, int bit) { return (r[bit >> 6] >> (bit & 63)) & 1ull; }
 
+// Pass-1 contribution of neighbour c of x (label lx): the label pairs
+// (l2 <= l3) that c's other neighbours cover, as four 64-bit words of the
+// 3-star-leaf set U[lab(c)]; row l2 holds the labels above l2 present in
+// N(c) \ {x}, and l2 itself when twice present.
+__device__ __forceinline__ void leaf_pairs(uint32_t pr, uint32_t tw, uint64_t& f0, uint64_t& f1, uint64_t& f2,
+                                           uint64_t& f3) {
+    f0 = f1 = f2 = f3 = 0;
+    uint32_t e2 = pr;
+    while (e2) {
+        const int l2 = __builtin_ctz(e2);
+        e2 &= e2 - 1;
+        const uint32_t row = (pr & ~((2u << l2) - 1u)) | (tw & (1u << l2));
+        const uint64_t sh = (uint64_t)row << ((l2 & 3) * 16);
+        const int wd = l2 >> 2;
+        f0 |= wd == 0 ? sh : 0ull;
+        f1 |= wd == 1 ? sh : 0ull;
+        f2 |= wd == 2 ? sh : 0ull;
+        f3 |= wd == 3 ? sh : 0ull;
+    }
+}
+
+// Path-inner row set M[lc] of x: bit (la*16 + ld) when a path a-x-c-d with
+// lab(a) = la, lab(c) = lc, lab(d) = ld exists.  pd / t2: labels present once
+// / twice among N(c) \ {x}, OR-ed over the neighbours c of label lc.
+__device__ void inner_rows(const FsmArgs& a, uint32_t x, int lx, int lc, uint32_t pd, uint32_t t2, uint64_t& m0,
+                           uint64_t& m1, uint64_t& m2, uint64_t& m3) {
+    const int L = a.L;
+    const uint32_t xs = a.rp[x], xe = a.rp[x + 1];
+    const uint32_t* hx = a.hist + (uint64_t)x * FSM_LMAX;
+    // a: labels of N(x) \ {c} for some c of label lc
+    const uint32_t pa = hx[lc] >= 2 ? a.pres[(uint64_t)x * 3] : (a.pres[(uint64_t)x * 3] & ~(1u << lc));
+    m0 = m1 = m2 = m3 = 0;
+    uint32_t ea = pa & ((1u << L) - 1u);
+    while (ea) {
+        const int la = __builtin_ctz(ea);
+        ea &= ea - 1;
+        uint32_t row = pd;   // labels ld of d
+        if ((row >> la) & 1) {
+            // ld == la needs a != d
+            const uint32_t na = hx[la] - (lc == la ? 1u : 0u);
+            if (na < 2 && !((t2 >> la) & 1)) {
+                // every candidate c has one witness d; x one witness a:
+                // valid iff some c (label lc) has its witness d != a
+                bool ok = false;
+                for (uint32_t p = xs; p < xe && !ok; ++p) {
+                    const uint32_t c = a.col[p];
+                    if (a.lab[c] != lc) continue;
+                    if (!((present_minus(a, c, lx) >> la) & 1)) continue;
+                    const uint32_t aa = unique_other(a, x, la, c);
+                    if (aa >= a.n) continue;
+                    if (!fsm_has(a.col, a.rp[c], a.rp[c + 1], aa)) ok = true;
+                }
+                if (!ok) row &= ~(1u << la);
+            }
+        }
+        const uint64_t sh = (uint64_t)row << ((la & 3) * 16);
+        const int wd = la >> 2;
+        m0 |= wd == 0 ? sh : 0ull;
+        m1 |= wd == 1 ? sh : 0ull;
+        m2 |= wd == 2 ? sh : 0ull;
+        m3 |= wd == 3 ? sh : 0ull;
+    }
+}
+
+// Path end: whether x (label lx) starts a path x-b-c-d through its
+// neighbour b (label lb) with lab(c) = lc, lab(d) = ld.  ex: labels present
+// among N(x) \ {b}.
+__device__ bool end_ok(const FsmArgs& a, uint32_t x, int lx, uint32_t b, int lb, int lc, int ld, uint32_t ex) {
+    const int bit = lc * FSM_LMAX + ld;
+    const uint32_t cn = a.bcnt[(uint64_t)b * FSM_LMAX * FSM_LMAX + bit];
+    const uint32_t fr = a.bfrag[(uint64_t)b * FSM_LMAX * FSM_LMAX + bit];
+    const uint32_t self = (lc == lx && ((ex >> ld) & 1)) ? 1u : 0u;
+    if (cn < 255 && cn < self + 1) return false;
+    if (cn < 255 && cn >= self + 1 + fr) return true;
+    if (ld != lx) return cn >= self + 1;
+    // exact: c in N(b) \ {x}, label lc, with a label-ld neighbour outside {b, x}
+    for (uint32_t q = a.rp[b]; q < a.rp[b + 1]; ++q) {
+        const uint32_t c = a.col[q];
+        if (c == x || a.lab[c] != lc) continue;
+        uint32_t k = a.hist[(uint64_t)c * FSM_LMAX + ld] - (ld == lb ? 1u : 0u);
+        if (k >= 1 && fsm_has(a.col, a.rp[c], a.rp[c + 1], x)) --k;
+        if (k >= 1) return true;
+    }
+    return false;
+}
+
+// 3-star centre: x's neighbour-label histogram covers the leaf labels
+// l1 <= l2 <= l3.
+__device__ __forceinline__ bool centre_ok(const uint32_t* hx, int l1, int l2, int l3) {
+    const uint32_t n1 = hx[l1], n2 = hx[l2], n3 = hx[l3];
+    if (l1 == l3) return n1 >= 3;
+    if (l1 == l2) return n1 >= 2 && n3 >= 1;
+    if (l2 == l3) return n1 >= 1 && n2 >= 2;
+    return n1 >= 1 && n2 >= 1 && n3 >= 1;
+}
+
 // Vertices are taken in label order, so most wavefronts hold one label and
 // the domain counters see one atomic per (pattern, column) per wavefront.
 __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
@@ -396,8 +492,10 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
     uint64_t* V = M + FSM_LMAX * 4;
     for (uint64_t base = tid - lane; base < a.n; base += stride) {   // wave-uniform trip count
         const uint64_t i = base + lane;
-        const bool act = i < a.n;
-        const uint32_t x = act ? a.order[i] : 0u;
+        // vertices of degree FSM_HUB or more are left to fsm_hub
+        const uint32_t xo = i < a.n ? a.order[i] : 0u;
+        const bool act = i < a.n && a.rp[xo + 1] - a.rp[xo] < FSM_HUB;
+        const uint32_t x = act ? xo : 0u;
         const int lx = act ? (int)a.lab[x] : -1;
         const uint32_t xs = act ? a.rp[x] : 0u, xe = act ? a.rp[x + 1] : 0u;
         // label-uniform wave: every active lane has the first lane's label
@@ -416,21 +514,8 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
                 const uint32_t pr = present_minus(a, c, lx), tw = twice_minus(a, c, lx);
                 Pd[lc] |= pr;
                 T2[lc] |= tw;
-                // pairs (l2 <= l3) c's other neighbours cover: row l2 holds
-                // the labels above l2 in pr, and l2 itself when twice present
-                uint64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-                uint32_t e2 = pr;
-                while (e2) {
-                    const int l2 = __builtin_ctz(e2);
-                    e2 &= e2 - 1;
-                    const uint32_t row = (pr & ~((2u << l2) - 1u)) | (tw & (1u << l2));
-                    const uint64_t sh = (uint64_t)row << ((l2 & 3) * 16);
-                    const int wd = l2 >> 2;
-                    f0 |= wd == 0 ? sh : 0ull;
-                    f1 |= wd == 1 ? sh : 0ull;
-                    f2 |= wd == 2 ? sh : 0ull;
-                    f3 |= wd == 3 ? sh : 0ull;
-                }
+                uint64_t f0, f1, f2, f3;
+                leaf_pairs(pr, tw, f0, f1, f2, f3);
                 uint64_t* u = U + lc * 4;
                 if (f0 & ~u[0]) u[0] |= f0;
                 if (f1 & ~u[1]) u[1] |= f1;
@@ -439,39 +524,8 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
             }
             for (int lc = 0; lc < L; ++lc) {
                 if (!Pd[lc]) continue;
-                // a: labels of N(x) \ {c} for some c of label lc
-                const uint32_t pa = hx[lc] >= 2 ? a.pres[(uint64_t)x * 3] : (a.pres[(uint64_t)x * 3] & ~(1u << lc));
-                uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-                uint32_t ea = pa & ((1u << L) - 1u);
-                while (ea) {
-                    const int la = __builtin_ctz(ea);
-                    ea &= ea - 1;
-                    uint32_t row = Pd[lc];   // labels ld of d
-                    if ((row >> la) & 1) {
-                        // ld == la needs a != d
-                        const uint32_t na = hx[la] - (lc == la ? 1u : 0u);
-                        if (na < 2 && !((T2[lc] >> la) & 1)) {
-                            // every candidate c has one witness d; x one witness a:
-                            // valid iff some c (label lc) has its witness d != a
-                            bool ok = false;
-                            for (uint32_t p = xs; p < xe && !ok; ++p) {
-                                const uint32_t c = a.col[p];
-                                if (a.lab[c] != lc) continue;
-                                if (!((present_minus(a, c, lx) >> la) & 1)) continue;
-                                const uint32_t aa = unique_other(a, x, la, c);
-                                if (aa >= a.n) continue;
-                                if (!fsm_has(a.col, a.rp[c], a.rp[c + 1], aa)) ok = true;
-                            }
-                            if (!ok) row &= ~(1u << la);
-                        }
-                    }
-                    const uint64_t sh = (uint64_t)row << ((la & 3) * 16);
-                    const int wd = la >> 2;
-                    m0 |= wd == 0 ? sh : 0ull;
-                    m1 |= wd == 1 ? sh : 0ull;
-                    m2 |= wd == 2 ? sh : 0ull;
-                    m3 |= wd == 3 ? sh : 0ull;
-                }
+                uint64_t m0, m1, m2, m3;
+                inner_rows(a, x, lx, lc, Pd[lc], T2[lc], m0, m1, m2, m3);
                 uint64_t* mm = M + lc * 4;
                 mm[0] = m0;
                 mm[1] = m1;
@@ -483,8 +537,6 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
                 const uint32_t b = a.col[p];
                 const int lb = a.lab[b];
                 const uint32_t* wm = a.bmask + (uint64_t)b * FSM_LMAX;
-                const uint8_t* cnt = a.bcnt + (uint64_t)b * FSM_LMAX * FSM_LMAX;
-                const uint8_t* frag = a.bfrag + (uint64_t)b * FSM_LMAX * FSM_LMAX;
                 const uint32_t ex = present_minus(a, x, lb);  // x as a c-candidate of b
                 uint64_t* v = V + lb * 4;
                 for (int lc = 0; lc < L; ++lc) {
@@ -495,25 +547,7 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
                         const int ld = __builtin_ctz(dm);
                         dm &= dm - 1;
                         const int bit = lc * FSM_LMAX + ld;
-                        const uint32_t cn = cnt[bit];
-                        const uint32_t fr = frag[bit];
-                        const uint32_t self = (lc == lx && ((ex >> ld) & 1)) ? 1u : 0u;
-                        bool ok;
-                        if (cn < 255 && cn < self + 1) ok = false;
-                        else if (cn < 255 && cn >= self + 1 + fr) ok = true;
-                        else if (ld != lx) ok = cn >= self + 1;
-                        else {
-                            // exact: c in N(b) \ {x}, label lc, with a label-ld neighbour
-                            // outside {b, x}
-                            ok = false;
-                            for (uint32_t q = a.rp[b]; q < a.rp[b + 1] && !ok; ++q) {
-                                const uint32_t c = a.col[q];
-                                if (c == x || a.lab[c] != lc) continue;
-                                uint32_t k = a.hist[(uint64_t)c * FSM_LMAX + ld] - (ld == lb ? 1u : 0u);
-                                if (k >= 1 && fsm_has(a.col, a.rp[c], a.rp[c + 1], x)) --k;
-                                if (k >= 1) ok = true;
-                            }
-                        }
+                        const bool ok = end_ok(a, x, lx, b, lb, lc, ld, ex);
                         if (ok) set_bit(v, bit);
                     }
                 }
@@ -526,14 +560,7 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
         for (int l1 = 0; l1 < L; ++l1)
             for (int l2 = l1; l2 < L; ++l2)
                 for (int l3 = l2; l3 < L; ++l3) {
-                    bool ok = false;
-                    if (act && xs != xe) {
-                        const uint32_t n1 = hx[l1], n2 = hx[l2], n3 = hx[l3];
-                        if (l1 == l3) ok = n1 >= 3;
-                        else if (l1 == l2) ok = n1 >= 2 && n3 >= 1;
-                        else if (l2 == l3) ok = n1 >= 1 && n2 >= 2;
-                        else ok = n1 >= 1 && n2 >= 1 && n3 >= 1;
-                    }
+                    const bool ok = act && xs != xe && centre_ok(hx, l1, l2, l3);
                     if (uniform) {
                         const uint64_t who = __ballot(ok);
                         if (lane == 0 && who)
@@ -554,6 +581,113 @@ __global__ void __launch_bounds__(256) fsm_main(FsmArgs a) {
     }
 }
 
+// Vertices of degree FSM_HUB or more: one wavefront each.  The lanes split
+// N(x) in both passes and OR their findings into the vertex's membership
+// sets in LDS; the path-inner rows take one lane per label lc; the 3-star
+// centre triples and the set words are spread over the lanes for emission.
+// The decisions are the lane path's (leaf_pairs, inner_rows, end_ok,
+// centre_ok), so both paths give the same sets.  Ids ascend with degree, so
+// the hubs are the ids from a.hub0 on.
+__global__ void __launch_bounds__(256) fsm_hub(FsmArgs a) {
+    __shared__ unsigned long long sU[4][FSM_LMAX * 4], sM[4][FSM_LMAX * 4], sV[4][FSM_LMAX * 4];
+    __shared__ uint32_t sPd[4][FSM_LMAX], sT2[4][FSM_LMAX];
+    const int L = a.L;
+    const int lane = __lane_id();
+    const int wv = threadIdx.x >> 6;
+    unsigned long long* U = sU[wv];
+    unsigned long long* M = sM[wv];
+    unsigned long long* V = sV[wv];
+    uint32_t* Pd = sPd[wv];
+    uint32_t* T2 = sT2[wv];
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t x = a.hub0 + blockIdx.x * (blockDim.x >> 6) + wv; x < a.n; x += nw) {
+        const uint32_t xs = a.rp[x], xe = a.rp[x + 1];
+        if (xe - xs < FSM_HUB) continue;
+        const int lx = a.lab[x];
+        const uint32_t* hx = a.hist + (uint64_t)x * FSM_LMAX;
+        for (uint32_t i = lane; i < FSM_LMAX * 4; i += 64) U[i] = M[i] = V[i] = 0ull;
+        if (lane < FSM_LMAX) Pd[lane] = T2[lane] = 0u;
+        ft_sync();
+        // ---- pass 1: 3-star leaf sets and the per-label presence masks ----
+        for (uint32_t p = xs + lane; p < xe; p += 64) {
+            const uint32_t c = a.col[p];
+            const int lc = a.lab[c];
+            const uint32_t pr = present_minus(a, c, lx), tw = twice_minus(a, c, lx);
+            if (pr) atomicOr(&Pd[lc], pr);
+            if (tw) atomicOr(&T2[lc], tw);
+            uint64_t f[4];
+            leaf_pairs(pr, tw, f[0], f[1], f[2], f[3]);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (f[w] & ~U[lc * 4 + w]) atomicOr(&U[lc * 4 + w], (unsigned long long)f[w]);
+        }
+        ft_sync();
+        // ---- path inner: one lane per label lc --------------------------
+        if (lane < L && Pd[lane]) {
+            uint64_t m0, m1, m2, m3;
+            inner_rows(a, x, lx, lane, Pd[lane], T2[lane], m0, m1, m2, m3);
+            M[lane * 4 + 0] = m0;
+            M[lane * 4 + 1] = m1;
+            M[lane * 4 + 2] = m2;
+            M[lane * 4 + 3] = m3;
+        }
+        // ---- path end: lanes split the neighbours b ---------------------
+        for (uint32_t p = xs + lane; p < xe; p += 64) {
+            const uint32_t b = a.col[p];
+            const int lb = a.lab[b];
+            const uint32_t* wm = a.bmask + (uint64_t)b * FSM_LMAX;
+            const uint32_t ex = present_minus(a, x, lb);
+            for (int lc = 0; lc < L; ++lc) {
+                // bits another lane has set need no second decision (bits
+                // are only ever set, so a stale read costs work, not results)
+                const uint64_t vw = __atomic_load_n(&V[lb * 4 + (lc >> 2)], __ATOMIC_RELAXED);
+                const uint32_t known = (uint32_t)((vw >> ((lc & 3) * 16)) & 0xffffu);
+                uint32_t dm = wm[lc] & ~known;
+                while (dm) {
+                    const int ld = __builtin_ctz(dm);
+                    dm &= dm - 1;
+                    if (end_ok(a, x, lx, b, lb, lc, ld, ex)) {
+                        const int bit = lc * FSM_LMAX + ld;
+                        atomicOr(&V[lb * 4 + (bit >> 6)], 1ull << (bit & 63));
+                    }
+                }
+            }
+        }
+        ft_sync();
+        // ---- 3-star centre: triples l1 <= l2 <= l3 over the lanes --------
+        for (int t = lane; t < L * L * L; t += 64) {
+            const int l1 = t / (L * L), l2 = (t / L) % L, l3 = t % L;
+            if (l1 > l2 || l2 > l3) continue;
+            if (centre_ok(hx, l1, l2, l3))
+                atomicAdd(&a.counts[(uint64_t)a.s3code[((lx * L + l1) * L + l2) * L + l3] * 4], 1u);
+        }
+        // ---- emit: one set word per lane at a time ------------------------
+        for (int t = lane; t < 3 * L * 4 + 4; t += 64) {
+            int reg, lab, w;
+            uint64_t m;
+            if (t < 3 * L * 4) {
+                reg = t / (L * 4);
+                lab = (t / 4) % L;
+                w = t % 4;
+                m = reg == REG_U ? U[lab * 4 + w] : (reg == REG_M ? M[lab * 4 + w] : V[lab * 4 + w]);
+            } else {
+                reg = 3;
+                lab = 0;
+                w = t - 3 * L * 4;
+                m = a.tri[(uint64_t)x * 4 + w];
+            }
+            while (m) {
+                const int b = __builtin_ctzll(m);
+                m &= m - 1;
+                int slot, colidx;
+                where_of(a, reg, lab, (w << 6) + b, lx, slot, colidx);
+                atomicAdd(&a.counts[(uint64_t)slot * 4 + colidx], 1u);
+            }
+        }
+        ft_sync();
+    }
+}
+
 int launch_fsm(const FsmArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
     if (ev) hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(fsm_hist, dim3(grid), dim3(256), 0, s, a);
@@ -566,7 +700,10 @@ int launch_fsm(const FsmArgs& a, int grid, hipStream_t s, hipEvent_t* ev) {
     if (hipGetLastError() != hipSuccess) return -1;
     if (ev) hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(fsm_main, dim3(grid), dim3(256), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return -1;
     if (ev) hipEventRecord(ev[4], s);
+    if (a.hub0 < a.n) hipLaunchKernelGGL(fsm_hub, dim3(grid), dim3(256), 0, s, a);
+    if (ev) hipEventRecord(ev[5], s);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

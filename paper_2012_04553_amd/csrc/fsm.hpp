@@ -7,6 +7,10 @@ namespace pm {
 
 constexpr int FSM_LMAX = 16;                    // labels supported
 constexpr int FSM_SCRATCH_WORDS = FSM_LMAX * 12;  // per-thread 64-bit words (three 256-bit sets per label)
+#ifndef PM_FSM_HUB
+#define PM_FSM_HUB 32
+#endif
+constexpr uint32_t FSM_HUB = PM_FSM_HUB;  // vertices with this many neighbours or more: one wavefront each
 
 struct FsmArgs {
     const uint32_t* rp;
@@ -27,10 +31,12 @@ struct FsmArgs {
     const uint32_t* order;  // n vertices sorted by label
     const uint32_t* split;  // per vertex: index of the first neighbour above it
     unsigned long long* tri;  // n * 4: label pairs of the triangles at each vertex
+    uint32_t hub0;      // first id of degree >= FSM_HUB (ids ascend with degree), or n
 };
 
-// The four FSM kernels in order; with `ev` (5 events), ev[i] is recorded
-// before kernel i and ev[4] after the last.
+// The five FSM kernels in order (fsm_hist, fsm_tri, fsm_btab, fsm_main for
+// vertices below FSM_HUB neighbours, fsm_hub for the others); with `ev`
+// (6 events), ev[i] is recorded before kernel i and ev[5] after the last.
 int launch_fsm(const FsmArgs& a, int grid, hipStream_t s, hipEvent_t* ev = nullptr);
 
 }  // namespace pm

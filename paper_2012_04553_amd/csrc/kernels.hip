@@ -1238,8 +1238,10 @@ constexpr int AW_UNROLL = PM_AW_UNROLL;
 #define PM_AW_LONG 64
 #endif
 constexpr uint32_t AW_LONG = PM_AW_LONG;     // a segment this long is streamed by the whole wave
+constexpr uint32_t AW_CHUNK = 512;           // long segments are queued in chunks this long
+constexpr uint32_t AW_CQCAP = 2048;          // chunk queue capacity
 // workgroups of this kernel that fit one CU's 160 KB of LDS
-constexpr int AW_CU_BLOCKS = (int)(160u * 1024u / (AW_WORDS * 4u + AW_WAVES * AW_QCAP * 6u + 4096u));
+constexpr int AW_CU_BLOCKS = (int)(160u * 1024u / (AW_WORDS * 4u + AW_WAVES * AW_QCAP * 6u + AW_CQCAP * 6u + 4096u));
 static_assert(AW_CU_BLOCKS >= 1, "window does not fit the LDS");
 
 // With H16 (a graph whose degrees fit 16 bits, so does every path count)
@@ -1253,7 +1255,9 @@ __global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
     __shared__ uint16_t glist[NGROUPS];
     __shared__ uint16_t qoff[AW_WAVES][AW_QCAP];
     __shared__ uint32_t qm[AW_WAVES][AW_QCAP];
-    __shared__ uint32_t s_item, s_next[2], s_ng[2], s_batch;
+    __shared__ uint32_t cq_q[AW_CQCAP];    // queued chunks of long segments: start
+    __shared__ uint16_t cq_n[AW_CQCAP];    //                                 length
+    __shared__ uint32_t s_item, s_next[2], s_ng[2], s_batch, s_nck, s_ckhead;
     const int lane = wave_lane();
     const uint32_t tid = threadIdx.x;
     const uint32_t w = tid >> 6;
@@ -1287,6 +1291,7 @@ __global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
             s_next[0] = s_next[1] = NOB;
             s_ng[0] = s_ng[1] = 0;
             s_batch = 0;
+            s_nck = s_ckhead = 0;
         }
         __syncthreads();
         const uint32_t it = s_item;
@@ -1357,6 +1362,23 @@ __global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
             const uint32_t wlo = s_next[ph];
             if (wlo == NOB || wlo >= top) break;
             const uint32_t whi = (uint32_t)min((uint64_t)top, (uint64_t)wlo + WIN_IDS);
+            // a window target: count it; its first touch marks its group
+            auto take = [&](uint32_t x) {
+                if ((L.label >= 0 && G.lab[x] != (uint8_t)L.label) || ((L.neq & 1) && x == r)) return;
+                const uint32_t off = x - wlo;
+                bool first;
+                if (H16) {
+                    const uint32_t sh = (off & 1u) * 16;
+                    first = ((atomicAdd(&win[off >> 1], 1u << sh) >> sh) & 0xffffu) == 0u;
+                } else {
+                    first = atomicAdd(&win[off], 1u) == 0u;
+                }
+                if (first) {
+                    const uint32_t g = off >> 6, bit = 1u << (g & 31);
+                    if (!(gbits[g >> 5] & bit) && !(atomicOr(&gbits[g >> 5], bit) & bit))
+                        glist[atomicAdd(&s_ng[ph], 1u)] = (uint16_t)g;
+                }
+            };
             // fill
             mine = NOB;
             for (;;) {
@@ -1372,27 +1394,30 @@ __global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
                 // entry does; else gallop to the window's end
                 const uint32_t qend = x0 >= whi ? q : (lst[k] < whi ? qe : gallop_u32(G.col, q, qe, whi));
                 const uint32_t len = qend - q;
-                // a window target: count it; its first touch marks its group
-                auto take = [&](uint32_t x) {
-                    if ((L.label >= 0 && G.lab[x] != (uint8_t)L.label) || ((L.neq & 1) && x == r)) return;
-                    const uint32_t off = x - wlo;
-                    bool first;
-                    if (H16) {
-                        const uint32_t sh = (off & 1u) * 16;
-                        first = ((atomicAdd(&win[off >> 1], 1u << sh) >> sh) & 0xffffu) == 0u;
-                    } else {
-                        first = atomicAdd(&win[off], 1u) == 0u;
-                    }
-                    if (first) {
-                        const uint32_t g = off >> 6, bit = 1u << (g & 31);
-                        if (!(gbits[g >> 5] & bit) && !(atomicOr(&gbits[g >> 5], bit) & bit))
-                            glist[atomicAdd(&s_ng[ph], 1u)] = (uint16_t)g;
-                    }
-                };
-                // long segments (most of the entries: hub bridges) are
-                // streamed by the whole wave, one after the other, with
-                // coalesced reads and no search for an entry's owner
+                // long segments (most of the entries: hub bridges) are cut
+                // into chunks that every wave of the workgroup streams after
+                // the batches are taken, each chunk by a whole wave with
+                // coalesced reads and no search for an entry's owner; when
+                // the chunk queue is full the wave streams them itself
                 uint64_t longm = __ballot(len >= AW_LONG);
+                if (longm) {
+                    const uint32_t nck = len >= AW_LONG ? (len + AW_CHUNK - 1) / AW_CHUNK : 0u;
+                    const uint32_t cincl = wave_incl_scan(nck);
+                    const uint32_t ctot = __shfl(cincl, 63);
+                    uint32_t cbase = 0;
+                    if (lane == 0) cbase = atomicAdd(&s_nck, ctot);
+                    cbase = __shfl(cbase, 0);
+                    if (cbase + ctot <= AW_CQCAP) {
+                        for (uint32_t i = 0; i < nck; ++i) {
+                            const uint32_t slot = cbase + cincl - nck + i;
+                            cq_q[slot] = q + i * AW_CHUNK;
+                            cq_n[slot] = (uint16_t)min(AW_CHUNK, len - i * AW_CHUNK);
+                        }
+                        longm = 0;
+                    } else {
+                        for (uint32_t i = lane; i < ctot && cbase + i < AW_CQCAP; i += 64) cq_n[cbase + i] = 0;
+                    }
+                }
                 while (longm) {
                     const int o = __builtin_ctzll(longm);
                     longm &= longm - 1;
@@ -1441,11 +1466,33 @@ __global__ void __launch_bounds__(AW_THREADS) agg_window_kernel(KArgs a) {
             for (int off = 32; off >= 1; off >>= 1) mine = min(mine, (uint32_t)__shfl_xor(mine, off));
             if (lane == 0 && mine != NOB) atomicMin(&s_next[ph ^ 1], mine);
             __syncthreads();
+            // every wave streams queued chunks until none is left
+            {
+                const uint32_t nck = min(s_nck, AW_CQCAP);
+                for (;;) {
+                    uint32_t ci = 0;
+                    if (lane == 0) ci = atomicAdd(&s_ckhead, 1u);
+                    ci = __shfl(ci, 0);
+                    if (ci >= nck) break;
+                    const uint32_t qo = cq_q[ci], cn = cq_n[ci];
+                    for (uint32_t tb = 0; tb < cn; tb += 64 * AW_UNROLL) {
+                        uint32_t xs[AW_UNROLL];
+#pragma unroll
+                        for (int u = 0; u < AW_UNROLL; ++u)
+                            xs[u] = G.col[qo + min(tb + (uint32_t)(u * 64) + lane, cn - 1u)];
+#pragma unroll
+                        for (int u = 0; u < AW_UNROLL; ++u)
+                            if (tb + (uint32_t)(u * 64) + lane < cn) take(xs[u]);
+                    }
+                }
+            }
+            __syncthreads();
             const uint32_t ng = s_ng[ph];
             if (tid == 0) {
                 s_next[ph] = NOB;   // read by every thread before the barrier
                 s_ng[ph ^ 1] = 0;   // next window's group count; last read a window ago
                 s_batch = 0;        // every wave has left the fill
+                s_nck = s_ckhead = 0;
             }
             for (uint32_t i = tid; i < NGROUPS / 32; i += AW_THREADS) gbits[i] = 0;
             // evaluate: walk the marked groups, clear their counters, queue

@@ -2211,13 +2211,16 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     a.order = ord;
     a.tri = (unsigned long long*)carve(sz_tri);
     a.split = (const uint32_t*)c.dptr(G->off_split);
+    // ids ascend with degree: the hubs are a suffix of the id range
+    a.hub0 = (uint32_t)n;
+    while (a.hub0 > 0 && G->host_rp[a.hub0] - G->host_rp[a.hub0 - 1] >= FSM_HUB) --a.hub0;
     std::vector<int32_t> tabs;
     tabs.insert(tabs.end(), T.tricode.begin(), T.tricode.end());
     tabs.insert(tabs.end(), T.p4code.begin(), T.p4code.end());
     tabs.insert(tabs.end(), T.s3code.begin(), T.s3code.end());
     int rc = PM_OK;
     std::vector<uint32_t> counts(nslots * 4);
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     do {
         if (hipMemcpyAsync(tab, tabs.data(), 4 * tabs.size(), hipMemcpyHostToDevice, c.stream) != hipSuccess ||
             hipMemcpyAsync(ord, G->label_order.data(), sz_ord, hipMemcpyHostToDevice, c.stream) != hipSuccess ||
@@ -2242,13 +2245,18 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     } while (0);
     float kms = 0;
     c.last_launches.clear();
-    if (rc == PM_OK && ev[0] && ev[4]) {
-        hipEventElapsedTime(&kms, ev[0], ev[4]);
+    if (rc == PM_OK && ev[0] && ev[5]) {
+        hipEventElapsedTime(&kms, ev[0], ev[5]);
         // algorithmic bytes per launch: every array a kernel reads or writes,
         // with the fixed-size per-vertex records of a neighbour counted once
         // per adjacency entry that reaches them (m2 = adjacency entries)
         const uint64_t m2 = G->host_rp[n];
-        const uint64_t per[4] = {
+        // the vertices below and from a.hub0 (fsm_main and fsm_hub split them)
+        const uint64_t nl = a.hub0, nh = n - a.hub0, ml = G->host_rp[a.hub0], mh = m2 - ml;
+        auto main_bytes = [](uint64_t nv, uint64_t me) {
+            return nv * (4 + 8 + 1 + 4 * FSM_LMAX + 12 + 32) + me * (2 * (4 + 1 + 12) + 4 * FSM_LMAX);
+        };
+        const uint64_t per[5] = {
             // hist: row offsets, lists, neighbour labels; writes histogram,
             // presence masks and the cleared triangle masks
             n * (8 + 4 * FSM_LMAX + 12 + 32) + m2 * (4 + 1),
@@ -2258,12 +2266,12 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
             // btab: per vertex b, its neighbours' histograms and masks; writes
             // b's (lc, ld) masks, counts and witness counts
             n * (8 + 4 * FSM_LMAX + FSM_LMAX * FSM_LMAX * 2) + m2 * (4 + 1 + 4 * FSM_LMAX + 12),
-            // main: per vertex its records; per adjacency entry the
-            // neighbour's label and presence masks in two passes and its
-            // (lc, ld) mask row in the path-end pass
-            n * (4 + 8 + 1 + 4 * FSM_LMAX + 12 + 32) + m2 * (2 * (4 + 1 + 12) + 4 * FSM_LMAX)};
-        static const char* names[4] = {"fsm_hist", "fsm_tri", "fsm_btab", "fsm_main"};
-        for (int i = 0; i < 4; ++i) {
+            // main (and hub, over their own vertices): per vertex its
+            // records; per adjacency entry the neighbour's label and presence
+            // masks in two passes and its (lc, ld) mask row in the path-end pass
+            main_bytes(nl, ml), main_bytes(nh, mh)};
+        static const char* names[5] = {"fsm_hist", "fsm_tri", "fsm_btab", "fsm_main", "fsm_hub"};
+        for (int i = 0; i < 5; ++i) {
             pm_launch_stat ls_{};
             snprintf(ls_.kernel, sizeof(ls_.kernel), "%s", names[i]);
             ls_.alg_bytes = per[i];
@@ -2301,7 +2309,7 @@ pm_status pm_fsm(pm_ctx* ctx, uint32_t gid, uint32_t num_labels, int64_t thresho
     pm_query_stats st{};
     st.kernel_ms = kms;
     st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    st.launches = 4;
+    st.launches = a.hub0 < n ? 5 : 4;
     st.num_alt = (uint32_t)nslots;
     c.last_stats = st;
     return PM_OK;
