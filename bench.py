@@ -440,7 +440,7 @@ def wl_serving(args, eng):
                      f"serving {args.serve_queries} queries at {args.serve_qps} QPS over 4 Chung-Lu graphs "
                      f"(beta 2.1, mean degree 20, n = {sizes}), k in {ks}, 30% labeled, cost-based morphing",
                      {"p50_s": st["p50_s"], "p99_s": st["p99_s"], "matches_per_s": st["matches_per_s"],
-                      "completed": st["completed"], "timeouts": st["timeouts"],
+                      "completed": st["completed"], "timeouts": st["timeouts"], "shed": st["shed"],
                       "mean_inflight": st["mean_inflight"], "batches": st["batches"],
                       "sustained_qps": st["sustained_qps"], "offered_qps": args.serve_qps,
                       "mean_setup_s": st["mean_setup_s"], "mean_service_s": st["mean_service_s"],

@@ -339,13 +339,20 @@ pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
 /* ---- serving ----------------------------------------------------------
  * A request loop over resident graphs (continuous batching).  pm_serve
  * replays a request trace in real time: request i becomes visible at
- * arrival_s seconds after the call starts.  Pending requests are admitted
- * in arrival order into up to max_slots slots, each with its own HIP
- * stream: the requests pending on the same graph as the oldest one (up to
- * max_batch) form one batch whose patterns are matched in a single
- * multi-pattern launch; a batch is admitted only while the arena bytes of
- * all in-flight batches stay within budget_bytes.  Batches run
- * concurrently on the device, and a finished slot is refilled at once.
+ * arrival_s seconds after the call starts, and is planned then (morph plan
+ * and compiled plans, which give its estimated kernel work by the cost
+ * model of §4.1).  Pending requests are admitted cheapest first into up to
+ * max_slots slots, each with its own HIP stream: the pending request of
+ * least estimated work and the requests pending on the same graph whose
+ * estimate is at most four times its own (up to max_batch) form one batch
+ * whose patterns are matched in a single multi-pattern launch; a batch is
+ * admitted only while the arena bytes of all in-flight batches stay within
+ * budget_bytes.  Batches run concurrently on the device, and a finished
+ * slot is refilled at once.  With a deadline, once a batch has timed out,
+ * pending requests on the same graph with the same largest pattern size as
+ * its costliest request, estimated at that request's work or more, end at
+ * once with PM_E_TIMEOUT (stats.shed) instead of occupying a slot until the
+ * deadline.
  * Latency of a request = completion time - scheduled arrival (queueing
  * included).  Not to be called concurrently with other calls on the same
  * context.  Results are identical to pm_submit/pm_wait of the same
@@ -389,6 +396,10 @@ typedef struct {
     uint64_t batches, completed, failed, timeouts;
     double mean_setup_s, mean_service_s; /* per completed request          */
     double sustained_qps;                /* completed / makespan          */
+    uint64_t shed;                       /* of the timeouts: refused at admission
+                                            (a request of the same graph and
+                                            pattern size, estimated no
+                                            cheaper, timed out)            */
 } pm_serve_stats;
 
 pm_status pm_serve(pm_ctx* ctx, const pm_serve_request* reqs, uint32_t nreq,

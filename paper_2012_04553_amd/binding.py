@@ -81,7 +81,7 @@ class pm_serve_stats(ctypes.Structure):
                 ("batches", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("timeouts", ctypes.c_uint64),
                 ("mean_setup_s", ctypes.c_double), ("mean_service_s", ctypes.c_double),
-                ("sustained_qps", ctypes.c_double)]
+                ("sustained_qps", ctypes.c_double), ("shed", ctypes.c_uint64)]
 
 
 # name -> (restype, argtypes) for every function declared in include/pm.h

@@ -115,6 +115,11 @@ struct DPlan {
 // Edge-core plans whose set-size terms all intersect N(v0) and N(v1): the
 // heavy roots of such plans can run in edge_window_kernel.
 constexpr uint32_t EW_TERMS = 4;
+
+// Graph membership bitmaps: vertices of at least HUB_BM_DEG neighbours, the
+// highest degrees first, HUB_BM_BYTES at most in all.
+constexpr uint32_t HUB_BM_DEG = 64;
+constexpr uint64_t HUB_BM_BYTES = 512ull << 20;
 inline bool edge_window_ok(const DPlan& d) {
     if (d.ncore != 2 || d.agg_last || d.local || d.nterm == 0) return false;
     const DLevel& L = d.lev[1];

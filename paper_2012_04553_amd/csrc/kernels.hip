@@ -61,6 +61,8 @@ struct DGraph {
     gcp<uint32_t> rp, col, split;
     gcp<uint8_t> lab;
     uint32_t n;
+    gcp<uint32_t> hubbm;
+    uint32_t hub0, hub_words;
 };
 
 // Copy of a plan record (plain words) out of global memory.
@@ -76,7 +78,8 @@ __device__ __forceinline__ T gload(const PM_GLOBAL T* p) {
 }
 
 __device__ __forceinline__ DGraph dgraph(const KGraph& g) {
-    return DGraph{(gcp<uint32_t>)g.rp, (gcp<uint32_t>)g.col, (gcp<uint32_t>)g.split, (gcp<uint8_t>)g.lab, g.n};
+    return DGraph{(gcp<uint32_t>)g.rp, (gcp<uint32_t>)g.col,   (gcp<uint32_t>)g.split,
+                  (gcp<uint8_t>)g.lab, g.n, (gcp<uint32_t>)g.hubbm, g.hub0, g.hub_words};
 }
 
 template <class P>
@@ -143,9 +146,25 @@ struct Ctx {
     uint64_t bytes;          // algorithmic bytes (counting build only)
     gp<uint32_t> bmw;        // this wave's root bitmap (n bits) or null
     gcp<uint32_t> bm;        // bmw while it holds N(v0), else null
+    const int* cancel = nullptr;   // host-visible cancel flag (matching kernel) or null
+    uint32_t ctick = 0;            // inner steps since the flag was last read
+    uint32_t stopped = 0;          // the flag was seen set: inner loops end early
 };
 
 // ---------------------------------------------------------------- wave helpers
+
+// Cancellation inside long inner loops (a flattened filter chunk, a batch of
+// 64 finishing candidates): lane 0 reads the host flag every 64th step; once
+// it is seen set every inner loop ends at its next step, and the results are
+// discarded with the query.  Wave-uniform.
+__device__ __forceinline__ bool ctx_stop(Ctx& c) {
+    if (c.stopped) return true;
+    if (!c.cancel || ((++c.ctick) & 63u)) return false;
+    uint32_t f = 0;
+    if (__lane_id() == 0) f = (uint32_t)__atomic_load_n(c.cancel, __ATOMIC_RELAXED);
+    c.stopped = __builtin_amdgcn_readfirstlane(f) != 0 ? 1u : 0u;
+    return c.stopped != 0;
+}
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     const int lane = wave_lane();
@@ -302,8 +321,16 @@ __device__ __forceinline__ bool probe_ok(const Ctx& c, const uint32_t* vv, const
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         if (i == 0 && pr.bm) continue;
-        if (((pr.adj >> i) & 1) && !in_sorted(c.g.col, pr.pb[i], pr.pe[i], x)) return false;
-        if (((pr.anti >> i) & 1) && in_sorted(c.g.col, pr.pb[i], pr.pe[i], x)) return false;
+        if (!(((pr.adj | pr.anti) >> i) & 1)) continue;
+        // x lies inside the bounds the list was cut to, so membership in the
+        // cut list is membership in N(v_i): a hub answers from its bitmap
+        // with one load, any other list by binary search
+        const uint32_t v = vv[i];
+        const bool in = (c.g.hubbm && v >= c.g.hub0)
+                            ? (c.g.hubbm[(uint64_t)(v - c.g.hub0) * c.g.hub_words + (x >> 5)] >> (x & 31)) & 1u
+                            : in_sorted(c.g.col, pr.pb[i], pr.pe[i], x);
+        if (((pr.adj >> i) & 1) && !in) return false;
+        if (((pr.anti >> i) & 1) && in) return false;
     }
     return true;
 }
@@ -503,6 +530,7 @@ __device__ uint64_t flat_filter(Ctx& c, const uint32_t* vv, gcp<uint32_t> drv, u
     const uint8_t nl = (uint8_t)(lists & (c.bm ? 0xfe : 0xff));
     uint64_t cnt = 0;
     for (uint32_t base = 0; base < total; base += 64) {
+        if (ctx_stop(c)) break;
         const uint32_t t = base + lane;
         const bool act = t < total;
         const int o = owner_of(incl, act ? t : total - 1);
@@ -857,6 +885,7 @@ __device__ __forceinline__ void lanes_finish(Ctx& c, int j, uint32_t b, uint32_t
     const int last = P->ncore - 1;
     gcp<uint32_t> bj = c.buf + (uint64_t)j * c.stride;
     for (uint32_t base = b; base < e; base += 64) {
+        if (ctx_stop(c)) break;
         const uint32_t idx = base + lane;
         const bool valid = idx < e;
         uint32_t vv[KMAX];
@@ -900,6 +929,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
     c.bytes = 0;
     c.bmw = a.rootbm ? (gp<uint32_t>)(a.rootbm + (uint64_t)wid * a.bm_words) : nullptr;
     c.bm = nullptr;
+    c.cancel = a.cancel;
     int cur = -1;
     u128 acc = 0;
     uint32_t tick = 0;
@@ -940,7 +970,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
             continue;
         }
         for (uint32_t r = item.r0; r < item.r1; ++r) {
-            if (stopped || should_stop(a, tick, 1u + ((a.g.rp[r + 1] - a.g.rp[r]) >> 6))) {
+            if (stopped || c.stopped || should_stop(a, tick, 1u + ((a.g.rp[r + 1] - a.g.rp[r]) >> 6))) {
                 stopped = true;
                 break;
             }
@@ -1007,7 +1037,7 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                     --j;
                     continue;
                 }
-                if (should_stop(a, tick)) {
+                if (c.stopped || should_stop(a, tick)) {
                     stopped = true;
                     break;
                 }
@@ -1028,7 +1058,10 @@ __global__ void __launch_bounds__(256) match_kernel(KArgs a) {
                     } else {
                         lanes_finish<BYTES>(c, j, 0, c.size[j], acc);
                     }
-                    if (stopped) break;
+                    if (stopped || c.stopped) {
+                        stopped = true;
+                        break;
+                    }
                     --j;
                     continue;
                 }
@@ -2310,6 +2343,40 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
         hipLaunchKernelGGL(edge_window_kernel<true>, dim3(grid), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(edge_window_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------- hub bitmaps
+
+// One wavefront per hub sets the bits of its adjacency list in its zeroed
+// bitmap (lists are sorted, so the lane holding the first entry of a word
+// assembles the word and writes it alone).
+__global__ void hub_bitmap_kernel(KGraph g, uint32_t* bm, uint32_t hub0, uint32_t words) {
+    const int lane = wave_lane();
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t h = hub0 + blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); h < g.n; h += nw) {
+        uint32_t* row = bm + (uint64_t)(h - hub0) * words;
+        const uint32_t b = g.rp[h], e = g.rp[h + 1];
+        for (uint32_t p = b + lane; p < e; p += 64) {
+            const uint32_t x = g.col[p], w = x >> 5;
+            if (p == b || (g.col[p - 1] >> 5) != w) {
+                uint32_t bits = 0;
+                for (uint32_t q = p; q < e; ++q) {
+                    const uint32_t y = g.col[q];
+                    if ((y >> 5) != w) break;
+                    bits |= 1u << (y & 31);
+                }
+                row[w] = bits;
+            }
+        }
+    }
+}
+
+int launch_hub_bitmaps(const KGraph& g, uint32_t* bm, uint32_t hub0, uint32_t words, hipStream_t s) {
+    if (hub0 >= g.n) return 0;
+    const uint32_t hubs = g.n - hub0;
+    const int grid = (int)std::min<uint32_t>(4096, (hubs + 3) / 4);
+    hipLaunchKernelGGL(hub_bitmap_kernel, dim3(grid), dim3(256), 0, s, g, bm, hub0, words);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -13,6 +13,10 @@ struct KGraph {
     const uint32_t* split;  // per vertex: index of the first neighbour above it
     const uint8_t* lab;   // labels or null
     uint32_t n;
+    // membership bitmaps (n bits, hub_words words each) of the vertices
+    // hub0 .. n-1, the highest degrees; null when the graph has none
+    const uint32_t* hubbm;
+    uint32_t hub0, hub_words;
 };
 
 // A work item: roots [r0, r1) of one plan; for a single high-degree root,
@@ -52,6 +56,9 @@ int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStrea
 // {root, 0, slice, slices}; `grid` should not exceed the CU count times
 // agg_window_cu_blocks(), the workgroups one CU holds.
 int launch_agg_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Fills the membership bitmaps of vertices hub0 .. n-1 (bm: (n - hub0) *
+// words zeroed words).
+int launch_hub_bitmaps(const KGraph& g, uint32_t* bm, uint32_t hub0, uint32_t words, hipStream_t s);
 int agg_window_cu_blocks();
 // Heavy roots of edge-core plans (edge_window_ok): one workgroup per root.
 int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s);

@@ -392,6 +392,37 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
             G->device_bytes += 16 * (nc + nl + nh + nx);
         }
     }
+    // membership bitmaps of the highest-degree vertices (ids ascend with
+    // degree, so they are a suffix): a probe of such a list costs one load
+    // instead of a binary search.  At least HUB_BM_DEG neighbours, at most
+    // HUB_BM_BYTES in all; skipped when the arena cannot hold them.
+    G->hub0 = n;
+    G->hub_words = (n + 31) / 32;
+    {
+        uint32_t h = n;
+        while (h > 0 && nrp[h] - nrp[h - 1] >= HUB_BM_DEG) --h;
+        const uint64_t row = 4ull * G->hub_words, cap = HUB_BM_BYTES / std::max<uint64_t>(row, 1);
+        if (n - h > cap) h = (uint32_t)(n - cap);
+        if (h < n) {
+            const uint64_t bytes = row * (n - h);
+            G->off_hubbm = arena.alloc(bytes);
+            if (G->off_hubbm != UINT64_MAX) {
+                KGraph kg{};
+                kg.rp = (const uint32_t*)dptr(G->off_rp);
+                kg.col = (const uint32_t*)dptr(G->off_col);
+                kg.n = n;
+                HIPCHK(hipMemsetAsync(dptr(G->off_hubbm), 0, bytes, stream));
+                if (launch_hub_bitmaps(kg, (uint32_t*)dptr(G->off_hubbm), h, G->hub_words, stream)) {
+                    arena.release(G->off_hubbm);
+                    G->off_hubbm = UINT64_MAX;
+                } else {
+                    HIPCHK(hipStreamSynchronize(stream));
+                    G->hub0 = h;
+                    G->device_bytes += bytes;
+                }
+            }
+        }
+    }
     G->host_rp = std::move(nrp);
     if (labels) {
         // vertices by label (stable: degree order within a label), for the
@@ -417,7 +448,7 @@ int Ctx_::graph_unload(uint32_t gid) {
     if (it->second->inflight) return fail(PM_E_BUSY, "queries in flight on this graph");
     GraphRes& G = *it->second;
     for (uint64_t o : {G.off_rp, G.off_col, G.off_split, G.off_lab, G.off_items, G.off_support, G.off_cq,
-                       G.off_lorder})
+                       G.off_lorder, G.off_hubbm})
         if (o < UINT64_MAX - 1) arena.release(o);
     for (auto& is : G.itemsets) arena.release(is.second.off);
     for (auto& ls : G.launches) free_launchset(ls.second.get());
@@ -983,6 +1014,11 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     a.g.split = (const uint32_t*)dptr(G.off_split);
     a.g.lab = G.labeled ? (const uint8_t*)dptr(G.off_lab) : nullptr;
     a.g.n = G.n;
+    if (G.off_hubbm != UINT64_MAX && hub_bitmaps_opt) {
+        a.g.hubbm = (const uint32_t*)dptr(G.off_hubbm);
+        a.g.hub0 = G.hub0;
+        a.g.hub_words = G.hub_words;
+    }
     a.items = (const KItem*)dptr(is->off);
     a.nitems = is->count;
     a.scratch = ls->scratch;
@@ -1410,7 +1446,7 @@ int Ctx_::launch(GraphRes& G, Query& Q) {
                       std::to_string(agg_split) + "," + std::to_string(heavy_roots_opt) + "," +
                       std::to_string(heavy_min_mass) + "," + std::to_string(clique_opt) + "," +
                       std::to_string(heavy_span_shift) + "," + std::to_string(support_opt) + "," +
-                      std::to_string(window_wide);
+                      std::to_string(window_wide) + "," + std::to_string(hub_bitmaps_opt);
     if (replay) {
         auto it = G.launches.find(key);
         if (it != G.launches.end() && !it->second->busy && it->second->agg_gen &&
@@ -1958,6 +1994,7 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     else if (k == "window_counters" && (value == 16 || value == 32)) c.window_wide = value == 32;
     else if (k == "launch_events" && (value == 0 || value == 1)) c.launch_events = value != 0;
     else if (k == "fork_launches" && (value == 0 || value == 1)) c.fork_launches = value != 0;
+    else if (k == "hub_bitmaps" && (value == 0 || value == 1)) c.hub_bitmaps_opt = value != 0;
     else return fail(PM_E_INVAL, "unknown option or value out of range: " + k);
     return PM_OK;
 }

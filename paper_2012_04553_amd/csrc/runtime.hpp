@@ -162,6 +162,8 @@ struct GraphRes {
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
     uint64_t off_lorder = UINT64_MAX;        // label-sorted vertex order on the device (first MNI use)
+    uint64_t off_hubbm = UINT64_MAX;         // membership bitmaps of the vertices hub0 .. n-1
+    uint32_t hub0 = 0, hub_words = 0;
     std::vector<uint32_t> label_begin;       // labeled graphs: first position of each label in label_order
     uint64_t hash = 0;                       // FNV-1a of the degree-ordered CSR (+labels)
     int inflight = 0;
@@ -219,6 +221,7 @@ struct Ctx_ {
     hipStream_t branch[2] = {nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
     bool fork_launches = false;      // measured slower at R-MAT 20 (127 vs 120 ms a step)
+    bool hub_bitmaps_opt = true;     // probes of hub lists through the graph's membership bitmaps
     std::map<std::string, std::pair<LaunchCfg, double>> tune_cache;
     std::string tune_file;
     std::mutex mu, plan_mu;

@@ -4,10 +4,21 @@
 // One host thread runs the loop.  Each iteration (1) makes visible the
 // requests whose scheduled arrival has passed, (2) retires finished slots
 // (event query), converting the batch's closure counts into every request's
-// values with that request's own morph plan, and (3) admits new batches:
-// the oldest pending request and the other pending requests on the same
-// graph (up to max_batch) are planned together, and the batch is admitted
-// when a slot is free and its footprint fits the remaining byte budget.
+// values with that request's own morph plan, and (3) admits new batches.
+// Every request is planned once when it arrives (morph plan and compiled
+// plans of its alternatives), which gives its estimated kernel work (the
+// planner's cost model).  Admission is cheapest first: the pending request
+// of least estimated work heads a batch, joined by other pending requests
+// on the same graph whose estimate is at most four times the head's (or
+// than SMALL_WORK), up to max_batch, so a light request never waits inside
+// a heavy batch.  The
+// batch is admitted when a slot is free and its footprint fits the
+// remaining byte budget.  With a deadline, a batch that timed out teaches
+// the loop the estimated work of its costliest request, per graph and
+// largest pattern size (the cost model ranks plans within such a class far
+// better than across them): a later request of that class estimated at that
+// much or more is shed at once (PM_E_TIMEOUT, counted in `shed`) instead of
+// holding a slot until the deadline.
 // Every slot owns a HIP stream (default priority) and dense two-hop
 // counter arrays, so batches in different slots run concurrently on the
 // device without sharing mutable memory.
@@ -18,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <thread>
 
 #include <cstdio>
@@ -36,6 +48,7 @@ struct Batch {
     LaunchSet ls;
     uint64_t bytes = 0;
     double admitted = 0;
+    double cost = 0;                  // estimated kernel work of its requests
     bool cancelled = false;
 };
 
@@ -53,6 +66,9 @@ struct Slot {
 constexpr uint64_t SLOT_STAGE_BYTES = 1024 * sizeof(DPlan);
 
 constexpr uint64_t SLOT_HOST_WORDS = 2 * 1024 + 8;
+
+// estimated work below which requests count as equally cheap for batching
+constexpr double SMALL_WORK = 1e6;
 
 using Clock = std::chrono::steady_clock;
 
@@ -180,6 +196,16 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     }
 
     std::deque<uint32_t> pending;
+    // per request: its morph plan and estimated kernel work (planned once)
+    std::vector<MorphPlan> rmp(nreq);
+    std::vector<double> rcost(nreq, -1.0);
+    // per (graph, largest pattern size): least estimated work of a request
+    // that headed a timed-out batch's work (its costliest request)
+    std::vector<int> rk(nreq, 0);
+    for (uint32_t i = 0; i < nreq; ++i)
+        for (const Pat& q : pats[i]) rk[i] = std::max(rk[i], (int)q.k);
+    std::map<std::pair<const GraphRes*, int>, double> timeout_cost;
+    uint64_t shed = 0;
     uint32_t next = 0, finished = 0;
     uint64_t used = 0, batches = 0;
     double inflight_sum = 0;
@@ -196,9 +222,30 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     while (finished < nreq && rc == PM_OK) {
         const double t = now_s();
         while (next < nreq && reqs[next].arrival_s <= t) {
-            if (!res[next].status) pending.push_back(next);
-            ++next;
+            const uint32_t r = next++;
+            if (res[r].status) continue;
+            std::string err;
+            GraphRes& G = *gr[r];
+            int prc = morph_plan_count(pats[r], reqs[r].morph, &rmp[r], &err, cost_fn(G));
+            std::vector<Pat> cl;
+            std::vector<PlanInfo> pl;
+            if (!prc) prc = plan_closure(G, rmp[r].alt, &cl, &pl);
+            if (prc == PM_E_NOMEM || prc == PM_E_DEVICE) {
+                rc = prc;
+                break;
+            }
+            if (prc) {
+                res[r].status = prc;
+                res[r].latency_s = now_s() - reqs[r].arrival_s;
+                ++finished;
+                continue;
+            }
+            double c = 0;
+            for (const PlanInfo& p : pl) c += p.est_cost;
+            rcost[r] = c;
+            pending.push_back(r);
         }
+        if (rc) break;
         bool progressed = false;
         // retire finished batches; cancel those past the deadline
         for (Slot& s : slots) {
@@ -217,6 +264,16 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             std::vector<int> rst;
             std::vector<std::string> rerr;
             const int brc = e == hipSuccess ? (B.cancelled ? PM_E_TIMEOUT : PM_OK) : PM_E_DEVICE;
+            if (brc == PM_E_TIMEOUT) {
+                // the costliest request of the batch takes the blame
+                uint32_t worst = B.reqs[0];
+                for (uint32_t r : B.reqs)
+                    if (rcost[r] > rcost[worst]) worst = r;
+                auto key = std::make_pair((const GraphRes*)gr[worst], rk[worst]);
+                auto it = timeout_cost.find(key);
+                if (it == timeout_cost.end()) timeout_cost[key] = rcost[worst];
+                else it->second = std::min(it->second, rcost[worst]);
+            }
             if (brc == PM_OK) batch_values(B, &vals, &rst, &rerr);
             for (size_t r = 0; r < B.reqs.size(); ++r) {
                 pm_serve_result& R = res[B.reqs[r]];
@@ -251,36 +308,52 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                 else if (!free_slot) free_slot = &s;
             }
             if (!free_slot) break;
-            const uint32_t head = pending.front();
+            // shed what an observed timeout says cannot finish in time
+            if (cfg->deadline_s > 0 && !timeout_cost.empty()) {
+                bool any = false;
+                for (auto it = pending.begin(); it != pending.end();) {
+                    auto tc = timeout_cost.find(std::make_pair((const GraphRes*)gr[*it], rk[*it]));
+                    if (tc != timeout_cost.end() && rcost[*it] >= tc->second) {
+                        res[*it].status = PM_E_TIMEOUT;
+                        res[*it].latency_s = now_s() - reqs[*it].arrival_s;
+                        ++finished;
+                        ++shed;
+                        any = true;
+                        it = pending.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                if (any) progressed = true;
+                if (pending.empty()) break;
+            }
+            // the cheapest pending request heads the batch (earliest first
+            // among equals); others on its graph of at most four times its
+            // estimated work join, cheapest first
+            uint32_t head = pending.front();
+            for (uint32_t r : pending)
+                if (rcost[r] < rcost[head]) head = r;
             GraphRes& G = *gr[head];
             const double t_setup = now_s();
             auto B = std::make_unique<Batch>();
-            for (auto it = pending.begin(); it != pending.end() && B->reqs.size() < cfg->max_batch; ++it)
-                if (gr[*it] == &G) B->reqs.push_back(*it);
-            // plan every request, union the closures
-            bool bad = false;
+            B->reqs.push_back(head);
+            {
+                std::vector<uint32_t> cand;
+                for (uint32_t r : pending)
+                    if (r != head && gr[r] == &G && rcost[r] <= 4 * std::max(rcost[head], SMALL_WORK)) cand.push_back(r);
+                std::stable_sort(cand.begin(), cand.end(), [&](uint32_t x, uint32_t y) { return rcost[x] < rcost[y]; });
+                for (uint32_t r : cand) {
+                    if (B->reqs.size() >= cfg->max_batch) break;
+                    B->reqs.push_back(r);
+                }
+            }
+            // union the requests' alternatives (morph plans made on arrival)
             std::vector<Pat> alts;
             for (uint32_t r : B->reqs) {
-                MorphPlan mp;
-                std::string err;
-                int prc = morph_plan_count(pats[r], reqs[r].morph, &mp, &err, cost_fn(G));
-                if (prc) {
-                    res[r].status = prc;
-                    bad = true;
-                }
-                B->mps.push_back(mp);
-                for (const Pat& a : mp.alt)
+                B->mps.push_back(rmp[r]);
+                B->cost += rcost[r];
+                for (const Pat& a : rmp[r].alt)
                     if (std::find(alts.begin(), alts.end(), a) == alts.end()) alts.push_back(a);
-            }
-            if (bad) {
-                // drop the failed requests from the pending queue, try again
-                for (uint32_t r : B->reqs)
-                    if (res[r].status) {
-                        pending.erase(std::find(pending.begin(), pending.end(), r));
-                        res[r].latency_s = now_s() - reqs[r].arrival_s;
-                        ++finished;
-                    }
-                continue;
             }
             int prc = plan_closure(G, alts, &B->closure, &B->plans);
             if (prc) {
@@ -398,6 +471,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
         stats->mean_setup_s = lat.empty() ? 0 : setup_sum / lat.size();
         stats->mean_service_s = lat.empty() ? 0 : service_sum / lat.size();
         stats->sustained_qps = stats->makespan_s > 0 ? (double)stats->completed / stats->makespan_s : 0;
+        stats->shed = shed;
     }
     return PM_OK;
 }

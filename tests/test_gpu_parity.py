@@ -172,3 +172,23 @@ def test_relabel_invariance_and_mode_agreement(eng):
     b = _gpu_counts(eng, h, 4, True, pm.MORPH_NAIVE)
     c = _gpu_counts(eng, g, 4, True, pm.MORPH_NONE)
     assert a == b == c
+
+
+def test_hub_bitmaps_off_equals_on(eng):
+    """Probes of hub lists answer from membership bitmaps (vertices of 64 or
+    more neighbours); with the bitmaps switched off every probe is a binary
+    search.  All 5-vertex classes, both ways, against the oracle's census."""
+    import paper_2012_04553_amd as pm
+    g = gen.rmat(8, 16, seed=21)
+    vi5 = oracle.census(g, 5)
+    ei5 = P.edge_induced_from_vertex_induced(5, vi5)
+    want_ei = [ei5[m] for m in P.connected_classes(5)]
+    want_vi = [vi5[m] for m in P.connected_classes(5)]
+    for hb in (1, 0):
+        eng.set_option("hub_bitmaps", hb)
+        try:
+            _say(f"hub bitmaps {hb}")
+            assert _gpu_counts(eng, g, 5, False, pm.MORPH_NONE) == want_ei, hb
+            assert _gpu_counts(eng, g, 5, True, pm.MORPH_NAIVE) == want_vi, hb
+        finally:
+            eng.set_option("hub_bitmaps", 1)
