@@ -804,7 +804,22 @@ std::string Ctx_::closure_key(const GraphRes& G, const std::vector<Pat>& closure
 LaunchCfg Ctx_::cfg_for(const GraphRes& G, const std::vector<Pat>& closure) const {
     auto it = tune_cache.find(closure_key(G, closure));
     if (it != tune_cache.end()) return it->second.first;
-    return default_cfg();
+    return start_cfg(closure);
+}
+
+// Untuned launch parameters: the context's, except that a closure with
+// 5-vertex patterns gets fine work items (its hub roots' subtrees dominate:
+// R-MAT 12 5-MC 1,085 ms with 1024/512, 304 ms with 256/64), unless the
+// caller set the item options.
+LaunchCfg Ctx_::start_cfg(const std::vector<Pat>& closure) const {
+    LaunchCfg c = default_cfg();
+    int kmax = 0;
+    for (const Pat& q : closure) kmax = std::max(kmax, (int)q.k);
+    if (kmax >= 5 && !items_set) {
+        c.item_budget = std::min<uint64_t>(c.item_budget, 256);
+        c.item_split = std::min<uint32_t>(c.item_split, 64);
+    }
+    return c;
 }
 
 int Ctx_::get_items(GraphRes& G, const LaunchCfg& c, ItemSet** out) {
@@ -1304,15 +1319,15 @@ int Ctx_::autotune(uint32_t gid, const pm_pattern* pats, uint32_t npat, int morp
     auto hit = tune_cache.find(key);
     if (hit == tune_cache.end()) {
         // coordinate descent over the launch parameters, timed on the graph
-        LaunchCfg best = default_cfg();
+        LaunchCfg best = start_cfg(closure);
         double best_ms;
         rc = run_eager_ms(*G, plans, best, &best_ms);
         if (rc) return rc;
         const int bpcs[] = {1, 2, 4, 8};
-        const uint64_t budgets[] = {1024, 4096, 16384, 65536};
-        const uint32_t splits[] = {512, 2048, 8192};
+        const uint64_t budgets[] = {256, 1024, 4096, 16384, 65536};
+        const uint32_t splits[] = {32, 64, 512, 2048, 8192};
         for (int stage = 0; stage < 3; ++stage) {
-            int nvals = stage == 0 ? 4 : (stage == 1 ? 4 : 3);
+            int nvals = stage == 0 ? 4 : 5;
             for (int v = 0; v < nvals; ++v) {
                 LaunchCfg c = best;
                 if (stage == 0) c.blocks_per_cu = bpcs[v];
@@ -1981,8 +1996,13 @@ pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value) {
     Ctx_& c = ctx->c;
     if (k == "count_bytes") c.count_bytes = value != 0;
     else if (k == "blocks_per_cu" && value >= 1 && value <= 64) c.blocks_per_cu = (int)value;
-    else if (k == "item_budget" && value >= 1) c.item_budget = (uint64_t)value;
-    else if (k == "item_split" && value >= 64) c.item_split = (uint32_t)value;
+    else if (k == "item_budget" && value >= 1) {
+        c.item_budget = (uint64_t)value;
+        c.items_set = true;
+    } else if (k == "item_split" && value >= 16) {
+        c.item_split = (uint32_t)value;
+        c.items_set = true;
+    }
     else if (k == "agg_waves" && value >= 1) c.agg_waves_opt = (uint64_t)value;
     else if (k == "agg_split" && value >= 64 && value <= 0x7fffffff) c.agg_split = (uint32_t)value;
     else if (k == "heavy_roots" && (value == 0 || value == 1)) c.heavy_roots_opt = value != 0;

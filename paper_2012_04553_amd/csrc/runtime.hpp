@@ -264,6 +264,8 @@ struct Ctx_ {
         return std::min<uint64_t>(std::min<uint64_t>(agg_waves_opt, waves(c)), by_mem);
     }
     LaunchCfg default_cfg() const { return LaunchCfg{blocks_per_cu, item_budget, item_split}; }
+    LaunchCfg start_cfg(const std::vector<Pat>& closure) const;
+    bool items_set = false;          // item_budget / item_split set through pm_set_option
     std::string closure_key(const GraphRes& G, const std::vector<Pat>& closure) const;
     LaunchCfg cfg_for(const GraphRes& G, const std::vector<Pat>& closure) const;
     int get_items(GraphRes& G, const LaunchCfg& c, ItemSet** out);

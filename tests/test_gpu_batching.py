@@ -82,8 +82,8 @@ def test_autotune(eng):
         ref = eng.count(gid, pats, morph=pm.MORPH_NAIVE)
         cfg = eng.autotune(gid, pats, morph=pm.MORPH_NAIVE)
         assert cfg["blocks_per_cu"] in (1, 2, 4, 8)
-        assert cfg["item_budget"] in (1024, 4096, 16384, 65536)
-        assert cfg["item_split"] in (512, 2048, 8192)
+        assert cfg["item_budget"] in (256, 1024, 4096, 16384, 65536)
+        assert cfg["item_split"] in (32, 64, 512, 2048, 8192)
         assert cfg["ms"] > 0
         again = eng.autotune(gid, pats, morph=pm.MORPH_NAIVE)
         assert again == cfg            # cached
