@@ -119,6 +119,13 @@ constexpr uint32_t EW_TERMS = 4;
 // Graph membership bitmaps: vertices of at least HUB_BM_DEG neighbours, the
 // highest degrees first, HUB_BM_BYTES at most in all.
 constexpr uint32_t HUB_BM_DEG = 64;
+
+// Plan choice: an enumerated core level beyond three ranks this many times
+// dearer than its estimate.
+#ifndef PM_DEEP_PENALTY
+#define PM_DEEP_PENALTY 4.0
+#endif
+constexpr double DEEP_PENALTY = PM_DEEP_PENALTY;
 constexpr uint64_t HUB_BM_BYTES = 512ull << 20;
 inline bool edge_window_ok(const DPlan& d) {
     if (d.ncore != 2 || d.agg_last || d.local || d.nterm == 0) return false;
