@@ -160,13 +160,16 @@ def launch_roofline(eng, gid, pats, mode, steps):
     bytes_ = [x["alg_bytes"] for x in eng.launch_stats()]
     names = [x["kernel"] for x in eng.launch_stats()]
     eng.set_option("count_bytes", 0)
+    log("  per-launch bytes done")
     eng.set_option("launch_events", 1)
     ms = [0.0] * len(bytes_)
     eng.count(gid, pats, morph=mode)
+    log("  per-launch timing warm-up done")
     for _ in range(steps):
         eng.count(gid, pats, morph=mode)
         for i, x in enumerate(eng.launch_stats()):
             ms[i] += x["ms"] / steps
+        log("  per-launch timing pass done")
     eng.set_option("launch_events", 0)
     per = []
     for name, b, t in zip(names, bytes_, ms):
@@ -294,12 +297,15 @@ def wl_rmat_5mc(args, eng):
     else:
         log(f"  R-MAT scale {scale}: n={g.n} m={g.m}; the engine's default launch configuration")
     eng.set_option("count_bytes", 1)
+    t = time.perf_counter()
     ref = eng.count(gid, pats, morph=pm.MORPH_NAIVE)
     st = eng.last_stats()
     eng.set_option("count_bytes", 0)
+    log(f"  byte-tally pass in {time.perf_counter() - t:.1f} s")
 
     def step():
         assert eng.count(gid, pats, morph=pm.MORPH_NAIVE) == ref
+        log("  step done")
 
     ms_per_step, kms = timed_steps(eng, step, args)
     k_ms = sum(kms) / len(kms)

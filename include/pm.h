@@ -278,9 +278,11 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *                   kernel that tallies algorithmic bytes (see
  *                   pm_last_query_stats);
  *   "blocks_per_cu" persistent blocks per compute unit (1..64);
- *   "item_budget"   adjacency entries per root-range work item (>= 1);
- *   "item_split"    level-1 slice length for high-degree roots (>= 64);
- *                   takes effect for graphs loaded afterwards;
+ *   "item_budget"   adjacency entries per root-range work item (>= 1,
+ *                   default 4096; untuned sets with 5-vertex patterns use
+ *                   256 unless this or "item_split" was set);
+ *   "item_split"    level-1 slice length for high-degree roots (>= 16,
+ *                   default 2048; 64 for untuned 5-vertex sets, as above);
  *   "agg_waves"     upper bound on the wavefronts of two-hop aggregation
  *                   launches (>= 1, default 2048); each such wave holds
  *                   8 bytes per vertex, and their total is also kept within
@@ -319,14 +321,18 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "fork_launches" 0/1 (default 0): captured launch sets run the triangle
  *                   and edge-support launches and the 4-clique launches on
  *                   two more branches of the hipGraph, beside the general
- *                   kernel's launches.
+ *                   kernel's launches;
+ *   "hub_bitmaps"   0/1 (default 1): probes of the adjacency lists of the
+ *                   highest-degree vertices (64 neighbours or more, up to
+ *                   512 MiB of n-bit bitmaps built at graph load) answer
+ *                   from the bitmaps instead of by binary search.
  * Errors: PM_E_INVAL for an unknown key or a value out of range. */
 pm_status pm_set_option(pm_ctx* ctx, const char* key, int64_t value);
 
 /* Batching: tune the launch of one query set on one graph.  Times the
  * whole multi-pattern launch under a coordinate search over blocks per
- * compute unit {1,2,4,8}, root budget per work item {1K,4K,16K,64K}
- * adjacency entries and hub slice {512,2K,8K}, and keeps the fastest for
+ * compute unit {1,2,4,8}, root budget per work item {256,1K,4K,16K,64K}
+ * adjacency entries and hub slice {32,64,512,2K,8K}, and keeps the fastest for
  * that (graph, matched pattern set): later pm_submit calls of the same set
  * use it.  Results are cached per context and, when the environment
  * variable PM_AUTOTUNE_CACHE names a file, appended there and reloaded by
