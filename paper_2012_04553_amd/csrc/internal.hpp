@@ -107,6 +107,10 @@ struct DPlan {
                          //    bitmap of the root's adjacency list
     int32_t cyc5;        // 1: the edge-induced 5-cycle's pair sum, run by
                          //    cycle5_kernel (no levels or terms of its own)
+    int32_t tagg;        // a closed form over per-edge triangle counts t(e)
+                         // and per-vertex triangle counts T(v), evaluated
+                         // per edge by support_kernel (no levels or terms):
+                         // TAGG_BOWTIE or TAGG_TRIPATH
     DLevel lev[KMAX];
     DTerm term[MAX_TERMS];
     DMono mono[MAX_MONO];
@@ -282,7 +286,9 @@ struct GraphStats {             // degree statistics used by the cost model
     double s_pp = 0, s_pq = 0, s_pd = 0, s_qq = 0, s_qd = 0, s_dd = 0;
 };
 
-int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err);
+// tri: the graph's triangle counts per edge are available to the launch
+// (closed forms of tagg_kind may be chosen)
+int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err, bool tri = false);
 // The companion of the 5-cycle plan: a marker pattern (labels -2, never a
 // query) whose plan sums, over the triangles {u < v < w}, the neighbours of
 // u, v and w below u.
@@ -297,6 +303,42 @@ inline bool is_cycle5(const Pat& p) {
         if (d != 2) return false;
     }
     return is_connected(5, p.em);
+}
+// Edge-induced, unlabeled 5-vertex patterns counted in closed form from
+// triangle counts (no enumeration):
+//  TAGG_BOWTIE  two triangles sharing one vertex: every pair of triangles at
+//    a vertex v that share only v, sum_v C(T(v), 2) - sum_e t(e)(t(e) - 1)
+//    (two triangles at v that share a second vertex u share the edge vu);
+//  TAGG_TRIPATH a triangle with a two-edge path hanging off one corner: for
+//    every edge {u, w}, both orientations (apex, path vertex), the triangles
+//    at the apex that avoid the path vertex times the path vertex's other
+//    neighbours, (T(u) - t)(d(w) - 1) + (T(w) - t)(d(u) - 1), less the
+//    choices whose path end lies on the triangle, 2 t (t - 1) over the edges.
+constexpr int32_t TAGG_BOWTIE = 1;
+constexpr int32_t TAGG_TRIPATH = 2;
+inline int tagg_kind(const Pat& p) {
+    if (p.k != 5 || p.vi || !is_connected(5, p.em)) return 0;
+    int deg[5] = {0, 0, 0, 0, 0};
+    for (int v = 0; v < 5; ++v) {
+        if (p.lab[v] != -1) return 0;
+        for (int w = 0; w < 5; ++w)
+            if (w != v && has_edge(p.em, v, w)) ++deg[v];
+    }
+    int hist[5] = {0, 0, 0, 0, 0};
+    for (int v = 0; v < 5; ++v) ++hist[deg[v]];
+    bool tri = false;
+    for (int a = 0; a < 5; ++a)
+        for (int b = a + 1; b < 5; ++b)
+            for (int c = b + 1; c < 5; ++c)
+                tri = tri || (has_edge(p.em, a, b) && has_edge(p.em, a, c) && has_edge(p.em, b, c));
+    // six edges, one vertex of degree 4 and four of degree 2: the leaves pair
+    // up into two triangles with the centre
+    if (popc(p.em) == 6 && hist[4] == 1 && hist[2] == 4) return TAGG_BOWTIE;
+    // five edges with degrees 3, 2, 2, 2, 1 and a triangle: the corner of
+    // degree 3 carries the path (without a triangle it is a 4-cycle with a
+    // pendant vertex)
+    if (popc(p.em) == 5 && hist[3] == 1 && hist[2] == 3 && hist[1] == 1 && tri) return TAGG_TRIPATH;
+    return 0;
 }
 // all candidate plans (for tests / autotuning)
 int candidate_plans(const Pat& p, const GraphStats& gs, std::vector<PlanInfo>* out, std::string* err);

@@ -2067,11 +2067,58 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
     }
 }
 
+// Per-vertex support sums: every edge {u < w} adds its support t to both
+// ends (a register sum for u, one global atomic for w), so vtri[v] ends at
+// twice the triangles through v.
+template <bool BYTES>
+__global__ void __launch_bounds__(256) vtri_kernel(KArgs a) {
+    uint64_t bytes = 0;
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < a.g.n; u += step) {
+        const uint32_t pb = a.g.split[u], pe = a.g.rp[u + 1];
+        if (BYTES) bytes += 8 + 8ull * (pe - pb);
+        uint64_t su = 0;
+        for (uint32_t p = pb; p < pe; ++p) {
+            const uint32_t t = a.support[p];
+            if (t) {
+                atomicAdd((unsigned long long*)&a.vtri[a.g.col[p]], (unsigned long long)t);
+                su += t;
+                if (BYTES) bytes += 8;
+            }
+        }
+        if (su) atomicAdd((unsigned long long*)&a.vtri[u], (unsigned long long)su);
+        if (BYTES && su) bytes += 8;
+    }
+    if (BYTES) {
+        unsigned long long bsum = bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (wave_lane() == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
+// The triangle-count closed forms (DPlan::tagg) at one vertex u with T(u)
+// triangles: the per-vertex part, then the part of each out-edge {u < w}
+// with support t.  Sums wrap modulo 2^128 (the plan's total is a count,
+// never negative, so the wrapped partial sums add up to it exactly).
+__device__ __forceinline__ u128 tagg_vertex(int32_t kind, uint64_t Tu) {
+    if (kind == TAGG_BOWTIE) return ((u128)Tu * (u128)(Tu ? Tu - 1 : 0)) >> 1;
+    return 0;
+}
+__device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw, uint32_t du, uint32_t dw,
+                                          uint32_t t) {
+    const u128 pairs = (u128)t * (u128)(t ? t - 1 : 0);   // t (t - 1)
+    if (kind == TAGG_BOWTIE) return (u128)0 - pairs;
+    // TAGG_TRIPATH: apex u with path vertex w, then apex w with path vertex u
+    const u128 fwd = (u128)(Tu - t) * (u128)(dw - 1) + (u128)(Tw - t) * (u128)(du - 1);
+    return fwd - 2 * pairs;
+}
+
 // Edge-support plans, and edge-core plans with cheap terms only (then
 // without a support array): one thread per vertex u walks its out-list;
-// each edge {u < w} takes its support t (and returns the counter to zero),
-// orients itself as the plan's level 1 requires, and adds the tail with the
-// set-size term equal to t.
+// each edge {u < w} takes its support t (the last such launch of a replay
+// returns the counter to zero), orients itself as the plan's level 1
+// requires, and adds the tail with the set-size term equal to t.  Plans
+// with a triangle-count closed form add their per-vertex and per-edge parts.
 template <bool BYTES>
 __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
     const int np = a.nplans;
@@ -2091,16 +2138,38 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
         const uint32_t pb = a.g.split[u], pe = a.g.rp[u + 1];
         const uint32_t du = pe - a.g.rp[u];
         if (BYTES) c.bytes += 12 + 8ull * (pe - pb);
+        const uint64_t Tu = a.vtri ? a.vtri[u] >> 1 : 0;
+        if (a.vtri) {
+            if (BYTES) c.bytes += 8;
+#pragma unroll 1
+            for (int q = 0; q < np; ++q) {
+                const int32_t kind = ((gcp<DPlan>)a.plans + q)->tagg;
+                if (!kind) continue;
+                const u128 add = tagg_vertex(kind, Tu);
+#pragma unroll
+                for (int k = 0; k < CQ_PLANS; ++k)
+                    if (k == q) acc[k] += add;
+            }
+        }
         for (uint32_t p = pb; p < pe; ++p) {
             const uint32_t w = a.g.col[p];
             // an edge on no triangle still adds the tail's terms without t
             const uint32_t t = a.support ? a.support[p] : 0u;
-            if (t) a.support[p] = 0;
+            if (t && a.sup_clear) a.support[p] = 0;
             const uint32_t dw = a.g.rp[w + 1] - a.g.rp[w];
             if (BYTES) c.bytes += 8;
+            const uint64_t Tw = a.vtri ? a.vtri[w] >> 1 : 0;
+            if (BYTES && a.vtri) c.bytes += 8;
 #pragma unroll 1
             for (int q = 0; q < np; ++q) {
                 gcp<DPlan> P = (gcp<DPlan>)a.plans + q;
+                if (P->tagg) {
+                    const u128 add = tagg_edge(P->tagg, Tu, Tw, du, dw, t);
+#pragma unroll
+                    for (int k = 0; k < CQ_PLANS; ++k)
+                        if (k == q) acc[k] += add;
+                    continue;
+                }
                 const bool up = P->lev[1].gt != 0;
                 const uint32_t v0 = up ? u : w, v1 = up ? w : u;
                 const uint32_t d0 = up ? du : dw, d1 = up ? dw : du;
@@ -2406,6 +2475,12 @@ int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
         if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((clique_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_vtri(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes) hipLaunchKernelGGL(vtri_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(vtri_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

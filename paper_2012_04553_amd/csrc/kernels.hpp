@@ -48,6 +48,9 @@ struct KArgs {
     uint32_t* support;        // per out-list position: triangles on that edge, or null
     uint32_t wide;            // 1: agg_window_kernel keeps 32-bit counters even
                               //    when every degree fits 16 bits
+    uint32_t sup_clear;       // 1: support_kernel returns the supports to zero
+    uint64_t* vtri;           // per vertex: the supports of its edges summed
+                              // (twice its triangles), zeroed; or null
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
@@ -66,9 +69,14 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
 // wavefront per item {r0, r1, i0, i1} (roots [r0, r1), rows [i0, i1) of
 // N+(r)).
 int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
-// Edge-support plans (support_ok) over a support array filled by a
-// launch_clique with a.support set; returns every counter to zero.
+// Edge-support plans (support_ok) and triangle-count closed forms (tagg)
+// over a support array filled by a launch_clique with a.support set (and,
+// for the closed forms, a.vtri filled by launch_vtri); with a.sup_clear it
+// returns every support counter to zero.
 int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Per-vertex sums of the supports (a.vtri, zeroed beforehand): one thread
+// per vertex over its out-list, one atomic per edge for the far end.
+int launch_vtri(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
 // wavefront (mode 0: up to C4_LIGHT_MAX out-neighbours) or one workgroup
 // (mode 1: up to C4_HEAVY_MAX, mode 2: up to C4_ROOT_MAX) per root of the

@@ -720,6 +720,8 @@ std::string PlanInfo::describe() const {
         s += buf;
     }
     if (cyc5) s += " | cycle5 pair sum minus the companion triangle plan";
+    if (d.tagg == TAGG_BOWTIE) s += " | triangle counts: bowtie";
+    if (d.tagg == TAGG_TRIPATH) s += " | triangle counts: triangle with a two-edge path";
     if (d.lane_par) s += " lane_par";
     if (d.local) s += " local_bitmap";
     if (d.bm0) s += " root_bitmap";
@@ -858,7 +860,36 @@ static void cycle5_plans(const GraphStats& gs, PlanInfo* pc, PlanInfo* aux) {
     aux->total_cost = aux->est_cost;
 }
 
-int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err) {
+// Patterns with a closed form over triangle counts (tagg_kind): no levels
+// or terms; the cost is the triangle pass that fills the per-edge counts
+// (about the out-wedges, s_pp) and a few passes over the edges.
+static void tagg_plan(const Pat& p, int kind, const GraphStats& gs, PlanInfo* out) {
+    DPlan d;
+    memset(&d, 0, sizeof(d));
+    d.ncore = 1;
+    d.mult = 1;
+    d.tagg = kind;
+    d.bridge_src = 0xff;
+    d.lev[0].base = 0xff;
+    d.lev[0].label = -1;
+    out->d = d;
+    out->pat = p;
+    out->divisor = 1;
+    out->formulation = 0;
+    for (int j = 0; j < KMAX; ++j) out->order[j] = j < 1 ? 0 : -1;
+    out->est_cost = gs.s_pp + 4 * gs.m + gs.n;
+    out->total_cost = out->est_cost;
+    out->subs.clear();
+}
+
+int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err, bool tri) {
+    if (tri) {
+        const int kind = tagg_kind(p);
+        if (kind) {
+            tagg_plan(p, kind, gs, out);
+            return PM_OK;
+        }
+    }
     if (p.k == 3 && p.lab[0] == -2) {
         PlanInfo pc;
         cycle5_plans(gs, &pc, out);
@@ -884,7 +915,7 @@ int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string*
                 PlanInfo sp;
                 std::string e2;
                 double c = 1e300;
-                if (compile_plan(sq.first, gs, &sp, &e2) == PM_OK) c = sp.total_cost;
+                if (compile_plan(sq.first, gs, &sp, &e2, tri) == PM_OK) c = sp.total_cost;
                 it = sub_cost.emplace(key, c).first;
             }
             extra += it->second;

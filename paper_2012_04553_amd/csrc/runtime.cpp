@@ -494,36 +494,44 @@ int to_pat(const pm_pattern& q, Pat* out, std::string* err) {
 }
 
 
-const PlanInfo& Ctx_::plan_for(GraphRes& G, const Pat& p, int* rc) {
+// Closed forms over triangle counts need every triangle met by the
+// triangle pass that fills the per-edge counts (no root beyond CQ_SMAX).
+bool Ctx_::tri_forms(const GraphRes& G) const {
+    return clique_opt && support_opt && !G.clique_items.empty() && G.clique_big.empty();
+}
+
+const PlanInfo& Ctx_::plan_for(GraphRes& G, const Pat& p, int* rc, bool tri_ok) {
     std::lock_guard<std::mutex> g(plan_mu);
-    for (auto& e : G.plan_cache)
+    const bool tri = tri_ok && tri_forms(G);
+    auto& cache = tri ? G.plan_cache : G.plan_cache_notri;
+    for (auto& e : cache)
         if (e.first == p) {
             *rc = PM_OK;
             return e.second;
         }
     PlanInfo pi;
     std::string err;
-    *rc = compile_plan(p, G.st, &pi, &err);
+    *rc = compile_plan(p, G.st, &pi, &err, tri);
     if (*rc) g_err = err;
-    G.plan_cache.push_back({p, pi});
-    return G.plan_cache.back().second;
+    cache.push_back({p, pi});
+    return cache.back().second;
 }
 
-std::function<double(const Pat&)> Ctx_::cost_fn(GraphRes& G) {
-    return [this, &G](const Pat& p) {
+std::function<double(const Pat&)> Ctx_::cost_fn(GraphRes& G, bool tri_ok) {
+    return [this, &G, tri_ok](const Pat& p) {
         int rc;
-        const PlanInfo& pi = plan_for(G, p, &rc);
+        const PlanInfo& pi = plan_for(G, p, &rc, tri_ok);
         return rc ? 1e300 : pi.total_cost;
     };
 }
 
 int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
-                       std::vector<PlanInfo>* plans) {
+                       std::vector<PlanInfo>* plans, bool tri_ok) {
     std::vector<Pat> cl = alt;
     std::vector<PlanInfo> pl;
     for (size_t i = 0; i < cl.size(); ++i) {
         int rc;
-        PlanInfo pi = plan_for(G, cl[i], &rc);
+        PlanInfo pi = plan_for(G, cl[i], &rc, tri_ok);
         if (rc) return rc;
         for (auto& sq : pi.subs)
             if (std::find(cl.begin(), cl.end(), sq.first) == cl.end()) cl.push_back(sq.first);
@@ -537,6 +545,7 @@ int Ctx_::plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat
     auto group = [&](size_t a) {
         const DPlan& d = pl[a].d;
         if (d.cyc5) return 5;
+        if (d.tagg) return 3;
         return d.agg_last ? 4
                           : (clique_ok(d) ? 1 : (clique4_ok(d) ? 2 : (edge_window_ok(d) || edge_cheap_ok(d) ? 3 : 0)));
     };
@@ -655,7 +664,7 @@ bool Ctx_::use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) co
 bool Ctx_::use_support(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
     if (!clique_opt || !support_opt || G.clique_items.empty() || !G.clique_big.empty()) return false;
     for (const PlanInfo& p : plans)
-        if (!clique_ok(p.d) && support_ok(p.d)) return true;
+        if (p.d.tagg || (!clique_ok(p.d) && support_ok(p.d))) return true;
     return false;
 }
 
@@ -908,6 +917,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const std::vector<KItem> cq_big = cq ? clique_big_items(G, cfg) : std::vector<KItem>();
     const bool c4 = use_clique4(G, plans) && (agg == nullptr || G.c4_big.empty());
     const bool sup = agg == nullptr && use_support(G, plans);
+    bool any_tagg = false;
+    for (const PlanInfo& p : plans) any_tagg = any_tagg || p.d.tagg != 0;
+    if (any_tagg && !sup) return fail(PM_E_DEVICE, "internal: a triangle-count plan without triangle counts");
     if (sup) {
         int rc2 = ensure_support(G);
         if (rc2) return rc2;
@@ -929,7 +941,8 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const uint64_t bm_words = bitmap_words(G, plans);
     const uint64_t zhead = (16 * np + 512 + 255) & ~uint64_t(255);
     const uint64_t zbm = (waves(cfg) * bm_words * 4 + 255) & ~uint64_t(255);
-    const uint64_t zbytes = zhead + zbm;
+    const uint64_t zvt = any_tagg ? ((8ull * G.n + 255) & ~uint64_t(255)) : 0;
+    const uint64_t zbytes = zhead + zbm + zvt;
     char* zb = carve(zbytes);
     ls->heavy_items = nullptr;
     ls->heavy_nitems = 0;
@@ -964,6 +977,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->cq_nitems = ls->cq_nbig = 0;
     ls->support = sup ? (uint32_t*)dptr(G.off_support) : nullptr;
     ls->sup_run = -1;
+    ls->sup_last = -1;
     if (cqs) {
         ls->cq_items = G.d_cq;
         ls->cq_nitems = (uint32_t)G.clique_items.size();
@@ -996,6 +1010,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->heads = (uint32_t*)(zb + 16 * np);
     ls->bytes = (uint64_t*)(zb + 16 * np + 256);
     uint32_t* rootbm = bm_words ? (uint32_t*)(zb + zhead) : nullptr;
+    ls->vtri = any_tagg ? (uint64_t*)(zb + zhead + zbm) : nullptr;
     ls->scratch = (uint32_t*)carve(waves(cfg) * (uint64_t)KMAX * ls->stride * 4);
     std::vector<DPlan> hp(np);
     for (size_t i = 0; i < np; ++i) hp[i] = plans[i].d;
@@ -1065,6 +1080,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     // two-hop plans (light roots, then heavy roots)
     auto group = [&](int q) {
         if (plans[q].d.cyc5) return 6;
+        if (plans[q].d.tagg) return 5;
         if (plans[q].d.agg_last) return 2;
         if (cq && clique_runs(G, plans[q].d)) return 3;
         if ((sup && support_ok(plans[q].d)) || (clique_opt && edge_cheap_ok(plans[q].d))) return 5;
@@ -1072,6 +1088,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
         return (ek && edge_window_ok(plans[q].d)) ? 1 : 0;
     };
     int i = 0;
+    bool vtri_added = false;
     while (i < (int)np) {
         const int grp = group(i);
         int j = i;
@@ -1091,15 +1108,25 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                 ls->run_agg.push_back(6);
             }
         } else if (grp == 5) {
-            bool need = false;
-            for (int k = i; k < j; ++k) need = need || !edge_cheap_ok(plans[k].d);
+            bool need = false, tg = false;
+            for (int k = i; k < j; ++k) {
+                need = need || !edge_cheap_ok(plans[k].d);
+                tg = tg || plans[k].d.tagg != 0;
+            }
             if (need && ls->sup_run < 0) {
                 // no triangle-core plan: a pass that only fills the supports
                 ls->sup_run = (int)ls->runs.size();
                 ls->runs.push_back({i, i});
                 ls->run_agg.push_back(5);
             }
+            if (tg && !vtri_added) {
+                // per-vertex triangle counts from the supports, once
+                vtri_added = true;
+                ls->runs.push_back({i, i});
+                ls->run_agg.push_back(13);
+            }
             for (int k = i; k < j; k += CQ_PLANS) {
+                if (sup) ls->sup_last = (int)ls->runs.size();
                 ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
                 ls->run_agg.push_back(10);
             }
@@ -1155,6 +1182,7 @@ const char* run_kernel_name(int kind) {
         case 7: case 8: case 11: return "clique4_kernel";
         case 10: return "support_kernel";
         case 12: return "cycle5_kernel";
+        case 13: return "vtri_kernel";
         default: return "match_kernel";
     }
 }
@@ -1167,7 +1195,7 @@ const char* run_kernel_name(int kind) {
 // 4-cliques; 0 = the rest (general kernel and window kernels, which share
 // the per-wavefront level buffers and window scratch).
 static int run_branch(int kind) {
-    if (kind == 5 || kind == 10) return 1;
+    if (kind == 5 || kind == 10 || kind == 13) return 1;
     if (kind == 7 || kind == 8 || kind == 11) return 2;
     return 0;
 }
@@ -1229,7 +1257,14 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             continue;
         } else if (ls.run_agg[r] == 10) {
             b.support = ls.support;
+            b.vtri = ls.vtri;
+            b.sup_clear = (int)r == ls.sup_last ? 1u : 0u;
             if (launch_support(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 13) {
+            b.support = ls.support;
+            b.vtri = ls.vtri;
+            if (launch_vtri(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 6) {
             b.items = ls.cq_big;

@@ -103,7 +103,9 @@ struct LaunchSet {
                                              // 5 triangle-core (clique_kernel), 6 their larger roots,
                                              // 7/8 4-cliques (clique4_kernel, light/heavy roots),
                                              // 9 their larger roots, 10 edge-support plans,
-                                             // 11 4-cliques (clique4_kernel, largest roots)
+                                             // 11 4-cliques (clique4_kernel, largest roots),
+                                             // 12 5-cycles (cycle5_kernel), 13 per-vertex
+                                             // triangle counts (vtri_kernel)
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
     const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
@@ -121,6 +123,8 @@ struct LaunchSet {
     uint32_t c4_nlight = 0, c4_nheavy = 0, c4_nhuge = 0, c4_nbig = 0;
     uint32_t* support = nullptr;             // edge supports (the graph's), when used
     int sup_run = -1;                        // the triangle run that fills them
+    int sup_last = -1;                       // the last run that reads them (and clears them)
+    uint64_t* vtri = nullptr;                // per vertex: twice its triangle count (closed forms)
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel
@@ -161,6 +165,7 @@ struct GraphRes {
     std::map<std::pair<uint64_t, uint32_t>, ItemSet> itemsets;
     std::map<std::string, std::unique_ptr<LaunchSet>> launches;
     std::vector<std::pair<Pat, PlanInfo>> plan_cache;
+    std::vector<std::pair<Pat, PlanInfo>> plan_cache_notri;   // without triangle-count closed forms
     uint64_t off_lorder = UINT64_MAX;        // label-sorted vertex order on the device (first MNI use)
     uint64_t off_hubbm = UINT64_MAX;         // membership bitmaps of the vertices hub0 .. n-1
     uint32_t hub0 = 0, hub_words = 0;
@@ -287,7 +292,7 @@ struct Ctx_ {
     };
     int make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, LaunchSet* ls,
                        hipStream_t s = nullptr, const AggArrays* agg = nullptr);
-    std::function<double(const Pat&)> cost_fn(GraphRes& G);
+    std::function<double(const Pat&)> cost_fn(GraphRes& G, bool tri_ok = true);
     int serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_config* cfg, pm_serve_result* res,
               pm_serve_stats* stats);
     void free_launchset(LaunchSet* ls);
@@ -297,11 +302,15 @@ struct Ctx_ {
     void load_tune_file();
     int graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const uint8_t* labels, uint32_t* gid);
     int graph_unload(uint32_t gid);
-    const PlanInfo& plan_for(GraphRes& G, const Pat& p, int* rc);
+    // tri_ok: the launch may use the graph's per-edge triangle counts (not in
+    // serving slots, which share the graph); the closed forms over them are
+    // chosen only when the options and the graph allow it too (tri_forms)
+    const PlanInfo& plan_for(GraphRes& G, const Pat& p, int* rc, bool tri_ok = true);
+    bool tri_forms(const GraphRes& G) const;
     // alternative patterns plus every sub-pattern their quotient plans need,
     // aggregation plans last (they run in a launch of their own)
     int plan_closure(GraphRes& G, const std::vector<Pat>& alt, std::vector<Pat>* closure,
-                     std::vector<PlanInfo>* plans);
+                     std::vector<PlanInfo>* plans, bool tri_ok = true);
     uint64_t footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c,
                        uint64_t* stride, bool* any_agg, bool heavy_ok = true) const;
     std::vector<uint32_t> heavy_roots(const GraphRes& G, const std::vector<PlanInfo>& plans,

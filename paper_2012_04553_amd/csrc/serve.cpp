@@ -226,10 +226,10 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             if (res[r].status) continue;
             std::string err;
             GraphRes& G = *gr[r];
-            int prc = morph_plan_count(pats[r], reqs[r].morph, &rmp[r], &err, cost_fn(G));
+            int prc = morph_plan_count(pats[r], reqs[r].morph, &rmp[r], &err, cost_fn(G, false));
             std::vector<Pat> cl;
             std::vector<PlanInfo> pl;
-            if (!prc) prc = plan_closure(G, rmp[r].alt, &cl, &pl);
+            if (!prc) prc = plan_closure(G, rmp[r].alt, &cl, &pl, false);
             if (prc == PM_E_NOMEM || prc == PM_E_DEVICE) {
                 rc = prc;
                 break;
@@ -355,7 +355,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                 for (const Pat& a : rmp[r].alt)
                     if (std::find(alts.begin(), alts.end(), a) == alts.end()) alts.push_back(a);
             }
-            int prc = plan_closure(G, alts, &B->closure, &B->plans);
+            int prc = plan_closure(G, alts, &B->closure, &B->plans, false);
             if (prc) {
                 rc = prc;
                 break;
