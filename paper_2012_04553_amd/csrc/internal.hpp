@@ -314,8 +314,14 @@ inline bool is_cycle5(const Pat& p) {
 //    at the apex that avoid the path vertex times the path vertex's other
 //    neighbours, (T(u) - t)(d(w) - 1) + (T(w) - t)(d(u) - 1), less the
 //    choices whose path end lies on the triangle, 2 t (t - 1) over the edges.
+//  TAGG_HOUSE   a 4-cycle with a triangle on one of its edges (a 5-cycle
+//    with one chord): per edge e, its triangles times the 4-cycles through
+//    it, less the choices whose apex lies on the 4-cycle, which is the sum
+//    over all 4-cycles of their edges' triangle counts (house_kernel) less
+//    2 t (t - 1) over the edges.
 constexpr int32_t TAGG_BOWTIE = 1;
 constexpr int32_t TAGG_TRIPATH = 2;
+constexpr int32_t TAGG_HOUSE = 3;
 inline int tagg_kind(const Pat& p) {
     if (p.k != 5 || p.vi || !is_connected(5, p.em)) return 0;
     int deg[5] = {0, 0, 0, 0, 0};
@@ -338,6 +344,14 @@ inline int tagg_kind(const Pat& p) {
     // degree 3 carries the path (without a triangle it is a 4-cycle with a
     // pendant vertex)
     if (popc(p.em) == 5 && hist[3] == 1 && hist[2] == 3 && hist[1] == 1 && tri) return TAGG_TRIPATH;
+    // six edges with degrees 3, 3, 2, 2, 2 and the two corners of degree 3
+    // adjacent (apart, they are K_{2,3})
+    if (popc(p.em) == 6 && hist[3] == 2 && hist[2] == 3) {
+        int u = -1, w = -1;
+        for (int v = 0; v < 5; ++v)
+            if (deg[v] == 3) (u < 0 ? u : w) = v;
+        if (has_edge(p.em, u, w)) return TAGG_HOUSE;
+    }
     return 0;
 }
 // all candidate plans (for tests / autotuning)

@@ -1233,6 +1233,117 @@ __global__ void __launch_bounds__(256) cycle5_kernel(KArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- house: 4-cycle support sums
+
+// The sum over all 4-cycles of the triangle counts of their four edges.
+// Every 4-cycle is met once, at its highest vertex x (degree-order ids),
+// through the pair (x, y) with y its opposite vertex: the cycle's other two
+// vertices are two of the c(x, y) common neighbours a < x (the bridges), so
+// the pair contributes (c - 1) times the sum over its bridges of
+// t(x, a) + t(a, y).  A wave takes one root x (or one slice of its target
+// ids: a hub's work item cuts N(x) at its own neighbours' ids) and streams
+// the bridges' lists below x twice, flattened over the lanes: first every
+// target's c into the wave's dense counter array, then every wedge
+// x - a - y adds (c(x, y) - 1)(t(x, a) + t(a, y)).  The supports are read
+// at both ends of an edge: vtri_kernel mirrors each edge's count into the
+// position of its lower end's entry in the higher end's list.
+template <bool BYTES>
+__global__ void __launch_bounds__(256) house_kernel(KArgs a) {
+    __shared__ uint32_t s_touch[4];
+    const int lane = wave_lane();
+    const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    uint32_t* my_touch = &s_touch[threadIdx.x >> 6];
+    uint32_t* cnt = a.aggcnt + (uint64_t)wid * a.g.n;
+    uint32_t* touched = a.aggtouch + (uint64_t)wid * a.g.n;
+    const KGraph& g = a.g;
+    const uint32_t* sup = a.support;
+    u128 acc = 0;
+    uint64_t bytes = 0;
+    int cur = -1;
+    uint32_t tick = 0;
+    bool stopped = false;
+    const uint64_t total = (uint64_t)a.nplans * a.nitems;
+    for (;;) {
+        if (stopped) break;
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(a.head, 1u);
+        it = bcast(it);
+        if (it >= total) break;
+        if (a.cancel) {
+            uint32_t stop = 0;
+            if (lane == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
+            if (bcast(stop)) break;
+        }
+        const int pi = (int)(it / a.nitems);
+        const KItem item = a.items[it % a.nitems];
+        if (pi != cur) {
+            if (cur >= 0) flush(a, cur, acc);
+            acc = 0;
+            cur = pi;
+        }
+        for (uint32_t x = item.r0; x < item.r1; ++x) {
+            if (should_stop(a, tick)) {
+                stopped = true;
+                break;
+            }
+            const uint32_t xs = g.rp[x], xb = g.split[x], dx = g.rp[x + 1] - xs;
+            if (xb - xs < 2) continue;
+            // targets [lo, hi): the whole range below x, or the ids between
+            // the neighbours at the slice's two ends
+            const uint32_t lo = item.s0 == 0 ? 0u : g.col[xs + item.s0];
+            const uint32_t hi = item.s1 >= dx ? x : min(g.col[xs + item.s1], x);
+            if (lo >= hi) continue;
+            if (BYTES && lane == 0) bytes += 8 + 4ull * (xb - xs);
+            if (lane == 0) *my_touch = 0;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+            for (int pass = 0; pass < 2; ++pass) {
+                for (uint32_t base = xs; base < xb; base += 64) {
+                    const uint32_t k = base + lane;
+                    uint32_t yb = 0, yf = 0, txa = 0;
+                    if (k < xb) {
+                        list_range(g, g.col[k], lo, hi, yb, yf);
+                        if (pass) txa = sup[k];
+                        if (BYTES) bytes += (pass ? 12 : 8) + (pass ? 8ull : 4ull) * (yf - yb);
+                    }
+                    const uint32_t len = yf - yb;
+                    const uint32_t incl = wave_incl_scan(len);
+                    const uint32_t tot = __shfl(incl, 63);
+                    const uint32_t excl = incl - len;
+                    for (uint32_t tb = 0; tb < tot; tb += 64) {
+                        const uint32_t t = tb + lane;
+                        const bool act = t < tot;
+                        const int o = owner_of(incl, act ? t : tot - 1);
+                        const uint32_t src = __shfl(yb, o) + (t - __shfl(excl, o));
+                        const uint32_t ot = __shfl(txa, o);
+                        if (!act) continue;
+                        const uint32_t y = g.col[src];
+                        if (pass == 0) {
+                            if (wave_add(&cnt[y]) == 0u) touched[atomicAdd(my_touch, 1u)] = y;
+                        } else {
+                            const uint32_t c = wave_peek(&cnt[y]);
+                            if (c > 1) acc += (u128)((uint64_t)(c - 1) * ((uint64_t)ot + sup[src]));
+                        }
+                    }
+                }
+                __threadfence_block();
+                __builtin_amdgcn_wave_barrier();
+            }
+            // every counter back to zero
+            const uint32_t nt = bcast(*(volatile uint32_t*)my_touch);
+            for (uint32_t i = lane; i < nt; i += 64) wave_take(&cnt[touched[i]]);
+            __threadfence_block();
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (cur >= 0) flush(a, cur, acc);
+    if (BYTES) {
+        unsigned long long bsum = bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
 // ---------------------------------------------------------------- heavy two-hop roots
 
 // Roots of a plan whose first level is the aggregation level and whose
@@ -2069,7 +2180,8 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
 
 // Per-vertex support sums: every edge {u < w} adds its support t to both
 // ends (a register sum for u, one global atomic for w), so vtri[v] ends at
-// twice the triangles through v.
+// twice the triangles through v.  With a.mirror each count is also written
+// at u's entry in N(w), so that both ends' lists hold it.
 template <bool BYTES>
 __global__ void __launch_bounds__(256) vtri_kernel(KArgs a) {
     uint64_t bytes = 0;
@@ -2081,9 +2193,16 @@ __global__ void __launch_bounds__(256) vtri_kernel(KArgs a) {
         for (uint32_t p = pb; p < pe; ++p) {
             const uint32_t t = a.support[p];
             if (t) {
-                atomicAdd((unsigned long long*)&a.vtri[a.g.col[p]], (unsigned long long)t);
+                const uint32_t w = a.g.col[p];
+                atomicAdd((unsigned long long*)&a.vtri[w], (unsigned long long)t);
                 su += t;
                 if (BYTES) bytes += 8;
+                if (a.mirror) {
+                    // u's entry in the lower part of N(w)
+                    const uint32_t q = lower_bound_u32(a.g.col, a.g.rp[w], a.g.split[w], u);
+                    a.support[q] = t;
+                    if (BYTES) bytes += 12;
+                }
             }
         }
         if (su) atomicAdd((unsigned long long*)&a.vtri[u], (unsigned long long)su);
@@ -2108,6 +2227,7 @@ __device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw
                                           uint32_t t) {
     const u128 pairs = (u128)t * (u128)(t ? t - 1 : 0);   // t (t - 1)
     if (kind == TAGG_BOWTIE) return (u128)0 - pairs;
+    if (kind == TAGG_HOUSE) return (u128)0 - 2 * pairs;
     // TAGG_TRIPATH: apex u with path vertex w, then apex w with path vertex u
     const u128 fwd = (u128)(Tu - t) * (u128)(dw - 1) + (u128)(Tw - t) * (u128)(du - 1);
     return fwd - 2 * pairs;
@@ -2138,6 +2258,9 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
         const uint32_t pb = a.g.split[u], pe = a.g.rp[u + 1];
         const uint32_t du = pe - a.g.rp[u];
         if (BYTES) c.bytes += 12 + 8ull * (pe - pb);
+        if (a.mirror && a.sup_clear)
+            for (uint32_t p = a.g.rp[u]; p < pb; ++p)
+                if (a.support[p]) a.support[p] = 0;
         const uint64_t Tu = a.vtri ? a.vtri[u] >> 1 : 0;
         if (a.vtri) {
             if (BYTES) c.bytes += 8;
@@ -2475,6 +2598,12 @@ int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
         if (count_bytes) hipLaunchKernelGGL((clique_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((clique_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_house(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes) hipLaunchKernelGGL(house_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(house_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -51,6 +51,9 @@ struct KArgs {
     uint32_t sup_clear;       // 1: support_kernel returns the supports to zero
     uint64_t* vtri;           // per vertex: the supports of its edges summed
                               // (twice its triangles), zeroed; or null
+    uint32_t mirror;          // 1: vtri_kernel also writes every support at
+                              //    the lower end's entry in the higher end's
+                              //    list (support_kernel with sup_clear clears it)
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
@@ -77,6 +80,10 @@ int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Per-vertex sums of the supports (a.vtri, zeroed beforehand): one thread
 // per vertex over its out-list, one atomic per edge for the far end.
 int launch_vtri(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// The house's 4-cycle support sums (TAGG_HOUSE plans) over the root items,
+// one wavefront per item with its dense counter array (aggcnt/aggtouch),
+// over supports mirrored by launch_vtri.
+int launch_house(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
 // wavefront (mode 0: up to C4_LIGHT_MAX out-neighbours) or one workgroup
 // (mode 1: up to C4_HEAVY_MAX, mode 2: up to C4_ROOT_MAX) per root of the

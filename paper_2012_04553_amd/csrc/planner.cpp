@@ -722,6 +722,7 @@ std::string PlanInfo::describe() const {
     if (cyc5) s += " | cycle5 pair sum minus the companion triangle plan";
     if (d.tagg == TAGG_BOWTIE) s += " | triangle counts: bowtie";
     if (d.tagg == TAGG_TRIPATH) s += " | triangle counts: triangle with a two-edge path";
+    if (d.tagg == TAGG_HOUSE) s += " | triangle counts: house (4-cycle support sums)";
     if (d.lane_par) s += " lane_par";
     if (d.local) s += " local_bitmap";
     if (d.bm0) s += " root_bitmap";
@@ -862,7 +863,9 @@ static void cycle5_plans(const GraphStats& gs, PlanInfo* pc, PlanInfo* aux) {
 
 // Patterns with a closed form over triangle counts (tagg_kind): no levels
 // or terms; the cost is the triangle pass that fills the per-edge counts
-// (about the out-wedges, s_pp) and a few passes over the edges.
+// (about the out-wedges, s_pp) and a few passes over the edges, and for the
+// house two streams of every bridge's list below its higher end (about
+// sum_a d(a) d+(a), s_pd).
 static void tagg_plan(const Pat& p, int kind, const GraphStats& gs, PlanInfo* out) {
     DPlan d;
     memset(&d, 0, sizeof(d));
@@ -877,7 +880,7 @@ static void tagg_plan(const Pat& p, int kind, const GraphStats& gs, PlanInfo* ou
     out->divisor = 1;
     out->formulation = 0;
     for (int j = 0; j < KMAX; ++j) out->order[j] = j < 1 ? 0 : -1;
-    out->est_cost = gs.s_pp + 4 * gs.m + gs.n;
+    out->est_cost = gs.s_pp + 4 * gs.m + gs.n + (kind == TAGG_HOUSE ? 2 * gs.s_pd : 0.0);
     out->total_cost = out->est_cost;
     out->subs.clear();
 }

@@ -706,7 +706,7 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
             bool out_list = (L.adj & L.gt) != 0;
             stride = std::max<uint64_t>(stride, (out_list ? G.max_out : G.max_deg) + 64);
         }
-        if (p.d.agg_last || p.d.cyc5) agg = true;
+        if (p.d.agg_last || p.d.cyc5 || p.d.tagg == TAGG_HOUSE) agg = true;
         if (p.d.local) {
             // bitmap rows: max_out rows of ceil(max_out/64) 64-bit words
             uint64_t words = (uint64_t)G.max_out * ((G.max_out + 63) / 64);
@@ -978,6 +978,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->support = sup ? (uint32_t*)dptr(G.off_support) : nullptr;
     ls->sup_run = -1;
     ls->sup_last = -1;
+    ls->mirror = false;
     if (cqs) {
         ls->cq_items = G.d_cq;
         ls->cq_nitems = (uint32_t)G.clique_items.size();
@@ -1120,11 +1121,18 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                 ls->run_agg.push_back(5);
             }
             if (tg && !vtri_added) {
-                // per-vertex triangle counts from the supports, once
+                // per-vertex triangle counts from the supports (mirrored for
+                // the house), once
                 vtri_added = true;
                 ls->runs.push_back({i, i});
                 ls->run_agg.push_back(13);
             }
+            for (int k = i; k < j; ++k)
+                if (plans[k].d.tagg == TAGG_HOUSE) {
+                    ls->mirror = true;
+                    ls->runs.push_back({k, k + 1});
+                    ls->run_agg.push_back(14);
+                }
             for (int k = i; k < j; k += CQ_PLANS) {
                 if (sup) ls->sup_last = (int)ls->runs.size();
                 ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
@@ -1183,6 +1191,7 @@ const char* run_kernel_name(int kind) {
         case 10: return "support_kernel";
         case 12: return "cycle5_kernel";
         case 13: return "vtri_kernel";
+        case 14: return "house_kernel";
         default: return "match_kernel";
     }
 }
@@ -1195,7 +1204,7 @@ const char* run_kernel_name(int kind) {
 // 4-cliques; 0 = the rest (general kernel and window kernels, which share
 // the per-wavefront level buffers and window scratch).
 static int run_branch(int kind) {
-    if (kind == 5 || kind == 10 || kind == 13) return 1;
+    if (kind == 5 || kind == 10 || kind == 13 || kind == 14) return 1;
     if (kind == 7 || kind == 8 || kind == 11) return 2;
     return 0;
 }
@@ -1205,6 +1214,9 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
     if (ls.runs.size() > MAX_RUNS) return fail(PM_E_DEVICE, "internal: too many launches in one set");
     if (launch_zero(ls.zero_base, ls.zero_words, s0)) return fail(PM_E_DEVICE, "zero-fill launch failed");
     if (run_ev) HIPCHK(hipEventRecord(run_ev[0], s0));
+    // house_kernel shares the per-wave dense counters with the two-hop and
+    // 5-cycle launches of the main branch: no fork then
+    fork = fork && !ls.mirror;
     bool used[3] = {true, false, false};
     if (fork) {
         for (int k = 0; k < 2; ++k) {
@@ -1258,13 +1270,20 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
         } else if (ls.run_agg[r] == 10) {
             b.support = ls.support;
             b.vtri = ls.vtri;
+            b.mirror = ls.mirror ? 1u : 0u;
             b.sup_clear = (int)r == ls.sup_last ? 1u : 0u;
             if (launch_support(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 13) {
             b.support = ls.support;
             b.vtri = ls.vtri;
+            b.mirror = ls.mirror ? 1u : 0u;
             if (launch_vtri(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 14) {
+            b.support = ls.support;
+            gb = (int)std::max<uint64_t>(1, ls.agg_w / (block / 64));
+            if (b.nitems && launch_house(b, gb, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 6) {
             b.items = ls.cq_big;

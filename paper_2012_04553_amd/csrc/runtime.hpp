@@ -105,7 +105,8 @@ struct LaunchSet {
                                              // 9 their larger roots, 10 edge-support plans,
                                              // 11 4-cliques (clique4_kernel, largest roots),
                                              // 12 5-cycles (cycle5_kernel), 13 per-vertex
-                                             // triangle counts (vtri_kernel)
+                                             // triangle counts (vtri_kernel), 14 the
+                                             // house's 4-cycle sums (house_kernel)
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
     const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
@@ -125,6 +126,7 @@ struct LaunchSet {
     int sup_run = -1;                        // the triangle run that fills them
     int sup_last = -1;                       // the last run that reads them (and clears them)
     uint64_t* vtri = nullptr;                // per vertex: twice its triangle count (closed forms)
+    bool mirror = false;                     // supports mirrored to both list ends (house plans)
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel

@@ -125,14 +125,16 @@ def test_edge_supports_beyond_packed_ids(eng):
         eng.graph_unload(gid)
 
 
-_BOWTIE, _TRIPATH = 0x0EB, 0x075
+_BOWTIE, _TRIPATH, _HOUSE = 0x0EB, 0x075, 0x0ED
 
 
 @pytest.mark.parametrize("gname", ["rmat8", "er", "k12_rmat6"])
 def test_triangle_count_closed_forms(eng, gname):
-    """The bowtie (two triangles sharing a vertex) and the triangle with a
-    two-edge path hanging off a corner are counted in closed form from the
-    per-edge and per-vertex triangle counts; against the oracle census, in a
+    """The bowtie (two triangles sharing a vertex), the triangle with a
+    two-edge path hanging off a corner and the house (a 4-cycle with a
+    triangle on one edge) are counted in closed form from the per-edge and
+    per-vertex triangle counts and the 4-cycles' sums of them; against the
+    oracle census, in a
     single-pattern set, in the 21-pattern edge-induced set (several
     edge-support launches in one replay) and in the morphed vertex-induced
     5-motif set, and the same with the triangle kernels off (enumerating
@@ -149,8 +151,9 @@ def test_triangle_count_closed_forms(eng, gname):
         eng.set_option("clique_kernel", 1)
         assert "triangle counts: bowtie" in eng.plan_describe(gid, (5, _BOWTIE, False))
         assert "triangle counts: triangle with a two-edge path" in eng.plan_describe(gid, (5, _TRIPATH, False))
+        assert "triangle counts: house" in eng.plan_describe(gid, (5, _HOUSE, False))
         for on in (True, False):
-            for m in (_BOWTIE, _TRIPATH):
+            for m in (_BOWTIE, _TRIPATH, _HOUSE):
                 assert _count(eng, gid, [(5, m, False)], pm.MORPH_NONE, on) == [ei[m]]
             assert _count(eng, gid, [(5, m, False) for m in classes], pm.MORPH_NONE, on) == \
                 [ei[m] for m in classes]
@@ -159,8 +162,15 @@ def test_triangle_count_closed_forms(eng, gname):
         eng.set_option("clique_kernel", 1)
         # a second replay of the same cached launch set starts from cleared
         # supports and per-vertex counts
-        assert eng.count(gid, [(5, _BOWTIE, False), (5, _TRIPATH, False)], morph=pm.MORPH_NONE) == \
-            [ei[_BOWTIE], ei[_TRIPATH]]
+        three = [(5, _BOWTIE, False), (5, _TRIPATH, False), (5, _HOUSE, False)]
+        want = [ei[_BOWTIE], ei[_TRIPATH], ei[_HOUSE]]
+        assert eng.count(gid, three, morph=pm.MORPH_NONE) == want
+        # forked launch sets are not forked with the house's dense counters
+        eng.set_option("fork_launches", 1)
+        try:
+            assert eng.count(gid, three + [(4, 0x3F, False)], morph=pm.MORPH_NONE)[:3] == want
+        finally:
+            eng.set_option("fork_launches", 0)
     finally:
         eng.graph_unload(gid)
 
@@ -171,7 +181,7 @@ def test_triangle_count_closed_forms_match_enumeration(eng):
     out-neighbours than the triangle kernel takes (not every triangle would
     be counted per edge), no closed form is chosen."""
     import paper_2012_04553_amd as pm
-    pats = [(5, _BOWTIE, False), (5, _TRIPATH, False)]
+    pats = [(5, _BOWTIE, False), (5, _TRIPATH, False), (5, _HOUSE, False)]
     g = gen.rmat(13, 16, seed=34)
     gid = eng.load(g)
     try:
