@@ -125,9 +125,9 @@ constexpr uint32_t EW_TERMS = 4;
 constexpr uint32_t HUB_BM_DEG = 64;
 
 // Plan choice: an enumerated core level beyond three ranks this many times
-// dearer than its estimate.
+// dearer than its estimate (cliques on the root's local bitmap excepted).
 #ifndef PM_DEEP_PENALTY
-#define PM_DEEP_PENALTY 4.0
+#define PM_DEEP_PENALTY 16.0
 #endif
 constexpr double DEEP_PENALTY = PM_DEEP_PENALTY;
 constexpr uint64_t HUB_BM_BYTES = 512ull << 20;

@@ -929,10 +929,15 @@ int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string*
     // constraints were independent, which undercounts the partial matches of
     // deep dense cores on clustered graphs: on R-MAT 15 it preferred a plan
     // enumerating all five levels of the K4-with-ear (0xff) over one
-    // enumerating three, and took 30 s instead of a fraction of one.  Each
+    // enumerating three, and took 30 s instead of a fraction of one; on
+    // R-MAT 18 four-level plans of the wheel (0x1fb) and of K_{2,3} plus an
+    // edge (0xfe), estimated below the three-level ones by a factor of up to
+    // four, took 94 s and more than 180 s against a few seconds.  Each
     // enumerated core level beyond three therefore ranks DEEP_PENALTY times
-    // dearer when choosing (est_cost itself stays as estimated).
+    // dearer when choosing (est_cost itself stays as estimated); cliques
+    // counted on the root's local bitmap are exempt.
     auto ranked = [](const PlanInfo& pi) {
+        if (pi.d.local) return pi.total_cost;   // deep levels on the root's local bitmap
         return pi.total_cost * std::pow(DEEP_PENALTY, (double)std::max(0, pi.d.ncore - 3));
     };
     size_t best = 0;
