@@ -319,24 +319,32 @@ inline bool is_cycle5(const Pat& p) {
 //    it, less the choices whose apex lies on the 4-cycle, which is the sum
 //    over all 4-cycles of their edges' triangle counts (house_kernel) less
 //    2 t (t - 1) over the edges.
+//  TAGG_TAILED  (four vertices) a triangle with a pendant edge: the
+//    triangles at v times its other neighbours, sum_v T(v)(d(v) - 2), which
+//    is half the sum over the edges of t (d(u) + d(w) - 4).
 constexpr int32_t TAGG_BOWTIE = 1;
 constexpr int32_t TAGG_TRIPATH = 2;
 constexpr int32_t TAGG_HOUSE = 3;
+constexpr int32_t TAGG_TAILED = 4;
+// closed forms that read the per-vertex triangle counts
+inline bool tagg_vtri(int32_t kind) { return kind == TAGG_BOWTIE || kind == TAGG_TRIPATH; }
 inline int tagg_kind(const Pat& p) {
-    if (p.k != 5 || p.vi || !is_connected(5, p.em)) return 0;
+    if ((p.k != 5 && p.k != 4) || p.vi || !is_connected(p.k, p.em)) return 0;
     int deg[5] = {0, 0, 0, 0, 0};
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < p.k; ++v) {
         if (p.lab[v] != -1) return 0;
-        for (int w = 0; w < 5; ++w)
+        for (int w = 0; w < p.k; ++w)
             if (w != v && has_edge(p.em, v, w)) ++deg[v];
     }
     int hist[5] = {0, 0, 0, 0, 0};
-    for (int v = 0; v < 5; ++v) ++hist[deg[v]];
+    for (int v = 0; v < p.k; ++v) ++hist[deg[v]];
     bool tri = false;
-    for (int a = 0; a < 5; ++a)
-        for (int b = a + 1; b < 5; ++b)
-            for (int c = b + 1; c < 5; ++c)
+    for (int a = 0; a < p.k; ++a)
+        for (int b = a + 1; b < p.k; ++b)
+            for (int c = b + 1; c < p.k; ++c)
                 tri = tri || (has_edge(p.em, a, b) && has_edge(p.em, a, c) && has_edge(p.em, b, c));
+    // four edges with a triangle: the fourth hangs off one corner
+    if (p.k == 4) return popc(p.em) == 4 && tri ? TAGG_TAILED : 0;
     // six edges, one vertex of degree 4 and four of degree 2: the leaves pair
     // up into two triangles with the centre
     if (popc(p.em) == 6 && hist[4] == 1 && hist[2] == 4) return TAGG_BOWTIE;

@@ -2228,6 +2228,8 @@ __device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw
     const u128 pairs = (u128)t * (u128)(t ? t - 1 : 0);   // t (t - 1)
     if (kind == TAGG_BOWTIE) return (u128)0 - pairs;
     if (kind == TAGG_HOUSE) return (u128)0 - 2 * pairs;
+    // an edge on a triangle has both ends of degree 2 or more
+    if (kind == TAGG_TAILED) return t ? (u128)t * (u128)(du + dw - 4) : (u128)0;
     // TAGG_TRIPATH: apex u with path vertex w, then apex w with path vertex u
     const u128 fwd = (u128)(Tu - t) * (u128)(dw - 1) + (u128)(Tw - t) * (u128)(du - 1);
     return fwd - 2 * pairs;

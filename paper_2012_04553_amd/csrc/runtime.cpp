@@ -917,8 +917,11 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const std::vector<KItem> cq_big = cq ? clique_big_items(G, cfg) : std::vector<KItem>();
     const bool c4 = use_clique4(G, plans) && (agg == nullptr || G.c4_big.empty());
     const bool sup = agg == nullptr && use_support(G, plans);
-    bool any_tagg = false;
-    for (const PlanInfo& p : plans) any_tagg = any_tagg || p.d.tagg != 0;
+    bool any_tagg = false, any_vtri = false;
+    for (const PlanInfo& p : plans) {
+        any_tagg = any_tagg || p.d.tagg != 0;
+        any_vtri = any_vtri || tagg_vtri(p.d.tagg) || p.d.tagg == TAGG_HOUSE;
+    }
     if (any_tagg && !sup) return fail(PM_E_DEVICE, "internal: a triangle-count plan without triangle counts");
     if (sup) {
         int rc2 = ensure_support(G);
@@ -941,7 +944,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const uint64_t bm_words = bitmap_words(G, plans);
     const uint64_t zhead = (16 * np + 512 + 255) & ~uint64_t(255);
     const uint64_t zbm = (waves(cfg) * bm_words * 4 + 255) & ~uint64_t(255);
-    const uint64_t zvt = any_tagg ? ((8ull * G.n + 255) & ~uint64_t(255)) : 0;
+    const uint64_t zvt = any_vtri ? ((8ull * G.n + 255) & ~uint64_t(255)) : 0;
     const uint64_t zbytes = zhead + zbm + zvt;
     char* zb = carve(zbytes);
     ls->heavy_items = nullptr;
@@ -1011,7 +1014,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->heads = (uint32_t*)(zb + 16 * np);
     ls->bytes = (uint64_t*)(zb + 16 * np + 256);
     uint32_t* rootbm = bm_words ? (uint32_t*)(zb + zhead) : nullptr;
-    ls->vtri = any_tagg ? (uint64_t*)(zb + zhead + zbm) : nullptr;
+    ls->vtri = any_vtri ? (uint64_t*)(zb + zhead + zbm) : nullptr;
     ls->scratch = (uint32_t*)carve(waves(cfg) * (uint64_t)KMAX * ls->stride * 4);
     std::vector<DPlan> hp(np);
     for (size_t i = 0; i < np; ++i) hp[i] = plans[i].d;
@@ -1112,7 +1115,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
             bool need = false, tg = false;
             for (int k = i; k < j; ++k) {
                 need = need || !edge_cheap_ok(plans[k].d);
-                tg = tg || plans[k].d.tagg != 0;
+                tg = tg || tagg_vtri(plans[k].d.tagg) || plans[k].d.tagg == TAGG_HOUSE;
             }
             if (need && ls->sup_run < 0) {
                 // no triangle-core plan: a pass that only fills the supports

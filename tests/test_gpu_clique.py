@@ -53,7 +53,7 @@ def test_clique_kernel_rmat(eng, scale, seed):
     gid = eng.load(g)
     try:
         names = oracle.named_4()
-        assert "triangle_core" in eng.plan_describe(gid, (4, names["tailed_triangle"], False))
+        assert "triangle counts: tailed triangle" in eng.plan_describe(gid, (4, names["tailed_triangle"], False))
         assert "triangle_core" in eng.plan_describe(gid, (3, 0x7, False))
         assert "edge_support" in eng.plan_describe(gid, (4, names["diamond"], False))
         for on in (True, False):
@@ -62,6 +62,15 @@ def test_clique_kernel_rmat(eng, scale, seed):
                 [want_e[m] for m in classes]
             assert _count(eng, gid, [(4, m, True) for m in classes], pm.MORPH_NAIVE, on) == \
                 [want_v[m] for m in classes]
+        # without edge supports the tailed triangle runs as a triangle-core
+        # plan with its tail evaluated per triangle
+        eng.set_option("edge_support", 0)
+        try:
+            assert "triangle_core" in eng.plan_describe(gid, (4, names["tailed_triangle"], False))
+            assert _count(eng, gid, [(4, m, False) for m in classes], pm.MORPH_NONE, True) == \
+                [want_e[m] for m in classes]
+        finally:
+            eng.set_option("edge_support", 1)
     finally:
         eng.graph_unload(gid)
 
