@@ -2237,10 +2237,10 @@ __device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw
 
 // Edge-support plans, and edge-core plans with cheap terms only (then
 // without a support array): one thread per vertex u walks its out-list;
-// each edge {u < w} takes its support t (the last such launch of a replay
-// returns the counter to zero), orients itself as the plan's level 1
-// requires, and adds the tail with the set-size term equal to t.  Plans
-// with a triangle-count closed form add their per-vertex and per-edge parts.
+// each edge {u < w} takes its support t, orients itself as the plan's
+// level 1 requires, and adds the tail with the set-size term equal to t.
+// Plans with a triangle-count closed form add their per-vertex and per-edge
+// parts.  The supports stay as they are (every replay clears them first).
 template <bool BYTES>
 __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
     const int np = a.nplans;
@@ -2260,9 +2260,6 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
         const uint32_t pb = a.g.split[u], pe = a.g.rp[u + 1];
         const uint32_t du = pe - a.g.rp[u];
         if (BYTES) c.bytes += 12 + 8ull * (pe - pb);
-        if (a.mirror && a.sup_clear)
-            for (uint32_t p = a.g.rp[u]; p < pb; ++p)
-                if (a.support[p]) a.support[p] = 0;
         const uint64_t Tu = a.vtri ? a.vtri[u] >> 1 : 0;
         if (a.vtri) {
             if (BYTES) c.bytes += 8;
@@ -2280,7 +2277,6 @@ __global__ void __launch_bounds__(256) support_kernel(KArgs a) {
             const uint32_t w = a.g.col[p];
             // an edge on no triangle still adds the tail's terms without t
             const uint32_t t = a.support ? a.support[p] : 0u;
-            if (t && a.sup_clear) a.support[p] = 0;
             const uint32_t dw = a.g.rp[w + 1] - a.g.rp[w];
             if (BYTES) c.bytes += 8;
             const uint64_t Tw = a.vtri ? a.vtri[w] >> 1 : 0;

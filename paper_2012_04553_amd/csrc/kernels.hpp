@@ -48,12 +48,11 @@ struct KArgs {
     uint32_t* support;        // per out-list position: triangles on that edge, or null
     uint32_t wide;            // 1: agg_window_kernel keeps 32-bit counters even
                               //    when every degree fits 16 bits
-    uint32_t sup_clear;       // 1: support_kernel returns the supports to zero
     uint64_t* vtri;           // per vertex: the supports of its edges summed
                               // (twice its triangles), zeroed; or null
     uint32_t mirror;          // 1: vtri_kernel also writes every support at
                               //    the lower end's entry in the higher end's
-                              //    list (support_kernel with sup_clear clears it)
+                              //    list
 };
 
 int launch_match(const KArgs& a, int grid, int block, bool count_bytes, hipStream_t s);
@@ -74,8 +73,7 @@ int launch_edge_window(const KArgs& a, int grid, bool count_bytes, hipStream_t s
 int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Edge-support plans (support_ok) and triangle-count closed forms (tagg)
 // over a support array filled by a launch_clique with a.support set (and,
-// for the closed forms, a.vtri filled by launch_vtri); with a.sup_clear it
-// returns every support counter to zero.
+// for the closed forms, a.vtri filled by launch_vtri).
 int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Per-vertex sums of the supports (a.vtri, zeroed beforehand): one thread
 // per vertex over its out-list, one atomic per edge for the far end.

@@ -668,15 +668,13 @@ bool Ctx_::use_support(const GraphRes& G, const std::vector<PlanInfo>& plans) co
     return false;
 }
 
-// The graph's support counters (one u32 per adjacency entry), allocated
-// and cleared on first use; every launch returns them to zero.
+// The graph's support counters (one u32 per adjacency entry), allocated on
+// first use; every replay clears them before its triangle pass.
 int Ctx_::ensure_support(GraphRes& G) {
     if (G.off_support != UINT64_MAX) return PM_OK;
     const uint64_t words = std::max<uint64_t>(1, 2 * G.m);
     G.off_support = arena.alloc(4 * words);
     if (G.off_support == UINT64_MAX) return fail(PM_E_NOMEM, "arena too small for the edge supports");
-    if (launch_zero((uint32_t*)dptr(G.off_support), words, stream)) return fail(PM_E_DEVICE, "zero-fill failed");
-    HIPCHK(hipStreamSynchronize(stream));
     return PM_OK;
 }
 
@@ -721,6 +719,10 @@ uint64_t Ctx_::footprint(const GraphRes& G, const std::vector<PlanInfo>& plans, 
     b += sizeof(DPlan) * plans.size() + 16 * plans.size() + 512 + 256 * 4;
     b += waves(cfg) * (uint64_t)KMAX * stride * 4;
     b += waves(cfg) * bitmap_words(G, plans) * 4;
+    // per-vertex triangle counts of the closed forms (cleared with the counters)
+    bool vt = false;
+    for (const PlanInfo& p : plans) vt = vt || tagg_vtri(p.d.tagg) || p.d.tagg == TAGG_HOUSE;
+    if (vt) b += (8ull * G.n + 255) & ~uint64_t(255);
     uint32_t pa = 0;
     const size_t hk = heavy_ok ? heavy_roots(G, plans, &pa).size() : 0;
     const size_t ek = heavy_ok ? edge_heavy_roots(G, plans).size() : 0;
@@ -916,14 +918,16 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     const bool cq = use_clique(G, plans) && (agg == nullptr || G.clique_big.empty());
     const std::vector<KItem> cq_big = cq ? clique_big_items(G, cfg) : std::vector<KItem>();
     const bool c4 = use_clique4(G, plans) && (agg == nullptr || G.c4_big.empty());
-    const bool sup = agg == nullptr && use_support(G, plans);
+    // supports: the graph's own array, or a serving slot's (slots run side
+    // by side on one graph)
+    const bool sup = use_support(G, plans) && (agg == nullptr || (agg->support && agg->support_words >= 2 * G.m));
     bool any_tagg = false, any_vtri = false;
     for (const PlanInfo& p : plans) {
         any_tagg = any_tagg || p.d.tagg != 0;
         any_vtri = any_vtri || tagg_vtri(p.d.tagg) || p.d.tagg == TAGG_HOUSE;
     }
     if (any_tagg && !sup) return fail(PM_E_DEVICE, "internal: a triangle-count plan without triangle counts");
-    if (sup) {
+    if (sup && !agg) {
         int rc2 = ensure_support(G);
         if (rc2) return rc2;
     }
@@ -978,9 +982,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     }
     ls->cq_items = ls->cq_big = nullptr;
     ls->cq_nitems = ls->cq_nbig = 0;
-    ls->support = sup ? (uint32_t*)dptr(G.off_support) : nullptr;
+    ls->support = sup ? (agg ? agg->support : (uint32_t*)dptr(G.off_support)) : nullptr;
+    ls->sup_words = sup ? std::max<uint64_t>(1, 2 * G.m) : 0;
     ls->sup_run = -1;
-    ls->sup_last = -1;
     ls->mirror = false;
     if (cqs) {
         ls->cq_items = G.d_cq;
@@ -1016,6 +1020,8 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     uint32_t* rootbm = bm_words ? (uint32_t*)(zb + zhead) : nullptr;
     ls->vtri = any_vtri ? (uint64_t*)(zb + zhead + zbm) : nullptr;
     ls->scratch = (uint32_t*)carve(waves(cfg) * (uint64_t)KMAX * ls->stride * 4);
+    // footprint() must account for every carve above
+    if (o > need) return fail(PM_E_DEVICE, "internal: launch scratch exceeds its footprint");
     std::vector<DPlan> hp(np);
     for (size_t i = 0; i < np; ++i) hp[i] = plans[i].d;
     if (agg && agg->stage) {
@@ -1137,7 +1143,6 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                     ls->run_agg.push_back(14);
                 }
             for (int k = i; k < j; k += CQ_PLANS) {
-                if (sup) ls->sup_last = (int)ls->runs.size();
                 ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
                 ls->run_agg.push_back(10);
             }
@@ -1216,6 +1221,9 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
     const LaunchCfg& cfg = ls.cfg;
     if (ls.runs.size() > MAX_RUNS) return fail(PM_E_DEVICE, "internal: too many launches in one set");
     if (launch_zero(ls.zero_base, ls.zero_words, s0)) return fail(PM_E_DEVICE, "zero-fill launch failed");
+    // the supports start from zero on every replay, also after a cancelled
+    // one that stopped before reading them
+    if (ls.support && launch_zero(ls.support, ls.sup_words, s0)) return fail(PM_E_DEVICE, "zero-fill launch failed");
     if (run_ev) HIPCHK(hipEventRecord(run_ev[0], s0));
     // house_kernel shares the per-wave dense counters with the two-hop and
     // 5-cycle launches of the main branch: no fork then
@@ -1274,7 +1282,6 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             b.support = ls.support;
             b.vtri = ls.vtri;
             b.mirror = ls.mirror ? 1u : 0u;
-            b.sup_clear = (int)r == ls.sup_last ? 1u : 0u;
             if (launch_support(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 13) {

@@ -124,7 +124,7 @@ struct LaunchSet {
     uint32_t c4_nlight = 0, c4_nheavy = 0, c4_nhuge = 0, c4_nbig = 0;
     uint32_t* support = nullptr;             // edge supports (the graph's), when used
     int sup_run = -1;                        // the triangle run that fills them
-    int sup_last = -1;                       // the last run that reads them (and clears them)
+    uint64_t sup_words = 0;                  // their words (2m), cleared at the head of a replay
     uint64_t* vtri = nullptr;                // per vertex: twice its triangle count (closed forms)
     bool mirror = false;                     // supports mirrored to both list ends (house plans)
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
@@ -291,6 +291,8 @@ struct Ctx_ {
         int* cancel_dev = nullptr;
         void* stage = nullptr;         // pinned staging for the plan upload
         uint64_t stage_bytes = 0;
+        uint32_t* support = nullptr;   // the slot's edge supports (u32 per adjacency entry)
+        uint64_t support_words = 0;
     };
     int make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const LaunchCfg& c, LaunchSet* ls,
                        hipStream_t s = nullptr, const AggArrays* agg = nullptr);

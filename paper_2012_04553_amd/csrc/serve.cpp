@@ -55,6 +55,7 @@ struct Batch {
 struct Slot {
     hipStream_t stream = nullptr;
     uint64_t agg_off = UINT64_MAX, agg_touch_off = UINT64_MAX;
+    uint64_t sup_off = UINT64_MAX;   // edge supports for the triangle-count closed forms
     uint64_t* host = nullptr;     // pinned result words, reused by every batch
     int* cancel_host = nullptr;   // pinned coherent cancel flag
     int* cancel_dev = nullptr;
@@ -113,6 +114,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     HIPCHK(hipSetDevice(device));
     // validate requests and resolve graphs
     uint32_t maxn = 0;
+    uint64_t maxm = 0;
     std::vector<GraphRes*> gr(nreq, nullptr);
     std::vector<std::vector<Pat>> pats(nreq);
     for (uint32_t i = 0; i < nreq; ++i) {
@@ -124,6 +126,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
         if (it == graphs.end()) return fail(PM_E_NOTFOUND, "unknown graph id in request");
         gr[i] = it->second.get();
         maxn = std::max(maxn, gr[i]->n);
+        maxm = std::max<uint64_t>(maxm, gr[i]->m);
         pats[i].resize(q.npat);
         for (uint32_t k = 0; k < q.npat; ++k) {
             std::string err;
@@ -146,6 +149,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     const uint64_t slot_agg_waves = 64;
     std::vector<Slot> slots(cfg->max_slots);
     int rc = PM_OK;
+    bool serve_tri = clique_opt && support_opt;
     for (Slot& s : slots) {
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
             rc = fail(PM_E_DEVICE, "stream creation failed");
@@ -161,6 +165,13 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
         if (launch_zero((uint32_t*)dptr(s.agg_off), need / 4, s.stream)) {
             rc = fail(PM_E_DEVICE, "zero-fill failed");
             break;
+        }
+        // each slot its own edge supports, so that batches on one graph run
+        // side by side (every replay clears the words it uses first); with
+        // no room for them the slots plan without the closed forms
+        if (serve_tri) {
+            s.sup_off = arena.alloc(4 * std::max<uint64_t>(1, 2 * maxm));
+            if (s.sup_off == UINT64_MAX) serve_tri = false;
         }
         if (hipHostMalloc((void**)&s.host, 8 * SLOT_HOST_WORDS, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&s.cancel_host, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
@@ -183,6 +194,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
         for (Slot& s : slots) {
             if (s.agg_off != UINT64_MAX) arena.release(s.agg_off);
             if (s.agg_touch_off != UINT64_MAX) arena.release(s.agg_touch_off);
+            if (s.sup_off != UINT64_MAX) arena.release(s.sup_off);
             if (s.done) hipEventDestroy(s.done);
             if (s.host) hipHostFree(s.host);
             if (s.cancel_host) hipHostFree(s.cancel_host);
@@ -194,6 +206,12 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
         cleanup();
         return rc;
     }
+    if (!serve_tri)
+        for (Slot& s : slots)
+            if (s.sup_off != UINT64_MAX) {
+                arena.release(s.sup_off);
+                s.sup_off = UINT64_MAX;
+            }
 
     std::deque<uint32_t> pending;
     // per request: its morph plan and estimated kernel work (planned once)
@@ -226,10 +244,10 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             if (res[r].status) continue;
             std::string err;
             GraphRes& G = *gr[r];
-            int prc = morph_plan_count(pats[r], reqs[r].morph, &rmp[r], &err, cost_fn(G, false));
+            int prc = morph_plan_count(pats[r], reqs[r].morph, &rmp[r], &err, cost_fn(G, serve_tri));
             std::vector<Pat> cl;
             std::vector<PlanInfo> pl;
-            if (!prc) prc = plan_closure(G, rmp[r].alt, &cl, &pl, false);
+            if (!prc) prc = plan_closure(G, rmp[r].alt, &cl, &pl, serve_tri);
             if (prc == PM_E_NOMEM || prc == PM_E_DEVICE) {
                 rc = prc;
                 break;
@@ -355,7 +373,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                 for (const Pat& a : rmp[r].alt)
                     if (std::find(alts.begin(), alts.end(), a) == alts.end()) alts.push_back(a);
             }
-            int prc = plan_closure(G, alts, &B->closure, &B->plans, false);
+            int prc = plan_closure(G, alts, &B->closure, &B->plans, serve_tri);
             if (prc) {
                 rc = prc;
                 break;
@@ -388,6 +406,10 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             ag.cancel_dev = free_slot->cancel_dev;
             ag.stage = free_slot->stage;
             ag.stage_bytes = SLOT_STAGE_BYTES;
+            if (free_slot->sup_off != UINT64_MAX) {
+                ag.support = (uint32_t*)dptr(free_slot->sup_off);
+                ag.support_words = std::max<uint64_t>(1, 2 * maxm);
+            }
             int mrc = make_launchset(G, B->plans, lc, &B->ls, free_slot->stream, &ag);
             if (mrc == PM_E_NOMEM) {
                 free_launchset(&B->ls);

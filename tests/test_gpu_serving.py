@@ -63,15 +63,22 @@ def test_serving_mix_equals_alone(eng, graphs):
 
 
 def test_serving_five_vertex_and_cost_mode(eng, graphs):
+    """Five-vertex requests side by side (each slot fills its own edge
+    supports for the triangle-count closed forms) equal the same requests
+    counted alone, with the closed forms and without, and in cost mode."""
     import paper_2012_04553_amd as pm
     gs, ids = graphs
     reqs = _trace(ids[:2], 40, 1000.0, seed=8, k_choices=(5,))
     res, st = eng.serve(reqs, max_slots=3, max_batch=2)
     assert st["failed"] == 0
+    for (t, gid, pats, morph), r in zip(reqs, res):
+        assert r["values"] == eng.count(gid, pats, morph=morph)
+    with _enumerating(eng):
+        res1, st1 = eng.serve(reqs, max_slots=3, max_batch=2)
     cost = [(t, gid, pats, pm.MORPH_COST) for (t, gid, pats, m) in reqs]
     res2, st2 = eng.serve(cost, max_slots=3, max_batch=2)
-    for a, b in zip(res, res2):
-        assert a["values"] == b["values"]
+    for a, b, c in zip(res, res1, res2):
+        assert a["values"] == b["values"] == c["values"]
 
 
 def test_serving_admission_by_budget(eng, graphs):
@@ -92,9 +99,23 @@ def test_serving_admission_by_budget(eng, graphs):
 
 
 def _heavy5():
-    """The house (a 5-cycle with one chord), edge-induced: its plan
-    enumerates long enough on R-MAT 12 to be cancelled or timed out."""
+    """The house (a 5-cycle with one chord), edge-induced: with the
+    triangle-count closed forms off (edge_support 0) its plan enumerates long
+    enough on R-MAT 14 to be cancelled, or to time out in a
+    serving slot (a share of the GPU)."""
     return P.canonical(5, 0xED)[0]
+
+
+class _enumerating:
+    """Closed forms over triangle counts off for the duration."""
+    def __init__(self, eng):
+        self.eng = eng
+
+    def __enter__(self):
+        self.eng.set_option("edge_support", 0)
+
+    def __exit__(self, *exc):
+        self.eng.set_option("edge_support", 1)
 
 
 def test_cancel_heavy_query(eng):
@@ -103,23 +124,35 @@ def test_cancel_heavy_query(eng):
     import time
     import paper_2012_04553_amd as pm
     from paper_2012_04553_amd.binding import PMError
-    g = gen.rmat(12, 16, seed=3)
+    g = gen.rmat(14, 16, seed=3)
     gid = eng.load(g)
     try:
-        # the edge-induced house alone runs for seconds here
+        # the edge-induced house alone, enumerated, runs for about a second here
         heavy = [(5, _heavy5(), False)]
         t = time.time()
-        tk = eng.submit(gid, heavy, morph=pm.MORPH_NONE)
-        time.sleep(0.2)
-        eng.cancel(tk)
-        with pytest.raises(PMError) as ei:
-            eng.wait(tk, 1)
+        with _enumerating(eng):
+            tk = eng.submit(gid, heavy, morph=pm.MORPH_NONE)
+            time.sleep(0.2)
+            eng.cancel(tk)
+            with pytest.raises(PMError) as ei:
+                eng.wait(tk, 1)
         assert ei.value.status == -8
         assert time.time() - t < 5.0
         pats = [(4, m, True) for m in P.connected_classes(4)]
         got = eng.count(gid, pats, morph=pm.MORPH_NAIVE)
         want = oracle.vertex_induced_4_from_tier_c(g)
         assert got == [want[m] for m in P.connected_classes(4)]
+        # a morphed 5-motif query that fills edge supports, cancelled at once
+        # (its kernels may stop anywhere): the next query, which reads
+        # supports too, is still exact
+        five = [(5, m, True) for m in P.connected_classes(5)]
+        tk = eng.submit(gid, five, morph=pm.MORPH_NAIVE)
+        eng.cancel(tk)
+        try:
+            eng.wait(tk, 1)
+        except PMError as e:
+            assert e.status == -8
+        assert eng.count(gid, pats, morph=pm.MORPH_NAIVE) == [want[m] for m in P.connected_classes(4)]
     finally:
         eng.graph_unload(gid)
 
@@ -127,14 +160,15 @@ def test_cancel_heavy_query(eng):
 def test_serving_deadline(eng, graphs):
     import paper_2012_04553_amd as pm
     gs, ids = graphs
-    heavy_g = gen.rmat(12, 16, seed=3)
+    heavy_g = gen.rmat(14, 16, seed=3)
     hid = eng.load(heavy_g)
     try:
         heavy = [(5, _heavy5(), False)]
         reqs = [(0.0, hid, heavy, pm.MORPH_NONE)]
         light = _trace(ids[:1], 10, 1000.0, seed=11)
         reqs += [(t + 0.01, gid, pats, m) for (t, gid, pats, m) in light]
-        res, st = eng.serve(reqs, max_slots=4, max_batch=1, deadline_s=0.5)
+        with _enumerating(eng):
+            res, st = eng.serve(reqs, max_slots=4, max_batch=1, deadline_s=0.5)
         assert res[0]["status"] == -7
         # a light batch may wait behind the long one if their streams share a
         # hardware queue; what completes must be exact, and most must complete
@@ -152,7 +186,7 @@ def test_serving_sheds_after_timeout(eng, graphs):
     at admission; cheaper requests still complete, exactly."""
     import paper_2012_04553_amd as pm
     gs, ids = graphs
-    heavy_g = gen.rmat(12, 16, seed=3)
+    heavy_g = gen.rmat(14, 16, seed=3)
     hid = eng.load(heavy_g)
     try:
         heavy = [(5, _heavy5(), False)]
@@ -161,7 +195,8 @@ def test_serving_sheds_after_timeout(eng, graphs):
         reqs += [(t, gid, pats, m) for (t, gid, pats, m) in light]
         reqs.append((light[-1][0] + 1.5, hid, heavy, pm.MORPH_NONE))
         reqs.sort(key=lambda q: q[0])
-        res, st = eng.serve(reqs, max_slots=4, max_batch=4, deadline_s=0.5)
+        with _enumerating(eng):
+            res, st = eng.serve(reqs, max_slots=4, max_batch=4, deadline_s=0.5)
         heavy_idx = [i for i, q in enumerate(reqs) if q[1] == hid]
         assert [res[i]["status"] for i in heavy_idx] == [-7, -7]
         assert st["shed"] >= 1
