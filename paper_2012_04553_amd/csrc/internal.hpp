@@ -322,10 +322,24 @@ inline bool is_cycle5(const Pat& p) {
 //  TAGG_TAILED  (four vertices) a triangle with a pendant edge: the
 //    triangles at v times its other neighbours, sum_v T(v)(d(v) - 2), which
 //    is half the sum over the edges of t (d(u) + d(w) - 4).
+//  TAGG_DTAIL   a diamond with a pendant edge at one of its two tips: over
+//    the triangles, sum_c (d(c) - 2)(t(opposite edge) - 1) for each corner c
+//    (the diamond's tip c with the other triangle on the opposite edge, and
+//    c's other neighbour), less 12 per 4-clique (the other tip is adjacent
+//    to c);
+//  TAGG_FAN     a vertex adjacent to all of a 3-edge path (three triangles in
+//    a fan): over the triangles, the products (t(e) - 1)(t(f) - 1) of each
+//    two of its edges (the triangles on e and f beyond this one), less 12
+//    per 4-clique (both are the same vertex).
+// The last two are summed per triangle by trisup_kernel; the 4-cliques
+// enter as a quotient sub-pattern.
 constexpr int32_t TAGG_BOWTIE = 1;
 constexpr int32_t TAGG_TRIPATH = 2;
 constexpr int32_t TAGG_HOUSE = 3;
 constexpr int32_t TAGG_TAILED = 4;
+constexpr int32_t TAGG_DTAIL = 5;
+constexpr int32_t TAGG_FAN = 6;
+inline bool tagg_tri(int32_t kind) { return kind == TAGG_DTAIL || kind == TAGG_FAN; }
 // closed forms that read the per-vertex triangle counts
 inline bool tagg_vtri(int32_t kind) { return kind == TAGG_BOWTIE || kind == TAGG_TRIPATH; }
 inline int tagg_kind(const Pat& p) {
@@ -360,6 +374,9 @@ inline int tagg_kind(const Pat& p) {
             if (deg[v] == 3) (u < 0 ? u : w) = v;
         if (has_edge(p.em, u, w)) return TAGG_HOUSE;
     }
+    // the only five-vertex graphs with these edge counts and degrees
+    if (popc(p.em) == 6 && hist[3] == 3 && hist[2] == 1 && hist[1] == 1) return TAGG_DTAIL;
+    if (popc(p.em) == 7 && hist[4] == 1 && hist[3] == 2 && hist[2] == 2) return TAGG_FAN;
     return 0;
 }
 // all candidate plans (for tests / autotuning)

@@ -2178,6 +2178,116 @@ __global__ void __launch_bounds__(256) clique_kernel(KArgs a) {
     }
 }
 
+// Closed forms summed over the triangles, with the triangle counts of their
+// three edges (DPlan::tagg TAGG_DTAIL, TAGG_FAN; the kernel total less
+// twelve times the 4-cliques is the count).  Every triangle once, at its
+// lowest vertex v0, as in clique_kernel: N+(v0) goes into the wave's LDS
+// hash table with each key's position in the list beside it, the rows N+(x)
+// of its out-neighbours x are streamed flattened over the lanes, and an
+// entry y found in the table closes the triangle (v0, x, y).  The supports
+// of (v0, x), (v0, y) and (x, y) sit at x's and y's places in N+(v0) and at
+// y's place in N+(x).  Each lane adds its triangles' terms for every plan.
+template <bool BYTES>
+__global__ void __launch_bounds__(256) trisup_kernel(KArgs a) {
+    __shared__ uint32_t s_hash[4][CQ_HASH];
+    __shared__ uint16_t s_pos[4][CQ_HASH];
+    const int lane = wave_lane();
+    const int wv = threadIdx.x >> 6;
+    uint32_t* H = s_hash[wv];
+    uint16_t* Pos = s_pos[wv];
+    for (uint32_t i = lane; i < CQ_HASH; i += 64) H[i] = CQ_EMPTY;
+    wave_sync();
+    const int np = a.nplans;
+    int32_t kind[CQ_PLANS];
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p) kind[p] = p < np ? ((gcp<DPlan>)a.plans + p)->tagg : 0;
+    u128 acc[CQ_PLANS];
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p) acc[p] = 0;
+    uint64_t bytes = 0;
+    const uint32_t* sup = a.support;
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(a.head, 1u);
+        it = bcast(it);
+        if (it >= a.nitems) break;
+        if (a.cancel) {
+            uint32_t stop = 0;
+            if (lane == 0) stop = (uint32_t)__atomic_load_n(a.cancel, __ATOMIC_RELAXED);
+            if (bcast(stop)) break;
+        }
+        const KItem item = a.items[it];
+        for (uint32_t r = item.r0; r < item.r1; ++r) {
+            const uint32_t b = a.g.split[r], e = a.g.rp[r + 1];
+            const uint32_t s = e - b;
+            if (s < 2 || s > CQ_SMAX) continue;
+            const uint32_t i0 = item.s0, i1 = min(item.s1, s);
+            if (i0 >= i1) continue;
+            const uint32_t d0 = e - a.g.rp[r];
+            if (BYTES && lane == 0) bytes += 12 + 4ull * s;
+            for (uint32_t i = lane; i < s; i += 64) {
+                const uint32_t x = a.g.col[b + i];
+                uint32_t h = cq_slot(x);
+                while (atomicCAS(&H[h], CQ_EMPTY, x) != CQ_EMPTY) h = (h + 1) & (CQ_HASH - 1);
+                Pos[h] = (uint16_t)i;
+            }
+            wave_sync();
+            for (uint32_t base = i0; base < i1; base += 64) {
+                const uint32_t i = base + lane;
+                const bool valid = i < i1;
+                uint32_t pb = 0, len = 0, dx = 0, t0x = 0;
+                if (valid) {
+                    const uint32_t x = a.g.col[b + i];
+                    pb = a.g.split[x];
+                    const uint32_t xe = a.g.rp[x + 1];
+                    len = xe - pb;
+                    dx = xe - a.g.rp[x];
+                    t0x = sup[b + i];
+                    if (BYTES) bytes += 20 + 4ull * len;
+                }
+                const uint32_t incl = wave_incl_scan(len);
+                const uint32_t total = __shfl(incl, 63);
+                const uint32_t excl = incl - len;
+                for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+                    const uint32_t t = t0 + lane;
+                    const bool act = t < total;
+                    const int o = owner_of(incl, act ? t : total - 1);
+                    const uint32_t src = __shfl(pb, o) + (t - __shfl(excl, o));
+                    const uint32_t odx = __shfl(dx, o), ot0x = __shfl(t0x, o);
+                    if (!act) continue;
+                    const uint32_t y = a.g.col[src];
+                    const int slot = cq_find<0>(H, y);
+                    if (slot < 0) continue;
+                    // the triangle (r, x, y) with its three edge supports
+                    const uint64_t t0y = sup[b + Pos[slot]], txy = sup[src];
+                    const uint64_t dy = a.g.rp[y + 1] - a.g.rp[y];
+                    if (BYTES) bytes += 16;
+                    const uint64_t u01 = ot0x - 1, u02 = t0y - 1, u12 = txy - 1;
+#pragma unroll
+                    for (int p = 0; p < CQ_PLANS; ++p) {
+                        if (kind[p] == TAGG_DTAIL)
+                            acc[p] += (u128)((uint64_t)(d0 - 2) * u12) + (u128)((uint64_t)(odx - 2) * u02) +
+                                      (u128)((dy - 2) * u01);
+                        else if (kind[p] == TAGG_FAN)
+                            acc[p] += (u128)(u01 * u02) + (u128)(u01 * u12) + (u128)(u02 * u12);
+                    }
+                }
+            }
+            wave_sync();
+            for (uint32_t i = lane; i < s; i += 64) H[cq_slot_of<0>(H, a.g.col[b + i])] = CQ_EMPTY;
+            wave_sync();
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < CQ_PLANS; ++p)
+        if (p < np) flush(a, p, acc[p]);
+    if (BYTES) {
+        unsigned long long bsum = bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
 // Per-vertex support sums: every edge {u < w} adds its support t to both
 // ends (a register sum for u, one global atomic for w), so vtri[v] ends at
 // twice the triangles through v.  With a.mirror each count is also written
@@ -2230,6 +2340,7 @@ __device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw
     if (kind == TAGG_HOUSE) return (u128)0 - 2 * pairs;
     // an edge on a triangle has both ends of degree 2 or more
     if (kind == TAGG_TAILED) return t ? (u128)t * (u128)(du + dw - 4) : (u128)0;
+    if (kind != TAGG_TRIPATH) return 0;   // summed elsewhere (trisup_kernel)
     // TAGG_TRIPATH: apex u with path vertex w, then apex w with path vertex u
     const u128 fwd = (u128)(Tu - t) * (u128)(dw - 1) + (u128)(Tw - t) * (u128)(du - 1);
     return fwd - 2 * pairs;
@@ -2602,6 +2713,12 @@ int launch_clique(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
 int launch_house(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
     if (count_bytes) hipLaunchKernelGGL(house_kernel<true>, dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(house_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_trisup(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes) hipLaunchKernelGGL(trisup_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(trisup_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -82,6 +82,10 @@ int launch_vtri(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // one wavefront per item with its dense counter array (aggcnt/aggtouch),
 // over supports mirrored by launch_vtri.
 int launch_house(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// Per-triangle closed forms (TAGG_DTAIL, TAGG_FAN plans, at most CQ_PLANS
+// a launch) over the triangle items {r0, r1, i0, i1}, reading the supports
+// a launch_clique with a.support filled.
+int launch_trisup(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
 // wavefront (mode 0: up to C4_LIGHT_MAX out-neighbours) or one workgroup
 // (mode 1: up to C4_HEAVY_MAX, mode 2: up to C4_ROOT_MAX) per root of the

@@ -724,6 +724,8 @@ std::string PlanInfo::describe() const {
     if (d.tagg == TAGG_TRIPATH) s += " | triangle counts: triangle with a two-edge path";
     if (d.tagg == TAGG_HOUSE) s += " | triangle counts: house (4-cycle support sums)";
     if (d.tagg == TAGG_TAILED) s += " | triangle counts: tailed triangle";
+    if (d.tagg == TAGG_DTAIL) s += " | triangle counts: diamond with a pendant at a tip (per triangle)";
+    if (d.tagg == TAGG_FAN) s += " | triangle counts: fan of three triangles (per triangle)";
     if (d.lane_par) s += " lane_par";
     if (d.local) s += " local_bitmap";
     if (d.bm0) s += " root_bitmap";
@@ -881,9 +883,21 @@ static void tagg_plan(const Pat& p, int kind, const GraphStats& gs, PlanInfo* ou
     out->divisor = kind == TAGG_TAILED ? 2 : 1;
     out->formulation = 0;
     for (int j = 0; j < KMAX; ++j) out->order[j] = j < 1 ? 0 : -1;
-    out->est_cost = gs.s_pp + 4 * gs.m + gs.n + (kind == TAGG_HOUSE ? 2 * gs.s_pd : 0.0);
+    out->est_cost = gs.s_pp + 4 * gs.m + gs.n + (kind == TAGG_HOUSE ? 2 * gs.s_pd : 0.0) +
+                    (tagg_tri(kind) ? gs.s_pq : 0.0);
     out->total_cost = out->est_cost;
     out->subs.clear();
+    if (tagg_tri(kind)) {
+        // the per-triangle sum counts each 4-clique twelve times too many
+        Pat k4;
+        k4.k = 4;
+        k4.em = full_mask(4);
+        k4.vi = false;
+        out->rewrite = true;
+        out->hmult = 1;
+        out->autp = 1;
+        out->subs.push_back({k4, 12});
+    }
 }
 
 int compile_plan(const Pat& p, const GraphStats& gs, PlanInfo* out, std::string* err, bool tri) {

@@ -1141,6 +1141,9 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                     ls->mirror = true;
                     ls->runs.push_back({k, k + 1});
                     ls->run_agg.push_back(14);
+                } else if (tagg_tri(plans[k].d.tagg)) {
+                    ls->runs.push_back({k, k + 1});
+                    ls->run_agg.push_back(15);
                 }
             for (int k = i; k < j; k += CQ_PLANS) {
                 ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
@@ -1200,6 +1203,7 @@ const char* run_kernel_name(int kind) {
         case 12: return "cycle5_kernel";
         case 13: return "vtri_kernel";
         case 14: return "house_kernel";
+        case 15: return "trisup_kernel";
         default: return "match_kernel";
     }
 }
@@ -1212,7 +1216,7 @@ const char* run_kernel_name(int kind) {
 // 4-cliques; 0 = the rest (general kernel and window kernels, which share
 // the per-wavefront level buffers and window scratch).
 static int run_branch(int kind) {
-    if (kind == 5 || kind == 10 || kind == 13 || kind == 14) return 1;
+    if (kind == 5 || kind == 10 || kind == 13 || kind == 14 || kind == 15) return 1;
     if (kind == 7 || kind == 8 || kind == 11) return 2;
     return 0;
 }
@@ -1289,6 +1293,13 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             b.vtri = ls.vtri;
             b.mirror = ls.mirror ? 1u : 0u;
             if (launch_vtri(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] == 15) {
+            b.items = ls.cq_items;
+            b.nitems = ls.cq_nitems;
+            b.support = ls.support;
+            // 48 KB of LDS a workgroup: three resident a CU
+            if (b.nitems && launch_trisup(b, num_cus * 3, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 14) {
             b.support = ls.support;

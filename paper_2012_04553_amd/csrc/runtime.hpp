@@ -106,7 +106,8 @@ struct LaunchSet {
                                              // 11 4-cliques (clique4_kernel, largest roots),
                                              // 12 5-cycles (cycle5_kernel), 13 per-vertex
                                              // triangle counts (vtri_kernel), 14 the
-                                             // house's 4-cycle sums (house_kernel)
+                                             // house's 4-cycle sums (house_kernel),
+                                             // 15 per-triangle sums (trisup_kernel)
     const KItem* agg_items = nullptr;        // work items of the two-hop launches
     uint32_t agg_nitems = 0;
     const KItem* heavy_items = nullptr;      // heavy two-hop roots, one item each
