@@ -339,11 +339,15 @@ constexpr int32_t TAGG_HOUSE = 3;
 constexpr int32_t TAGG_TAILED = 4;
 constexpr int32_t TAGG_DTAIL = 5;
 constexpr int32_t TAGG_FAN = 6;
+// (three vertices) the triangle: a third of the sum of t over the edges, so
+// that the 4-path's quotient needs no triangle pass of its own and the
+// 4-clique launches can fill the supports
+constexpr int32_t TAGG_TRIANGLE = 7;
 inline bool tagg_tri(int32_t kind) { return kind == TAGG_DTAIL || kind == TAGG_FAN; }
 // closed forms that read the per-vertex triangle counts
 inline bool tagg_vtri(int32_t kind) { return kind == TAGG_BOWTIE || kind == TAGG_TRIPATH; }
 inline int tagg_kind(const Pat& p) {
-    if ((p.k != 5 && p.k != 4) || p.vi || !is_connected(p.k, p.em)) return 0;
+    if (p.k < 3 || p.k > 5 || p.vi || !is_connected(p.k, p.em)) return 0;
     int deg[5] = {0, 0, 0, 0, 0};
     for (int v = 0; v < p.k; ++v) {
         if (p.lab[v] != -1) return 0;
@@ -357,6 +361,7 @@ inline int tagg_kind(const Pat& p) {
         for (int b = a + 1; b < p.k; ++b)
             for (int c = b + 1; c < p.k; ++c)
                 tri = tri || (has_edge(p.em, a, b) && has_edge(p.em, a, c) && has_edge(p.em, b, c));
+    if (p.k == 3) return tri ? TAGG_TRIANGLE : 0;
     // four edges with a triangle: the fourth hangs off one corner
     if (p.k == 4) return popc(p.em) == 4 && tri ? TAGG_TAILED : 0;
     // six edges, one vertex of degree 4 and four of degree 2: the leaves pair

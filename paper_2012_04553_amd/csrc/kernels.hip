@@ -2340,6 +2340,7 @@ __device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw
     if (kind == TAGG_HOUSE) return (u128)0 - 2 * pairs;
     // an edge on a triangle has both ends of degree 2 or more
     if (kind == TAGG_TAILED) return t ? (u128)t * (u128)(du + dw - 4) : (u128)0;
+    if (kind == TAGG_TRIANGLE) return (u128)t;
     if (kind != TAGG_TRIPATH) return 0;   // summed elsewhere (trisup_kernel)
     // TAGG_TRIPATH: apex u with path vertex w, then apex w with path vertex u
     const u128 fwd = (u128)(Tu - t) * (u128)(dw - 1) + (u128)(Tw - t) * (u128)(du - 1);
@@ -2488,12 +2489,16 @@ struct C4Table {
     }
 };
 
-// One root's 4-cliques by `nthr` cooperating threads (thread `tid`): a
-// wavefront (nthr = 64) or the workgroup (nthr = 256; `sync` is then
-// __syncthreads, otherwise a wavefront barrier).  Returns this thread's share.
-template <int LOGH, bool WG, bool BYTES>
-__device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r, uint32_t b, uint32_t s) {
-    constexpr uint32_t NT = WG ? 256 : 64;
+// One root's 4-cliques by NT cooperating threads: a wavefront (NT = 64) or
+// the whole workgroup (`sync` is then __syncthreads, otherwise a wavefront
+// barrier).  Returns this thread's share.  With SUP the row stream also
+// fills the edge supports of every triangle {r < x < y} it meets (the
+// triangles at their lowest vertex, each once): (x, y) by a global atomic
+// at y's place in N+(x); (r, x) and (r, y) once per root from the row's
+// popcount and a per-position LDS counter `pc` (s words).
+template <int LOGH, bool WG, bool BYTES, uint32_t NT, bool SUP>
+__device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r, uint32_t b, uint32_t s,
+                            uint32_t* sup, uint32_t* pc) {
     const uint32_t tid = WG ? threadIdx.x : (uint32_t)wave_lane();
     auto sync = [] {
         if (WG) __syncthreads();
@@ -2503,6 +2508,8 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
     const uint32_t W = (s + 31) >> 5;
     for (uint32_t i = tid; i < (1u << LOGH); i += NT) T.keys[i] = CQ_EMPTY;
     for (uint32_t i = tid; i < s * W; i += NT) T.rows[i] = 0;
+    if (SUP)
+        for (uint32_t i = tid; i < s; i += NT) pc[i] = 0;
     sync();
     for (uint32_t i = tid; i < s; i += NT) T.insert(g.col[b + i], i);
     if (BYTES && tid == 0) c.bytes += 12 + 4ull * s;
@@ -2524,7 +2531,7 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
         const uint32_t total = __shfl(incl, 63);
         const uint32_t excl = incl - len;
         for (uint32_t t0 = 0; t0 < total; t0 += 64 * CQ_UNROLL) {
-            uint32_t y[CQ_UNROLL];
+            uint32_t y[CQ_UNROLL], src[CQ_UNROLL];
             int o[CQ_UNROLL];
             bool act[CQ_UNROLL];
 #pragma unroll
@@ -2532,8 +2539,8 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
                 const uint32_t t = t0 + (uint32_t)(u * 64) + lane;
                 act[u] = t < total;
                 o[u] = owner_of(incl, act[u] ? t : total - 1);
-                const uint32_t src = __shfl(pb, o[u]) + (t - __shfl(excl, o[u]));
-                y[u] = act[u] ? g.col[src] : 0u;
+                src[u] = __shfl(pb, o[u]) + (t - __shfl(excl, o[u]));
+                y[u] = act[u] ? g.col[src[u]] : 0u;
             }
 #pragma unroll
             for (int u = 0; u < CQ_UNROLL; ++u) {
@@ -2541,11 +2548,24 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
                 if (j >= 0) {
                     const uint32_t row = base_i + (uint32_t)o[u];
                     atomicOr(&T.rows[row * W + ((uint32_t)j >> 5)], 1u << (j & 31));
+                    if (SUP) {
+                        atomicAdd(&sup[src[u]], 1u);
+                        atomicAdd(&pc[j], 1u);
+                    }
                 }
             }
         }
     }
     sync();
+    if (SUP) {
+        // (r, x_i): the triangles with x_i in the middle (row i's bits) and
+        // on top (the rows holding bit i)
+        for (uint32_t i = tid; i < s; i += NT) {
+            uint32_t k = pc[i];
+            for (uint32_t w = 0; w < W; ++w) k += (uint32_t)__popc(T.rows[i * W + w]);
+            if (k) atomicAdd(&sup[b + i], k);
+        }
+    }
     // triangles of the row graph: task (i, w) takes the bits of word w of row i
     uint64_t cnt = 0;
     for (uint32_t t = tid; t < s * W; t += NT) {
@@ -2564,13 +2584,35 @@ __device__ uint64_t c4_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t r,
 }
 
 // MODE 0: wavefront roots; 1: workgroup roots up to C4_HEAVY; 2: workgroup
-// roots up to C4_ROOT_MAX.
-template <bool BYTES, int MODE>
-__global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
+// roots up to C4_ROOT_MAX.  The 152 KB table of MODE 2 leaves one workgroup
+// a CU, so that mode runs C4_HUGE_NT threads a workgroup (rows and row pairs
+// of one root spread over more wavefronts); MODE 1 runs C4_HEAVY_NT.
+#ifndef PM_C4_HEAVY_NT
+#define PM_C4_HEAVY_NT 512
+#endif
+#ifndef PM_C4_HUGE_NT
+#define PM_C4_HUGE_NT 1024
+#endif
+constexpr uint32_t C4_HEAVY_NT = PM_C4_HEAVY_NT;
+constexpr uint32_t C4_HUGE_NT = PM_C4_HUGE_NT;
+constexpr uint32_t c4_threads(int mode) { return mode == 2 ? C4_HUGE_NT : (mode == 1 ? C4_HEAVY_NT : 256u); }
+// a table's words and the most out-neighbours a root of the mode has (the
+// per-position support counters follow the table)
+constexpr uint32_t c4_table_words(int mode) {
+    return mode == 2 ? C4_HUGE_WORDS : (mode == 1 ? C4_LDS_WORDS : C4_WAVE_WORDS);
+}
+constexpr uint32_t c4_max_s(int mode) { return mode == 2 ? C4_ROOT_MAX : (mode == 1 ? C4_HEAVY : C4_LIGHT); }
+
+// SUP: also fill the edge supports (a.support) of every triangle at roots
+// of 2 .. c4_max_s out-neighbours (the items then hold roots of two).
+template <bool BYTES, int MODE, bool SUP>
+__global__ void __launch_bounds__(c4_threads(MODE)) clique4_kernel(KArgs a) {
     constexpr bool WG = MODE != 0;
-    __shared__ uint32_t s_lds[MODE == 2 ? C4_HUGE_WORDS : (WG ? C4_LDS_WORDS : 4 * C4_WAVE_WORDS)];
+    constexpr uint32_t TW = c4_table_words(MODE) + c4_max_s(MODE);
+    __shared__ uint32_t s_lds[WG ? TW : 4 * TW];
     const int lane = wave_lane();
-    uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * C4_WAVE_WORDS;
+    uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * TW;
+    uint32_t* pc = base + c4_table_words(MODE);
     __shared__ uint32_t s_it;
     Ctx c;
     c.g = dgraph(a.g);
@@ -2605,10 +2647,10 @@ __global__ void __launch_bounds__(256) clique4_kernel(KArgs a) {
         for (uint32_t r = item.r0; r < item.r1; ++r) {
             const uint32_t b = a.g.split[r], e = a.g.rp[r + 1];
             const uint32_t s = e - b;
-            if (s < 3 || s > (MODE == 2 ? C4_ROOT_MAX : (WG ? C4_HEAVY : C4_LIGHT))) continue;
-            if (MODE == 2) cnt += c4_root<12, true, BYTES>(c, a.g, base, r, b, s);
-            else if (WG) cnt += c4_root<11, true, BYTES>(c, a.g, base, r, b, s);
-            else cnt += c4_root<8, false, BYTES>(c, a.g, base, r, b, s);
+            if (s < (SUP ? 2u : 3u) || s > c4_max_s(MODE)) continue;
+            if (MODE == 2) cnt += c4_root<12, true, BYTES, C4_HUGE_NT, SUP>(c, a.g, base, r, b, s, a.support, pc);
+            else if (WG) cnt += c4_root<11, true, BYTES, C4_HEAVY_NT, SUP>(c, a.g, base, r, b, s, a.support, pc);
+            else cnt += c4_root<8, false, BYTES, 64, SUP>(c, a.g, base, r, b, s, a.support, pc);
         }
     }
 #pragma unroll
@@ -2734,17 +2776,17 @@ int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int MODE, bool SUP>
+static void launch_c4(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
+    if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, MODE, SUP>), dim3(grid), dim3(c4_threads(MODE)), 0, s, a);
+    else hipLaunchKernelGGL((clique4_kernel<false, MODE, SUP>), dim3(grid), dim3(c4_threads(MODE)), 0, s, a);
+}
+
 int launch_clique4(const KArgs& a, int grid, int mode, bool count_bytes, hipStream_t s) {
-    if (mode == 2) {
-        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 2>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique4_kernel<false, 2>), dim3(grid), dim3(256), 0, s, a);
-    } else if (mode == 1) {
-        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 1>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique4_kernel<false, 1>), dim3(grid), dim3(256), 0, s, a);
-    } else {
-        if (count_bytes) hipLaunchKernelGGL((clique4_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((clique4_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
-    }
+    const bool sup = a.support != nullptr;
+    if (mode == 2) sup ? launch_c4<2, true>(a, grid, count_bytes, s) : launch_c4<2, false>(a, grid, count_bytes, s);
+    else if (mode == 1) sup ? launch_c4<1, true>(a, grid, count_bytes, s) : launch_c4<1, false>(a, grid, count_bytes, s);
+    else sup ? launch_c4<0, true>(a, grid, count_bytes, s) : launch_c4<0, false>(a, grid, count_bytes, s);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -194,7 +194,9 @@ static void clique_items(GraphRes& G, const std::vector<uint32_t>& rp, const std
     };
     for (uint32_t r = 0; r < G.n; ++r) {
         const uint32_t s = rp[r + 1] - split[r];
-        if (s < 3) continue;
+        // roots of two out-neighbours close no 4-clique, but the support
+        // filling variant meets their one triangle
+        if (s < 2) continue;
         uint64_t vol = 0;
         for (uint32_t p = split[r]; p < rp[r + 1]; ++p) vol += rp[col[p] + 1] - split[col[p]];
         if (s > C4_LIGHT_MAX) {
@@ -986,6 +988,8 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     ls->sup_words = sup ? std::max<uint64_t>(1, 2 * G.m) : 0;
     ls->sup_run = -1;
     ls->mirror = false;
+    ls->c4_sup = false;
+    ls->c4_fill_end = -1;
     if (cqs) {
         ls->cq_items = G.d_cq;
         ls->cq_nitems = (uint32_t)G.clique_items.size();
@@ -1150,6 +1154,13 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                 ls->run_agg.push_back(10);
             }
         } else if (grp == 4) {
+            // with no triangle pass before them, the first set of 4-clique
+            // launches fills the edge supports while it builds its rows
+            const bool fill = sup && ls->sup_run < 0;
+            if (fill) {
+                ls->c4_sup = true;
+                ls->sup_run = (int)ls->runs.size();
+            }
             for (int k = i; k < j; k += CQ_PLANS) {
                 const std::pair<int, int> rr{k, std::min(j, k + CQ_PLANS)};
                 if (ls->c4_nhuge) {
@@ -1164,6 +1175,7 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                     ls->runs.push_back(rr);
                     ls->run_agg.push_back(7);
                 }
+                if (fill && k == i) ls->c4_fill_end = (int)ls->runs.size();
             }
             if (!c4_big.empty()) {
                 ls->runs.push_back({i, j});
@@ -1230,8 +1242,9 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
     if (ls.support && launch_zero(ls.support, ls.sup_words, s0)) return fail(PM_E_DEVICE, "zero-fill launch failed");
     if (run_ev) HIPCHK(hipEventRecord(run_ev[0], s0));
     // house_kernel shares the per-wave dense counters with the two-hop and
-    // 5-cycle launches of the main branch: no fork then
-    fork = fork && !ls.mirror;
+    // 5-cycle launches of the main branch, and supports filled by 4-clique
+    // launches are read on the triangle branch: no fork then
+    fork = fork && !ls.mirror && !ls.c4_sup;
     bool used[3] = {true, false, false};
     if (fork) {
         for (int k = 0; k < 2; ++k) {
@@ -1313,6 +1326,7 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             const int mode = ls.run_agg[r] == 7 ? 0 : (ls.run_agg[r] == 8 ? 1 : 2);
             b.items = mode == 0 ? ls.c4_light : (mode == 1 ? ls.c4_heavy : ls.c4_huge);
             b.nitems = mode == 0 ? ls.c4_nlight : (mode == 1 ? ls.c4_nheavy : ls.c4_nhuge);
+            if (ls.c4_sup && (int)r >= ls.sup_run && (int)r < ls.c4_fill_end) b.support = ls.support;
             if (b.nitems && launch_clique4(b, clique4_blocks(mode), mode, bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;

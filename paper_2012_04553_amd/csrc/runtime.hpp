@@ -128,6 +128,8 @@ struct LaunchSet {
     uint64_t sup_words = 0;                  // their words (2m), cleared at the head of a replay
     uint64_t* vtri = nullptr;                // per vertex: twice its triangle count (closed forms)
     bool mirror = false;                     // supports mirrored to both list ends (house plans)
+    bool c4_sup = false;                     // the 4-clique launches [sup_run, c4_fill_end) fill them
+    int c4_fill_end = -1;
     uint64_t* host = nullptr;                // pinned: 2*np counter words + byte tally
     uint64_t agg_w = 0;                      // wavefronts of the aggregation launches
     int* cancel_host = nullptr;              // pinned coherent flag polled by the kernel

@@ -54,7 +54,7 @@ def test_clique_kernel_rmat(eng, scale, seed):
     try:
         names = oracle.named_4()
         assert "triangle counts: tailed triangle" in eng.plan_describe(gid, (4, names["tailed_triangle"], False))
-        assert "triangle_core" in eng.plan_describe(gid, (3, 0x7, False))
+        assert "triangle counts: triangle" in eng.plan_describe(gid, (3, 0x7, False))
         assert "edge_support" in eng.plan_describe(gid, (4, names["diamond"], False))
         for on in (True, False):
             assert _count(eng, gid, [(3, 0x7, False)], pm.MORPH_NONE, on) == [tc["triangles"]]
@@ -62,13 +62,17 @@ def test_clique_kernel_rmat(eng, scale, seed):
                 [want_e[m] for m in classes]
             assert _count(eng, gid, [(4, m, True) for m in classes], pm.MORPH_NAIVE, on) == \
                 [want_v[m] for m in classes]
-        # without edge supports the tailed triangle runs as a triangle-core
-        # plan with its tail evaluated per triangle
+        # without edge supports the triangle and the tailed triangle run as
+        # triangle-core plans, the tail evaluated per triangle
         eng.set_option("edge_support", 0)
         try:
             assert "triangle_core" in eng.plan_describe(gid, (4, names["tailed_triangle"], False))
+            assert "triangle_core" in eng.plan_describe(gid, (3, 0x7, False))
+            assert _count(eng, gid, [(3, 0x7, False)], pm.MORPH_NONE, True) == [tc["triangles"]]
             assert _count(eng, gid, [(4, m, False) for m in classes], pm.MORPH_NONE, True) == \
                 [want_e[m] for m in classes]
+            assert _count(eng, gid, [(4, m, True) for m in classes], pm.MORPH_NAIVE, True) == \
+                [want_v[m] for m in classes]
         finally:
             eng.set_option("edge_support", 1)
     finally:
