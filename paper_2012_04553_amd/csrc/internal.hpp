@@ -343,6 +343,11 @@ constexpr int32_t TAGG_FAN = 6;
 // that the 4-path's quotient needs no triangle pass of its own and the
 // 4-clique launches can fill the supports
 constexpr int32_t TAGG_TRIANGLE = 7;
+//  TAGG_K4EAR   a 4-clique with a triangle on one of its edges (the ear's
+//    apex another common neighbour of the edge): the sum over the 4-cliques
+//    of t(e) - 2 over their six edges, per root on the graph induced on its
+//    out-neighbourhood (k4ear_kernel).
+constexpr int32_t TAGG_K4EAR = 8;
 inline bool tagg_tri(int32_t kind) { return kind == TAGG_DTAIL || kind == TAGG_FAN; }
 // closed forms that read the per-vertex triangle counts
 inline bool tagg_vtri(int32_t kind) { return kind == TAGG_BOWTIE || kind == TAGG_TRIPATH; }
@@ -382,6 +387,7 @@ inline int tagg_kind(const Pat& p) {
     // the only five-vertex graphs with these edge counts and degrees
     if (popc(p.em) == 6 && hist[3] == 3 && hist[2] == 1 && hist[1] == 1) return TAGG_DTAIL;
     if (popc(p.em) == 7 && hist[4] == 1 && hist[3] == 2 && hist[2] == 2) return TAGG_FAN;
+    if (popc(p.em) == 8 && hist[4] == 2 && hist[3] == 2 && hist[2] == 1) return TAGG_K4EAR;
     return 0;
 }
 // all candidate plans (for tests / autotuning)

@@ -2341,7 +2341,7 @@ __device__ __forceinline__ u128 tagg_edge(int32_t kind, uint64_t Tu, uint64_t Tw
     // an edge on a triangle has both ends of degree 2 or more
     if (kind == TAGG_TAILED) return t ? (u128)t * (u128)(du + dw - 4) : (u128)0;
     if (kind == TAGG_TRIANGLE) return (u128)t;
-    if (kind != TAGG_TRIPATH) return 0;   // summed elsewhere (trisup_kernel)
+    if (kind != TAGG_TRIPATH) return 0;   // summed elsewhere (trisup_kernel, k4ear_kernel)
     // TAGG_TRIPATH: apex u with path vertex w, then apex w with path vertex u
     const u128 fwd = (u128)(Tu - t) * (u128)(dw - 1) + (u128)(Tw - t) * (u128)(du - 1);
     return fwd - 2 * pairs;
@@ -2773,6 +2773,153 @@ int launch_vtri(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
 int launch_support(const KArgs& a, int grid, bool count_bytes, hipStream_t s) {
     if (count_bytes) hipLaunchKernelGGL(support_kernel<true>, dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(support_kernel<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// The K4 with an ear on one edge (TAGG_K4EAR): each 4-clique once, at its
+// lowest vertex r, as a triangle {i, j, k} of the graph induced on N+(r);
+// the count is the sum over the 4-cliques of t(e) - 2 over their six edges
+// (the ear's apex is any other common neighbour of the edge).  Per root the
+// bit rows are built symmetric (row i holds every out-neighbour of r
+// adjacent to x_i), then the rows are streamed again: each edge (i, j) of
+// the induced graph, met as x_j in N+(x_i), has lt = |row i AND row j|
+// triangles of the induced graph on it and adds
+// lt (2 (t(x_i, x_j) - 2) + (t(r, x_i) - 2) + (t(r, x_j) - 2)), which over
+// all edges is twice the count (every triangle's vertex terms come from
+// two of its edges).  Needs complete supports.
+template <int LOGH, bool WG, bool BYTES, uint32_t NT>
+__device__ u128 c4_ear_root(Ctx& c, const KGraph& g, uint32_t* base, uint32_t b, uint32_t s,
+                            const uint32_t* sup) {
+    const uint32_t tid = WG ? threadIdx.x : (uint32_t)wave_lane();
+    auto sync = [] {
+        if (WG) __syncthreads();
+        else wave_sync();
+    };
+    C4Table<LOGH> T(base);
+    const uint32_t W = (s + 31) >> 5;
+    for (uint32_t i = tid; i < (1u << LOGH); i += NT) T.keys[i] = CQ_EMPTY;
+    for (uint32_t i = tid; i < s * W; i += NT) T.rows[i] = 0;
+    sync();
+    for (uint32_t i = tid; i < s; i += NT) T.insert(g.col[b + i], i);
+    if (BYTES && tid == 0) c.bytes += 12 + 4ull * s;
+    sync();
+    const int lane = wave_lane();
+    const uint32_t wv = WG ? (threadIdx.x >> 6) : 0;
+    u128 acc = 0;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t base_i = wv * 64; base_i < s; base_i += NT) {
+            const uint32_t i = base_i + lane;
+            const bool valid = i < s;
+            const uint32_t x = valid ? g.col[b + i] : 0u;
+            uint32_t pb = 0, len = 0, tri = 0;
+            if (valid) {
+                pb = g.split[x];
+                len = g.rp[x + 1] - pb;
+                if (pass) tri = sup[b + i];
+                if (BYTES) c.bytes += (pass ? 16 : 12) + 4ull * len;
+            }
+            const uint32_t incl = wave_incl_scan(len);
+            const uint32_t total = __shfl(incl, 63);
+            const uint32_t excl = incl - len;
+            for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+                const uint32_t t = t0 + lane;
+                const bool act = t < total;
+                const int o = owner_of(incl, act ? t : total - 1);
+                const uint32_t src = __shfl(pb, o) + (t - __shfl(excl, o));
+                const uint32_t ot = __shfl(tri, o);
+                if (!act) continue;
+                const int j = T.find(g.col[src]);
+                if (j < 0) continue;
+                const uint32_t row = base_i + (uint32_t)o;
+                if (pass == 0) {
+                    atomicOr(&T.rows[row * W + ((uint32_t)j >> 5)], 1u << (j & 31));
+                    atomicOr(&T.rows[(uint32_t)j * W + (row >> 5)], 1u << (row & 31));
+                } else {
+                    const uint32_t* ri = T.rows + row * W;
+                    const uint32_t* rj = T.rows + (uint32_t)j * W;
+                    uint32_t lt = 0;
+                    for (uint32_t w = 0; w < W; ++w) lt += (uint32_t)__popc(ri[w] & rj[w]);
+                    if (lt) {
+                        // an edge on a triangle of the induced graph lies on
+                        // two 4-cliques' worth of triangles: every t here is 2+
+                        const uint64_t wsum = 2ull * (sup[src] - 2) + (ot - 2) + (sup[b + j] - 2);
+                        acc += (u128)((uint64_t)lt * wsum);
+                        if (BYTES) c.bytes += 8;
+                    }
+                }
+            }
+        }
+        sync();
+    }
+    return acc;
+}
+
+template <bool BYTES, int MODE>
+__global__ void __launch_bounds__(c4_threads(MODE)) k4ear_kernel(KArgs a) {
+    constexpr bool WG = MODE != 0;
+    constexpr uint32_t TW = c4_table_words(MODE) + c4_max_s(MODE);
+    __shared__ uint32_t s_lds[WG ? TW : 4 * TW];
+    const int lane = wave_lane();
+    uint32_t* base = WG ? s_lds : s_lds + (threadIdx.x >> 6) * TW;
+    __shared__ uint32_t s_it;
+    Ctx c;
+    c.g = dgraph(a.g);
+    c.P = nullptr;
+    c.buf = nullptr;
+    c.stride = 0;
+    c.bytes = 0;
+    c.bmw = nullptr;
+    c.bm = nullptr;
+    u128 acc = 0;
+    for (;;) {
+        uint32_t it = 0;
+        if (WG) {
+            if (threadIdx.x == 0) {
+                uint32_t v = atomicAdd(a.head, 1u);
+                if (v < a.nitems && a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) v = a.nitems;
+                s_it = v;
+            }
+            __syncthreads();
+            it = s_it;
+            __syncthreads();
+        } else {
+            if (lane == 0) {
+                it = atomicAdd(a.head, 1u);
+                if (it < a.nitems && a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED)) it = a.nitems;
+            }
+            it = bcast(it);
+        }
+        if (it >= a.nitems) break;
+        const KItem item = a.items[it];
+        for (uint32_t r = item.r0; r < item.r1; ++r) {
+            const uint32_t b = a.g.split[r], e = a.g.rp[r + 1];
+            const uint32_t s = e - b;
+            if (s < 3 || s > c4_max_s(MODE)) continue;
+            if (MODE == 2) acc += c4_ear_root<12, true, BYTES, C4_HUGE_NT>(c, a.g, base, b, s, a.support);
+            else if (WG) acc += c4_ear_root<11, true, BYTES, C4_HEAVY_NT>(c, a.g, base, b, s, a.support);
+            else acc += c4_ear_root<8, false, BYTES, 64>(c, a.g, base, b, s, a.support);
+        }
+    }
+    flush(a, 0, acc);
+    if (BYTES) {
+        unsigned long long bsum = c.bytes;
+        for (int off = 32; off >= 1; off >>= 1) bsum += __shfl_xor(bsum, off);
+        if (lane == 0) atomicAdd((unsigned long long*)a.bytes, bsum);
+    }
+}
+
+int launch_k4ear(const KArgs& a, int grid, int mode, bool count_bytes, hipStream_t s) {
+    if (mode == 2) {
+        if (count_bytes) hipLaunchKernelGGL((k4ear_kernel<true, 2>), dim3(grid), dim3(c4_threads(2)), 0, s, a);
+        else hipLaunchKernelGGL((k4ear_kernel<false, 2>), dim3(grid), dim3(c4_threads(2)), 0, s, a);
+    } else if (mode == 1) {
+        if (count_bytes) hipLaunchKernelGGL((k4ear_kernel<true, 1>), dim3(grid), dim3(c4_threads(1)), 0, s, a);
+        else hipLaunchKernelGGL((k4ear_kernel<false, 1>), dim3(grid), dim3(c4_threads(1)), 0, s, a);
+    } else {
+        if (count_bytes) hipLaunchKernelGGL((k4ear_kernel<true, 0>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k4ear_kernel<false, 0>), dim3(grid), dim3(256), 0, s, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

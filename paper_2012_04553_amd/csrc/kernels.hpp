@@ -86,6 +86,9 @@ int launch_house(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
 // a launch) over the triangle items {r0, r1, i0, i1}, reading the supports
 // a launch_clique with a.support filled.
 int launch_trisup(const KArgs& a, int grid, bool count_bytes, hipStream_t s);
+// The K4 with an ear (one TAGG_K4EAR plan a launch) over the 4-clique items
+// of `mode` (as launch_clique4), reading complete supports.
+int launch_k4ear(const KArgs& a, int grid, int mode, bool count_bytes, hipStream_t s);
 // Ordered 4-clique plans (clique4_ok), at most CQ_PLANS per launch: one
 // wavefront (mode 0: up to C4_LIGHT_MAX out-neighbours) or one workgroup
 // (mode 1: up to C4_HEAVY_MAX, mode 2: up to C4_ROOT_MAX) per root of the

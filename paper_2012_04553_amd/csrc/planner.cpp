@@ -725,6 +725,7 @@ std::string PlanInfo::describe() const {
     if (d.tagg == TAGG_HOUSE) s += " | triangle counts: house (4-cycle support sums)";
     if (d.tagg == TAGG_TAILED) s += " | triangle counts: tailed triangle";
     if (d.tagg == TAGG_TRIANGLE) s += " | triangle counts: triangle";
+    if (d.tagg == TAGG_K4EAR) s += " | triangle counts: 4-clique with an ear (per 4-clique)";
     if (d.tagg == TAGG_DTAIL) s += " | triangle counts: diamond with a pendant at a tip (per triangle)";
     if (d.tagg == TAGG_FAN) s += " | triangle counts: fan of three triangles (per triangle)";
     if (d.lane_par) s += " lane_par";
@@ -881,11 +882,11 @@ static void tagg_plan(const Pat& p, int kind, const GraphStats& gs, PlanInfo* ou
     d.lev[0].label = -1;
     out->d = d;
     out->pat = p;
-    out->divisor = kind == TAGG_TAILED ? 2 : (kind == TAGG_TRIANGLE ? 3 : 1);
+    out->divisor = kind == TAGG_TAILED || kind == TAGG_K4EAR ? 2 : (kind == TAGG_TRIANGLE ? 3 : 1);
     out->formulation = 0;
     for (int j = 0; j < KMAX; ++j) out->order[j] = j < 1 ? 0 : -1;
     out->est_cost = gs.s_pp + 4 * gs.m + gs.n + (kind == TAGG_HOUSE ? 2 * gs.s_pd : 0.0) +
-                    (tagg_tri(kind) ? gs.s_pq : 0.0);
+                    (tagg_tri(kind) ? gs.s_pq : 0.0) + (kind == TAGG_K4EAR ? 2 * gs.s_pq : 0.0);
     out->total_cost = out->est_cost;
     out->subs.clear();
     if (tagg_tri(kind)) {

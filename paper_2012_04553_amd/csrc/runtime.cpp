@@ -657,7 +657,7 @@ bool Ctx_::use_clique(const GraphRes& G, const std::vector<PlanInfo>& plans) con
 bool Ctx_::use_clique4(const GraphRes& G, const std::vector<PlanInfo>& plans) const {
     if (!clique_opt || (G.c4_light.empty() && G.c4_heavy.empty() && G.c4_huge.empty())) return false;
     for (const PlanInfo& p : plans)
-        if (clique4_ok(p.d)) return true;
+        if (clique4_ok(p.d) || p.d.tagg == TAGG_K4EAR) return true;
     return false;
 }
 
@@ -1148,6 +1148,14 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
                 } else if (tagg_tri(plans[k].d.tagg)) {
                     ls->runs.push_back({k, k + 1});
                     ls->run_agg.push_back(15);
+                } else if (plans[k].d.tagg == TAGG_K4EAR) {
+                    // the 4-clique items of each size class
+                    for (int code : {18, 17, 16}) {
+                        const uint32_t n4 = code == 18 ? ls->c4_nhuge : (code == 17 ? ls->c4_nheavy : ls->c4_nlight);
+                        if (!n4) continue;
+                        ls->runs.push_back({k, k + 1});
+                        ls->run_agg.push_back(code);
+                    }
                 }
             for (int k = i; k < j; k += CQ_PLANS) {
                 ls->runs.push_back({k, std::min(j, k + CQ_PLANS)});
@@ -1216,6 +1224,7 @@ const char* run_kernel_name(int kind) {
         case 13: return "vtri_kernel";
         case 14: return "house_kernel";
         case 15: return "trisup_kernel";
+        case 16: case 17: case 18: return "k4ear_kernel";
         default: return "match_kernel";
     }
 }
@@ -1228,7 +1237,7 @@ const char* run_kernel_name(int kind) {
 // 4-cliques; 0 = the rest (general kernel and window kernels, which share
 // the per-wavefront level buffers and window scratch).
 static int run_branch(int kind) {
-    if (kind == 5 || kind == 10 || kind == 13 || kind == 14 || kind == 15) return 1;
+    if (kind == 5 || kind == 10 || (kind >= 13 && kind <= 18)) return 1;
     if (kind == 7 || kind == 8 || kind == 11) return 2;
     return 0;
 }
@@ -1306,6 +1315,14 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             b.vtri = ls.vtri;
             b.mirror = ls.mirror ? 1u : 0u;
             if (launch_vtri(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            continue;
+        } else if (ls.run_agg[r] >= 16 && ls.run_agg[r] <= 18) {
+            const int mode = ls.run_agg[r] - 16;
+            b.items = mode == 0 ? ls.c4_light : (mode == 1 ? ls.c4_heavy : ls.c4_huge);
+            b.nitems = mode == 0 ? ls.c4_nlight : (mode == 1 ? ls.c4_nheavy : ls.c4_nhuge);
+            b.support = ls.support;
+            if (b.nitems && launch_k4ear(b, clique4_blocks(mode), mode, bytes_pass, s))
+                return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 15) {
             b.items = ls.cq_items;

@@ -138,7 +138,7 @@ def test_edge_supports_beyond_packed_ids(eng):
         eng.graph_unload(gid)
 
 
-_BOWTIE, _TRIPATH, _HOUSE, _DTAIL, _FAN = 0x0EB, 0x075, 0x0ED, 0x077, 0x0EF
+_BOWTIE, _TRIPATH, _HOUSE, _DTAIL, _FAN, _K4EAR = 0x0EB, 0x075, 0x0ED, 0x077, 0x0EF, 0x0FF
 
 
 @pytest.mark.parametrize("gname", ["rmat8", "er", "k12_rmat6"])
@@ -146,9 +146,10 @@ def test_triangle_count_closed_forms(eng, gname):
     """The bowtie (two triangles sharing a vertex), the triangle with a
     two-edge path hanging off a corner, the house (a 4-cycle with a triangle
     on one edge), the diamond with a pendant at a tip and the fan of three
-    triangles are counted in closed form from the per-edge and per-vertex
-    triangle counts, the 4-cycles' sums of them and per-triangle sums of
-    them (less twelve per 4-clique); against the oracle census, in a
+    triangles and the 4-clique with an ear are counted in closed form from
+    the per-edge and per-vertex triangle counts, the 4-cycles' sums of them,
+    per-triangle sums of them (less twelve per 4-clique) and per-4-clique
+    sums of them; against the oracle census, in a
     single-pattern set, in the 21-pattern edge-induced set (several
     edge-support launches in one replay) and in the morphed vertex-induced
     5-motif set, and the same with the triangle kernels off (enumerating
@@ -168,8 +169,9 @@ def test_triangle_count_closed_forms(eng, gname):
         assert "triangle counts: house" in eng.plan_describe(gid, (5, _HOUSE, False))
         assert "triangle counts: diamond with a pendant" in eng.plan_describe(gid, (5, _DTAIL, False))
         assert "triangle counts: fan of three triangles" in eng.plan_describe(gid, (5, _FAN, False))
+        assert "triangle counts: 4-clique with an ear" in eng.plan_describe(gid, (5, _K4EAR, False))
         for on in (True, False):
-            for m in (_BOWTIE, _TRIPATH, _HOUSE, _DTAIL, _FAN):
+            for m in (_BOWTIE, _TRIPATH, _HOUSE, _DTAIL, _FAN, _K4EAR):
                 assert _count(eng, gid, [(5, m, False)], pm.MORPH_NONE, on) == [ei[m]]
             assert _count(eng, gid, [(5, m, False) for m in classes], pm.MORPH_NONE, on) == \
                 [ei[m] for m in classes]
@@ -197,7 +199,7 @@ def test_triangle_count_closed_forms_match_enumeration(eng):
     out-neighbours than the triangle kernel takes (not every triangle would
     be counted per edge), no closed form is chosen."""
     import paper_2012_04553_amd as pm
-    pats = [(5, m, False) for m in (_BOWTIE, _TRIPATH, _HOUSE, _DTAIL, _FAN)]
+    pats = [(5, m, False) for m in (_BOWTIE, _TRIPATH, _HOUSE, _DTAIL, _FAN, _K4EAR)]
     g = gen.rmat(13, 16, seed=34)
     gid = eng.load(g)
     try:
