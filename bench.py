@@ -277,7 +277,7 @@ def wl_er2000_4mc(args, eng):
     line["morphed_vs_plain"] = {"morphed_s": res["morphed"]["ms_per_step"] / 1e3,
                                 "plain_s": res["plain"]["ms_per_step"] / 1e3}
     line["config"]["workload"] = "4-motif counting, ER G(2000, 0.005) seed 1, morphed (plain beside it)"
-    line["cpu_baseline"] = None if args.no_cpu else cpu_baseline_4mc(g, budget_s=10.0)
+    line["cpu_baseline"] = None if args.no_cpu else cpu_baseline_4mc(g, stride=1)
     return line
 
 
