@@ -306,10 +306,17 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *                   kernel), edge-core plans with cheap terms per edge;
  *   "edge_support"  0/1 (default 1): edge-core plans whose set-size term
  *                   is the whole common neighbourhood (the diamond) take
- *                   it from per-edge triangle counts filled by the
- *                   triangle pass (needs "clique_kernel" and no root above
- *                   1024 out-neighbours; one u32 per adjacency entry of
- *                   the graph, allocated on first use);
+ *                   it from per-edge triangle counts, and nine unlabeled
+ *                   edge-induced patterns (the triangle, the tailed
+ *                   triangle, the bowtie, the triangle with a two-edge
+ *                   path, the house, the diamond with a pendant at a tip,
+ *                   the fan of three triangles, the 4-clique with an ear)
+ *                   are counted in closed form from them instead of being
+ *                   enumerated.  The counts are filled by the 4-clique or
+ *                   the triangle launches (needs "clique_kernel" and no
+ *                   root above 1024 out-neighbours; one u32 per adjacency
+ *                   entry of the graph, allocated on first use and cleared
+ *                   at the head of every replay);
  *   "hipgraph"      0/1 (default 1): capture a query set's launches in a
  *                   hipGraph on first use and replay it afterwards;
  *   "window_counters" 16 or 32 (default 16): counter width of the two-hop
@@ -321,7 +328,8 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *   "fork_launches" 0/1 (default 0): captured launch sets run the triangle
  *                   and edge-support launches and the 4-clique launches on
  *                   two more branches of the hipGraph, beside the general
- *                   kernel's launches;
+ *                   kernel's launches (not for sets with a house plan or
+ *                   whose 4-clique launches fill the edge supports);
  *   "hub_bitmaps"   0/1 (default 1): probes of the adjacency lists of the
  *                   highest-degree vertices (64 neighbours or more, up to
  *                   512 MiB of n-bit bitmaps built at graph load) answer
@@ -359,6 +367,9 @@ pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
  * its costliest request, estimated at that request's work or more, end at
  * once with PM_E_TIMEOUT (stats.shed) instead of occupying a slot until the
  * deadline.
+ * Each slot holds its own edge-support counters (a u32 per adjacency entry
+ * of the largest graph served) for the closed forms of "edge_support"; with
+ * no arena room for them the slots plan without those forms.
  * Latency of a request = completion time - scheduled arrival (queueing
  * included).  Not to be called concurrently with other calls on the same
  * context.  Results are identical to pm_submit/pm_wait of the same
