@@ -306,7 +306,7 @@ pm_status pm_fsm_slot(uint32_t num_labels, uint64_t slot, pm_pattern* out);
  *                   kernel), edge-core plans with cheap terms per edge;
  *   "edge_support"  0/1 (default 1): edge-core plans whose set-size term
  *                   is the whole common neighbourhood (the diamond) take
- *                   it from per-edge triangle counts, and nine unlabeled
+ *                   it from per-edge triangle counts, and eight unlabeled
  *                   edge-induced patterns (the triangle, the tailed
  *                   triangle, the bowtie, the triangle with a two-edge
  *                   path, the house, the diamond with a pendant at a tip,
