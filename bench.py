@@ -454,6 +454,19 @@ def wl_serving(args, eng):
     res, st = eng.serve(reqs, max_slots=8, max_batch=8, budget_bytes=32 << 30, deadline_s=args.serve_deadline,
                         progress_every=max(1, args.serve_queries // 20))
     wall = time.perf_counter() - t
+    # outcome per (graph, largest pattern size) class: completed, timed out
+    # on the device, shed at admission (a timeout with no service time)
+    by_class = {}
+    for q, r in zip(qs, res):
+        key = f"n={sizes[q.graph]} k={max(p[0] for p in q.patterns)}"
+        c = by_class.setdefault(key, {"offered": 0, "completed": 0, "timed_out": 0, "shed": 0, "other": 0})
+        c["offered"] += 1
+        if r["status"] == 0:
+            c["completed"] += 1
+        elif r["status"] == -7:
+            c["shed" if r["service_s"] == 0.0 else "timed_out"] += 1
+        else:
+            c["other"] += 1
     line = base_line(args, st["p99_s"], "s (p99 latency)", wall * 1e3,
                      f"serving {args.serve_queries} queries at {args.serve_qps} QPS over 4 Chung-Lu graphs "
                      f"(beta 2.1, mean degree 20, n = {sizes}), k in {ks}, 30% labeled, cost-based morphing",
@@ -463,7 +476,7 @@ def wl_serving(args, eng):
                       "sustained_qps": st["sustained_qps"], "offered_qps": args.serve_qps,
                       "mean_setup_s": st["mean_setup_s"], "mean_service_s": st["mean_service_s"],
                       "makespan_s": st["makespan_s"], "deadline_s": args.serve_deadline,
-                      "service_profile": profile}, higher=False)
+                      "by_class": dict(sorted(by_class.items())), "service_profile": profile}, higher=False)
     line["roofline"] = None
     line["cpu_baseline"] = None
     return line

@@ -366,7 +366,8 @@ pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
  * pending requests on the same graph with the same largest pattern size as
  * its costliest request, estimated at that request's work or more, end at
  * once with PM_E_TIMEOUT (stats.shed) instead of occupying a slot until the
- * deadline.
+ * deadline -- unless a request of that graph and size estimated at their
+ * work or more has completed in time.
  * Each slot holds its own edge-support counters (a u32 per adjacency entry
  * of the largest graph served) for the closed forms of "edge_support"; with
  * no arena room for them the slots plan without those forms.

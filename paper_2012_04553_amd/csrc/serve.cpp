@@ -18,10 +18,12 @@
 // largest pattern size (the cost model ranks plans within such a class far
 // better than across them): a later request of that class estimated at that
 // much or more is shed at once (PM_E_TIMEOUT, counted in `shed`) instead of
-// holding a slot until the deadline.
-// Every slot owns a HIP stream (default priority) and dense two-hop
-// counter arrays, so batches in different slots run concurrently on the
-// device without sharing mutable memory.
+// holding a slot until the deadline, unless a request of that class at
+// least as costly has completed in time (a cheap batch can time out behind
+// heavy neighbours on the device).
+// Every slot owns a HIP stream (default priority), dense two-hop counter
+// arrays and edge-support counters, so batches in different slots run
+// concurrently on the device without sharing mutable memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,6 +225,10 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     for (uint32_t i = 0; i < nreq; ++i)
         for (const Pat& q : pats[i]) rk[i] = std::max(rk[i], (int)q.k);
     std::map<std::pair<const GraphRes*, int>, double> timeout_cost;
+    // per class: the largest estimated work of a request that completed in
+    // time; a request no costlier than that is never shed (a timeout of a
+    // cheap batch behind heavy neighbours on the device says little about it)
+    std::map<std::pair<const GraphRes*, int>, double> done_cost;
     uint64_t shed = 0;
     uint32_t next = 0, finished = 0;
     uint64_t used = 0, batches = 0;
@@ -296,6 +302,11 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             for (size_t r = 0; r < B.reqs.size(); ++r) {
                 pm_serve_result& R = res[B.reqs[r]];
                 R.status = brc ? brc : rst[r];
+                if (R.status == PM_OK) {
+                    const uint32_t q = B.reqs[r];
+                    double& dc = done_cost[std::make_pair((const GraphRes*)gr[q], rk[q])];
+                    dc = std::max(dc, rcost[q]);
+                }
                 R.latency_s = tdone - reqs[B.reqs[r]].arrival_s;
                 R.service_s = tdone - B.admitted;
                 R.batch_size = (uint32_t)B.reqs.size();
@@ -330,8 +341,11 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             if (cfg->deadline_s > 0 && !timeout_cost.empty()) {
                 bool any = false;
                 for (auto it = pending.begin(); it != pending.end();) {
-                    auto tc = timeout_cost.find(std::make_pair((const GraphRes*)gr[*it], rk[*it]));
-                    if (tc != timeout_cost.end() && rcost[*it] >= tc->second) {
+                    const auto key = std::make_pair((const GraphRes*)gr[*it], rk[*it]);
+                    auto tc = timeout_cost.find(key);
+                    auto dc = done_cost.find(key);
+                    if (tc != timeout_cost.end() && rcost[*it] >= tc->second &&
+                        (dc == done_cost.end() || rcost[*it] > dc->second)) {
                         res[*it].status = PM_E_TIMEOUT;
                         res[*it].latency_s = now_s() - reqs[*it].arrival_s;
                         ++finished;
