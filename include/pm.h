@@ -367,7 +367,11 @@ pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
  * its costliest request, estimated at that request's work or more, end at
  * once with PM_E_TIMEOUT (stats.shed) instead of occupying a slot until the
  * deadline -- unless a request of that graph and size estimated at their
- * work or more has completed in time.
+ * work or more has completed in time (and a timeout of a request no
+ * costlier than one that completed teaches nothing: the device was busy).
+ * Each slot's launches take a 1/max_slots share of the grids (the general
+ * kernel's and those sized by the CU count), so a cheap batch is not held
+ * behind persistent workgroups of heavy ones.
  * Each slot holds its own edge-support counters (a u32 per adjacency entry
  * of the largest graph served) for the closed forms of "edge_support"; with
  * no arena room for them the slots plan without those forms.

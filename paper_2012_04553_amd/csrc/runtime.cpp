@@ -1245,6 +1245,9 @@ static int run_branch(int kind) {
 int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* run_ev, bool fork) {
     const LaunchCfg& cfg = ls.cfg;
     if (ls.runs.size() > MAX_RUNS) return fail(PM_E_DEVICE, "internal: too many launches in one set");
+    // a serving slot's share of the launches sized by CU count (persistent
+    // workgroups that hold CUs until their queue drains)
+    auto shared = [&](int grid) { return cfg.share_div > 1 ? std::max(1, grid / cfg.share_div) : grid; };
     if (launch_zero(ls.zero_base, ls.zero_words, s0)) return fail(PM_E_DEVICE, "zero-fill launch failed");
     // the supports start from zero on every replay, also after a cancelled
     // one that stopped before reading them
@@ -1301,27 +1304,27 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             b.items = ls.cq_items;
             b.nitems = ls.cq_nitems;
             b.support = (int)r == ls.sup_run ? ls.support : nullptr;
-            if (b.nitems && launch_clique(b, clique_blocks(b.support != nullptr, b.g.n), bytes_pass, s))
+            if (b.nitems && launch_clique(b, shared(clique_blocks(b.support != nullptr, b.g.n)), bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 10) {
             b.support = ls.support;
             b.vtri = ls.vtri;
             b.mirror = ls.mirror ? 1u : 0u;
-            if (launch_support(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            if (launch_support(b, shared(support_blocks()), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 13) {
             b.support = ls.support;
             b.vtri = ls.vtri;
             b.mirror = ls.mirror ? 1u : 0u;
-            if (launch_vtri(b, support_blocks(), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            if (launch_vtri(b, shared(support_blocks()), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] >= 16 && ls.run_agg[r] <= 18) {
             const int mode = ls.run_agg[r] - 16;
             b.items = mode == 0 ? ls.c4_light : (mode == 1 ? ls.c4_heavy : ls.c4_huge);
             b.nitems = mode == 0 ? ls.c4_nlight : (mode == 1 ? ls.c4_nheavy : ls.c4_nhuge);
             b.support = ls.support;
-            if (b.nitems && launch_k4ear(b, clique4_blocks(mode), mode, bytes_pass, s))
+            if (b.nitems && launch_k4ear(b, shared(clique4_blocks(mode)), mode, bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 15) {
@@ -1329,7 +1332,7 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             b.nitems = ls.cq_nitems;
             b.support = ls.support;
             // 48 KB of LDS a workgroup: three resident a CU
-            if (b.nitems && launch_trisup(b, num_cus * 3, bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
+            if (b.nitems && launch_trisup(b, shared(num_cus * 3), bytes_pass, s)) return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 14) {
             b.support = ls.support;
@@ -1344,7 +1347,7 @@ int Ctx_::enqueue(LaunchSet& ls, hipStream_t s0, bool bytes_pass, hipEvent_t* ru
             b.items = mode == 0 ? ls.c4_light : (mode == 1 ? ls.c4_heavy : ls.c4_huge);
             b.nitems = mode == 0 ? ls.c4_nlight : (mode == 1 ? ls.c4_nheavy : ls.c4_nhuge);
             if (ls.c4_sup && (int)r >= ls.sup_run && (int)r < ls.c4_fill_end) b.support = ls.support;
-            if (b.nitems && launch_clique4(b, clique4_blocks(mode), mode, bytes_pass, s))
+            if (b.nitems && launch_clique4(b, shared(clique4_blocks(mode)), mode, bytes_pass, s))
                 return fail(PM_E_DEVICE, "kernel launch failed");
             continue;
         } else if (ls.run_agg[r] == 9) {

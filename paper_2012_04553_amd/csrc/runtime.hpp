@@ -79,6 +79,7 @@ struct LaunchCfg {
     uint64_t item_budget = 4096;
     uint32_t item_split = 2048;
     int grid_override = 0;   // > 0: blocks of the match launch (a GPU share)
+    int share_div = 0;       // > 1: the fixed-grid LDS launches take 1/share_div of their grids
 };
 
 // Device state of one (graph, plan closure, launch configuration): plans,

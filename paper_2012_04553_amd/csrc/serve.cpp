@@ -293,10 +293,15 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                 uint32_t worst = B.reqs[0];
                 for (uint32_t r : B.reqs)
                     if (rcost[r] > rcost[worst]) worst = r;
+                // unless a request of its class at least as costly has
+                // completed in time: then the device was busy with others
                 auto key = std::make_pair((const GraphRes*)gr[worst], rk[worst]);
-                auto it = timeout_cost.find(key);
-                if (it == timeout_cost.end()) timeout_cost[key] = rcost[worst];
-                else it->second = std::min(it->second, rcost[worst]);
+                auto dc = done_cost.find(key);
+                if (dc == done_cost.end() || rcost[worst] > dc->second) {
+                    auto it = timeout_cost.find(key);
+                    if (it == timeout_cost.end()) timeout_cost[key] = rcost[worst];
+                    else it->second = std::min(it->second, rcost[worst]);
+                }
             }
             if (brc == PM_OK) batch_values(B, &vals, &rst, &rerr);
             for (size_t r = 0; r < B.reqs.size(); ++r) {
@@ -396,6 +401,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
             // a persistent launch holds its CUs until its queue drains: give
             // each slot a share of the GPU so batches really run side by side
             lc.grid_override = std::max(1, (int)(num_cus * 2 / cfg->max_slots));
+            lc.share_div = (int)cfg->max_slots;
             uint64_t stride;
             bool any_agg;
             B->bytes = footprint(G, B->plans, lc, &stride, &any_agg, false);
