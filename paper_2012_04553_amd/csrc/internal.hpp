@@ -116,6 +116,27 @@ struct DPlan {
     DMono mono[MAX_MONO];
 };
 
+// The edge-induced 4-cycle's two-hop plan: targets v1 < v0 aggregated over
+// bridges below v0, the tail T0^2 - T0 of the bridge count (each 4-cycle at
+// its highest vertex, halved by the divisor).  A root with fewer than two
+// lower neighbours adds nothing to it.
+inline bool c4_agg_plan(const DPlan& d) {
+    if (!d.agg_last || d.ncore != 2 || d.nterm != 1 || d.nmono != 2 || d.local || d.bridge_src != 0 ||
+        d.bridge_gt != 0 || d.bridge_lt != 1 || d.bridge_label >= 0 || d.lev[0].label >= 0)
+        return false;
+    const DLevel& L = d.lev[1];
+    const DTerm& T = d.term[0];
+    if (L.adj || L.anti || L.gt || L.lt != 1 || L.neq || L.label >= 0 || !L.agg) return false;
+    if (T.adj != 3 || T.anti || T.gt || T.lt != 1 || T.neq || T.label >= 0 || T.cheap || !T.agg) return false;
+    bool lin = false, sq = false;
+    for (int m = 0; m < 2; ++m) {
+        const DMono& M = d.mono[m];
+        lin = lin || (M.coef == -1 && M.nf == 1 && M.f[0] == 0);
+        sq = sq || (M.coef == 1 && M.nf == 2 && M.f[0] == 0 && M.f[1] == 0);
+    }
+    return lin && sq;
+}
+
 // Edge-core plans whose set-size terms all intersect N(v0) and N(v1): the
 // heavy roots of such plans can run in edge_window_kernel.
 constexpr uint32_t EW_TERMS = 4;

@@ -360,11 +360,13 @@ int Ctx_::graph_load(uint32_t n, const uint32_t* rp, const uint32_t* col, const 
     HIPCHK(hipStreamSynchronize(stream));
     // two-hop mass: summed degrees of the lower neighbours (entries before split)
     G->two_hop.assign(n, 0);
+    G->low2.assign(n, 0);
     parallel_for(n, [&](uint64_t b, uint64_t e) {
         for (uint64_t r = b; r < e; ++r) {
             uint64_t w = 0;
             for (uint32_t p = nrp[r]; p < nsplit[r]; ++p) w += nrp[ncol[p] + 1] - nrp[ncol[p]];
             G->two_hop[r] = w;
+            G->low2[r] = nsplit[r] - nrp[r] >= 2 ? 1 : 0;
         }
     });
     clique_items(*G, nrp, ncol, nsplit);
@@ -905,6 +907,15 @@ int Ctx_::make_launchset(GraphRes& G, const std::vector<PlanInfo>& plans, const 
     if (hk) {
         std::vector<uint8_t> is_heavy(G.n, 0);
         for (uint32_t r : heavy) is_heavy[r] = 1;
+        // when every two-hop plan is the 4-cycle's pair count over bridges
+        // below the root, a root with fewer than two lower neighbours adds
+        // nothing: leave it out of the light items too
+        bool c4only = true;
+        for (const PlanInfo& p : plans)
+            if (p.d.agg_last) c4only = c4only && c4_agg_plan(p.d);
+        if (c4only)
+            for (uint32_t r = 0; r < G.n; ++r)
+                if (!G.low2[r]) is_heavy[r] = 1;
         hitems = heavy_items(G, heavy, true);
         light = items_without(build_items(G.host_rp, G.n, cfg.item_budget, agg_split, 256), is_heavy);
     }

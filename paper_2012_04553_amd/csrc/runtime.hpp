@@ -164,6 +164,7 @@ struct GraphRes {
     std::vector<uint32_t> orig_id;           // degree-ordered id -> the caller's id
     std::vector<uint32_t> label_order;       // labeled graphs: vertices sorted by label
     std::vector<uint64_t> two_hop;           // per vertex: summed degrees of its lower neighbours
+    std::vector<uint8_t> low2;               // per vertex: 1 with two or more lower neighbours
     std::vector<KItem> clique_items;         // triangle-core kernel items
     std::vector<uint32_t> clique_big;        // roots with more than CQ_SMAX out-neighbours
     std::vector<KItem> c4_light, c4_heavy, c4_huge;   // 4-clique kernel items
