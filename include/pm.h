@@ -362,13 +362,14 @@ pm_status pm_autotune(pm_ctx* ctx, uint32_t graph_id, const pm_pattern* pats,
  * whose patterns are matched in a single multi-pattern launch; a batch is
  * admitted only while the arena bytes of all in-flight batches stay within
  * budget_bytes.  Batches run concurrently on the device, and a finished
- * slot is refilled at once.  With a deadline, once a batch has timed out,
- * pending requests on the same graph with the same largest pattern size as
- * its costliest request, estimated at that request's work or more, end at
- * once with PM_E_TIMEOUT (stats.shed) instead of occupying a slot until the
- * deadline -- unless a request of that graph and size estimated at their
- * work or more has completed in time (and a timeout of a request no
- * costlier than one that completed teaches nothing: the device was busy).
+ * slot is refilled at once.  With a deadline, once batches whose costliest
+ * requests share a graph and largest pattern size have timed out twice,
+ * pending requests of that class estimated at the least of those requests'
+ * work or more end at once with PM_E_TIMEOUT (stats.shed) instead of
+ * occupying a slot until the deadline -- unless a request of that class
+ * estimated at their work or more has completed in time (a timeout of a
+ * request no costlier than one that completed teaches nothing: the device
+ * was busy); one in 16 of the requests so ended is admitted instead.
  * Each slot's launches take a 1/max_slots share of the grids (the general
  * kernel's and those sized by the CU count), so a cheap batch is not held
  * behind persistent workgroups of heavy ones.

@@ -18,9 +18,10 @@
 // largest pattern size (the cost model ranks plans within such a class far
 // better than across them): a later request of that class estimated at that
 // much or more is shed at once (PM_E_TIMEOUT, counted in `shed`) instead of
-// holding a slot until the deadline, unless a request of that class at
-// least as costly has completed in time (a cheap batch can time out behind
-// heavy neighbours on the device).
+// holding a slot until the deadline, once the class has timed out twice and
+// unless a request of that class at least as costly has completed in time (a
+// cheap batch can time out behind heavy neighbours on the device); one in
+// SHED_PROBE of the requests it would shed is admitted anyway.
 // Every slot owns a HIP stream (default priority), dense two-hop counter
 // arrays and edge-support counters, so batches in different slots run
 // concurrently on the device without sharing mutable memory.
@@ -72,6 +73,9 @@ constexpr uint64_t SLOT_HOST_WORDS = 2 * 1024 + 8;
 
 // estimated work below which requests count as equally cheap for batching
 constexpr double SMALL_WORK = 1e6;
+
+// one in this many requests that shedding would end is admitted instead
+constexpr uint32_t SHED_PROBE = 16;
 
 using Clock = std::chrono::steady_clock;
 
@@ -229,6 +233,13 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
     // time; a request no costlier than that is never shed (a timeout of a
     // cheap batch behind heavy neighbours on the device says little about it)
     std::map<std::pair<const GraphRes*, int>, double> done_cost;
+    // per class: timeouts learnt (shedding starts at the second), and the
+    // requests shedding has passed over; every SHED_PROBE-th of those is
+    // admitted anyway (and never shed later), so that a class whose first
+    // timeouts were bad luck can show otherwise
+    std::map<std::pair<const GraphRes*, int>, int> timeouts_n;
+    std::map<std::pair<const GraphRes*, int>, uint32_t> shed_seen;
+    std::vector<uint8_t> probe(nreq, 0);
     uint64_t shed = 0;
     uint32_t next = 0, finished = 0;
     uint64_t used = 0, batches = 0;
@@ -301,6 +312,7 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                     auto it = timeout_cost.find(key);
                     if (it == timeout_cost.end()) timeout_cost[key] = rcost[worst];
                     else it->second = std::min(it->second, rcost[worst]);
+                    ++timeouts_n[key];
                 }
             }
             if (brc == PM_OK) batch_values(B, &vals, &rst, &rerr);
@@ -349,8 +361,13 @@ int Ctx_::serve(const pm_serve_request* reqs, uint32_t nreq, const pm_serve_conf
                     const auto key = std::make_pair((const GraphRes*)gr[*it], rk[*it]);
                     auto tc = timeout_cost.find(key);
                     auto dc = done_cost.find(key);
-                    if (tc != timeout_cost.end() && rcost[*it] >= tc->second &&
-                        (dc == done_cost.end() || rcost[*it] > dc->second)) {
+                    bool cut = !probe[*it] && tc != timeout_cost.end() && timeouts_n[key] >= 2 &&
+                               rcost[*it] >= tc->second && (dc == done_cost.end() || rcost[*it] > dc->second);
+                    if (cut && ++shed_seen[key] % SHED_PROBE == 0) {
+                        probe[*it] = 1;
+                        cut = false;
+                    }
+                    if (cut) {
                         res[*it].status = PM_E_TIMEOUT;
                         res[*it].latency_s = now_s() - reqs[*it].arrival_s;
                         ++finished;

@@ -182,8 +182,9 @@ def test_serving_deadline(eng, graphs):
 
 
 def test_serving_sheds_after_timeout(eng, graphs):
-    """A request estimated at the work of a batch that already timed out ends
-    at admission; cheaper requests still complete, exactly."""
+    """Once its class has timed out twice, a request estimated at the work of
+    a batch that timed out ends at admission; cheaper requests still
+    complete, exactly."""
     import paper_2012_04553_amd as pm
     gs, ids = graphs
     heavy_g = gen.rmat(14, 16, seed=3)
@@ -194,14 +195,17 @@ def test_serving_sheds_after_timeout(eng, graphs):
         light = _trace(ids[:1], 12, 10.0, seed=13)
         reqs += [(t, gid, pats, m) for (t, gid, pats, m) in light]
         reqs.append((light[-1][0] + 1.5, hid, heavy, pm.MORPH_NONE))
+        reqs.append((light[-1][0] + 3.0, hid, heavy, pm.MORPH_NONE))
         reqs.sort(key=lambda q: q[0])
         with _enumerating(eng):
             res, st = eng.serve(reqs, max_slots=4, max_batch=4, deadline_s=0.5)
         heavy_idx = [i for i, q in enumerate(reqs) if q[1] == hid]
-        assert [res[i]["status"] for i in heavy_idx] == [-7, -7]
+        assert [res[i]["status"] for i in heavy_idx] == [-7, -7, -7]
         assert st["shed"] >= 1
-        # the second heavy request never ran: it ended at admission
-        assert res[heavy_idx[1]]["service_s"] == 0.0
+        # the second heavy request ran to its deadline (one timeout is not
+        # enough); the third never ran: it ended at admission
+        assert res[heavy_idx[1]]["service_s"] > 0.0
+        assert res[heavy_idx[2]]["service_s"] == 0.0
         for q, r in zip(reqs, res):
             if q[1] == hid:
                 continue
